@@ -1,0 +1,88 @@
+"""MetaDE outer loop (the evolver) -- oracle (test infrastructure only).
+
+Restates Alg. 3 and Secs. III-B..III-E of the paper:
+  * the evolver is DE/rand/1/bin with F = 0.5, CR = 0.9 (Sec. III-E; the
+    experimental setup of Sec. IV-A1) over 6-D vectors in the theta box;
+  * the initial fitness of every evolver individual is +inf, so every trial
+    of the first outer generation is accepted;
+  * each trial is decoded (floor of the categorical parts) and scored by one
+    executor run; all executors share the same random stream (one-shot
+    evaluation, Sec. III-C), so the score is a deterministic function of theta;
+  * the last outer generation runs the executors for 5 G' generations
+    (power-up, Sec. III-D);
+  * selection keeps the trial iff its score <= the target's.
+
+The evolver draws its random numbers from the executor's Philox layout with
+the stream word's top bit set, so the two never share counters.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import philox
+from .pde import (BIN, RAND, clip_theta, decode, init_population, make_trials, order_key,
+                  run_executor, theta_bounds)
+
+OUTER_THETA = {"F": np.float32(0.5), "CR": np.float32(0.9), "bl": RAND, "br": RAND, "dn": 1,
+               "cs": BIN}
+
+
+def outer_stream(stream: int) -> int:
+    return philox.OUTER_STREAM_BIT | (int(stream) & 0x7FFFFFFF)
+
+
+def outer_init(P, seed, stream, n_cs):
+    lo, hi = theta_bounds(n_cs)
+    X = init_population(P, 6, seed, outer_stream(stream), lo, hi)
+    y = np.full(P, np.inf)
+    return X, y
+
+
+def outer_trials(X, y, g_o, seed, stream, n_cs, F=0.5, CR=0.9):
+    """DE/rand/1/bin trial vectors of the evolver, clipped to the theta box."""
+    lo, hi = theta_bounds(n_cs)
+    th = dict(OUTER_THETA)
+    th["F"], th["CR"] = np.float32(F), np.float32(CR)
+    U, desc = make_trials(X, y, th, g_o, seed, outer_stream(stream), lo, hi)
+    return clip_theta(U, n_cs), desc
+
+
+def outer_select(X, y, U, y_trial):
+    accept = ~np.isnan(y_trial) & (order_key(y_trial) <= order_key(y))
+    return (np.where(accept[:, None], U, X).astype(np.float32), np.where(accept, y_trial, y),
+            accept)
+
+
+def run_metade(wl, gens=None, power_up=None, decide="f32", executor=None, log=None):
+    """Alg. 3 on a workload with an outer loop.  Returns the evolver state and
+    the best (theta, y, x) found."""
+    o = wl.outer
+    P = o["P"]
+    gens = o["gens"] if gens is None else gens
+    pu = o.get("power_up", 5) if power_up is None else power_up
+    stream = int(wl.stream[0])
+    X, y = outer_init(P, wl.seed, stream, wl.n_cs)
+    best_x = np.zeros((P, wl.D_of(0)), np.float32)
+    for g_o in range(gens):
+        U, _ = outer_trials(X, y, g_o, wl.seed, stream, wl.n_cs, o["F"], o["CR"])
+        dec = decode(U, wl.n_cs)
+        G = wl.G * (pu if g_o == gens - 1 else 1)
+        ys = np.empty(P)
+        xs = np.zeros_like(best_x)
+        for i in range(P):
+            th = {k: v[i] for k, v in dec.items()}
+            prob = wl.problems[int(wl.problem[i])]
+            if executor is not None:
+                res = executor(i, th, G)
+            else:
+                res = run_executor(int(wl.N[i]), prob.D, th, G, wl.seed, int(wl.stream[i]),
+                                   wl.lb, wl.ub, prob, decide)
+            ys[i] = res["y"]
+            xs[i] = res["best_x"]
+        X, y, acc = outer_select(X, y, U, ys)
+        best_x = np.where(acc[:, None], xs, best_x)
+        if log is not None:
+            log.append({"g": g_o, "U": U, "y_trial": ys, "accept": acc})
+    b = int(np.lexsort((np.arange(P), order_key(y)))[0])
+    return {"X": X, "y": y, "best_index": b, "best_theta": X[b], "best_y": float(y[b]),
+            "best_x": best_x[b], "best_x_all": best_x}

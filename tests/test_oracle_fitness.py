@@ -1,0 +1,167 @@
+"""Pins of the oracle's objective functions: closed-form optima, textbook
+reductions, rotation orientation, and the control workload's closed form."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import fitness
+from oracle.fitness import evaluate
+
+KINDS = ["rastrigin", "elliptic", "ackley", "rosenbrock", "schwefel", "hybrid"]
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("D", [2, 10, 20])
+def test_optimum_is_bias_at_shift(kind, D):
+    p = W.make_problem(kind, D, 0, 3)
+    f = evaluate(p.o[None, :], p)[0]
+    assert abs(f - p.bias) < 1e-9 * max(1.0, abs(p.bias))
+
+
+def _identity(kind, D, seed=1):
+    return W.make_problem(kind, D, seed, 0, identity_rotation=True)
+
+
+def test_rastrigin_textbook_values():
+    p = _identity("rastrigin", 3)
+    u = p.o.astype(np.float64) + np.array([1.0, 0.5, 0.0])
+    u32 = u.astype(np.float32)
+    y = u32.astype(np.float64) - p.o
+    ref = sum(t * t - 10 * np.cos(2 * np.pi * t) + 10 for t in y) + 100
+    assert evaluate(u32, p) == pytest.approx(ref, rel=1e-14)
+    # integer offsets: cos term vanishes
+    off = np.array([1, -2, 3], np.float64)
+    u32 = (p.o + off).astype(np.float32)
+    y = u32.astype(np.float64) - p.o
+    assert evaluate(u32, p) == pytest.approx(float(np.sum(y * y - 10 * np.cos(2 * np.pi * y) + 10) + 100))
+
+
+def test_rastrigin_1d_grid_minimum_at_shift():
+    p = _identity("rastrigin", 1)
+    grid = (p.o[0] + np.linspace(-5, 5, 20001)).astype(np.float32)
+    f = evaluate(grid[:, None], p)
+    assert abs(float(grid[np.argmin(f)]) - float(p.o[0])) < 1e-3
+
+
+def test_sphere_rotation_invariance():
+    """Elliptic with condition 1 is the sphere, invariant under any orthogonal R."""
+    p = W.make_problem("elliptic", 12, 4, 0)
+    p.cond = 1.0
+    rng = np.random.default_rng(0)
+    u = rng.uniform(-100, 100, (50, 12)).astype(np.float32)
+    ref = np.sum((u.astype(np.float64) - p.o) ** 2, axis=1) + 100
+    assert np.allclose(evaluate(u, p), ref, rtol=1e-6)  # R is orthogonal to float32 accuracy
+
+
+def test_rotation_orientation():
+    """z = R (u - o): with R the cyclic map e0 -> e2, a unit step along e0 lands
+    on the last (heaviest) elliptic weight, not the middle one."""
+    p = _identity("elliptic", 3)
+    p.R = np.array([[0, 1, 0], [0, 0, 1], [1, 0, 0]], np.float32)
+    u = (p.o.astype(np.float64) + np.array([1.0, 0, 0])).astype(np.float32)
+    y0 = float(u[0]) - float(p.o[0])
+    assert evaluate(u, p) == pytest.approx(100 + 1e6 * y0 * y0, rel=1e-12)
+
+
+def test_elliptic_weights():
+    w = fitness.elliptic_weights(7)
+    assert w[0] == 1.0 and w[-1] == pytest.approx(1e6) and np.allclose(np.diff(np.log10(w)), 1.0)
+
+
+def test_ackley_values():
+    p = _identity("ackley", 4)
+    y = np.array([0.5, 0.5, 0.5, 0.5])
+    u = (p.o + y).astype(np.float32)
+    y = u.astype(np.float64) - p.o
+    ref = -20 * np.exp(-0.2 * np.sqrt(np.mean(y * y))) - np.exp(np.mean(np.cos(2 * np.pi * y))) + 20 + np.e + 100
+    assert evaluate(u, p) == pytest.approx(ref, rel=1e-14)
+    far = (p.o + 1e3).astype(np.float32)
+    assert evaluate(far, p) > 100 + 19
+
+
+def test_rosenbrock_values():
+    p = _identity("rosenbrock", 2)
+    # z = u - o + 1 = (0, 0) -> 100*(0-0)^2 + (0-1)^2 = 1
+    u = (p.o.astype(np.float64) - 1.0).astype(np.float32)
+    z = u.astype(np.float64) - p.o + 1
+    assert evaluate(u, p) == pytest.approx(100 * (z[0] ** 2 - z[1]) ** 2 + (z[0] - 1) ** 2 + 100, rel=1e-12)
+    assert abs(evaluate(u, p) - 101) < 1e-3
+
+
+def test_schwefel_textbook_form():
+    """g = 418.98... D - sum x sin(sqrt|x|) at x = z + z*, minimised near x = 420.97."""
+    p = _identity("schwefel", 3)
+    assert fitness.SCHWEFEL_CS == pytest.approx(418.9829, abs=1e-4)
+    u = (p.o + np.array([10.0, -20.0, 0.0])).astype(np.float32)
+    x = u.astype(np.float64) - p.o + fitness.SCHWEFEL_ZSTAR
+    ref = 3 * fitness.SCHWEFEL_CS - np.sum(x * np.sin(np.sqrt(np.abs(x)))) + 100
+    assert evaluate(u, p) == pytest.approx(ref, rel=1e-13)
+    assert evaluate(u, p) > 100
+
+
+def test_hybrid_is_sum_of_parts():
+    p = W.make_problem("hybrid", 20, 2, 0)
+    assert p.split == (6, 7, 7)
+    assert sorted(p.perm.tolist()) == list(range(20))
+    rng = np.random.default_rng(1)
+    u = rng.uniform(-100, 100, 20).astype(np.float32)
+    z = p.R.astype(np.float64) @ (u.astype(np.float64) - p.o)
+    zp = z[p.perm.astype(int)]
+    s = fitness.g_schwefel(zp[:6]) + fitness.g_rastrigin(zp[6:13]) + fitness.g_elliptic(zp[13:])
+    assert evaluate(u, p) == pytest.approx(s + 100, rel=1e-13)
+
+
+def test_rotation_is_orthogonal():
+    for D in (2, 10, 20, 100):
+        R = W.make_problem("rastrigin", D, 3, 1).R.astype(np.float64)
+        assert np.abs(R @ R.T - np.eye(D)).max() < 1e-5
+
+
+# ---------------------------------------------------------------- control workload
+
+def test_policy_sizes_table_vii():
+    """Table VII: in->32->32->out policies of Hopper (11->3), Swimmer (8->2),
+    Reacher (11->2) have 1539, 1410 and 1506 parameters; 17->64->64->6 has 5702."""
+    assert W.mlp_param_count(11, (32, 32), 3) == 1539
+    assert W.mlp_param_count(8, (32, 32), 2) == 1410
+    assert W.mlp_param_count(11, (32, 32), 2) == 1506
+    assert W.mlp_param_count(17, (64, 64), 6) == 5702
+
+
+def test_lqr_zero_policy_closed_form():
+    """W = 0 gives u = 0, so J = sum_t |A^t x0|^2."""
+    p = W.make_problem("lqr_mlp", 5702, 4, 0)
+    A = p.A.astype(np.float64)
+    x = p.x0[0].astype(np.float64)
+    ref = 0.0
+    for t in range(p.steps):
+        xt = np.linalg.matrix_power(A, t) @ x
+        ref += xt @ xt
+    assert fitness.lqr_mlp(np.zeros(5702, np.float32), p) == pytest.approx(ref, rel=1e-10)
+    rho = np.max(np.abs(np.linalg.eigvals(A)))
+    assert rho == pytest.approx(0.95, abs=1e-6)
+
+
+def test_lqr_constant_action_closed_form():
+    """Only the last layer's bias nonzero: u_t = tanh(b3) for every t."""
+    p = W.make_problem("lqr_mlp", 5702, 4, 1)
+    w = np.zeros(5702, np.float32)
+    b3 = np.array([0.5, -0.3, 0.2, 0.0, 1.0, -1.0], np.float32)
+    w[-6:] = b3
+    ua = np.tanh(b3.astype(np.float64))
+    A, B = p.A.astype(np.float64), p.B.astype(np.float64)
+    x = p.x0[0].astype(np.float64)
+    ref = 0.0
+    for t in range(p.steps):
+        ref += x @ x + 0.01 * ua @ ua
+        x = A @ x + B @ ua
+    assert fitness.lqr_mlp(w, p) == pytest.approx(ref, rel=1e-10)
+
+
+def test_lqr_flatten_order():
+    """The first 64*17 weights are W1 row-major: W1[k, j] multiplies x[j] into unit k."""
+    layers = fitness.unflatten_policy(np.arange(5702, dtype=np.float64), 17, (64, 64), 6)
+    W1, b1 = layers[0]
+    assert W1.shape == (64, 17) and W1[1, 0] == 17 and b1[0] == 64 * 17
+    W3, b3 = layers[2]
+    assert W3.shape == (6, 64) and b3[-1] == 5701
