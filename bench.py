@@ -1,0 +1,191 @@
+#!/usr/bin/env python3
+"""Throughput of the MetaDE inner-DE path on one MI355X.
+
+Metric: inner-DE individual evaluations per second, sum over runs of
+N * generations / wall time, with the inputs resident in HBM.  One step is one
+full pass of the workload: for the default workload (full MetaDE at D=20:
+evolver population 64, 10 outer generations of executors with N=100 and 1000
+generations, the last one powered up 5x) that is every row of the path --
+theta decode, initialisation, ranking, index sampling, mutation, crossover,
+fitness, selection, float64 best record and the evolver step.
+
+Prints one JSON line.  The generation kernel's average duration is taken with
+HIP events on the library's stream around every launch of it inside the
+timed region; its algorithmic work is the VALU lane-slot count of the
+operations each trial needs (see ``alg_slots_per_trial``).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz, one full-rate VALU
+# instruction per lane per clock (packed float32 not used).
+VALU_PEAK_SLOTS = 256 * 64 * 2.4e9
+HBM_PEAK_GBS = 8000.0
+
+PHILOX_SLOTS = 100   # 10 rounds x (2 quarter-rate 32x32->64 multiplies + 2 three-input XORs)
+ELEM_SLOTS = {       # per element of z: square/accumulate + the element function
+    "rastrigin": 9, "ackley": 9, "elliptic": 3, "rosenbrock": 6, "schwefel": 14,
+}
+ELEM_SLOTS["hybrid"] = (6 * ELEM_SLOTS["schwefel"] + 7 * ELEM_SLOTS["rastrigin"]
+                        + 7 * ELEM_SLOTS["elliptic"]) / 20.0
+
+
+def decode(theta, n_cs):
+    lo = np.array([0, 0, 1, 1, 1, 1], np.float32)
+    hi = np.array([1, 1, 5, 5, 5, 1 + n_cs], np.float32)
+    t = np.minimum(np.maximum(np.nan_to_num(theta, nan=0.0), lo), hi)
+    cat = np.minimum(np.floor(t[:, 2:]).astype(int), [4, 4, 4, n_cs])
+    return t[:, 0], t[:, 1], cat[:, 0], cat[:, 1], cat[:, 2], cat[:, 3]
+
+
+def alg_slots_per_trial(N, D, kind, bl, br, dn, cs, CR):
+    """VALU lane-slots one trial evaluation needs (algorithmic count, weighted
+    by issue cost: quarter-rate integer multiplies and transcendentals = 4)."""
+    m = int(1 in (bl, br)) + 2 * dn
+    calls = 2 + (1 if m > 4 else 0)
+    words = m + 3
+    if cs == 1:
+        calls += math.ceil(D / 4)
+        words += D
+    elif cs == 2:
+        tests = sum(float(CR) ** k for k in range(max(D - 1, 0)))
+        calls += tests / 4.0
+        words += tests
+    rng = calls * PHILOX_SLOTS + 3 * words
+    sampler = m * 4 + m * (m + 1)
+    mutation = D * (2 * dn + 1 + (3 if bl != br else 0))
+    cross = D * (3 if cs in (1, 3) else 2)
+    clip_shift = 3 * D
+    rotation = D * D
+    elem = D * ELEM_SLOTS[kind] + D
+    ranking = 2 * math.log2(max(N, 2))
+    return rng + sampler + mutation + cross + clip_shift + rotation + elem + ranking + 2
+
+
+def launch_slots(wl, theta, G):
+    F, CR, bl, br, dn, cs = decode(theta, wl.n_cs)
+    tot = 0.0
+    for r in range(wl.n_runs):
+        p = wl.problems[int(wl.problem[r])]
+        N = int(wl.N[r])
+        tot += N * G * alg_slots_per_trial(N, p.D, p.kind, bl[r], br[r], dn[r], cs[r], CR[r])
+    return tot
+
+
+def cpu_baseline(wl, budget_s=12.0):
+    """The oracle (untuned) on a bounded sample of the same workload."""
+    try:
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(limits=1)
+    except Exception:  # pragma: no cover
+        limiter = None
+    from oracle import metade as ometa
+    from oracle import pde
+
+    X, y = ometa.outer_init(wl.outer["P"] if wl.outer else wl.n_runs, wl.seed, int(wl.stream[0]),
+                            wl.n_cs)
+    U, _ = ometa.outer_trials(X, y, 0, wl.seed, int(wl.stream[0]), wl.n_cs)
+    th = pde.decode(U, wl.n_cs)
+    evals = 0
+    runs = 0
+    G = 100
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s and runs < wl.n_runs:
+        r = runs
+        prob = wl.problems[int(wl.problem[r])]
+        t = {k: v[r] for k, v in th.items()}
+        pde.run_executor(int(wl.N[r]), prob.D, t, G, wl.seed, int(wl.stream[r]), wl.lb, wl.ub, prob)
+        evals += int(wl.N[r]) * G
+        runs += 1
+    dt = time.perf_counter() - t0
+    if limiter is not None:
+        limiter.unregister() if hasattr(limiter, "unregister") else None
+    return {"value": evals / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"{runs} executor runs of the workload's shape (N={int(wl.N[0])}, "
+                      f"D={wl.problems[0].D}, {wl.problems[0].kind}), {G} generations each, "
+                      f"theta from the first evolver trial, {dt:.1f} s on one host core"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c3", choices=["c3"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU: the executor batch is not "
+                                   "sharded across GPUs (run with --gpus 1)"}))
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    from paper_2502_10470_amd import Batch
+
+    wl = W.workload_c3()
+    P, gens, G, pu = wl.outer["P"], wl.outer["gens"], wl.G, wl.outer["power_up"]
+    b = Batch(wl)
+    evals = wl.evals_per_pass()
+
+    # theta of every outer generation (deterministic: identical in every pass)
+    b.outer_reset()
+    thetas = []
+    for g in range(gens):
+        b.outer_step(G, pu if g == gens - 1 else 1)
+        thetas.append(b.get_outer()[2].copy())
+    slots = sum(launch_slots(wl, thetas[g], G * (pu if g == gens - 1 else 1)) for g in range(gens))
+
+    for _ in range(args.warmup):
+        b.run(gens, G, pu)
+    torch.cuda.synchronize()
+    b.kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    best = None
+    for _ in range(args.steps):
+        best = b.run(gens, G, pu)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    k_ms, k_launches = b.kernel_time()
+    b.kernel_timing(False)
+    dt = t1 - t0
+    ms_per_step = 1000.0 * dt / args.steps
+    value = evals * args.steps / dt
+    avg_launch_ms = k_ms / max(k_launches, 1)
+    slots_per_launch = slots / gens
+    achieved = slots_per_launch / (avg_launch_ms * 1e-3)
+
+    line = {
+        "metric": "inner-DE individual-evals/sec (runs x N x gens / s) at D=20",
+        "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "full MetaDE at D=20 (evolver 64 x 10 gens, executors N=100, "
+                               "1000 gens, power-up 5x, seeded hybrid Schwefel/Rastrigin/elliptic)",
+                   "runs": P, "N": 100, "D": 20, "inner_gens": G, "outer_gens": gens,
+                   "evals_per_step": evals, "best_y": best[0]},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_SLOTS / 1e12,
+                     "unit": "Tslot/s", "frac": achieved / VALU_PEAK_SLOTS, "traffic": None,
+                     "kernel": "k_generations", "avg_launch_ms": avg_launch_ms,
+                     "launches": k_launches, "slots_per_launch": slots_per_launch,
+                     "occupied_cu_frac": min(P, 256) / 256.0},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

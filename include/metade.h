@@ -1,0 +1,226 @@
+/*
+ * metade.h -- C ABI of the MetaDE inner-DE library for AMD Instinct MI355X (gfx950).
+ *
+ * What it computes (paper: "MetaDE: Evolving Differential Evolution by
+ * Differential Evolution", arXiv 2502.10470):
+ *   - many Parameterized DE executors (Sec. III-A, Alg. 2) side by side, each
+ *     with its own hyperparameter vector theta = (F, CR, bl, br, dn, cs);
+ *     per generation: ranking (best / top-p), index sampling, mutation
+ *     (Eq. 12), crossover (Eqs. 8-10), clipping to the search box, fitness,
+ *     greedy selection (Alg. 1 selection rule);
+ *   - the evolver of MetaDE (Alg. 3): DE/rand/1/bin over theta with one-shot
+ *     evaluation (Sec. III-C) and the power-up schedule (Sec. III-D).
+ *
+ * Conventions shared by every entry point:
+ *   - All device pointers are plain HIP device addresses owned by the caller
+ *     unless stated otherwise; the context keeps them (non-owning) and they
+ *     must outlive it.  The context owns only its internal scratch memory.
+ *   - Work is enqueued on the caller's HIP stream (metade_config.stream) and
+ *     is asynchronous unless an entry point says it synchronises.
+ *   - Errors are returned as metade_status; nothing is thrown across the ABI.
+ *     Device errors of asynchronous work surface as METADE_EDEVICE at the next
+ *     synchronising call.  metade_last_error() gives a readable message.
+ *   - A context is not thread-safe; use one context per stream.
+ *   - Random numbers: Philox4x32-10 (Salmon et al., SC'11) with
+ *     key = (seed & 0xffffffff, seed >> 32) and
+ *     counter = (block, individual, phase, stream); phase is the generation
+ *     number, 0xffffffff for the initial population; the evolver uses
+ *     stream | 0x80000000.  Word w of an individual is word w % 4 of block
+ *     w / 4: words 0..8 index draws, 9 pbest pick, 10 j_rand or start n,
+ *     11 K, 12 + t crossover uniform t.
+ *
+ * Memory layouts (device, caller-owned):
+ *   pop    float32, runs packed in order; run r occupies N_r * D_r floats
+ *          starting at float offset sum_{s<r} N_s D_s, individual-major
+ *          (individual i, gene j at i * D_r + j).
+ *   fit    float32 [sum_r N_r], same run packing; fitness in the precision
+ *          selection decisions are taken in.
+ *   best_y float64 [n_runs]: y* of each run (fitness of its best individual,
+ *          evaluated in float64 on the GPU).
+ *   best_x float32 [sum_r D_r]: that individual.
+ */
+#ifndef METADE_H
+#define METADE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct metade_ctx metade_ctx;
+
+typedef enum {
+  METADE_OK = 0,
+  METADE_EINVAL = -1,   /* invalid argument or configuration */
+  METADE_ENOMEM = -2,   /* device allocation of internal scratch failed */
+  METADE_EDEVICE = -3,  /* a HIP call or an earlier asynchronous launch failed */
+  METADE_ESTATE = -4    /* call out of order (e.g. outer step before outer reset) */
+} metade_status;
+
+typedef enum {
+  METADE_FP32 = 0,        /* fitness contraction in float32 (plain path) */
+  METADE_BF16_REFINE = 1  /* bf16 matrix-core contraction, float32 re-evaluation of near ties */
+} metade_precision;
+
+/* Objective functions: z = R (u - o) [+ c], f = g(z) + bias (textbook base
+ * functions standing in for the paper's CEC2022 suite, Sec. IV-A). */
+typedef enum {
+  METADE_FN_RASTRIGIN = 1,
+  METADE_FN_ROSENBROCK = 2,  /* c = 1 */
+  METADE_FN_ACKLEY = 3,
+  METADE_FN_ELLIPTIC = 4,    /* weights cond^(j/(D-1)) */
+  METADE_FN_SCHWEFEL = 5,    /* c = 420.96875 */
+  METADE_FN_HYBRID = 6,      /* permuted blocks: Schwefel | Rastrigin | elliptic */
+  METADE_FN_LQR_MLP = 7      /* tanh policy scored by a linear-system rollout */
+} metade_fn;
+
+/* One problem instance.  Device pointers are caller-owned. */
+typedef struct {
+  uint32_t kind;         /* metade_fn */
+  uint32_t D;            /* decision dimension */
+  float bias;            /* added to g(z) */
+  float cond;            /* elliptic condition number (elliptic and hybrid) */
+  const float *o;        /* device [D] shift (not used by LQR_MLP) */
+  const float *R;        /* device [D*D] row-major orthogonal rotation, z_j = sum_k R[j*D+k] y_k */
+  const uint32_t *perm;  /* device [D] hybrid permutation (HYBRID only, else NULL) */
+  uint32_t split[3];     /* hybrid block sizes, sum = D */
+  /* control workload (LQR_MLP): policy obs -> hidden1 -> hidden2 -> act with
+   * tanh on every layer, weights flattened W1 (hidden1 x obs, row-major), b1,
+   * W2, b2, W3, b3; cost sum_{t<steps} |x_t|^2 + ctrl_weight |u_t|^2 averaged
+   * over n_rollouts initial states; x_{t+1} = A x_t + B u_t. */
+  uint32_t obs, act, hidden1, hidden2, steps, n_rollouts;
+  float ctrl_weight;
+  const float *A;        /* device [obs*obs] row-major */
+  const float *B;        /* device [obs*act] row-major */
+  const float *x0;       /* device [n_rollouts*obs] */
+} metade_problem;
+
+typedef struct {
+  uint32_t n_runs;                 /* number of executors (>= 1) */
+  const uint32_t *N;               /* host [n_runs] population sizes */
+  const uint32_t *problem;         /* host [n_runs] index into problems */
+  const uint32_t *stream_id;       /* host [n_runs] Philox stream; equal streams give the
+                                      one-shot common seed of Sec. III-C */
+  uint32_t n_problems;
+  const metade_problem *problems;  /* host [n_problems]; copied at init */
+  uint64_t seed;                   /* Philox key */
+  float lb, ub;                    /* search box of every gene, lb < ub */
+  uint32_t n_cs;                   /* crossover schemes in the theta space: 2 (bin, exp) or 3 (+arith) */
+  uint32_t precision;              /* metade_precision */
+  float *pop;                      /* device, caller-owned, see layouts above */
+  float *fit;
+  double *best_y;
+  float *best_x;
+  void *stream;                    /* hipStream_t (NULL = default stream) */
+} metade_config;
+
+/* Sizes in bytes of the caller-owned buffers and of the library's internal
+ * scratch for this configuration.  Validates the configuration (see
+ * metade_init).  Any output pointer may be NULL. */
+metade_status metade_query_sizes(const metade_config *cfg, size_t *pop_bytes, size_t *fit_bytes,
+                                 size_t *best_y_bytes, size_t *best_x_bytes, size_t *scratch_bytes);
+
+/* Validate cfg, allocate internal scratch, copy the run and problem tables to
+ * the device, set every run's theta to DE/rand/1/bin with F = 0.5, CR = 0.9,
+ * and initialise every population (Alg. 2 initialisation and first
+ * evaluation; x = lb + (ub - lb) (w >> 8) 2^-24 in float64, rounded once).
+ * Rejected with METADE_EINVAL: n_runs = 0, N_r < 10 (the largest index draw,
+ * 1 + 2 * 4 distinct indices plus the target), N_r > 256 or D_r > 128 for the
+ * shifted-rotated kinds, N_r > 1024 for LQR_MLP, lb >= ub, |lb| or |ub|
+ * > 1e30, n_cs not in {2, 3}, a problem index out of range, a missing device
+ * pointer, an unknown kind.  On success *out owns the context. */
+metade_status metade_init(const metade_config *cfg, metade_ctx **out);
+
+/* Re-run the initialisation and first evaluation of every run and reset the
+ * generation counter to 0 (a fresh executor run with the same streams). */
+metade_status metade_reset(metade_ctx *ctx);
+
+/* Set every run's theta from host memory theta[n_runs][6] = (F, CR, bl, br,
+ * dn, cs) in the continuous encoding.  On the device each vector is clipped
+ * to the box [0,1]^2 x [1,5]^3 x [1, 1 + n_cs] (NaN -> lower bound) and
+ * decoded as in Alg. 3: F, CR as is, categorical parts by floor with the box
+ * end mapped to the last category (bl, br: 1 rand, 2 best, 3 pbest,
+ * 4 current; dn 1..4; cs: 1 bin, 2 exp, 3 arith). */
+metade_status metade_set_theta(metade_ctx *ctx, const float *theta);
+
+/* Advance every run by n_generations generations of Alg. 2 (ranking, index
+ * sampling, Eq. 12 mutation, Eq. 8-10 crossover, clip, fitness, greedy
+ * selection), then refresh the best record (best_y in float64, best_x).
+ * Asynchronous.  n_generations = 0 only refreshes the record. */
+metade_status metade_inner_step(metade_ctx *ctx, uint32_t n_generations);
+
+/* Sizes of the trace buffers of metade_inner_step_trace, in bytes. */
+metade_status metade_trace_sizes(metade_ctx *ctx, size_t *u_bytes, size_t *fu_bytes,
+                                 size_t *desc_bytes);
+
+/* One generation exactly like metade_inner_step(ctx, 1), additionally writing
+ * per trial (device buffers, caller-owned, packed like pop / fit):
+ *   u    float32 trial vector after crossover and clipping;
+ *   fu   float32 its fitness as used by selection;
+ *   desc int32 [sum_r N_r][16]: 0 base-left index, 1 base-right index,
+ *        2..9 difference pairs (a1,b1,..,a4,b4; -1 unused), 10 j_rand or n,
+ *        11 L (exponential) or -1, 12 pbest rank, 13 rand index or -1,
+ *        14 K bits (float32) , 15 accept flag. */
+metade_status metade_inner_step_trace(metade_ctx *ctx, float *u, float *fu, int32_t *desc);
+
+/* Evolver (Alg. 3).  The context's runs are the P = n_runs executors of one
+ * outer population.  metade_outer_reset draws the initial population in the
+ * theta box on the device and sets every fitness to +inf. */
+metade_status metade_outer_reset(metade_ctx *ctx);
+
+/* One outer generation: DE/rand/1/bin trial vectors (F = 0.5, CR = 0.9),
+ * clipped and decoded into the runs' theta; all executors re-initialised
+ * (same streams: one-shot evaluation) and run for G_inner generations
+ * (G_inner * power_up if power_up > 1: Sec. III-D); y* of each run; the
+ * trial replaces its target iff y*(trial) <= y(target).  Asynchronous. */
+metade_status metade_outer_step(metade_ctx *ctx, uint32_t G_inner, uint32_t power_up);
+
+/* Copy the evolver state to host memory (synchronises): X[n_runs][6],
+ * y[n_runs], the last trial vectors U[n_runs][6] and their scores
+ * y_trial[n_runs]; any pointer may be NULL. */
+metade_status metade_get_outer(metade_ctx *ctx, float *X, double *y, float *U, double *y_trial);
+
+/* Set the evolver state from host memory (X[n_runs][6], y[n_runs]) and the
+ * outer generation counter. */
+metade_status metade_set_outer(metade_ctx *ctx, const float *X, const double *y, uint32_t gen);
+
+/* Whole MetaDE run (synchronises): outer reset, outer_gens outer generations
+ * of G_inner inner generations, the last multiplied by power_up, then the
+ * best evolver individual: its score, theta, and the best x of the executor
+ * run that produced it.  Host outputs; best_x has D of that run's problem. */
+metade_status metade_run(metade_ctx *ctx, uint32_t outer_gens, uint32_t G_inner, uint32_t power_up,
+                         double *best_y, float *best_theta, float *best_x);
+
+/* Copy best_y[n_runs] to host memory (synchronises). */
+metade_status metade_get_best(metade_ctx *ctx, double *y);
+
+/* Checkpoint: all state that determines future results (populations,
+ * fitness, theta, generation counters, evolver state, best records) as an
+ * opaque host blob.  With blob == NULL only *bytes is set.  Synchronises. */
+metade_status metade_get_state(metade_ctx *ctx, void *blob, size_t *bytes);
+metade_status metade_set_state(metade_ctx *ctx, const void *blob, size_t bytes);
+
+/* Timing of the generation kernel: when enabled, every launch of it is
+ * bracketed by HIP events on the context's stream; metade_kernel_time
+ * synchronises and returns the summed milliseconds and launch count since
+ * the last enable. */
+metade_status metade_kernel_timing(metade_ctx *ctx, int enable);
+metade_status metade_kernel_time(metade_ctx *ctx, double *ms, uint64_t *launches);
+
+/* Counters of the last metade_inner_step / outer step (synchronises):
+ * trials evaluated, trials re-evaluated in float32 (BF16_REFINE only). */
+metade_status metade_get_counters(metade_ctx *ctx, uint64_t *trials, uint64_t *refined);
+
+/* Readable message of the last error on ctx (or of the last failed
+ * metade_init when ctx is NULL).  Never NULL. */
+const char *metade_last_error(const metade_ctx *ctx);
+
+/* Release the context's scratch.  Safe on NULL. */
+void metade_destroy(metade_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* METADE_H */

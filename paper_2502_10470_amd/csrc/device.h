@@ -1,0 +1,279 @@
+// Device-side building blocks of the MetaDE inner-DE path (gfx950).
+//
+// Everything here follows the paper's Parameterized DE (Sec. III-A, Alg. 2)
+// and MetaDE (Alg. 3); random numbers come from Philox4x32-10 (Salmon et al.,
+// SC'11).  Floating-point DE arithmetic is float32 with one rounding per
+// operation and no contraction (the library is compiled with
+// -ffp-contract=off), so trial vectors are bit-reproducible.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mde {
+
+// ---------------------------------------------------------------- constants
+
+constexpr uint32_t PH_M0 = 0xD2511F53u;
+constexpr uint32_t PH_M1 = 0xCD9E8D57u;
+constexpr uint32_t PH_W0 = 0x9E3779B9u;
+constexpr uint32_t PH_W1 = 0xBB67AE85u;
+constexpr uint32_t INIT_PHASE = 0xFFFFFFFFu;
+constexpr uint32_t OUTER_BIT = 0x80000000u;
+
+enum Base { RAND = 1, BEST = 2, PBEST = 3, CURRENT = 4 };
+enum Cross { BIN = 1, EXP = 2, ARITH = 3 };
+enum Word { W_PBEST = 9, W_JRAND = 10, W_K = 11, W_GENE0 = 12 };
+enum Kind { FN_RASTRIGIN = 1, FN_ROSENBROCK = 2, FN_ACKLEY = 3, FN_ELLIPTIC = 4,
+            FN_SCHWEFEL = 5, FN_HYBRID = 6, FN_LQR_MLP = 7 };
+
+constexpr int MAX_N = 256;     // LDS-resident kernel: indices fit in 8 bits
+constexpr int MAX_D = 128;
+constexpr int MAX_KP = 32;     // top-p set size for N <= 256 is at most 26
+constexpr uint32_t LDS_BUDGET = 160 * 1024;
+constexpr float SCHWEFEL_ZSTAR = 420.96875f;
+
+// ---------------------------------------------------------------- tables
+
+// One executor run.  Theta fields are written by the decode kernel.
+struct RunDev {
+  uint32_t N, D, Dp, prob;      // Dp = D rounded up to a multiple of 4
+  uint32_t stream, kp, C, pad0; // kp = top-p count, C = trials per LDS chunk
+  uint64_t pop_off;             // float offset of the run in pop (N*D packing)
+  uint64_t pend_off;            // float offset in the pending buffer (N*Dp packing)
+  uint32_t fit_off, bx_off;     // offsets in fit / best_x
+  float F, CR;
+  int32_t bl, br, dn, cs;
+};
+
+struct ProbDev {
+  uint32_t kind, D;
+  float bias, ell_scale_f;      // log2(cond)/(D-1) (elliptic), or over the hybrid's third block
+  double ell_scale_d;
+  float cs_f, pad1;             // Schwefel constant z* sin(sqrt z*)
+  double cs_d;
+  const float *o;
+  const float *R;
+  const uint32_t *perm;
+  uint32_t n1, n2, n3, pad2;
+  // control workload
+  uint32_t obs, act, h1, h2, steps, nroll;
+  float cw, pad3;
+  const float *A;
+  const float *B;
+  const float *x0;
+};
+
+// ---------------------------------------------------------------- Philox4x32-10
+
+__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)PH_M0 * c0;
+    const uint64_t p1 = (uint64_t)PH_M1 * c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+    k0 += PH_W0;
+    k1 += PH_W1;
+  }
+  return make_uint4(c0, c1, c2, c3);
+}
+
+__device__ __forceinline__ uint32_t word_of(const uint4 &w, int t) {
+  return t == 0 ? w.x : (t == 1 ? w.y : (t == 2 ? w.z : w.w));
+}
+
+// floor(w * m / 2^32)
+__device__ __forceinline__ uint32_t lemire(uint32_t w, uint32_t m) { return __umulhi(w, m); }
+
+// ((w >> 8) + 1) 2^-24 in (0, 1], exact in float32
+__device__ __forceinline__ float unit_oc(uint32_t w) {
+  return (float)((w >> 8) + 1u) * 0x1p-24f;
+}
+
+// ---------------------------------------------------------------- ordering
+
+// Total order key of a fitness value: NaN counts as +inf, -0 as +0.
+__device__ __forceinline__ uint32_t okey(float f) {
+  if (f != f) f = __int_as_float(0x7F800000);
+  if (f == 0.0f) f = 0.0f;
+  const uint32_t b = __float_as_uint(f);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+// Selection rule: accept iff f(u) <= f(x), never a NaN trial, NaN target = +inf.
+__device__ __forceinline__ bool accept_trial(float fu, float fx) {
+  return (fu == fu) && ((fx != fx) || fu <= fx);
+}
+__device__ __forceinline__ bool accept_trial_d(double fu, double fx) {
+  return (fu == fu) && ((fx != fx) || fu <= fx);
+}
+
+// ---------------------------------------------------------------- LDS layout
+
+struct Lds {
+  uint32_t pop, fit, topk, desc, T, Y, Z, P, fu, acc, total;
+};
+
+__host__ __device__ inline uint32_t al16(uint32_t b) { return (b + 15u) & ~15u; }
+
+__host__ __device__ inline Lds lds_layout(uint32_t N, uint32_t Dp, uint32_t C) {
+  Lds l;
+  uint32_t o = 0;
+  const uint32_t Q = Dp / 4;
+  l.pop = o;  o += al16(N * Dp * 4);
+  l.fit = o;  o += al16(N * 4);
+  l.topk = o; o += al16(MAX_KP * 4);
+  l.desc = o; o += al16(N * 16);
+  l.T = o;    o += al16(C * Dp * 4);
+  l.Y = o;    o += al16(C * Dp * 4);
+  l.Z = o;    o += al16(C * Dp * 4);
+  l.P = o;    o += al16(C * Q * 8);
+  l.fu = o;   o += al16(N * 4);
+  l.acc = o;  o += al16(N * 4);
+  l.total = o;
+  return l;
+}
+
+// ---------------------------------------------------------------- sampler
+
+// Index sampling without rejection: draw k is the t_k-th smallest element of
+// {0..N-1} minus {i} minus the earlier draws, t_k = floor(w_k (N-1-k) / 2^32).
+// The excluded set is kept sorted; skipping every excluded value <= r in
+// ascending order turns the rank t into the element.
+__device__ __forceinline__ void sample_distinct(const uint32_t *w, int m, uint32_t i, uint32_t N,
+                                                uint32_t *draws) {
+  uint32_t ex[10];
+  ex[0] = i;
+#pragma unroll
+  for (int q = 1; q < 10; ++q) ex[q] = 0xFFFFFFFFu;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    if (k < m) {
+      uint32_t r = lemire(w[k], N - 1u - (uint32_t)k);
+#pragma unroll
+      for (int q = 0; q < 10; ++q) r += (ex[q] <= r) ? 1u : 0u;
+      draws[k] = r;
+      uint32_t carry = r;
+#pragma unroll
+      for (int q = 0; q < 10; ++q) {
+        const uint32_t lo = min(carry, ex[q]);
+        carry = max(carry, ex[q]);
+        ex[q] = lo;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- math per precision
+
+template <typename T> struct Math;
+
+template <> struct Math<float> {
+  // cos(2 pi z): exact reduction z - rint(z), then cos(pi * 2r)
+  static __device__ __forceinline__ float cos2pi(float z) {
+    const float r = z - rintf(z);
+    return cospif(2.0f * r);
+  }
+  static __device__ __forceinline__ float sin_(float x) { return sinf(x); }
+  static __device__ __forceinline__ float sqrt_(float x) { return sqrtf(x); }
+  static __device__ __forceinline__ float exp_(float x) { return expf(x); }
+  static __device__ __forceinline__ float exp2_(float x) { return exp2f(x); }
+  static __device__ __forceinline__ float abs_(float x) { return fabsf(x); }
+};
+
+template <> struct Math<double> {
+  static __device__ __forceinline__ double cos2pi(double z) {
+    const double r = z - rint(z);
+    return cospi(2.0 * r);
+  }
+  static __device__ __forceinline__ double sin_(double x) { return sin(x); }
+  static __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
+  static __device__ __forceinline__ double exp_(double x) { return exp(x); }
+  static __device__ __forceinline__ double exp2_(double x) { return exp2(x); }
+  static __device__ __forceinline__ double abs_(double x) { return fabs(x); }
+};
+
+template <typename T> __device__ __forceinline__ T ell_scale(const ProbDev &p);
+template <> __device__ __forceinline__ float ell_scale<float>(const ProbDev &p) { return p.ell_scale_f; }
+template <> __device__ __forceinline__ double ell_scale<double>(const ProbDev &p) { return p.ell_scale_d; }
+template <typename T> __device__ __forceinline__ T schwefel_cs(const ProbDev &p);
+template <> __device__ __forceinline__ float schwefel_cs<float>(const ProbDev &p) { return p.cs_f; }
+template <> __device__ __forceinline__ double schwefel_cs<double>(const ProbDev &p) { return p.cs_d; }
+
+// Per-element terms of the shifted-rotated functions.  z points at the run's
+// rotated vector; j is the element (for the hybrid: the permuted position).
+// Returns (term, second term) -- the second is used by Ackley only.
+template <typename T>
+__device__ __forceinline__ void fn_term(const ProbDev &p, const T *z, uint32_t j, T &t0, T &t1) {
+  using Mt = Math<T>;
+  t1 = T(0);
+  switch (p.kind) {
+    case FN_RASTRIGIN: {
+      const T v = z[j];
+      t0 = (v * v - T(10) * Mt::cos2pi(v)) + T(10);
+      break;
+    }
+    case FN_ELLIPTIC: {
+      const T v = z[j];
+      t0 = Mt::exp2_(T(j) * ell_scale<T>(p)) * (v * v);
+      break;
+    }
+    case FN_ACKLEY: {
+      const T v = z[j];
+      t0 = v * v;
+      t1 = Mt::cos2pi(v);
+      break;
+    }
+    case FN_ROSENBROCK: {
+      if (j + 1 < p.D) {
+        const T a = z[j] + T(1);
+        const T b = z[j + 1] + T(1);
+        const T c = a * a - b;
+        const T e = a - T(1);
+        t0 = T(100) * (c * c) + e * e;
+      } else {
+        t0 = T(0);
+      }
+      break;
+    }
+    case FN_SCHWEFEL: {
+      const T x = z[j] + T(SCHWEFEL_ZSTAR);
+      t0 = schwefel_cs<T>(p) - x * Mt::sin_(Mt::sqrt_(Mt::abs_(x)));
+      break;
+    }
+    case FN_HYBRID: {
+      const T v = z[p.perm[j]];
+      if (j < p.n1) {
+        const T x = v + T(SCHWEFEL_ZSTAR);
+        t0 = schwefel_cs<T>(p) - x * Mt::sin_(Mt::sqrt_(Mt::abs_(x)));
+      } else if (j < p.n1 + p.n2) {
+        t0 = (v * v - T(10) * Mt::cos2pi(v)) + T(10);
+      } else {
+        t0 = Mt::exp2_(T(j - p.n1 - p.n2) * ell_scale<T>(p)) * (v * v);
+      }
+      break;
+    }
+    default:
+      t0 = T(0);
+  }
+}
+
+// Final value from the summed terms.
+template <typename T>
+__device__ __forceinline__ T fn_finish(const ProbDev &p, T s0, T s1) {
+  using Mt = Math<T>;
+  if (p.kind == FN_ACKLEY) {
+    const T n = T(p.D);
+    const T e = T(2.718281828459045);
+    return ((T(-20) * Mt::exp_(T(-0.2) * Mt::sqrt_(s0 / n)) - Mt::exp_(s1 / n)) + T(20) + e) + T(p.bias);
+  }
+  return s0 + T(p.bias);
+}
+
+}  // namespace mde

@@ -1,0 +1,117 @@
+"""Host-side checks of the C ABI (no GPU needed): the built library exports
+every entry point the header declares, the binding's structs have the C
+layout, and configuration validation rejects what the header says it does."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "metade.h")
+
+
+def _lib():
+    from paper_2502_10470_amd import metade as M
+    if not os.path.exists(M.LIB_PATH):
+        pytest.skip("libmetade.so not built")
+    return M
+
+
+def test_header_symbols_exported():
+    M = _lib()
+    text = open(HEADER).read()
+    declared = set(re.findall(r"\b(metade_[a-z_]+)\s*\(", text))
+    assert len(declared) >= 20
+    L = M.lib()
+    for name in declared:
+        assert hasattr(L, name), name
+    assert declared == set(M.EXPORTED)
+    out = subprocess.run(["nm", "-D", "--defined-only", M.LIB_PATH], capture_output=True, text=True).stdout
+    for name in declared:
+        assert re.search(rf"\bT {name}\b", out), name
+
+
+def test_struct_layout_matches_c(tmp_path):
+    M = _lib()
+    src = tmp_path / "lay.c"
+    fields_p = [f[0] for f in M.MetadeProblem._fields_]
+    fields_c = [f[0] for f in M.MetadeConfig._fields_]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "metade.h"', 'int main(void){']
+    lines.append('printf("%zu %zu\\n", sizeof(metade_problem), sizeof(metade_config));')
+    for f in fields_p:
+        lines.append(f'printf("%zu\\n", offsetof(metade_problem, {f}));')
+    for f in fields_c:
+        lines.append(f'printf("%zu\\n", offsetof(metade_config, {f}));')
+    lines.append("return 0;}")
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "lay"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
+    assert vals[0] == ctypes.sizeof(M.MetadeProblem) and vals[1] == ctypes.sizeof(M.MetadeConfig)
+    k = 2
+    for f in fields_p:
+        assert vals[k] == getattr(M.MetadeProblem, f).offset, f
+        k += 1
+    for f in fields_c:
+        assert vals[k] == getattr(M.MetadeConfig, f).offset, f
+        k += 1
+
+
+def _cfg(M, N=(32,), D=10, kind="rastrigin", lb=-100.0, ub=100.0, n_cs=2, precision=0):
+    n = len(N)
+    keep = {}
+    keep["N"] = np.array(N, np.uint32)
+    keep["P"] = np.zeros(n, np.uint32)
+    keep["S"] = np.zeros(n, np.uint32)
+    probs = (M.MetadeProblem * 1)()
+    probs[0].kind = M.FN[kind]
+    probs[0].D = D
+    probs[0].bias = 100.0
+    probs[0].o = 0x1000      # never dereferenced by size queries
+    probs[0].R = 0x2000
+    cfg = M.MetadeConfig()
+    cfg.n_runs = n
+    cfg.N = keep["N"].ctypes.data
+    cfg.problem = keep["P"].ctypes.data
+    cfg.stream_id = keep["S"].ctypes.data
+    cfg.n_problems = 1
+    cfg.problems = ctypes.addressof(probs)
+    cfg.lb, cfg.ub, cfg.n_cs, cfg.precision = lb, ub, n_cs, precision
+    keep["probs"] = probs
+    return cfg, keep
+
+
+def test_query_sizes_packing():
+    M = _lib()
+    cfg, keep = _cfg(M, N=(32, 50, 10), D=7)
+    pop, fit, by, bx, scratch = M.metade_query_sizes(cfg)
+    assert pop == 4 * 7 * (32 + 50 + 10) and fit == 4 * 92 and by == 8 * 3 and bx == 4 * 21
+    assert scratch > 0
+
+
+@pytest.mark.parametrize("kw,msg", [
+    ({"N": (9,)}, "N must be"),
+    ({"N": (257,)}, "N must be"),
+    ({"D": 0}, "D must be"),
+    ({"D": 129}, "D must be"),
+    ({"lb": 1.0, "ub": 1.0}, "lb < ub"),
+    ({"n_cs": 4}, "n_cs"),
+    ({"kind": "lqr_mlp"}, "unsupported kind"),
+])
+def test_validation_rejects(kw, msg):
+    M = _lib()
+    cfg, keep = _cfg(M, **kw)
+    with pytest.raises(M.MetadeError) as ei:
+        M.metade_query_sizes(cfg)
+    assert "status -1" in str(ei.value) and msg in str(ei.value)
+
+
+def test_init_requires_buffers():
+    M = _lib()
+    cfg, keep = _cfg(M)
+    with pytest.raises(M.MetadeError) as ei:
+        M.metade_init(cfg)
+    assert "device buffers" in str(ei.value)
