@@ -47,6 +47,7 @@ struct metade_ctx {
   float *Xo = nullptr, *Uo = nullptr, *bxo = nullptr;
   double *yo = nullptr, *yt = nullptr;
   int32_t *bidx = nullptr;
+  std::vector<double *> r64;   // float64 copies of the rotations
   uint32_t outer_gen = 0;
   bool outer_ready = false;
   // measurement
@@ -252,6 +253,8 @@ metade_status metade_query_sizes(const metade_config *cfg, size_t *pop_bytes, si
     *scratch_bytes = pl.runs.size() * sizeof(RunDev) + pl.probs.size() * sizeof(ProbDev) +
                      pl.pend_floats * sizeof(float) + (size_t)cfg->n_runs * (6 * 4 * 2 + 16) +
                      pl.bx_n * sizeof(float) + 16;
+  if (scratch_bytes)
+    for (const ProbDev &p : pl.probs) *scratch_bytes += (size_t)p.D * p.D * sizeof(double);
   return METADE_OK;
 }
 
@@ -312,6 +315,16 @@ metade_status metade_init(const metade_config *cfg, metade_ctx **out) {
   if ((st = dalloc(c, &c->yt, c->n_runs)) != METADE_OK) return bail(st);
   if ((st = dalloc(c, &c->bxo, c->bx_n)) != METADE_OK) return bail(st);
   if ((st = dalloc(c, &c->bidx, 4)) != METADE_OK) return bail(st);
+  for (size_t k = 0; k < c->probs_h.size(); ++k) {
+    ProbDev &p = c->probs_h[k];
+    double *d = nullptr;
+    const size_t n = (size_t)p.D * p.D;
+    if ((st = dalloc(c, &d, n)) != METADE_OK) return bail(st);
+    c->r64.push_back(d);
+    hipError_t e2 = mde::launch_to_f64(p.R, d, (uint32_t)n, c->stream);
+    if (e2 != hipSuccess) { c->err = std::string("rotation copy: ") + hipGetErrorString(e2); return bail(METADE_EDEVICE); }
+    p.R64 = d;
+  }
   hipError_t e = mde::set_lds_limits();
   if (e != hipSuccess) { c->err = std::string("set_lds_limits: ") + hipGetErrorString(e); return bail(METADE_EDEVICE); }
   e = hipMemcpyAsync(c->runs_d, c->runs_h.data(), c->n_runs * sizeof(RunDev), hipMemcpyHostToDevice, c->stream);
@@ -587,6 +600,7 @@ void metade_destroy(metade_ctx *c) {
   (void)hipFree(c->yt);
   (void)hipFree(c->bxo);
   (void)hipFree(c->bidx);
+  for (double *d : c->r64) (void)hipFree(d);
   delete c;
 }
 

@@ -54,6 +54,7 @@ struct ProbDev {
   double cs_d;
   const float *o;
   const float *R;
+  const double *R64;            // float64 copy of R (library-owned)
   const uint32_t *perm;
   uint32_t n1, n2, n3, pad2;
   // control workload
@@ -118,6 +119,7 @@ __device__ __forceinline__ bool accept_trial_d(double fu, double fx) {
 
 struct Lds {
   uint32_t pop, fit, topk, desc, T, Y, Z, P, fu, acc, total;
+  uint32_t ys;  // row stride of Y in doubles (odd: spreads LDS banks)
 };
 
 __host__ __device__ inline uint32_t al16(uint32_t b) { return (b + 15u) & ~15u; }
@@ -130,10 +132,11 @@ __host__ __device__ inline Lds lds_layout(uint32_t N, uint32_t Dp, uint32_t C) {
   l.fit = o;  o += al16(N * 4);
   l.topk = o; o += al16(MAX_KP * 4);
   l.desc = o; o += al16(N * 16);
+  l.ys = Dp + 1;
   l.T = o;    o += al16(C * Dp * 4);
-  l.Y = o;    o += al16(C * Dp * 4);
+  l.Y = o;    o += al16(C * l.ys * 8);
   l.Z = o;    o += al16(C * Dp * 4);
-  l.P = o;    o += al16(C * Q * 8);
+  l.P = o;    o += al16(C * Q * 16);
   l.fu = o;   o += al16(N * 4);
   l.acc = o;  o += al16(N * 4);
   l.total = o;

@@ -29,6 +29,7 @@ struct LaunchArgs {
 };
 
 hipError_t set_lds_limits();
+hipError_t launch_to_f64(const float *src, double *dst, uint32_t n, hipStream_t s);
 hipError_t launch_init(const LaunchArgs &a, double lb, double ub);
 hipError_t launch_generations(const LaunchArgs &a, uint32_t g0, uint32_t n_gens, float lb,
                               float ub, TraceArgs tr);

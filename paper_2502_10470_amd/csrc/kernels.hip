@@ -24,21 +24,23 @@ __device__ __forceinline__ void set_comp(float4 &v, int t, float x) {
   if (t == 0) v.x = x; else if (t == 1) v.y = x; else if (t == 2) v.z = x; else v.w = x;
 }
 
-// Fitness of nC staged rows Y (y = u - o, row stride Dp) into out[il].
-// Plain float32 path: z = R y by fused multiply-adds in k order, then the
-// element terms summed four at a time and the partial sums in order.
+// Fitness of nC staged rows Y (y = u - o in float64, row stride ys) into
+// out[il].  Plain path: z = R y accumulated in float64 (y is exact, so a
+// small z_j that cancels between large products keeps its relative accuracy),
+// z rounded once to float32, element terms in float32 summed four at a time,
+// the partial sums accumulated in float64.
 template <int BLOCK>
-__device__ void eval_rows_f32(const ProbDev &p, uint32_t D, uint32_t Dp, uint32_t nC,
-                              const float *Y, float *Z, float2 *P, float *out) {
+__device__ void eval_rows(const ProbDev &p, uint32_t D, uint32_t Dp, uint32_t ys, uint32_t nC,
+                          const double *Y, float *Z, double2 *P, float *out) {
   const uint32_t tid = threadIdx.x;
   const uint32_t Q = Dp / 4;
   for (uint32_t u = tid; u < nC * D; u += BLOCK) {
-    const uint32_t il = u / D, j = u - il * D;
-    const float *Rj = p.R + (size_t)j * D;
-    const float *y = Y + il * Dp;
-    float acc = 0.0f;
-    for (uint32_t k = 0; k < D; ++k) acc = fmaf(Rj[k], y[k], acc);
-    Z[il * Dp + j] = acc;
+    const uint32_t j = u / nC, il = u - j * nC;
+    const double *Rj = p.R64 + (size_t)j * D;
+    const double *y = Y + il * ys;
+    double acc = 0.0;
+    for (uint32_t k = 0; k < D; ++k) acc = fma(Rj[k], y[k], acc);
+    Z[il * Dp + j] = (float)acc;
   }
   __syncthreads();
   for (uint32_t u = tid; u < nC * Q; u += BLOCK) {
@@ -54,17 +56,18 @@ __device__ void eval_rows_f32(const ProbDev &p, uint32_t D, uint32_t Dp, uint32_
         s1 += b;
       }
     }
-    P[il * Q + q] = make_float2(s0, s1);
+    P[il * Q + q] = make_double2((double)s0, (double)s1);
   }
   __syncthreads();
   for (uint32_t il = tid; il < nC; il += BLOCK) {
-    float s0 = 0.0f, s1 = 0.0f;
+    double s0 = 0.0, s1 = 0.0;
     for (uint32_t q = 0; q < Q; ++q) {
-      const float2 v = P[il * Q + q];
+      const double2 v = P[il * Q + q];
       s0 += v.x;
       s1 += v.y;
     }
-    out[il] = fn_finish<float>(p, s0, s1);
+    out[il] = p.kind == FN_ACKLEY ? fn_finish<float>(p, (float)s0, (float)s1)
+                                  : (float)(s0 + (double)p.bias);
   }
 }
 
@@ -81,9 +84,9 @@ __global__ __launch_bounds__(BLOCK) void k_init(const RunDev *__restrict__ runs,
   const uint32_t N = run.N, D = run.D, Dp = run.Dp, C = run.C, Q = Dp / 4;
   const Lds L = lds_layout(N, Dp, C);
   float *pop_s = reinterpret_cast<float *>(smem + L.pop);
-  float *Y = reinterpret_cast<float *>(smem + L.Y);
+  double *Y = reinterpret_cast<double *>(smem + L.Y);
   float *Z = reinterpret_cast<float *>(smem + L.Z);
-  float2 *P = reinterpret_cast<float2 *>(smem + L.P);
+  double2 *P = reinterpret_cast<double2 *>(smem + L.P);
   float *fu_s = reinterpret_cast<float *>(smem + L.fu);
   const uint32_t tid = threadIdx.x;
 
@@ -106,16 +109,14 @@ __global__ __launch_bounds__(BLOCK) void k_init(const RunDev *__restrict__ runs,
     for (uint32_t u = tid; u < nC * Q; u += BLOCK) {
       const uint32_t il = u / Q, q = u - il * Q;
       const float4 x = ld4(pop_s, (c0 + il) * Dp + 4 * q);
-      float4 y;
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const uint32_t j = 4 * q + t;
-        set_comp(y, t, j < D ? comp(x, t) - p.o[j] : 0.0f);
+        Y[il * L.ys + j] = j < D ? (double)comp(x, t) - (double)p.o[j] : 0.0;
       }
-      st4(Y, il * Dp + 4 * q, y);
     }
     __syncthreads();
-    eval_rows_f32<BLOCK>(p, D, Dp, nC, Y, Z, P, fu_s + c0);
+    eval_rows<BLOCK>(p, D, Dp, L.ys, nC, Y, Z, P, fu_s + c0);
     __syncthreads();
   }
   for (uint32_t u = tid; u < N * D; u += BLOCK) {
@@ -142,9 +143,9 @@ __global__ __launch_bounds__(BLOCK) void k_generations(
   uint32_t *topk = reinterpret_cast<uint32_t *>(smem + L.topk);
   uint4 *desc = reinterpret_cast<uint4 *>(smem + L.desc);
   float *T = reinterpret_cast<float *>(smem + L.T);
-  float *Y = reinterpret_cast<float *>(smem + L.Y);
+  double *Y = reinterpret_cast<double *>(smem + L.Y);
   float *Z = reinterpret_cast<float *>(smem + L.Z);
-  float2 *P = reinterpret_cast<float2 *>(smem + L.P);
+  double2 *P = reinterpret_cast<double2 *>(smem + L.P);
   float *fu_s = reinterpret_cast<float *>(smem + L.fu);
   int *acc_s = reinterpret_cast<int *>(smem + L.acc);
   const uint32_t tid = threadIdx.x;
@@ -300,20 +301,18 @@ __global__ __launch_bounds__(BLOCK) void k_generations(
             set_comp(uu, t, off < Lx ? comp(v, t) : comp(xi, t));
           }
         }
-        float4 yy;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           const uint32_t j = j0 + t;
           const float c = fminf(fmaxf(comp(uu, t), lb), ub);
           set_comp(uu, t, j < D ? c : 0.0f);
-          set_comp(yy, t, j < D ? c - p.o[j] : 0.0f);
+          Y[il * L.ys + j] = j < D ? (double)c - (double)p.o[j] : 0.0;
           if (tr.u && j < D) tr.u[run.pop_off + (size_t)i * D + j] = c;
         }
         st4(T, il * Dp + j0, uu);
-        st4(Y, il * Dp + j0, yy);
       }
       __syncthreads();
-      eval_rows_f32<BLOCK>(p, D, Dp, nC, Y, Z, P, fu_s + c0);
+      eval_rows<BLOCK>(p, D, Dp, L.ys, nC, Y, Z, P, fu_s + c0);
       __syncthreads();
       // (4) greedy selection decision
       for (uint32_t il = tid; il < nC; il += BLOCK) {
@@ -386,7 +385,7 @@ __global__ __launch_bounds__(FIN_BLOCK) void k_finalize(const RunDev *__restrict
   for (uint32_t j = tid; j < D; j += FIN_BLOCK) {
     double acc = 0.0;
     for (uint32_t k = 0; k < D; ++k)
-      acc = fma((double)p.R[(size_t)j * D + k], (double)x[k] - (double)p.o[k], acc);
+      acc = fma(p.R64[(size_t)j * D + k], (double)x[k] - (double)p.o[k], acc);
     z[j] = acc;
   }
   __syncthreads();
@@ -533,7 +532,17 @@ __global__ void k_outer_best(const double *__restrict__ y, uint32_t P, int32_t *
   if (tid == 0) out[0] = si[0] == 0x7FFFFFFF ? 0 : si[0];
 }
 
+__global__ void k_to_f64(const float *__restrict__ src, double *__restrict__ dst, uint32_t n) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (double)src[i];
+}
+
 // ---------------------------------------------------------------- launchers
+
+hipError_t launch_to_f64(const float *src, double *dst, uint32_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_to_f64, dim3((n + 255) / 256), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
 
 hipError_t set_lds_limits() {
   hipError_t e = hipFuncSetAttribute((const void *)k_generations<GEN_BLOCK>,

@@ -30,11 +30,18 @@ def near(a, b, rtol=TIE_RTOL):
 
 
 def ranking_ambiguous(fit, kp, th):
-    """True when the ranking positions the trials depend on (best, top-p set)
-    contain values closer than the tie tolerance."""
-    if th["bl"] not in (pde.BEST, pde.PBEST) and th["br"] not in (pde.BEST, pde.PBEST):
+    """True when the ranking positions the trials read contain values closer
+    than the tie tolerance: positions 0-1 for 'best', 0..kp for 'pbest'
+    (pbest maps a drawn rank to an individual, so order inside the top-p set
+    matters, and so does its boundary)."""
+    uses = {th["bl"], th["br"]}
+    if pde.PBEST in uses:
+        last = kp
+    elif pde.BEST in uses:
+        last = 1
+    else:
         return False
-    f = np.sort(pde.order_key(fit))[: kp + 1]
+    f = np.sort(pde.order_key(fit))[: last + 1]
     return bool(np.any(near(f[:-1], f[1:])))
 
 

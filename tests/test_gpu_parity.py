@@ -91,8 +91,8 @@ def _oracle_final(wl, r, G):
     return o, ambiguous
 
 
-@pytest.mark.parametrize("name,G,sample", [("c4", 2, 12), ("c2", 5, 24)])
-def test_full_size_multi_generation_launch(name, G, sample):
+@pytest.mark.parametrize("name,G,sample,need", [("c4", 2, 40, 6), ("c2", 5, 32, 12)])
+def test_full_size_multi_generation_launch(name, G, sample, need):
     """Full-size workloads in the launch shape the benchmark times (all
     generations in one persistent launch): sampled runs must end in exactly the
     oracle's state when the oracle saw no near-tie on the way."""
@@ -111,7 +111,8 @@ def test_full_size_multi_generation_launch(name, G, sample):
         e = rel_err(b.run_fit(fit, r), evaluate(o.pop, o.prob))
         assert e.max() <= FIT_RTOL
         checked += 1
-    assert checked >= sample // 2
+    print(f"{name}: {checked} of {sample} sampled runs free of near-ties, all identical", flush=True)
+    assert checked >= need
 
 
 def test_best_record_float64():
