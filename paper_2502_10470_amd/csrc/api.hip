@@ -47,7 +47,7 @@ struct metade_ctx {
   float *Xo = nullptr, *Uo = nullptr, *bxo = nullptr;
   double *yo = nullptr, *yt = nullptr;
   int32_t *bidx = nullptr;
-  std::vector<double *> r64;   // float64 copies of the rotations
+  unsigned char *tab = nullptr; // read-only problem tables (shift, float64 rotation, weights)
   uint32_t outer_gen = 0;
   bool outer_ready = false;
   // measurement
@@ -76,6 +76,7 @@ uint32_t round4(uint32_t d) { return (d + 3u) & ~3u; }
 struct Plan {
   std::vector<RunDev> runs;
   std::vector<ProbDev> probs;
+  size_t tab_bytes = 0;
   size_t pop_floats = 0, fit_n = 0, bx_n = 0, pend_floats = 0;
   uint32_t lds_bytes = 0;
 };
@@ -113,23 +114,23 @@ metade_status plan_config(const metade_config *cfg, Plan &pl, std::string &msg) 
       msg = "problem " + std::to_string(k) + ": D must be in 1..128"; return METADE_EINVAL;
     }
     if (!q.o || !q.R) { msg = "problem " + std::to_string(k) + ": o and R are required"; return METADE_EINVAL; }
-    p.o = q.o;
-    p.R = q.R;
-    if (q.kind == METADE_FN_ELLIPTIC) {
-      p.ell_scale_d = q.D > 1 ? std::log2(cond) / (double)(q.D - 1) : 0.0;
+    if (q.kind == METADE_FN_HYBRID &&
+        (!q.perm || (uint64_t)q.split[0] + q.split[1] + q.split[2] != q.D)) {
+      msg = "problem " + std::to_string(k) + ": hybrid needs perm and split summing to D";
+      return METADE_EINVAL;
     }
-    if (q.kind == METADE_FN_HYBRID) {
-      if (!q.perm || (uint64_t)q.split[0] + q.split[1] + q.split[2] != q.D) {
-        msg = "problem " + std::to_string(k) + ": hybrid needs perm and split summing to D";
-        return METADE_EINVAL;
-      }
-      p.perm = q.perm;
-      p.n1 = q.split[0];
-      p.n2 = q.split[1];
-      p.n3 = q.split[2];
-      p.ell_scale_d = p.n3 > 1 ? std::log2(cond) / (double)(p.n3 - 1) : 0.0;
-    }
-    p.ell_scale_f = (float)p.ell_scale_d;
+    (void)cond;
+    // read-only table layout of this problem
+    auto take = [&](size_t bytes) {
+      const uint64_t off = pl.tab_bytes;
+      pl.tab_bytes += (bytes + 255) & ~(size_t)255;
+      return off;
+    };
+    p.o_off = take((size_t)q.D * sizeof(float));
+    p.r64t_off = take((size_t)q.D * mde::rt_stride(q.D) * sizeof(double));
+    p.ew_off = take((size_t)q.D * sizeof(float));
+    p.ew64_off = take((size_t)q.D * sizeof(double));
+    p.ek_off = take((size_t)q.D * sizeof(uint32_t));
     pl.probs[k] = p;
   }
   pl.runs.resize(cfg->n_runs);
@@ -151,20 +152,21 @@ metade_status plan_config(const metade_config *cfg, Plan &pl, std::string &msg) 
     d.prob = cfg->problem[r];
     d.stream = cfg->stream_id[r];
     d.kp = std::max<uint32_t>(1, (N * 10 + 99) / 100);
-    uint32_t C = N;
-    while (C > 1 && mde::lds_layout(N, d.Dp, C).total > mde::LDS_BUDGET) --C;
-    const uint32_t bytes = mde::lds_layout(N, d.Dp, C).total;
+    // lanes per part: whole waves covering N; parts: as many as fit the block
+    d.Np = ((N + 63u) / 64u) * 64u;
+    d.L = std::max<uint32_t>(1, std::min<uint32_t>(4, (uint32_t)mde::GEN_BLOCK / d.Np));
+    d.t_lds = mde::lds_layout(N, d.Dp, d.L, d.Np, true).total <= mde::LDS_BUDGET ? 1u : 0u;
+    const uint32_t bytes = mde::lds_layout(N, d.Dp, d.L, d.Np, d.t_lds != 0).total;
     if (bytes > mde::LDS_BUDGET) {
       msg = "run " + std::to_string(r) + ": population does not fit in LDS"; return METADE_EINVAL;
     }
-    d.C = C;
     pl.lds_bytes = std::max(pl.lds_bytes, bytes);
     d.pop_off = pl.pop_floats;
     d.pend_off = pl.pend_floats;
     d.fit_off = (uint32_t)pl.fit_n;
     d.bx_off = (uint32_t)pl.bx_n;
     pl.pop_floats += (size_t)N * D;
-    if (C < N) pl.pend_floats += (size_t)N * d.Dp;
+    if (!d.t_lds) pl.pend_floats += (size_t)N * D;
     pl.fit_n += N;
     pl.bx_n += D;
     d.F = 0.5f;
@@ -180,6 +182,7 @@ LaunchArgs largs(metade_ctx *c) {
   LaunchArgs a;
   a.runs = c->runs_d;
   a.probs = c->probs_d;
+  a.tab = c->tab;
   a.pop = c->pop;
   a.fit = c->fit;
   a.pending = c->pend_d;
@@ -253,8 +256,7 @@ metade_status metade_query_sizes(const metade_config *cfg, size_t *pop_bytes, si
     *scratch_bytes = pl.runs.size() * sizeof(RunDev) + pl.probs.size() * sizeof(ProbDev) +
                      pl.pend_floats * sizeof(float) + (size_t)cfg->n_runs * (6 * 4 * 2 + 16) +
                      pl.bx_n * sizeof(float) + 16;
-  if (scratch_bytes)
-    for (const ProbDev &p : pl.probs) *scratch_bytes += (size_t)p.D * p.D * sizeof(double);
+  if (scratch_bytes) *scratch_bytes += pl.tab_bytes;
   return METADE_OK;
 }
 
@@ -292,19 +294,22 @@ metade_status metade_init(const metade_config *cfg, metade_ctx **out) {
     return st;
   };
   metade_status st;
+  std::vector<std::vector<uint32_t>> perms(c->probs_h.size());
   for (size_t k = 0; k < c->probs_h.size(); ++k) {
-    const ProbDev &p = c->probs_h[k];
-    if (p.kind != mde::FN_HYBRID) continue;
-    // the kernels index z by the permutation: it must be one
-    std::vector<uint32_t> perm(p.D);
-    hipError_t e = hipMemcpy(perm.data(), p.perm, p.D * sizeof(uint32_t), hipMemcpyDeviceToHost);
+    const metade_problem &q = cfg->problems[k];
+    if (q.kind != METADE_FN_HYBRID) continue;
+    // the element tables are built from the permutation: it must be one
+    std::vector<uint32_t> &perm = perms[k];
+    perm.resize(q.D);
+    hipError_t e = hipMemcpy(perm.data(), q.perm, q.D * sizeof(uint32_t), hipMemcpyDeviceToHost);
     if (e != hipSuccess) { c->err = std::string("reading hybrid permutation: ") + hipGetErrorString(e); return bail(METADE_EDEVICE); }
-    std::vector<char> seen(p.D, 0);
+    std::vector<char> seen(q.D, 0);
     for (uint32_t v : perm) {
-      if (v >= p.D || seen[v]) { c->err = "problem " + std::to_string(k) + ": perm is not a permutation of 0..D-1"; return bail(METADE_EINVAL); }
+      if (v >= q.D || seen[v]) { c->err = "problem " + std::to_string(k) + ": perm is not a permutation of 0..D-1"; return bail(METADE_EINVAL); }
       seen[v] = 1;
     }
   }
+  if ((st = dalloc(c, &c->tab, pl.tab_bytes)) != METADE_OK) return bail(st);
   if ((st = dalloc(c, &c->runs_d, c->n_runs)) != METADE_OK) return bail(st);
   if ((st = dalloc(c, &c->probs_d, c->probs_h.size())) != METADE_OK) return bail(st);
   if ((st = dalloc(c, &c->theta_d, (size_t)c->n_runs * 6)) != METADE_OK) return bail(st);
@@ -316,14 +321,43 @@ metade_status metade_init(const metade_config *cfg, metade_ctx **out) {
   if ((st = dalloc(c, &c->bxo, c->bx_n)) != METADE_OK) return bail(st);
   if ((st = dalloc(c, &c->bidx, 4)) != METADE_OK) return bail(st);
   for (size_t k = 0; k < c->probs_h.size(); ++k) {
-    ProbDev &p = c->probs_h[k];
-    double *d = nullptr;
-    const size_t n = (size_t)p.D * p.D;
-    if ((st = dalloc(c, &d, n)) != METADE_OK) return bail(st);
-    c->r64.push_back(d);
-    hipError_t e2 = mde::launch_to_f64(p.R, d, (uint32_t)n, c->stream);
-    if (e2 != hipSuccess) { c->err = std::string("rotation copy: ") + hipGetErrorString(e2); return bail(METADE_EDEVICE); }
-    p.R64 = d;
+    // per-output element tables: elliptic weights cond^(idx/(n-1)) and, for
+    // the hybrid, the block each rotated output falls in after permutation
+    const ProbDev &p = c->probs_h[k];
+    const metade_problem &q = cfg->problems[k];
+    const double cond = q.cond > 0 ? (double)q.cond : 1e6;
+    std::vector<float> ew(p.D, 0.0f);
+    std::vector<double> ew64(p.D, 0.0);
+    std::vector<uint32_t> ek(p.D, 0);
+    if (p.kind == mde::FN_ELLIPTIC) {
+      for (uint32_t j = 0; j < p.D; ++j) {
+        ew64[j] = p.D > 1 ? std::pow(cond, (double)j / (double)(p.D - 1)) : 1.0;
+        ew[j] = (float)ew64[j];
+      }
+    } else if (p.kind == mde::FN_HYBRID) {
+      const uint32_t n1 = q.split[0], n2 = q.split[1], n3 = q.split[2];
+      for (uint32_t pos = 0; pos < p.D; ++pos) {
+        const uint32_t j = perms[k][pos];
+        if (pos < n1) {
+          ek[j] = 0;
+        } else if (pos < n1 + n2) {
+          ek[j] = 1;
+        } else {
+          ek[j] = 2;
+          const uint32_t idx = pos - n1 - n2;
+          ew64[j] = n3 > 1 ? std::pow(cond, (double)idx / (double)(n3 - 1)) : 1.0;
+          ew[j] = (float)ew64[j];
+        }
+      }
+    }
+    unsigned char *t = c->tab;
+    hipError_t e4 = hipMemcpy(t + p.ew_off, ew.data(), p.D * sizeof(float), hipMemcpyHostToDevice);
+    if (e4 == hipSuccess) e4 = hipMemcpy(t + p.ew64_off, ew64.data(), p.D * sizeof(double), hipMemcpyHostToDevice);
+    if (e4 == hipSuccess) e4 = hipMemcpy(t + p.ek_off, ek.data(), p.D * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e4 == hipSuccess) e4 = hipMemcpy(t + p.o_off, q.o, p.D * sizeof(float), hipMemcpyDeviceToDevice);
+    if (e4 == hipSuccess)
+      e4 = mde::launch_rot_t64(q.R, reinterpret_cast<double *>(t + p.r64t_off), p.D, c->stream);
+    if (e4 != hipSuccess) { c->err = std::string("problem tables: ") + hipGetErrorString(e4); return bail(METADE_EDEVICE); }
   }
   hipError_t e = mde::set_lds_limits();
   if (e != hipSuccess) { c->err = std::string("set_lds_limits: ") + hipGetErrorString(e); return bail(METADE_EDEVICE); }
@@ -600,7 +634,7 @@ void metade_destroy(metade_ctx *c) {
   (void)hipFree(c->yt);
   (void)hipFree(c->bxo);
   (void)hipFree(c->bidx);
-  for (double *d : c->r64) (void)hipFree(d);
+  (void)hipFree(c->tab);
   delete c;
 }
 

@@ -38,32 +38,43 @@ constexpr float SCHWEFEL_ZSTAR = 420.96875f;
 // One executor run.  Theta fields are written by the decode kernel.
 struct RunDev {
   uint32_t N, D, Dp, prob;      // Dp = D rounded up to a multiple of 4
-  uint32_t stream, kp, C, pad0; // kp = top-p count, C = trials per LDS chunk
+  uint32_t stream, kp;          // kp = top-p count
+  uint32_t L, Np;               // lanes per trial (parts) and lanes per part (multiple of 64)
+  uint32_t t_lds, pad0;         // trial rows in LDS (1) or in the global trial buffer (0)
   uint64_t pop_off;             // float offset of the run in pop (N*D packing)
-  uint64_t pend_off;            // float offset in the pending buffer (N*Dp packing)
+  uint64_t pend_off;            // float offset in the global trial buffer (D*N packing)
   uint32_t fit_off, bx_off;     // offsets in fit / best_x
   float F, CR;
   int32_t bl, br, dn, cs;
 };
 
+// One problem instance.  Its arrays live in the library's read-only table
+// buffer (one allocation for all problems), addressed by byte offsets so that
+// every kernel reads them through one const __restrict__ pointer: uniform
+// reads then become scalar loads.
 struct ProbDev {
   uint32_t kind, D;
-  float bias, ell_scale_f;      // log2(cond)/(D-1) (elliptic), or over the hybrid's third block
-  double ell_scale_d;
-  float cs_f, pad1;             // Schwefel constant z* sin(sqrt z*)
+  float bias, cs_f;             // cs = Schwefel constant z* sin(sqrt z*)
   double cs_d;
-  const float *o;
-  const float *R;
-  const double *R64;            // float64 copy of R (library-owned)
-  const uint32_t *perm;
-  uint32_t n1, n2, n3, pad2;
+  uint64_t o_off;               // float  [D]    shift
+  uint64_t r64t_off;            // double [D*D]  rotation transposed: element (k, j) = R[j][k]
+  uint64_t ew_off;              // float  [D]    elliptic weight of output j
+  uint64_t ew64_off;            // double [D]    same in float64
+  uint64_t ek_off;              // uint32 [D]    hybrid block of output j (0 Schwefel, 1 Rastrigin, 2 elliptic)
   // control workload
   uint32_t obs, act, h1, h2, steps, nroll;
-  float cw, pad3;
-  const float *A;
-  const float *B;
-  const float *x0;
+  float cw, pad0;
+  uint64_t A_off, B_off, x0_off;  // float [obs*obs], [obs*act], [nroll*obs]
 };
+
+// Row stride of the transposed float64 rotation: D plus zero padding for the
+// widest output block (16), rounded to 4 doubles.
+__host__ __device__ inline uint32_t rt_stride(uint32_t D) { return ((D + 16u) + 3u) & ~3u; }
+
+template <typename T>
+__host__ __device__ __forceinline__ const T *tab_ptr(const unsigned char *tab, uint64_t off) {
+  return reinterpret_cast<const T *>(tab + off);
+}
 
 // ---------------------------------------------------------------- Philox4x32-10
 
@@ -117,28 +128,27 @@ __device__ __forceinline__ bool accept_trial_d(double fu, double fx) {
 
 // ---------------------------------------------------------------- LDS layout
 
+// LDS of the generation kernel: population [N][Dp] (row-major, float4 rows
+// for the gathers of the mutation), 64-bit ranking keys, fitness, the top-p
+// list, per-part partial fitness sums and -- when it fits -- the trial rows
+// stored gene-major ([D][Np]) so that lane i reading gene k of its own trial
+// touches consecutive words.
 struct Lds {
-  uint32_t pop, fit, topk, desc, T, Y, Z, P, fu, acc, total;
-  uint32_t ys;  // row stride of Y in doubles (odd: spreads LDS banks)
+  uint32_t pop, key, fit, topk, ps, T, total;
 };
 
 __host__ __device__ inline uint32_t al16(uint32_t b) { return (b + 15u) & ~15u; }
 
-__host__ __device__ inline Lds lds_layout(uint32_t N, uint32_t Dp, uint32_t C) {
+__host__ __device__ inline Lds lds_layout(uint32_t N, uint32_t Dp, uint32_t L, uint32_t Np,
+                                          bool t_lds) {
   Lds l;
   uint32_t o = 0;
-  const uint32_t Q = Dp / 4;
   l.pop = o;  o += al16(N * Dp * 4);
+  l.key = o;  o += al16(N * 8);
   l.fit = o;  o += al16(N * 4);
   l.topk = o; o += al16(MAX_KP * 4);
-  l.desc = o; o += al16(N * 16);
-  l.ys = Dp + 1;
-  l.T = o;    o += al16(C * Dp * 4);
-  l.Y = o;    o += al16(C * l.ys * 8);
-  l.Z = o;    o += al16(C * Dp * 4);
-  l.P = o;    o += al16(C * Q * 16);
-  l.fu = o;   o += al16(N * 4);
-  l.acc = o;  o += al16(N * 4);
+  l.ps = o;   o += al16(L * Np * 16);
+  l.T = o;    o += t_lds ? al16(Dp * Np * 4) : 0u;
   l.total = o;
   return l;
 }
@@ -202,68 +212,50 @@ template <> struct Math<double> {
   static __device__ __forceinline__ double abs_(double x) { return fabs(x); }
 };
 
-template <typename T> __device__ __forceinline__ T ell_scale(const ProbDev &p);
-template <> __device__ __forceinline__ float ell_scale<float>(const ProbDev &p) { return p.ell_scale_f; }
-template <> __device__ __forceinline__ double ell_scale<double>(const ProbDev &p) { return p.ell_scale_d; }
 template <typename T> __device__ __forceinline__ T schwefel_cs(const ProbDev &p);
 template <> __device__ __forceinline__ float schwefel_cs<float>(const ProbDev &p) { return p.cs_f; }
 template <> __device__ __forceinline__ double schwefel_cs<double>(const ProbDev &p) { return p.cs_d; }
+template <typename T> __device__ __forceinline__ T ell_w(const unsigned char *tab, const ProbDev &p, uint32_t j);
+template <> __device__ __forceinline__ float ell_w<float>(const unsigned char *tab, const ProbDev &p, uint32_t j) {
+  return tab_ptr<float>(tab, p.ew_off)[j];
+}
+template <> __device__ __forceinline__ double ell_w<double>(const unsigned char *tab, const ProbDev &p, uint32_t j) {
+  return tab_ptr<double>(tab, p.ew64_off)[j];
+}
 
-// Per-element terms of the shifted-rotated functions.  z points at the run's
-// rotated vector; j is the element (for the hybrid: the permuted position).
-// Returns (term, second term) -- the second is used by Ackley only.
-template <typename T>
-__device__ __forceinline__ void fn_term(const ProbDev &p, const T *z, uint32_t j, T &t0, T &t1) {
+template <typename T> __device__ __forceinline__ T h_rastrigin(T v) {
+  return (v * v - T(10) * Math<T>::cos2pi(v)) + T(10);
+}
+template <typename T> __device__ __forceinline__ T h_schwefel(const ProbDev &p, T v) {
   using Mt = Math<T>;
+  const T x = v + T(SCHWEFEL_ZSTAR);
+  return schwefel_cs<T>(p) - x * Mt::sin_(Mt::sqrt_(Mt::abs_(x)));
+}
+template <typename T> __device__ __forceinline__ T h_rosenbrock(T v, T vn) {
+  const T a = v + T(1);
+  const T b = vn + T(1);
+  const T c = a * a - b;
+  const T e = a - T(1);
+  return T(100) * (c * c) + e * e;
+}
+
+// Term of output j (value v) for every kind but Rosenbrock, whose term pairs
+// z_j with z_{j+1} and is formed by the caller.  t1 is Ackley's cosine sum.
+template <typename T>
+__device__ __forceinline__ void elem_term(const unsigned char *tab, const ProbDev &p, uint32_t j,
+                                          T v, T &t0, T &t1) {
   t1 = T(0);
   switch (p.kind) {
-    case FN_RASTRIGIN: {
-      const T v = z[j];
-      t0 = (v * v - T(10) * Mt::cos2pi(v)) + T(10);
-      break;
-    }
-    case FN_ELLIPTIC: {
-      const T v = z[j];
-      t0 = Mt::exp2_(T(j) * ell_scale<T>(p)) * (v * v);
-      break;
-    }
-    case FN_ACKLEY: {
-      const T v = z[j];
-      t0 = v * v;
-      t1 = Mt::cos2pi(v);
-      break;
-    }
-    case FN_ROSENBROCK: {
-      if (j + 1 < p.D) {
-        const T a = z[j] + T(1);
-        const T b = z[j + 1] + T(1);
-        const T c = a * a - b;
-        const T e = a - T(1);
-        t0 = T(100) * (c * c) + e * e;
-      } else {
-        t0 = T(0);
-      }
-      break;
-    }
-    case FN_SCHWEFEL: {
-      const T x = z[j] + T(SCHWEFEL_ZSTAR);
-      t0 = schwefel_cs<T>(p) - x * Mt::sin_(Mt::sqrt_(Mt::abs_(x)));
-      break;
-    }
+    case FN_RASTRIGIN: t0 = h_rastrigin<T>(v); break;
+    case FN_ELLIPTIC: t0 = ell_w<T>(tab, p, j) * (v * v); break;
+    case FN_ACKLEY: t0 = v * v; t1 = Math<T>::cos2pi(v); break;
+    case FN_SCHWEFEL: t0 = h_schwefel<T>(p, v); break;
     case FN_HYBRID: {
-      const T v = z[p.perm[j]];
-      if (j < p.n1) {
-        const T x = v + T(SCHWEFEL_ZSTAR);
-        t0 = schwefel_cs<T>(p) - x * Mt::sin_(Mt::sqrt_(Mt::abs_(x)));
-      } else if (j < p.n1 + p.n2) {
-        t0 = (v * v - T(10) * Mt::cos2pi(v)) + T(10);
-      } else {
-        t0 = Mt::exp2_(T(j - p.n1 - p.n2) * ell_scale<T>(p)) * (v * v);
-      }
+      const uint32_t e = tab_ptr<uint32_t>(tab, p.ek_off)[j];
+      t0 = e == 0 ? h_schwefel<T>(p, v) : (e == 1 ? h_rastrigin<T>(v) : ell_w<T>(tab, p, j) * (v * v));
       break;
     }
-    default:
-      t0 = T(0);
+    default: t0 = T(0);
   }
 }
 

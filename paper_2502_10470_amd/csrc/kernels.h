@@ -19,6 +19,7 @@ struct TraceArgs {
 struct LaunchArgs {
   const RunDev *runs;
   const ProbDev *probs;
+  const unsigned char *tab;
   float *pop;
   float *fit;
   float *pending;
@@ -29,7 +30,7 @@ struct LaunchArgs {
 };
 
 hipError_t set_lds_limits();
-hipError_t launch_to_f64(const float *src, double *dst, uint32_t n, hipStream_t s);
+hipError_t launch_rot_t64(const float *R, double *Rt, uint32_t D, hipStream_t s);
 hipError_t launch_init(const LaunchArgs &a, double lb, double ub);
 hipError_t launch_generations(const LaunchArgs &a, uint32_t g0, uint32_t n_gens, float lb,
                               float ub, TraceArgs tr);

@@ -24,51 +24,240 @@ __device__ __forceinline__ void set_comp(float4 &v, int t, float x) {
   if (t == 0) v.x = x; else if (t == 1) v.y = x; else if (t == 2) v.z = x; else v.w = x;
 }
 
-// Fitness of nC staged rows Y (y = u - o in float64, row stride ys) into
-// out[il].  Plain path: z = R y accumulated in float64 (y is exact, so a
-// small z_j that cancels between large products keeps its relative accuracy),
-// z rounded once to float32, element terms in float32 summed four at a time,
-// the partial sums accumulated in float64.
-template <int BLOCK>
-__device__ void eval_rows(const ProbDev &p, uint32_t D, uint32_t Dp, uint32_t ys, uint32_t nC,
-                          const double *Y, float *Z, double2 *P, float *out) {
-  const uint32_t tid = threadIdx.x;
-  const uint32_t Q = Dp / 4;
-  for (uint32_t u = tid; u < nC * D; u += BLOCK) {
-    const uint32_t j = u / nC, il = u - j * nC;
-    const double *Rj = p.R64 + (size_t)j * D;
-    const double *y = Y + il * ys;
-    double acc = 0.0;
-    for (uint32_t k = 0; k < D; ++k) acc = fma(Rj[k], y[k], acc);
-    Z[il * Dp + j] = (float)acc;
-  }
-  __syncthreads();
-  for (uint32_t u = tid; u < nC * Q; u += BLOCK) {
-    const uint32_t il = u / Q, q = u - il * Q;
-    float s0 = 0.0f, s1 = 0.0f;
+// 64-bit ranking key: order of (fitness, index), NaN as +inf.
+__device__ __forceinline__ uint64_t mkkey(float f, uint32_t i) {
+  return ((uint64_t)okey(f) << 32) | i;
+}
+
+// ---------------------------------------------------------------- fitness of one row, split by output
+
+// acc[q] = sum_k R[jc+q][k] (u_k - o_k) in float64 for q < J, from the
+// transposed rotation Rt[k][j]: the J coefficients of one k are contiguous
+// and wave-uniform, so they arrive by wide scalar loads and feed the FMAs as
+// scalar operands.  u_k = t[k*ts] is the lane's own trial.  Outputs past D
+// read the padding columns of Rt (zero) and are not used.
+template <int J, typename TP>
+__device__ __forceinline__ void rot_block(const double *__restrict__ Rt, uint32_t D, uint32_t Dr,
+                                          uint32_t jc, TP t, uint32_t ts,
+                                          const float *__restrict__ o, double (&acc)[J]) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const uint32_t j = 4 * q + t;
-      if (j < D) {
-        float a, b;
-        fn_term<float>(p, Z + il * Dp, j, a, b);
-        s0 += a;
-        s1 += b;
+  for (int q = 0; q < J; ++q) acc[q] = 0.0;
+  const double *col = Rt + jc;
+#pragma unroll 2
+  for (uint32_t k = 0; k < D; ++k) {
+    const double yk = (double)t[k * ts] - (double)o[k];
+    const double *c = col + (size_t)k * Dr;
+#pragma unroll
+    for (int q = 0; q < J; ++q) acc[q] = fma(c[q], yk, acc[q]);
+  }
+}
+
+struct TermAcc {
+  double s0, s1;
+  float prevz;
+  bool have;
+};
+
+template <int J>
+__device__ __forceinline__ void consume(const unsigned char *tab, const ProbDev &p,
+                                        const double (&a)[J], uint32_t jc, uint32_t n,
+                                        uint32_t j1, TermAcc &ta) {
+#pragma unroll
+  for (int q = 0; q < J; ++q) {
+    if ((uint32_t)q < n) {
+      const float z = (float)a[q];
+      const uint32_t j = jc + q;
+      if (p.kind == FN_ROSENBROCK) {
+        if (ta.have && j - 1 < j1) ta.s0 += (double)h_rosenbrock<float>(ta.prevz, z);
+        ta.prevz = z;
+        ta.have = true;
+      } else {
+        float t0, t1;
+        elem_term<float>(tab, p, j, z, t0, t1);
+        ta.s0 += (double)t0;
+        ta.s1 += (double)t1;
       }
     }
-    P[il * Q + q] = make_double2((double)s0, (double)s1);
   }
-  __syncthreads();
-  for (uint32_t il = tid; il < nC; il += BLOCK) {
-    double s0 = 0.0, s1 = 0.0;
-    for (uint32_t q = 0; q < Q; ++q) {
-      const double2 v = P[il * Q + q];
-      s0 += v.x;
-      s1 += v.y;
+}
+
+// Sum of the element terms of outputs [j0, j1) of the row at t (gene stride
+// ts).  Plain path: z = R (u - o) accumulated in float64 -- y is exact, so a
+// small z_j that cancels between large products keeps its relative accuracy --
+// z rounded once to float32, element terms in float32, sums in float64.
+template <typename TP>
+__device__ __forceinline__ void eval_part(const unsigned char *__restrict__ tab, const ProbDev &p,
+                                          uint32_t D, uint32_t j0, uint32_t j1, TP t, uint32_t ts,
+                                          double &s0, double &s1) {
+  const double *Rt = tab_ptr<double>(tab, p.r64t_off);
+  const uint32_t Dr = rt_stride(D);
+  const float *o = tab_ptr<float>(tab, p.o_off);
+  TermAcc ta{0.0, 0.0, 0.0f, false};
+  const uint32_t jend = p.kind == FN_ROSENBROCK ? min(j1 + 1, D) : j1;
+  uint32_t jc = j0;
+  while (jc < jend) {
+    const uint32_t rem = jend - jc;
+    if (rem > 12) {
+      double a[16];
+      rot_block<16>(Rt, D, Dr, jc, t, ts, o, a);
+      consume<16>(tab, p, a, jc, min(rem, 16u), j1, ta);
+      jc += 16;
+    } else if (rem > 8) {
+      double a[12];
+      rot_block<12>(Rt, D, Dr, jc, t, ts, o, a);
+      consume<12>(tab, p, a, jc, rem, j1, ta);
+      jc += 12;
+    } else if (rem > 4) {
+      double a[8];
+      rot_block<8>(Rt, D, Dr, jc, t, ts, o, a);
+      consume<8>(tab, p, a, jc, rem, j1, ta);
+      jc += 8;
+    } else {
+      double a[4];
+      rot_block<4>(Rt, D, Dr, jc, t, ts, o, a);
+      consume<4>(tab, p, a, jc, rem, j1, ta);
+      jc += 4;
     }
-    out[il] = p.kind == FN_ACKLEY ? fn_finish<float>(p, (float)s0, (float)s1)
-                                  : (float)(s0 + (double)p.bias);
   }
+  s0 = ta.s0;
+  s1 = ta.s1;
+}
+
+__device__ __forceinline__ float finish_f32(const ProbDev &p, double s0, double s1) {
+  return p.kind == FN_ACKLEY ? fn_finish<float>(p, (float)s0, (float)s1)
+                             : (float)(s0 + (double)p.bias);
+}
+
+// ---------------------------------------------------------------- per-trial draws
+
+struct Desc {
+  uint32_t ibl, ibr, jn, Lx, pb_rank;
+  int32_t r0;
+  uint32_t a[4], b[4];
+  float K;
+};
+
+// Index draws (rand base and difference pairs, distinct and != i), pbest pick
+// from the top-p list, j_rand or the exponential start n, K, and the
+// exponential length L (censored geometric: continue while uniform t <= CR).
+__device__ __forceinline__ Desc make_desc(uint32_t i, uint32_t N, uint32_t D, uint32_t g,
+                                          uint32_t stream, uint32_t k0, uint32_t k1,
+                                          const RunDev &run, uint32_t kp,
+                                          const uint32_t *topk) {
+  const int bl = run.bl, br = run.br, dn = run.dn;
+  const int use_rand = (bl == RAND || br == RAND) ? 1 : 0;
+  const int m = use_rand + 2 * dn;
+  uint32_t w[12];
+  const uint4 wa = philox(0, i, g, stream, k0, k1);
+  const uint4 wc = philox(2, i, g, stream, k0, k1);
+  w[0] = wa.x; w[1] = wa.y; w[2] = wa.z; w[3] = wa.w;
+  if (m > 4) {
+    const uint4 wb = philox(1, i, g, stream, k0, k1);
+    w[4] = wb.x; w[5] = wb.y; w[6] = wb.z; w[7] = wb.w;
+  } else {
+    w[4] = w[5] = w[6] = w[7] = 0;
+  }
+  w[8] = wc.x; w[9] = wc.y; w[10] = wc.z; w[11] = wc.w;
+  uint32_t dr[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) dr[k] = 0;
+  sample_distinct(w, m, i, N, dr);
+  Desc d;
+  d.r0 = use_rand ? (int32_t)dr[0] : -1;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    d.a[k] = (k < dn) ? dr[use_rand + 2 * k] : 0u;
+    d.b[k] = (k < dn) ? dr[use_rand + 2 * k + 1] : 0u;
+  }
+  d.pb_rank = lemire(w[W_PBEST], kp);
+  const uint32_t ipb = topk[d.pb_rank];
+  const uint32_t ibest = topk[0];
+  d.ibl = bl == RAND ? (uint32_t)d.r0 : (bl == BEST ? ibest : (bl == PBEST ? ipb : i));
+  d.ibr = br == RAND ? (uint32_t)d.r0 : (br == BEST ? ibest : (br == PBEST ? ipb : i));
+  d.jn = lemire(w[W_JRAND], D);
+  d.K = unit_oc(w[W_K]);
+  d.Lx = 1;
+  if (run.cs == EXP) {
+    bool go = true;
+    uint32_t blk = W_GENE0 / 4;
+    while (go && d.Lx < D) {
+      const uint4 wr = philox(blk++, i, g, stream, k0, k1);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (go && d.Lx < D) {
+          if (unit_oc(word_of(wr, t)) <= run.CR) ++d.Lx; else go = false;
+        }
+      }
+    }
+  }
+  return d;
+}
+
+// Genes 4q..4q+3 of trial i: mutation Eq. (12), crossover Eqs. (8)-(10),
+// clip to the box.  Genes >= D come back as 0.
+__device__ __forceinline__ float4 trial_quad(const float *pop_s, uint32_t Dp, uint32_t D,
+                                             uint32_t i, uint32_t q, const Desc &d,
+                                             const RunDev &run, uint32_t g, uint32_t k0,
+                                             uint32_t k1, float lb, float ub) {
+  const uint32_t j0 = 4 * q;
+  const float F = run.F;
+  const float4 xi = ld4(pop_s, i * Dp + j0);
+  const float4 xb = ld4(pop_s, d.ibl * Dp + j0);
+  float4 base = xb;
+  if (run.bl != run.br) {
+    const float4 xr = ld4(pop_s, d.ibr * Dp + j0);
+    base.x = xb.x + F * (xr.x - xb.x);
+    base.y = xb.y + F * (xr.y - xb.y);
+    base.z = xb.z + F * (xr.z - xb.z);
+    base.w = xb.w + F * (xr.w - xb.w);
+  }
+  float4 dd;
+  {
+    const float4 a = ld4(pop_s, d.a[0] * Dp + j0);
+    const float4 b = ld4(pop_s, d.b[0] * Dp + j0);
+    dd.x = a.x - b.x; dd.y = a.y - b.y; dd.z = a.z - b.z; dd.w = a.w - b.w;
+  }
+#pragma unroll
+  for (int k = 1; k < 4; ++k) {
+    if (k < run.dn) {
+      const float4 a = ld4(pop_s, d.a[k] * Dp + j0);
+      const float4 b = ld4(pop_s, d.b[k] * Dp + j0);
+      dd.x = dd.x + (a.x - b.x);
+      dd.y = dd.y + (a.y - b.y);
+      dd.z = dd.z + (a.z - b.z);
+      dd.w = dd.w + (a.w - b.w);
+    }
+  }
+  float4 v;
+  v.x = base.x + F * dd.x;
+  v.y = base.y + F * dd.y;
+  v.z = base.z + F * dd.z;
+  v.w = base.w + F * dd.w;
+  float4 uu;
+  if (run.cs == ARITH) {
+    const float K = d.K;
+    uu.x = xi.x + K * (v.x - xi.x);
+    uu.y = xi.y + K * (v.y - xi.y);
+    uu.z = xi.z + K * (v.z - xi.z);
+    uu.w = xi.w + K * (v.w - xi.w);
+  } else if (run.cs == BIN) {
+    const uint4 wr = philox(W_GENE0 / 4 + q, i, g, run.stream, k0, k1);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const bool take = (unit_oc(word_of(wr, t)) <= run.CR) || (j0 + t == d.jn);
+      set_comp(uu, t, take ? comp(v, t) : comp(xi, t));
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const uint32_t off = (j0 + t + D - d.jn) % D;
+      set_comp(uu, t, off < d.Lx ? comp(v, t) : comp(xi, t));
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+    set_comp(uu, t, j0 + t < D ? fminf(fmaxf(comp(uu, t), lb), ub) : 0.0f);
+  return uu;
 }
 
 // ---------------------------------------------------------------- init (Alg. 2, lines 1-2)
@@ -76,24 +265,25 @@ __device__ void eval_rows(const ProbDev &p, uint32_t D, uint32_t Dp, uint32_t ys
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_init(const RunDev *__restrict__ runs,
                                                 const ProbDev *__restrict__ probs,
+                                                const unsigned char *__restrict__ tab,
                                                 float *__restrict__ pop, float *__restrict__ fit,
                                                 uint32_t k0, uint32_t k1, double lb, double ub) {
   extern __shared__ __align__(16) unsigned char smem[];
   const RunDev run = runs[blockIdx.x];
   const ProbDev p = probs[run.prob];
-  const uint32_t N = run.N, D = run.D, Dp = run.Dp, C = run.C, Q = Dp / 4;
-  const Lds L = lds_layout(N, Dp, C);
-  float *pop_s = reinterpret_cast<float *>(smem + L.pop);
-  double *Y = reinterpret_cast<double *>(smem + L.Y);
-  float *Z = reinterpret_cast<float *>(smem + L.Z);
-  double2 *P = reinterpret_cast<double2 *>(smem + L.P);
-  float *fu_s = reinterpret_cast<float *>(smem + L.fu);
+  const uint32_t N = run.N, D = run.D, Dp = run.Dp, Q = Dp / 4, L = run.L, Np = run.Np;
+  const Lds lay = lds_layout(N, Dp, L, Np, run.t_lds != 0);
+  float *pop_s = reinterpret_cast<float *>(smem + lay.pop);
+  double2 *Ps = reinterpret_cast<double2 *>(smem + lay.ps);
   const uint32_t tid = threadIdx.x;
+  const uint32_t l = __builtin_amdgcn_readfirstlane(tid / Np);
+  const uint32_t i = tid - l * Np;
+  const bool act = l < L && i < N;
 
   // x = lb + (ub - lb) u0, u0 = (w >> 8) 2^-24, in float64, rounded once.
   for (uint32_t u = tid; u < N * Q; u += BLOCK) {
-    const uint32_t i = u / Q, q = u - i * Q;
-    const uint4 w = philox(q, i, INIT_PHASE, run.stream, k0, k1);
+    const uint32_t r = u / Q, q = u - r * Q;
+    const uint4 w = philox(q, r, INIT_PHASE, run.stream, k0, k1);
     float4 x;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -101,253 +291,188 @@ __global__ __launch_bounds__(BLOCK) void k_init(const RunDev *__restrict__ runs,
       const double u0 = (double)(word_of(w, t) >> 8) * 0x1p-24;
       set_comp(x, t, j < D ? (float)(lb + (ub - lb) * u0) : 0.0f);
     }
-    st4(pop_s, i * Dp + 4 * q, x);
+    st4(pop_s, r * Dp + 4 * q, x);
   }
   __syncthreads();
-  for (uint32_t c0 = 0; c0 < N; c0 += C) {
-    const uint32_t nC = min(C, N - c0);
-    for (uint32_t u = tid; u < nC * Q; u += BLOCK) {
-      const uint32_t il = u / Q, q = u - il * Q;
-      const float4 x = ld4(pop_s, (c0 + il) * Dp + 4 * q);
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const uint32_t j = 4 * q + t;
-        Y[il * L.ys + j] = j < D ? (double)comp(x, t) - (double)p.o[j] : 0.0;
-      }
+  if (act) {
+    double s0, s1;
+    eval_part(tab, p, D, l * D / L, (l + 1) * D / L, pop_s + i * Dp, 1u, s0, s1);
+    Ps[l * Np + i] = make_double2(s0, s1);
+  }
+  __syncthreads();
+  if (act && l == 0) {
+    double s0 = 0.0, s1 = 0.0;
+    for (uint32_t ll = 0; ll < L; ++ll) {
+      const double2 v = Ps[ll * Np + i];
+      s0 += v.x;
+      s1 += v.y;
     }
-    __syncthreads();
-    eval_rows<BLOCK>(p, D, Dp, L.ys, nC, Y, Z, P, fu_s + c0);
-    __syncthreads();
+    fit[run.fit_off + i] = finish_f32(p, s0, s1);
   }
   for (uint32_t u = tid; u < N * D; u += BLOCK) {
-    const uint32_t i = u / D, j = u - i * D;
-    pop[run.pop_off + u] = pop_s[i * Dp + j];
+    const uint32_t r = u / D, j = u - r * D;
+    pop[run.pop_off + u] = pop_s[r * Dp + j];
   }
-  for (uint32_t i = tid; i < N; i += BLOCK) fit[run.fit_off + i] = fu_s[i];
 }
 
 // ---------------------------------------------------------------- generations (Alg. 2, lines 6-12)
+//
+// Lane layout: the block is split into L parts of Np lanes (Np a multiple of
+// the wave size, Np >= N); lane i of part l works on trial i.  Each part
+// builds the genes 4q..4q+3 with q = l mod L and the fitness outputs
+// [l D / L, (l+1) D / L); the parts' partial sums meet in LDS.  Per
+// generation: rank | draws + trial genes | fitness parts | decision + commit,
+// separated by four barriers.
 
-template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_generations(
-    const RunDev *__restrict__ runs, const ProbDev *__restrict__ probs, float *__restrict__ pop,
-    float *__restrict__ fit, uint32_t g0, uint32_t n_gens, uint32_t k0, uint32_t k1, float lb,
-    float ub, float *__restrict__ pending, TraceArgs tr) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const RunDev run = runs[blockIdx.x];
-  const ProbDev p = probs[run.prob];
-  const uint32_t N = run.N, D = run.D, Dp = run.Dp, C = run.C, Q = Dp / 4, kp = run.kp;
-  const Lds L = lds_layout(N, Dp, C);
-  float *pop_s = reinterpret_cast<float *>(smem + L.pop);
-  float *fit_s = reinterpret_cast<float *>(smem + L.fit);
-  uint32_t *topk = reinterpret_cast<uint32_t *>(smem + L.topk);
-  uint4 *desc = reinterpret_cast<uint4 *>(smem + L.desc);
-  float *T = reinterpret_cast<float *>(smem + L.T);
-  double *Y = reinterpret_cast<double *>(smem + L.Y);
-  float *Z = reinterpret_cast<float *>(smem + L.Z);
-  double2 *P = reinterpret_cast<double2 *>(smem + L.P);
-  float *fu_s = reinterpret_cast<float *>(smem + L.fu);
-  int *acc_s = reinterpret_cast<int *>(smem + L.acc);
+template <int BLOCK, bool TLDS, bool TRACE>
+__device__ __forceinline__ void gen_body(unsigned char *smem, const RunDev &run, const ProbDev &p,
+                                         const unsigned char *__restrict__ tab,
+                                         float *__restrict__ pop, float *__restrict__ fit,
+                                         uint32_t g0, uint32_t n_gens, uint32_t k0, uint32_t k1,
+                                         float lb, float ub, float *__restrict__ pending,
+                                         const TraceArgs &tr) {
+  const uint32_t N = run.N, D = run.D, Dp = run.Dp, Q = Dp / 4, kp = run.kp, L = run.L,
+                 Np = run.Np;
+  const Lds lay = lds_layout(N, Dp, L, Np, TLDS);
+  float *pop_s = reinterpret_cast<float *>(smem + lay.pop);
+  uint64_t *key_s = reinterpret_cast<uint64_t *>(smem + lay.key);
+  float *fit_s = reinterpret_cast<float *>(smem + lay.fit);
+  uint32_t *topk = reinterpret_cast<uint32_t *>(smem + lay.topk);
+  double2 *Ps = reinterpret_cast<double2 *>(smem + lay.ps);
+  float *T = TLDS ? reinterpret_cast<float *>(smem + lay.T) : pending + run.pend_off;
+  const uint32_t ts = TLDS ? Np : N;
   const uint32_t tid = threadIdx.x;
-  const bool chunked = C < N;
-  float *pend = pending + run.pend_off;
-  const float F = run.F, CR = run.CR;
-  const int bl = run.bl, br = run.br, dn = run.dn, cs = run.cs;
-  const int use_rand = (bl == RAND || br == RAND) ? 1 : 0;
-  const int m = use_rand + 2 * dn;
+  const uint32_t l = __builtin_amdgcn_readfirstlane(tid / Np);
+  const uint32_t i = tid - l * Np;
+  const bool act = l < L && i < N;
+  const uint32_t j0 = l * D / L, j1 = (l + 1) * D / L;
 
   for (uint32_t u = tid; u < N * Dp; u += BLOCK) {
-    const uint32_t i = u / Dp, j = u - i * Dp;
-    pop_s[u] = j < D ? pop[run.pop_off + (size_t)i * D + j] : 0.0f;
+    const uint32_t r = u / Dp, j = u - r * Dp;
+    pop_s[u] = j < D ? pop[run.pop_off + (size_t)r * D + j] : 0.0f;
   }
-  for (uint32_t i = tid; i < N; i += BLOCK) fit_s[i] = fit[run.fit_off + i];
+  for (uint32_t r = tid; r < N; r += BLOCK) {
+    const float f = fit[run.fit_off + r];
+    fit_s[r] = f;
+    key_s[r] = mkkey(f, r);
+  }
 
   for (uint32_t gg = 0; gg < n_gens; ++gg) {
     const uint32_t g = g0 + gg;
     __syncthreads();
-    // (1) ranking by (fitness, index): best and the top-p set
-    for (uint32_t i = tid; i < N; i += BLOCK) {
-      const uint32_t ki = okey(fit_s[i]);
-      uint32_t rank = 0;
-      for (uint32_t j = 0; j < N; ++j) {
-        const uint32_t kj = okey(fit_s[j]);
-        rank += (kj < ki || (kj == ki && j < i)) ? 1u : 0u;
+    // (1) rank of every individual by (fitness, index); the first kp form
+    //     the top-p list, the first is the best
+    if (l == 0 && i < N) {
+      const uint64_t ki = key_s[i];
+      uint32_t rank = 0, j = 0;
+      for (; j + 8 <= N; j += 8) {
+        uint4 w[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) w[q] = *reinterpret_cast<const uint4 *>(key_s + j + 2 * q);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const uint64_t ka = ((uint64_t)w[q].y << 32) | w[q].x;
+          const uint64_t kb = ((uint64_t)w[q].w << 32) | w[q].z;
+          rank += (ka < ki ? 1u : 0u) + (kb < ki ? 1u : 0u);
+        }
       }
+      for (; j < N; ++j) rank += key_s[j] < ki ? 1u : 0u;
       if (rank < kp) topk[rank] = i;
     }
     __syncthreads();
-    // (2) per-target descriptors: index draws, pbest pick, j_rand / n, K, L
-    for (uint32_t i = tid; i < N; i += BLOCK) {
-      uint32_t w[12];
-      const uint4 wa = philox(0, i, g, run.stream, k0, k1);
-      const uint4 wc = philox(2, i, g, run.stream, k0, k1);
-      w[0] = wa.x; w[1] = wa.y; w[2] = wa.z; w[3] = wa.w;
-      if (m > 4) {
-        const uint4 wb = philox(1, i, g, run.stream, k0, k1);
-        w[4] = wb.x; w[5] = wb.y; w[6] = wb.z; w[7] = wb.w;
-      } else {
-        w[4] = w[5] = w[6] = w[7] = 0;
+    // (2) draws and this part's trial genes
+    float fx = 0.0f;
+    if (act) {
+      fx = fit_s[i];
+      const Desc d = make_desc(i, N, D, g, run.stream, k0, k1, run, kp, topk);
+      if (TRACE && l == 0) {
+        int32_t *o = tr.desc + (size_t)(run.fit_off + i) * 16;
+        o[0] = (int32_t)d.ibl;
+        o[1] = (int32_t)d.ibr;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          o[2 + 2 * k] = k < run.dn ? (int32_t)d.a[k] : -1;
+          o[3 + 2 * k] = k < run.dn ? (int32_t)d.b[k] : -1;
+        }
+        o[10] = (int32_t)d.jn;
+        o[11] = run.cs == EXP ? (int32_t)d.Lx : -1;
+        o[12] = (int32_t)d.pb_rank;
+        o[13] = d.r0;
+        o[14] = run.cs == ARITH ? (int32_t)__float_as_uint(d.K) : -1;
+        o[15] = 0;
       }
-      w[8] = wc.x; w[9] = wc.y; w[10] = wc.z; w[11] = wc.w;
-      uint32_t dr[9];
+      for (uint32_t q = l; q < Q; q += L) {
+        const float4 uu = trial_quad(pop_s, Dp, D, i, q, d, run, g, k0, k1, lb, ub);
 #pragma unroll
-      for (int k = 0; k < 9; ++k) dr[k] = 0;
-      sample_distinct(w, m, i, N, dr);
-      const int r0 = use_rand ? (int)dr[0] : -1;
-      uint32_t pr[8];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) pr[k] = (k < 2 * dn) ? dr[use_rand + k] : 0u;
-      const uint32_t pb_rank = lemire(w[W_PBEST], kp);
-      const uint32_t ipb = topk[pb_rank];
-      const uint32_t ibest = topk[0];
-      auto resolve = [&](int code) -> uint32_t {
-        return code == RAND ? (uint32_t)r0 : (code == BEST ? ibest : (code == PBEST ? ipb : i));
-      };
-      const uint32_t ibl = resolve(bl), ibr = resolve(br);
-      const uint32_t jn = lemire(w[W_JRAND], D);
-      const float K = unit_oc(w[W_K]);
-      uint32_t Lx = 1;
-      if (cs == EXP) {
-        // censored geometric length: continue while the t-th uniform <= CR
-        bool go = true;
-        uint32_t blk = W_GENE0 / 4;
-        while (go && Lx < D) {
-          const uint4 wr = philox(blk++, i, g, run.stream, k0, k1);
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            if (go && Lx < D) {
-              if (unit_oc(word_of(wr, t)) <= CR) ++Lx; else go = false;
-            }
+        for (int t = 0; t < 4; ++t) {
+          const uint32_t j = 4 * q + t;
+          if (j < D) {
+            T[j * ts + i] = comp(uu, t);
+            if (TRACE) tr.u[run.pop_off + (size_t)i * D + j] = comp(uu, t);
           }
         }
-      }
-      uint4 d;
-      d.x = ibl | (ibr << 8) | (jn << 16) | (Lx << 24);
-      d.y = pr[0] | (pr[1] << 8) | (pr[2] << 16) | (pr[3] << 24);
-      d.z = pr[4] | (pr[5] << 8) | (pr[6] << 16) | (pr[7] << 24);
-      d.w = __float_as_uint(K);
-      desc[i] = d;
-      if (tr.desc) {
-        int32_t *o = tr.desc + (size_t)(run.fit_off + i) * 16;
-        o[0] = (int32_t)ibl;
-        o[1] = (int32_t)ibr;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) o[2 + k] = (k < 2 * dn) ? (int32_t)pr[k] : -1;
-        o[10] = (int32_t)jn;
-        o[11] = cs == EXP ? (int32_t)Lx : -1;
-        o[12] = (int32_t)pb_rank;
-        o[13] = r0;
-        o[14] = cs == ARITH ? (int32_t)__float_as_uint(K) : -1;
-        o[15] = 0;
       }
     }
     __syncthreads();
-    // (3) trials chunk by chunk: mutation (Eq. 12), crossover (Eqs. 8-10), clip, fitness
-    for (uint32_t c0 = 0; c0 < N; c0 += C) {
-      const uint32_t nC = min(C, N - c0);
-      for (uint32_t u = tid; u < nC * Q; u += BLOCK) {
-        const uint32_t il = u / Q, q = u - il * Q, i = c0 + il, j0 = 4 * q;
-        const uint4 d = desc[i];
-        const uint32_t ibl = d.x & 0xFF, ibr = (d.x >> 8) & 0xFF, jn = (d.x >> 16) & 0xFF,
-                       Lx = d.x >> 24;
-        const float4 xi = ld4(pop_s, i * Dp + j0);
-        const float4 xb = ld4(pop_s, ibl * Dp + j0);
-        float4 base = xb;
-        if (bl != br) {
-          const float4 xr = ld4(pop_s, ibr * Dp + j0);
-          base.x = xb.x + F * (xr.x - xb.x);
-          base.y = xb.y + F * (xr.y - xb.y);
-          base.z = xb.z + F * (xr.z - xb.z);
-          base.w = xb.w + F * (xr.w - xb.w);
-        }
-        float4 dd;
-        {
-          const float4 a = ld4(pop_s, (d.y & 0xFF) * Dp + j0);
-          const float4 b = ld4(pop_s, ((d.y >> 8) & 0xFF) * Dp + j0);
-          dd.x = a.x - b.x; dd.y = a.y - b.y; dd.z = a.z - b.z; dd.w = a.w - b.w;
-        }
-        for (int k = 1; k < dn; ++k) {
-          const uint32_t word = k == 1 ? (d.y >> 16) : (k == 2 ? d.z : (d.z >> 16));
-          const float4 a = ld4(pop_s, (word & 0xFF) * Dp + j0);
-          const float4 b = ld4(pop_s, ((word >> 8) & 0xFF) * Dp + j0);
-          dd.x = dd.x + (a.x - b.x);
-          dd.y = dd.y + (a.y - b.y);
-          dd.z = dd.z + (a.z - b.z);
-          dd.w = dd.w + (a.w - b.w);
-        }
-        float4 v;
-        v.x = base.x + F * dd.x;
-        v.y = base.y + F * dd.y;
-        v.z = base.z + F * dd.z;
-        v.w = base.w + F * dd.w;
-        float4 uu;
-        if (cs == ARITH) {
-          const float K = __uint_as_float(d.w);
-          uu.x = xi.x + K * (v.x - xi.x);
-          uu.y = xi.y + K * (v.y - xi.y);
-          uu.z = xi.z + K * (v.z - xi.z);
-          uu.w = xi.w + K * (v.w - xi.w);
-        } else if (cs == BIN) {
-          const uint4 wr = philox(W_GENE0 / 4 + q, i, g, run.stream, k0, k1);
+    // (3) this part's share of the fitness
+    if (act) {
+      double s0, s1;
+      eval_part(tab, p, D, j0, j1, T + i, ts, s0, s1);
+      Ps[l * Np + i] = make_double2(s0, s1);
+    }
+    __syncthreads();
+    // (4) greedy selection (every part takes the same decision) and commit
+    if (act) {
+      double s0 = 0.0, s1 = 0.0;
+      for (uint32_t ll = 0; ll < L; ++ll) {
+        const double2 v = Ps[ll * Np + i];
+        s0 += v.x;
+        s1 += v.y;
+      }
+      const float f = finish_f32(p, s0, s1);
+      const bool a = accept_trial(f, fx);
+      if (a) {
+        for (uint32_t q = l; q < Q; q += L) {
+          float4 x;
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
-            const bool take = (unit_oc(word_of(wr, t)) <= CR) || (j0 + t == jn);
-            set_comp(uu, t, take ? comp(v, t) : comp(xi, t));
+            const uint32_t j = 4 * q + t;
+            set_comp(x, t, j < D ? T[j * ts + i] : 0.0f);
           }
-        } else {
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const uint32_t off = (j0 + t + D - jn) % D;
-            set_comp(uu, t, off < Lx ? comp(v, t) : comp(xi, t));
-          }
-        }
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const uint32_t j = j0 + t;
-          const float c = fminf(fmaxf(comp(uu, t), lb), ub);
-          set_comp(uu, t, j < D ? c : 0.0f);
-          Y[il * L.ys + j] = j < D ? (double)c - (double)p.o[j] : 0.0;
-          if (tr.u && j < D) tr.u[run.pop_off + (size_t)i * D + j] = c;
-        }
-        st4(T, il * Dp + j0, uu);
-      }
-      __syncthreads();
-      eval_rows<BLOCK>(p, D, Dp, L.ys, nC, Y, Z, P, fu_s + c0);
-      __syncthreads();
-      // (4) greedy selection decision
-      for (uint32_t il = tid; il < nC; il += BLOCK) {
-        const uint32_t i = c0 + il;
-        const int a = accept_trial(fu_s[i], fit_s[i]) ? 1 : 0;
-        acc_s[i] = a;
-        if (tr.fu) tr.fu[run.fit_off + i] = fu_s[i];
-        if (tr.desc) tr.desc[(size_t)(run.fit_off + i) * 16 + 15] = a;
-      }
-      if (chunked) {
-        __syncthreads();
-        for (uint32_t u = tid; u < nC * Q; u += BLOCK) {
-          const uint32_t il = u / Q, q = u - il * Q;
-          if (acc_s[c0 + il]) st4(pend, (c0 + il) * Dp + 4 * q, ld4(T, il * Dp + 4 * q));
+          st4(pop_s, i * Dp + 4 * q, x);
         }
       }
-      __syncthreads();
-    }
-    // (5) synchronous commit of accepted trials
-    for (uint32_t u = tid; u < N * Q; u += BLOCK) {
-      const uint32_t i = u / Q, q = u - i * Q;
-      if (acc_s[i]) {
-        const float4 x = chunked ? ld4(pend, i * Dp + 4 * q) : ld4(T, i * Dp + 4 * q);
-        st4(pop_s, i * Dp + 4 * q, x);
+      if (l == 0) {
+        if (a) {
+          fit_s[i] = f;
+          key_s[i] = mkkey(f, i);
+        }
+        if (TRACE) tr.fu[run.fit_off + i] = f;
+        if (TRACE) tr.desc[(size_t)(run.fit_off + i) * 16 + 15] = a ? 1 : 0;
       }
     }
-    for (uint32_t i = tid; i < N; i += BLOCK)
-      if (acc_s[i]) fit_s[i] = fu_s[i];
   }
   __syncthreads();
   for (uint32_t u = tid; u < N * D; u += BLOCK) {
-    const uint32_t i = u / D, j = u - i * D;
-    pop[run.pop_off + u] = pop_s[i * Dp + j];
+    const uint32_t r = u / D, j = u - r * D;
+    pop[run.pop_off + u] = pop_s[r * Dp + j];
   }
-  for (uint32_t i = tid; i < N; i += BLOCK) fit[run.fit_off + i] = fit_s[i];
+  for (uint32_t r = tid; r < N; r += BLOCK) fit[run.fit_off + r] = fit_s[r];
+}
+
+template <int BLOCK, bool TRACE>
+__global__ __launch_bounds__(BLOCK) void k_generations(
+    const RunDev *__restrict__ runs, const ProbDev *__restrict__ probs,
+    const unsigned char *__restrict__ tab, float *__restrict__ pop, float *__restrict__ fit,
+    uint32_t g0, uint32_t n_gens, uint32_t k0, uint32_t k1, float lb, float ub,
+    float *__restrict__ pending, TraceArgs tr) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const RunDev run = runs[blockIdx.x];
+  const ProbDev p = probs[run.prob];
+  if (run.t_lds)
+    gen_body<BLOCK, true, TRACE>(smem, run, p, tab, pop, fit, g0, n_gens, k0, k1, lb, ub, pending, tr);
+  else
+    gen_body<BLOCK, false, TRACE>(smem, run, p, tab, pop, fit, g0, n_gens, k0, k1, lb, ub, pending, tr);
 }
 
 // ---------------------------------------------------------------- best record in float64
@@ -356,6 +481,7 @@ constexpr int FIN_BLOCK = 128;
 
 __global__ __launch_bounds__(FIN_BLOCK) void k_finalize(const RunDev *__restrict__ runs,
                                                         const ProbDev *__restrict__ probs,
+                                                        const unsigned char *__restrict__ tab,
                                                         const float *__restrict__ pop,
                                                         const float *__restrict__ fit,
                                                         double *__restrict__ best_y,
@@ -382,14 +508,23 @@ __global__ __launch_bounds__(FIN_BLOCK) void k_finalize(const RunDev *__restrict
   }
   const uint32_t b = si[0];
   const float *x = pop + run.pop_off + (size_t)b * D;
+  const double *Rt = tab_ptr<double>(tab, p.r64t_off);
+  const uint32_t Dr = rt_stride(D);
+  const float *o = tab_ptr<float>(tab, p.o_off);
   for (uint32_t j = tid; j < D; j += FIN_BLOCK) {
     double acc = 0.0;
-    for (uint32_t k = 0; k < D; ++k)
-      acc = fma(p.R64[(size_t)j * D + k], (double)x[k] - (double)p.o[k], acc);
+    for (uint32_t k = 0; k < D; ++k) acc = fma(Rt[(size_t)k * Dr + j], (double)x[k] - (double)o[k], acc);
     z[j] = acc;
   }
   __syncthreads();
-  for (uint32_t j = tid; j < D; j += FIN_BLOCK) fn_term<double>(p, z, j, t0s[j], t1s[j]);
+  for (uint32_t j = tid; j < D; j += FIN_BLOCK) {
+    if (p.kind == FN_ROSENBROCK) {
+      t0s[j] = j + 1 < D ? h_rosenbrock<double>(z[j], z[j + 1]) : 0.0;
+      t1s[j] = 0.0;
+    } else {
+      elem_term<double>(tab, p, j, z[j], t0s[j], t1s[j]);
+    }
+  }
   __syncthreads();
   if (tid == 0) {
     double s0 = 0.0, s1 = 0.0;
@@ -532,21 +667,30 @@ __global__ void k_outer_best(const double *__restrict__ y, uint32_t P, int32_t *
   if (tid == 0) out[0] = si[0] == 0x7FFFFFFF ? 0 : si[0];
 }
 
-__global__ void k_to_f64(const float *__restrict__ src, double *__restrict__ dst, uint32_t n) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) dst[i] = (double)src[i];
+// Rt[k][j] = R[j][k] in float64, row stride Dr >= D + 16 (zero padding so a
+// block of 16 outputs starting anywhere below D stays inside the row).
+__global__ void k_rot_t64(const float *__restrict__ R, double *__restrict__ Rt, uint32_t D,
+                          uint32_t Dr) {
+  const uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= D * Dr) return;
+  const uint32_t k = u / Dr, j = u - k * Dr;
+  Rt[u] = j < D ? (double)R[(size_t)j * D + k] : 0.0;
 }
 
 // ---------------------------------------------------------------- launchers
 
-hipError_t launch_to_f64(const float *src, double *dst, uint32_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_to_f64, dim3((n + 255) / 256), dim3(256), 0, s, src, dst, n);
+hipError_t launch_rot_t64(const float *R, double *Rt, uint32_t D, hipStream_t s) {
+  const uint32_t n = D * rt_stride(D);
+  hipLaunchKernelGGL(k_rot_t64, dim3((n + 255) / 256), dim3(256), 0, s, R, Rt, D, rt_stride(D));
   return hipGetLastError();
 }
 
 hipError_t set_lds_limits() {
-  hipError_t e = hipFuncSetAttribute((const void *)k_generations<GEN_BLOCK>,
+  hipError_t e = hipFuncSetAttribute((const void *)k_generations<GEN_BLOCK, false>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BUDGET);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void *)k_generations<GEN_BLOCK, true>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BUDGET);
   if (e != hipSuccess) return e;
   return hipFuncSetAttribute((const void *)k_init<GEN_BLOCK>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BUDGET);
@@ -554,21 +698,26 @@ hipError_t set_lds_limits() {
 
 hipError_t launch_init(const LaunchArgs &a, double lb, double ub) {
   hipLaunchKernelGGL(k_init<GEN_BLOCK>, dim3(a.n_runs), dim3(GEN_BLOCK), a.lds_bytes, a.stream,
-                     a.runs, a.probs, a.pop, a.fit, a.k0, a.k1, lb, ub);
+                     a.runs, a.probs, a.tab, a.pop, a.fit, a.k0, a.k1, lb, ub);
   return hipGetLastError();
 }
 
 hipError_t launch_generations(const LaunchArgs &a, uint32_t g0, uint32_t n_gens, float lb,
                               float ub, TraceArgs tr) {
-  hipLaunchKernelGGL(k_generations<GEN_BLOCK>, dim3(a.n_runs), dim3(GEN_BLOCK), a.lds_bytes,
-                     a.stream, a.runs, a.probs, a.pop, a.fit, g0, n_gens, a.k0, a.k1, lb, ub,
-                     a.pending, tr);
+  if (tr.u)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_generations<GEN_BLOCK, true>), dim3(a.n_runs),
+                       dim3(GEN_BLOCK), a.lds_bytes, a.stream, a.runs, a.probs, a.tab, a.pop,
+                       a.fit, g0, n_gens, a.k0, a.k1, lb, ub, a.pending, tr);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_generations<GEN_BLOCK, false>), dim3(a.n_runs),
+                       dim3(GEN_BLOCK), a.lds_bytes, a.stream, a.runs, a.probs, a.tab, a.pop,
+                       a.fit, g0, n_gens, a.k0, a.k1, lb, ub, a.pending, tr);
   return hipGetLastError();
 }
 
 hipError_t launch_finalize(const LaunchArgs &a, double *best_y, float *best_x) {
   hipLaunchKernelGGL(k_finalize, dim3(a.n_runs), dim3(FIN_BLOCK), 0, a.stream, a.runs, a.probs,
-                     a.pop, a.fit, best_y, best_x);
+                     a.tab, a.pop, a.fit, best_y, best_x);
   return hipGetLastError();
 }
 
