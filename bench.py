@@ -33,12 +33,29 @@ sys.path.insert(0, ROOT)
 VALU_PEAK_SLOTS = 256 * 64 * 2.4e9
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per generation-kernel launch of the default workload, from two
+# rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE, KiB per dispatch) scaled by
+# what the same counters read for a 2 GiB device copy (FETCH_SIZE reads 0.5x
+# the copied bytes on this device, WRITE_SIZE 1.0x).  Keyed by a hash of the
+# kernel sources: a changed kernel reports null until measured again.
+KERNEL_SOURCES = ("paper_2502_10470_amd/csrc/kernels.hip", "paper_2502_10470_amd/csrc/device.h")
+MEASURED_TRAFFIC = {"31510c2b48ae8b29": (631.1 * 2.0 + 526.0 * 1.0) * 1024}
+
 PHILOX_SLOTS = 100   # 10 rounds x (2 quarter-rate 32x32->64 multiplies + 2 three-input XORs)
 ELEM_SLOTS = {       # per element of z: square/accumulate + the element function
     "rastrigin": 9, "ackley": 9, "elliptic": 3, "rosenbrock": 6, "schwefel": 14,
 }
 ELEM_SLOTS["hybrid"] = (6 * ELEM_SLOTS["schwefel"] + 7 * ELEM_SLOTS["rastrigin"]
                         + 7 * ELEM_SLOTS["elliptic"]) / 20.0
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def decode(theta, n_cs):
@@ -189,7 +206,8 @@ def main():
                    "runs": P, "N": 100, "D": 20, "inner_gens": G, "outer_gens": gens,
                    "evals_per_step": evals, "best_y": best[0]},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_SLOTS / 1e12,
-                     "unit": "Tslot/s", "frac": achieved / VALU_PEAK_SLOTS, "traffic": None,
+                     "unit": "Tslot/s", "frac": achieved / VALU_PEAK_SLOTS,
+                     "traffic": MEASURED_TRAFFIC.get(kernel_source_hash()),
                      "kernel": "k_generations", "avg_launch_ms": avg_launch_ms,
                      "launches": k_launches, "slots_per_launch": slots_per_launch,
                      "occupied_cu_frac": min(P, 256) / 256.0},

@@ -41,7 +41,7 @@ struct metade_ctx {
   float *theta_d = nullptr;
   float *pend_d = nullptr;
   size_t pop_floats = 0, fit_n = 0, bx_n = 0, pend_floats = 0;
-  uint32_t lds_bytes = 0;
+  uint32_t lds_bytes = 0, init_lds_bytes = 0;
   uint32_t gen = 0;
   // evolver
   float *Xo = nullptr, *Uo = nullptr, *bxo = nullptr;
@@ -77,6 +77,7 @@ struct Plan {
   std::vector<RunDev> runs;
   std::vector<ProbDev> probs;
   size_t tab_bytes = 0;
+  uint32_t init_lds_bytes = 0;
   size_t pop_floats = 0, fit_n = 0, bx_n = 0, pend_floats = 0;
   uint32_t lds_bytes = 0;
 };
@@ -154,13 +155,14 @@ metade_status plan_config(const metade_config *cfg, Plan &pl, std::string &msg) 
     d.kp = std::max<uint32_t>(1, (N * 10 + 99) / 100);
     // lanes per part: whole waves covering N; parts: as many as fit the block
     d.Np = ((N + 63u) / 64u) * 64u;
-    d.L = std::max<uint32_t>(1, std::min<uint32_t>(4, (uint32_t)mde::GEN_BLOCK / d.Np));
+    d.L = std::max<uint32_t>(1, std::min<uint32_t>(8, mde::GEN_CONSUMERS / d.Np));
     d.t_lds = mde::lds_layout(N, d.Dp, d.L, d.Np, true).total <= mde::LDS_BUDGET ? 1u : 0u;
     const uint32_t bytes = mde::lds_layout(N, d.Dp, d.L, d.Np, d.t_lds != 0).total;
     if (bytes > mde::LDS_BUDGET) {
       msg = "run " + std::to_string(r) + ": population does not fit in LDS"; return METADE_EINVAL;
     }
     pl.lds_bytes = std::max(pl.lds_bytes, bytes);
+    pl.init_lds_bytes = std::max(pl.init_lds_bytes, mde::init_lds_bytes(N, d.Dp, d.Np));
     d.pop_off = pl.pop_floats;
     d.pend_off = pl.pend_floats;
     d.fit_off = (uint32_t)pl.fit_n;
@@ -188,6 +190,7 @@ LaunchArgs largs(metade_ctx *c) {
   a.pending = c->pend_d;
   a.n_runs = c->n_runs;
   a.lds_bytes = c->lds_bytes;
+  a.init_lds_bytes = c->init_lds_bytes;
   a.k0 = (uint32_t)(c->seed & 0xFFFFFFFFu);
   a.k1 = (uint32_t)(c->seed >> 32);
   a.stream = c->stream;
@@ -288,6 +291,7 @@ metade_status metade_init(const metade_config *cfg, metade_ctx **out) {
   c->bx_n = pl.bx_n;
   c->pend_floats = pl.pend_floats;
   c->lds_bytes = pl.lds_bytes;
+  c->init_lds_bytes = pl.init_lds_bytes;
   auto bail = [&](metade_status st) {
     g_init_error = c->err;
     metade_destroy(c);

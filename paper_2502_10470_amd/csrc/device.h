@@ -128,13 +128,22 @@ __device__ __forceinline__ bool accept_trial_d(double fu, double fx) {
 
 // ---------------------------------------------------------------- LDS layout
 
+// Block shape of the generation kernel: GEN_THREADS lanes, the first half
+// consumers (the generation's ranking, mutation, fitness and commit), the
+// second half producers (the next generation's random draws).  Consumer lanes
+// form L parts of Np lanes (Np a multiple of the wave size, Np >= N).
+constexpr uint32_t GEN_THREADS = 1024;
+constexpr uint32_t GEN_CONSUMERS = GEN_THREADS / 2;
+constexpr uint32_t INIT_THREADS = 256;
+
 // LDS of the generation kernel: population [N][Dp] (row-major, float4 rows
 // for the gathers of the mutation), 64-bit ranking keys, fitness, the top-p
-// list, per-part partial fitness sums and -- when it fits -- the trial rows
-// stored gene-major ([D][Np]) so that lane i reading gene k of its own trial
-// touches consecutive words.
+// list, per-part partial fitness sums and ranks, the producers' Philox words
+// [N][12], binomial mask nibbles [N][Q] and packed draws [N], and -- when it
+// fits -- the trial rows stored gene-major ([D][Np]) so that lane i reading
+// gene k of its own trial touches consecutive words.
 struct Lds {
-  uint32_t pop, key, fit, topk, ps, T, total;
+  uint32_t pop, key, fit, topk, ps, rk, wb, msk, dsc, T, total;
 };
 
 __host__ __device__ inline uint32_t al16(uint32_t b) { return (b + 15u) & ~15u; }
@@ -148,9 +157,22 @@ __host__ __device__ inline Lds lds_layout(uint32_t N, uint32_t Dp, uint32_t L, u
   l.fit = o;  o += al16(N * 4);
   l.topk = o; o += al16(MAX_KP * 4);
   l.ps = o;   o += al16(L * Np * 16);
+  l.rk = o;   o += al16(L * Np * 4);
+  l.wb = o;   o += al16(N * 12 * 4);
+  l.msk = o;  o += al16(N * (Dp / 4));
+  l.dsc = o;  o += al16(N * 16);
   l.T = o;    o += t_lds ? al16(Dp * Np * 4) : 0u;
   l.total = o;
   return l;
+}
+
+// LDS of the initialisation kernel: population and per-part partial sums.
+__host__ __device__ inline uint32_t init_parts(uint32_t Np) {
+  const uint32_t L = INIT_THREADS / Np;
+  return L < 1 ? 1 : (L > 4 ? 4 : L);
+}
+__host__ __device__ inline uint32_t init_lds_bytes(uint32_t N, uint32_t Dp, uint32_t Np) {
+  return al16(N * Dp * 4) + al16(init_parts(Np) * Np * 16);
 }
 
 // ---------------------------------------------------------------- sampler
@@ -161,24 +183,23 @@ __host__ __device__ inline Lds lds_layout(uint32_t N, uint32_t Dp, uint32_t L, u
 // ascending order turns the rank t into the element.
 __device__ __forceinline__ void sample_distinct(const uint32_t *w, int m, uint32_t i, uint32_t N,
                                                 uint32_t *draws) {
-  uint32_t ex[10];
+  uint32_t ex[10];  // ex[0..k] hold the k+1 excluded values in ascending order
   ex[0] = i;
-#pragma unroll
-  for (int q = 1; q < 10; ++q) ex[q] = 0xFFFFFFFFu;
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
     if (k < m) {
       uint32_t r = lemire(w[k], N - 1u - (uint32_t)k);
 #pragma unroll
-      for (int q = 0; q < 10; ++q) r += (ex[q] <= r) ? 1u : 0u;
+      for (int q = 0; q <= k; ++q) r += (ex[q] <= r) ? 1u : 0u;
       draws[k] = r;
       uint32_t carry = r;
 #pragma unroll
-      for (int q = 0; q < 10; ++q) {
+      for (int q = 0; q <= k; ++q) {
         const uint32_t lo = min(carry, ex[q]);
         carry = max(carry, ex[q]);
         ex[q] = lo;
       }
+      ex[k + 1] = carry;
     }
   }
 }
@@ -188,10 +209,11 @@ __device__ __forceinline__ void sample_distinct(const uint32_t *w, int m, uint32
 template <typename T> struct Math;
 
 template <> struct Math<float> {
-  // cos(2 pi z): exact reduction z - rint(z), then cos(pi * 2r)
+  // cos(2 pi z): exact reduction r = z - rint(z) in [-1/2, 1/2], then the
+  // hardware cosine, whose argument is in revolutions
   static __device__ __forceinline__ float cos2pi(float z) {
     const float r = z - rintf(z);
-    return cospif(2.0f * r);
+    return __builtin_amdgcn_cosf(r);
   }
   static __device__ __forceinline__ float sin_(float x) { return sinf(x); }
   static __device__ __forceinline__ float sqrt_(float x) { return sqrtf(x); }

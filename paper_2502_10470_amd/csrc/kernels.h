@@ -8,8 +8,6 @@
 
 namespace mde {
 
-constexpr int GEN_BLOCK = 256;
-
 struct TraceArgs {
   float *u;        // [sum N*D] trial vectors, or null
   float *fu;       // [sum N] trial fitness, or null
@@ -25,6 +23,7 @@ struct LaunchArgs {
   float *pending;
   uint32_t n_runs;
   uint32_t lds_bytes;
+  uint32_t init_lds_bytes;
   uint32_t k0, k1;
   hipStream_t stream;
 };

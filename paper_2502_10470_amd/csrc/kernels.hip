@@ -43,8 +43,20 @@ __device__ __forceinline__ void rot_block(const double *__restrict__ Rt, uint32_
 #pragma unroll
   for (int q = 0; q < J; ++q) acc[q] = 0.0;
   const double *col = Rt + jc;
-#pragma unroll 2
-  for (uint32_t k = 0; k < D; ++k) {
+  uint32_t k = 0;
+  for (; k + 8 <= D; k += 8) {
+    float tv[8];
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) tv[kk] = t[(k + kk) * ts];
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+      const double yk = (double)tv[kk] - (double)o[k + kk];
+      const double *c = col + (size_t)(k + kk) * Dr;
+#pragma unroll
+      for (int q = 0; q < J; ++q) acc[q] = fma(c[q], yk, acc[q]);
+    }
+  }
+  for (; k < D; ++k) {
     const double yk = (double)t[k * ts] - (double)o[k];
     const double *c = col + (size_t)k * Dr;
 #pragma unroll
@@ -97,27 +109,22 @@ __device__ __forceinline__ void eval_part(const unsigned char *__restrict__ tab,
   uint32_t jc = j0;
   while (jc < jend) {
     const uint32_t rem = jend - jc;
-    if (rem > 12) {
-      double a[16];
-      rot_block<16>(Rt, D, Dr, jc, t, ts, o, a);
-      consume<16>(tab, p, a, jc, min(rem, 16u), j1, ta);
-      jc += 16;
-    } else if (rem > 8) {
-      double a[12];
-      rot_block<12>(Rt, D, Dr, jc, t, ts, o, a);
-      consume<12>(tab, p, a, jc, rem, j1, ta);
-      jc += 12;
-    } else if (rem > 4) {
-      double a[8];
-      rot_block<8>(Rt, D, Dr, jc, t, ts, o, a);
-      consume<8>(tab, p, a, jc, rem, j1, ta);
-      jc += 8;
-    } else {
-      double a[4];
-      rot_block<4>(Rt, D, Dr, jc, t, ts, o, a);
-      consume<4>(tab, p, a, jc, rem, j1, ta);
-      jc += 4;
-    }
+#define MDE_BLOCK(JJ)                                        \
+  {                                                          \
+    double a[JJ];                                            \
+    rot_block<JJ>(Rt, D, Dr, jc, t, ts, o, a);               \
+    consume<JJ>(tab, p, a, jc, min(rem, (uint32_t)JJ), j1, ta); \
+    jc += JJ;                                                \
+  }
+    if (rem > 12) MDE_BLOCK(16)
+    else if (rem > 10) MDE_BLOCK(12)
+    else if (rem > 8) MDE_BLOCK(10)
+    else if (rem > 6) MDE_BLOCK(8)
+    else if (rem == 6) MDE_BLOCK(6)
+    else if (rem == 5) MDE_BLOCK(5)
+    else if (rem > 2) MDE_BLOCK(4)
+    else MDE_BLOCK(2)
+#undef MDE_BLOCK
   }
   s0 = ta.s0;
   s1 = ta.s1;
@@ -128,84 +135,103 @@ __device__ __forceinline__ float finish_f32(const ProbDev &p, double s0, double 
                              : (float)(s0 + (double)p.bias);
 }
 
-// ---------------------------------------------------------------- per-trial draws
+// ---------------------------------------------------------------- random draws (producers)
+//
+// The random part of a generation does not depend on the population: index
+// draws, the pbest rank, j_rand / n, K, the exponential length L and the
+// binomial mask bits are functions of (seed, stream, generation, individual)
+// and theta only.  Producer lanes compute them one generation ahead.
 
-struct Desc {
-  uint32_t ibl, ibr, jn, Lx, pb_rank;
-  int32_t r0;
-  uint32_t a[4], b[4];
-  float K;
-};
+// Philox blocks of generation g: block b < 3 gives words 4b..4b+3 (kept for
+// the draws), block 3 + q gives the binomial uniforms of genes 4q..4q+3
+// (reduced at once to the mask nibble r <= CR).
+__device__ __forceinline__ void produce_words(uint32_t ptid, uint32_t nprod, const RunDev &run,
+                                              uint32_t N, uint32_t Q, uint32_t g, uint32_t k0,
+                                              uint32_t k1, uint32_t *wb, uint8_t *msk) {
+  const int use_rand = (run.bl == RAND || run.br == RAND) ? 1 : 0;
+  const int m = use_rand + 2 * run.dn;
+  const uint32_t NB = 3 + (run.cs == BIN ? Q : 0);
+  for (uint32_t it = ptid; it < N * NB; it += nprod) {
+    const uint32_t i = it / NB, b = it - i * NB;
+    if (b == 1 && m <= 4) continue;
+    const uint32_t blk = b < 3 ? b : W_GENE0 / 4 + (b - 3);
+    const uint4 w = philox(blk, i, g, run.stream, k0, k1);
+    if (b < 3) {
+      *reinterpret_cast<uint4 *>(wb + i * 12 + 4 * b) = w;
+    } else {
+      uint32_t nib = 0;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) nib |= (unit_oc(word_of(w, t)) <= run.CR ? 1u : 0u) << t;
+      msk[i * Q + (b - 3)] = (uint8_t)nib;
+    }
+  }
+}
 
-// Index draws (rand base and difference pairs, distinct and != i), pbest pick
-// from the top-p list, j_rand or the exponential start n, K, and the
-// exponential length L (censored geometric: continue while uniform t <= CR).
-__device__ __forceinline__ Desc make_desc(uint32_t i, uint32_t N, uint32_t D, uint32_t g,
-                                          uint32_t stream, uint32_t k0, uint32_t k1,
-                                          const RunDev &run, uint32_t kp,
-                                          const uint32_t *topk) {
-  const int bl = run.bl, br = run.br, dn = run.dn;
-  const int use_rand = (bl == RAND || br == RAND) ? 1 : 0;
+// Packed draws of one trial: x = a0|b0|a1|b1, y = a2|b2|a3|b3 (difference
+// pairs), z = r0 | pbest rank << 8 | j_rand (or n) << 16 | L << 24, w = K.
+__device__ __forceinline__ void produce_desc(uint32_t ptid, uint32_t nprod, const RunDev &run,
+                                             uint32_t N, uint32_t D, uint32_t kp, uint32_t g,
+                                             uint32_t k0, uint32_t k1, const uint32_t *wb,
+                                             uint4 *dsc) {
+  const int use_rand = (run.bl == RAND || run.br == RAND) ? 1 : 0;
+  const int dn = run.dn;
   const int m = use_rand + 2 * dn;
-  uint32_t w[12];
-  const uint4 wa = philox(0, i, g, stream, k0, k1);
-  const uint4 wc = philox(2, i, g, stream, k0, k1);
-  w[0] = wa.x; w[1] = wa.y; w[2] = wa.z; w[3] = wa.w;
-  if (m > 4) {
-    const uint4 wb = philox(1, i, g, stream, k0, k1);
-    w[4] = wb.x; w[5] = wb.y; w[6] = wb.z; w[7] = wb.w;
-  } else {
-    w[4] = w[5] = w[6] = w[7] = 0;
-  }
-  w[8] = wc.x; w[9] = wc.y; w[10] = wc.z; w[11] = wc.w;
-  uint32_t dr[9];
+  for (uint32_t i = ptid; i < N; i += nprod) {
+    uint32_t w[12];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) dr[k] = 0;
-  sample_distinct(w, m, i, N, dr);
-  Desc d;
-  d.r0 = use_rand ? (int32_t)dr[0] : -1;
+    for (int b = 0; b < 3; ++b) {
+      const uint4 v = *reinterpret_cast<const uint4 *>(wb + i * 12 + 4 * b);
+      w[4 * b] = v.x; w[4 * b + 1] = v.y; w[4 * b + 2] = v.z; w[4 * b + 3] = v.w;
+    }
+    uint32_t dr[9];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    d.a[k] = (k < dn) ? dr[use_rand + 2 * k] : 0u;
-    d.b[k] = (k < dn) ? dr[use_rand + 2 * k + 1] : 0u;
-  }
-  d.pb_rank = lemire(w[W_PBEST], kp);
-  const uint32_t ipb = topk[d.pb_rank];
-  const uint32_t ibest = topk[0];
-  d.ibl = bl == RAND ? (uint32_t)d.r0 : (bl == BEST ? ibest : (bl == PBEST ? ipb : i));
-  d.ibr = br == RAND ? (uint32_t)d.r0 : (br == BEST ? ibest : (br == PBEST ? ipb : i));
-  d.jn = lemire(w[W_JRAND], D);
-  d.K = unit_oc(w[W_K]);
-  d.Lx = 1;
-  if (run.cs == EXP) {
-    bool go = true;
-    uint32_t blk = W_GENE0 / 4;
-    while (go && d.Lx < D) {
-      const uint4 wr = philox(blk++, i, g, stream, k0, k1);
+    for (int k = 0; k < 9; ++k) dr[k] = 0;
+    sample_distinct(w, m, i, N, dr);
+    uint32_t pr[8];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        if (go && d.Lx < D) {
-          if (unit_oc(word_of(wr, t)) <= run.CR) ++d.Lx; else go = false;
+    for (int k = 0; k < 8; ++k) pr[k] = (k < 2 * dn) ? dr[use_rand + k] : 0u;
+    const uint32_t r0 = use_rand ? dr[0] : 0u;
+    const uint32_t pb = lemire(w[W_PBEST], kp);
+    const uint32_t jn = lemire(w[W_JRAND], D);
+    uint32_t Lx = 1;
+    if (run.cs == EXP) {
+      // censored geometric length: continue while uniform t (word 12 + t) <= CR
+      bool go = true;
+      uint32_t blk = W_GENE0 / 4;
+      while (go && Lx < D) {
+        const uint4 wr = philox(blk++, i, g, run.stream, k0, k1);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          if (go && Lx < D) {
+            if (unit_oc(word_of(wr, t)) <= run.CR) ++Lx; else go = false;
+          }
         }
       }
     }
+    uint4 d;
+    d.x = pr[0] | (pr[1] << 8) | (pr[2] << 16) | (pr[3] << 24);
+    d.y = pr[4] | (pr[5] << 8) | (pr[6] << 16) | (pr[7] << 24);
+    d.z = r0 | (pb << 8) | (jn << 16) | (Lx << 24);
+    d.w = __float_as_uint(unit_oc(w[W_K]));
+    dsc[i] = d;
   }
-  return d;
 }
+
+__device__ __forceinline__ uint32_t byte_of(uint32_t w, int k) { return (w >> (8 * k)) & 0xFFu; }
 
 // Genes 4q..4q+3 of trial i: mutation Eq. (12), crossover Eqs. (8)-(10),
 // clip to the box.  Genes >= D come back as 0.
 __device__ __forceinline__ float4 trial_quad(const float *pop_s, uint32_t Dp, uint32_t D,
-                                             uint32_t i, uint32_t q, const Desc &d,
-                                             const RunDev &run, uint32_t g, uint32_t k0,
-                                             uint32_t k1, float lb, float ub) {
+                                             uint32_t i, uint32_t q, uint32_t ibl, uint32_t ibr,
+                                             const uint4 &d, uint32_t nib, const RunDev &run,
+                                             float lb, float ub) {
   const uint32_t j0 = 4 * q;
   const float F = run.F;
   const float4 xi = ld4(pop_s, i * Dp + j0);
-  const float4 xb = ld4(pop_s, d.ibl * Dp + j0);
+  const float4 xb = ld4(pop_s, ibl * Dp + j0);
   float4 base = xb;
   if (run.bl != run.br) {
-    const float4 xr = ld4(pop_s, d.ibr * Dp + j0);
+    const float4 xr = ld4(pop_s, ibr * Dp + j0);
     base.x = xb.x + F * (xr.x - xb.x);
     base.y = xb.y + F * (xr.y - xb.y);
     base.z = xb.z + F * (xr.z - xb.z);
@@ -213,15 +239,16 @@ __device__ __forceinline__ float4 trial_quad(const float *pop_s, uint32_t Dp, ui
   }
   float4 dd;
   {
-    const float4 a = ld4(pop_s, d.a[0] * Dp + j0);
-    const float4 b = ld4(pop_s, d.b[0] * Dp + j0);
+    const float4 a = ld4(pop_s, byte_of(d.x, 0) * Dp + j0);
+    const float4 b = ld4(pop_s, byte_of(d.x, 1) * Dp + j0);
     dd.x = a.x - b.x; dd.y = a.y - b.y; dd.z = a.z - b.z; dd.w = a.w - b.w;
   }
 #pragma unroll
   for (int k = 1; k < 4; ++k) {
     if (k < run.dn) {
-      const float4 a = ld4(pop_s, d.a[k] * Dp + j0);
-      const float4 b = ld4(pop_s, d.b[k] * Dp + j0);
+      const uint32_t word = k == 1 ? (d.x >> 16) : (k == 2 ? d.y : (d.y >> 16));
+      const float4 a = ld4(pop_s, byte_of(word, 0) * Dp + j0);
+      const float4 b = ld4(pop_s, byte_of(word, 1) * Dp + j0);
       dd.x = dd.x + (a.x - b.x);
       dd.y = dd.y + (a.y - b.y);
       dd.z = dd.z + (a.z - b.z);
@@ -235,23 +262,24 @@ __device__ __forceinline__ float4 trial_quad(const float *pop_s, uint32_t Dp, ui
   v.w = base.w + F * dd.w;
   float4 uu;
   if (run.cs == ARITH) {
-    const float K = d.K;
+    const float K = __uint_as_float(d.w);
     uu.x = xi.x + K * (v.x - xi.x);
     uu.y = xi.y + K * (v.y - xi.y);
     uu.z = xi.z + K * (v.z - xi.z);
     uu.w = xi.w + K * (v.w - xi.w);
   } else if (run.cs == BIN) {
-    const uint4 wr = philox(W_GENE0 / 4 + q, i, g, run.stream, k0, k1);
+    const uint32_t jn = byte_of(d.z, 2);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      const bool take = (unit_oc(word_of(wr, t)) <= run.CR) || (j0 + t == d.jn);
+      const bool take = ((nib >> t) & 1u) || (j0 + t == jn);
       set_comp(uu, t, take ? comp(v, t) : comp(xi, t));
     }
   } else {
+    const uint32_t n0 = byte_of(d.z, 2), Lx = d.z >> 24;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      const uint32_t off = (j0 + t + D - d.jn) % D;
-      set_comp(uu, t, off < d.Lx ? comp(v, t) : comp(xi, t));
+      const uint32_t off = (j0 + t + D - n0) % D;
+      set_comp(uu, t, off < Lx ? comp(v, t) : comp(xi, t));
     }
   }
 #pragma unroll
@@ -262,26 +290,26 @@ __device__ __forceinline__ float4 trial_quad(const float *pop_s, uint32_t Dp, ui
 
 // ---------------------------------------------------------------- init (Alg. 2, lines 1-2)
 
-template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_init(const RunDev *__restrict__ runs,
-                                                const ProbDev *__restrict__ probs,
-                                                const unsigned char *__restrict__ tab,
-                                                float *__restrict__ pop, float *__restrict__ fit,
-                                                uint32_t k0, uint32_t k1, double lb, double ub) {
+__global__ __launch_bounds__(INIT_THREADS) void k_init(const RunDev *__restrict__ runs,
+                                                       const ProbDev *__restrict__ probs,
+                                                       const unsigned char *__restrict__ tab,
+                                                       float *__restrict__ pop,
+                                                       float *__restrict__ fit, uint32_t k0,
+                                                       uint32_t k1, double lb, double ub) {
   extern __shared__ __align__(16) unsigned char smem[];
   const RunDev run = runs[blockIdx.x];
   const ProbDev p = probs[run.prob];
-  const uint32_t N = run.N, D = run.D, Dp = run.Dp, Q = Dp / 4, L = run.L, Np = run.Np;
-  const Lds lay = lds_layout(N, Dp, L, Np, run.t_lds != 0);
-  float *pop_s = reinterpret_cast<float *>(smem + lay.pop);
-  double2 *Ps = reinterpret_cast<double2 *>(smem + lay.ps);
+  const uint32_t N = run.N, D = run.D, Dp = run.Dp, Q = Dp / 4;
+  const uint32_t Np = ((N + 63u) / 64u) * 64u, L = init_parts(Np);
+  float *pop_s = reinterpret_cast<float *>(smem);
+  double2 *Ps = reinterpret_cast<double2 *>(smem + al16(N * Dp * 4));
   const uint32_t tid = threadIdx.x;
   const uint32_t l = __builtin_amdgcn_readfirstlane(tid / Np);
   const uint32_t i = tid - l * Np;
   const bool act = l < L && i < N;
 
   // x = lb + (ub - lb) u0, u0 = (w >> 8) 2^-24, in float64, rounded once.
-  for (uint32_t u = tid; u < N * Q; u += BLOCK) {
+  for (uint32_t u = tid; u < N * Q; u += INIT_THREADS) {
     const uint32_t r = u / Q, q = u - r * Q;
     const uint4 w = philox(q, r, INIT_PHASE, run.stream, k0, k1);
     float4 x;
@@ -309,7 +337,7 @@ __global__ __launch_bounds__(BLOCK) void k_init(const RunDev *__restrict__ runs,
     }
     fit[run.fit_off + i] = finish_f32(p, s0, s1);
   }
-  for (uint32_t u = tid; u < N * D; u += BLOCK) {
+  for (uint32_t u = tid; u < N * D; u += INIT_THREADS) {
     const uint32_t r = u / D, j = u - r * D;
     pop[run.pop_off + u] = pop_s[r * Dp + j];
   }
@@ -317,14 +345,14 @@ __global__ __launch_bounds__(BLOCK) void k_init(const RunDev *__restrict__ runs,
 
 // ---------------------------------------------------------------- generations (Alg. 2, lines 6-12)
 //
-// Lane layout: the block is split into L parts of Np lanes (Np a multiple of
-// the wave size, Np >= N); lane i of part l works on trial i.  Each part
-// builds the genes 4q..4q+3 with q = l mod L and the fitness outputs
-// [l D / L, (l+1) D / L); the parts' partial sums meet in LDS.  Per
-// generation: rank | draws + trial genes | fitness parts | decision + commit,
-// separated by four barriers.
+// Consumer lane i of part l works on trial i: it builds genes 4q..4q+3 with
+// q = l mod L and the fitness outputs [l D / L, (l+1) D / L); the parts'
+// partial sums meet in LDS.  Per generation (five barriers):
+//   S0 partial ranks | S1 top-p list | S2 mutation + crossover |
+//   S3 fitness (producers: Philox words of g+1) | S4 selection + commit
+//   (producers: draws of g+1).
 
-template <int BLOCK, bool TLDS, bool TRACE>
+template <bool TLDS, bool TRACE>
 __device__ __forceinline__ void gen_body(unsigned char *smem, const RunDev &run, const ProbDev &p,
                                          const unsigned char *__restrict__ tab,
                                          float *__restrict__ pop, float *__restrict__ fit,
@@ -339,70 +367,91 @@ __device__ __forceinline__ void gen_body(unsigned char *smem, const RunDev &run,
   float *fit_s = reinterpret_cast<float *>(smem + lay.fit);
   uint32_t *topk = reinterpret_cast<uint32_t *>(smem + lay.topk);
   double2 *Ps = reinterpret_cast<double2 *>(smem + lay.ps);
+  uint32_t *rk = reinterpret_cast<uint32_t *>(smem + lay.rk);
+  uint32_t *wb = reinterpret_cast<uint32_t *>(smem + lay.wb);
+  uint8_t *msk = reinterpret_cast<uint8_t *>(smem + lay.msk);
+  uint4 *dsc = reinterpret_cast<uint4 *>(smem + lay.dsc);
   float *T = TLDS ? reinterpret_cast<float *>(smem + lay.T) : pending + run.pend_off;
   const uint32_t ts = TLDS ? Np : N;
   const uint32_t tid = threadIdx.x;
+  const bool producer = tid >= GEN_CONSUMERS;  // whole waves
+  const uint32_t ptid = tid - GEN_CONSUMERS;
   const uint32_t l = __builtin_amdgcn_readfirstlane(tid / Np);
   const uint32_t i = tid - l * Np;
-  const bool act = l < L && i < N;
+  const bool act = !producer && l < L && i < N;
   const uint32_t j0 = l * D / L, j1 = (l + 1) * D / L;
+  const uint32_t kr0 = l * N / L, kr1 = (l + 1) * N / L;
+  const int use_rand = (run.bl == RAND || run.br == RAND) ? 1 : 0;
 
-  for (uint32_t u = tid; u < N * Dp; u += BLOCK) {
+  for (uint32_t u = tid; u < N * Dp; u += GEN_THREADS) {
     const uint32_t r = u / Dp, j = u - r * Dp;
     pop_s[u] = j < D ? pop[run.pop_off + (size_t)r * D + j] : 0.0f;
   }
-  for (uint32_t r = tid; r < N; r += BLOCK) {
+  for (uint32_t r = tid; r < N; r += GEN_THREADS) {
     const float f = fit[run.fit_off + r];
     fit_s[r] = f;
     key_s[r] = mkkey(f, r);
   }
+  // draws of the first generation
+  if (producer) produce_words(ptid, GEN_CONSUMERS, run, N, Q, g0, k0, k1, wb, msk);
+  __syncthreads();
+  if (producer) produce_desc(ptid, GEN_CONSUMERS, run, N, D, kp, g0, k0, k1, wb, dsc);
 
   for (uint32_t gg = 0; gg < n_gens; ++gg) {
     const uint32_t g = g0 + gg;
     __syncthreads();
-    // (1) rank of every individual by (fitness, index); the first kp form
-    //     the top-p list, the first is the best
-    if (l == 0 && i < N) {
+    // S0: rank of individual i among this part's slice of the keys
+    if (act) {
       const uint64_t ki = key_s[i];
-      uint32_t rank = 0, j = 0;
-      for (; j + 8 <= N; j += 8) {
-        uint4 w[4];
+      uint32_t cnt = 0, j = kr0;
+      for (; j + 8 <= kr1; j += 8) {
+        uint64_t kv[8];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) w[q] = *reinterpret_cast<const uint4 *>(key_s + j + 2 * q);
+        for (int q = 0; q < 8; ++q) kv[q] = key_s[j + q];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const uint64_t ka = ((uint64_t)w[q].y << 32) | w[q].x;
-          const uint64_t kb = ((uint64_t)w[q].w << 32) | w[q].z;
-          rank += (ka < ki ? 1u : 0u) + (kb < ki ? 1u : 0u);
-        }
+        for (int q = 0; q < 8; ++q) cnt += kv[q] < ki ? 1u : 0u;
       }
-      for (; j < N; ++j) rank += key_s[j] < ki ? 1u : 0u;
-      if (rank < kp) topk[rank] = i;
+      for (; j < kr1; ++j) cnt += key_s[j] < ki ? 1u : 0u;
+      rk[l * Np + i] = cnt;
     }
     __syncthreads();
-    // (2) draws and this part's trial genes
+    // S1: the top-p list (first is the best)
     float fx = 0.0f;
     if (act) {
       fx = fit_s[i];
-      const Desc d = make_desc(i, N, D, g, run.stream, k0, k1, run, kp, topk);
+      if (l == 0) {
+        uint32_t rank = 0;
+        for (uint32_t ll = 0; ll < L; ++ll) rank += rk[ll * Np + i];
+        if (rank < kp) topk[rank] = i;
+      }
+    }
+    __syncthreads();
+    // S2: mutation, crossover, clip -> this part's genes of trial i
+    if (act) {
+      const uint4 d = dsc[i];
+      const uint32_t r0 = byte_of(d.z, 0), pb = byte_of(d.z, 1);
+      const uint32_t ibest = topk[0], ipb = topk[pb];
+      const uint32_t ibl = run.bl == RAND ? r0 : (run.bl == BEST ? ibest : (run.bl == PBEST ? ipb : i));
+      const uint32_t ibr = run.br == RAND ? r0 : (run.br == BEST ? ibest : (run.br == PBEST ? ipb : i));
       if (TRACE && l == 0) {
         int32_t *o = tr.desc + (size_t)(run.fit_off + i) * 16;
-        o[0] = (int32_t)d.ibl;
-        o[1] = (int32_t)d.ibr;
+        o[0] = (int32_t)ibl;
+        o[1] = (int32_t)ibr;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          o[2 + 2 * k] = k < run.dn ? (int32_t)d.a[k] : -1;
-          o[3 + 2 * k] = k < run.dn ? (int32_t)d.b[k] : -1;
+        for (int k = 0; k < 8; ++k) {
+          const uint32_t word = k < 4 ? d.x : d.y;
+          o[2 + k] = (k / 2) < run.dn ? (int32_t)byte_of(word, k & 3) : -1;
         }
-        o[10] = (int32_t)d.jn;
-        o[11] = run.cs == EXP ? (int32_t)d.Lx : -1;
-        o[12] = (int32_t)d.pb_rank;
-        o[13] = d.r0;
-        o[14] = run.cs == ARITH ? (int32_t)__float_as_uint(d.K) : -1;
+        o[10] = (int32_t)byte_of(d.z, 2);
+        o[11] = run.cs == EXP ? (int32_t)(d.z >> 24) : -1;
+        o[12] = (int32_t)pb;
+        o[13] = use_rand ? (int32_t)r0 : -1;
+        o[14] = run.cs == ARITH ? (int32_t)d.w : -1;
         o[15] = 0;
       }
       for (uint32_t q = l; q < Q; q += L) {
-        const float4 uu = trial_quad(pop_s, Dp, D, i, q, d, run, g, k0, k1, lb, ub);
+        const uint32_t nib = run.cs == BIN ? msk[i * Q + q] : 0u;
+        const float4 uu = trial_quad(pop_s, Dp, D, i, q, ibl, ibr, d, nib, run, lb, ub);
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           const uint32_t j = 4 * q + t;
@@ -414,14 +463,15 @@ __device__ __forceinline__ void gen_body(unsigned char *smem, const RunDev &run,
       }
     }
     __syncthreads();
-    // (3) this part's share of the fitness
+    // S3: this part's share of the fitness; producers draw generation g+1
     if (act) {
       double s0, s1;
       eval_part(tab, p, D, j0, j1, T + i, ts, s0, s1);
       Ps[l * Np + i] = make_double2(s0, s1);
     }
+    if (producer) produce_words(ptid, GEN_CONSUMERS, run, N, Q, g + 1, k0, k1, wb, msk);
     __syncthreads();
-    // (4) greedy selection (every part takes the same decision) and commit
+    // S4: greedy selection (every part takes the same decision) and commit
     if (act) {
       double s0 = 0.0, s1 = 0.0;
       for (uint32_t ll = 0; ll < L; ++ll) {
@@ -447,21 +497,24 @@ __device__ __forceinline__ void gen_body(unsigned char *smem, const RunDev &run,
           fit_s[i] = f;
           key_s[i] = mkkey(f, i);
         }
-        if (TRACE) tr.fu[run.fit_off + i] = f;
-        if (TRACE) tr.desc[(size_t)(run.fit_off + i) * 16 + 15] = a ? 1 : 0;
+        if (TRACE) {
+          tr.fu[run.fit_off + i] = f;
+          tr.desc[(size_t)(run.fit_off + i) * 16 + 15] = a ? 1 : 0;
+        }
       }
     }
+    if (producer) produce_desc(ptid, GEN_CONSUMERS, run, N, D, kp, g + 1, k0, k1, wb, dsc);
   }
   __syncthreads();
-  for (uint32_t u = tid; u < N * D; u += BLOCK) {
+  for (uint32_t u = tid; u < N * D; u += GEN_THREADS) {
     const uint32_t r = u / D, j = u - r * D;
     pop[run.pop_off + u] = pop_s[r * Dp + j];
   }
-  for (uint32_t r = tid; r < N; r += BLOCK) fit[run.fit_off + r] = fit_s[r];
+  for (uint32_t r = tid; r < N; r += GEN_THREADS) fit[run.fit_off + r] = fit_s[r];
 }
 
-template <int BLOCK, bool TRACE>
-__global__ __launch_bounds__(BLOCK) void k_generations(
+template <bool TRACE>
+__global__ __launch_bounds__(GEN_THREADS) void k_generations(
     const RunDev *__restrict__ runs, const ProbDev *__restrict__ probs,
     const unsigned char *__restrict__ tab, float *__restrict__ pop, float *__restrict__ fit,
     uint32_t g0, uint32_t n_gens, uint32_t k0, uint32_t k1, float lb, float ub,
@@ -470,9 +523,9 @@ __global__ __launch_bounds__(BLOCK) void k_generations(
   const RunDev run = runs[blockIdx.x];
   const ProbDev p = probs[run.prob];
   if (run.t_lds)
-    gen_body<BLOCK, true, TRACE>(smem, run, p, tab, pop, fit, g0, n_gens, k0, k1, lb, ub, pending, tr);
+    gen_body<true, TRACE>(smem, run, p, tab, pop, fit, g0, n_gens, k0, k1, lb, ub, pending, tr);
   else
-    gen_body<BLOCK, false, TRACE>(smem, run, p, tab, pop, fit, g0, n_gens, k0, k1, lb, ub, pending, tr);
+    gen_body<false, TRACE>(smem, run, p, tab, pop, fit, g0, n_gens, k0, k1, lb, ub, pending, tr);
 }
 
 // ---------------------------------------------------------------- best record in float64
@@ -686,18 +739,18 @@ hipError_t launch_rot_t64(const float *R, double *Rt, uint32_t D, hipStream_t s)
 }
 
 hipError_t set_lds_limits() {
-  hipError_t e = hipFuncSetAttribute((const void *)k_generations<GEN_BLOCK, false>,
+  hipError_t e = hipFuncSetAttribute((const void *)k_generations<false>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BUDGET);
   if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void *)k_generations<GEN_BLOCK, true>,
+  e = hipFuncSetAttribute((const void *)k_generations<true>,
                           hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BUDGET);
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void *)k_init<GEN_BLOCK>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BUDGET);
+  return hipFuncSetAttribute((const void *)k_init, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             LDS_BUDGET);
 }
 
 hipError_t launch_init(const LaunchArgs &a, double lb, double ub) {
-  hipLaunchKernelGGL(k_init<GEN_BLOCK>, dim3(a.n_runs), dim3(GEN_BLOCK), a.lds_bytes, a.stream,
+  hipLaunchKernelGGL(k_init, dim3(a.n_runs), dim3(INIT_THREADS), a.init_lds_bytes, a.stream,
                      a.runs, a.probs, a.tab, a.pop, a.fit, a.k0, a.k1, lb, ub);
   return hipGetLastError();
 }
@@ -705,13 +758,13 @@ hipError_t launch_init(const LaunchArgs &a, double lb, double ub) {
 hipError_t launch_generations(const LaunchArgs &a, uint32_t g0, uint32_t n_gens, float lb,
                               float ub, TraceArgs tr) {
   if (tr.u)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_generations<GEN_BLOCK, true>), dim3(a.n_runs),
-                       dim3(GEN_BLOCK), a.lds_bytes, a.stream, a.runs, a.probs, a.tab, a.pop,
-                       a.fit, g0, n_gens, a.k0, a.k1, lb, ub, a.pending, tr);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_generations<true>), dim3(a.n_runs), dim3(GEN_THREADS),
+                       a.lds_bytes, a.stream, a.runs, a.probs, a.tab, a.pop, a.fit, g0, n_gens,
+                       a.k0, a.k1, lb, ub, a.pending, tr);
   else
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_generations<GEN_BLOCK, false>), dim3(a.n_runs),
-                       dim3(GEN_BLOCK), a.lds_bytes, a.stream, a.runs, a.probs, a.tab, a.pop,
-                       a.fit, g0, n_gens, a.k0, a.k1, lb, ub, a.pending, tr);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_generations<false>), dim3(a.n_runs), dim3(GEN_THREADS),
+                       a.lds_bytes, a.stream, a.runs, a.probs, a.tab, a.pop, a.fit, g0, n_gens,
+                       a.k0, a.k1, lb, ub, a.pending, tr);
   return hipGetLastError();
 }
 
