@@ -134,12 +134,81 @@ def cpu_baseline(wl, budget_s=12.0):
                       f"theta from the first evolver trial, {dt:.1f} s on one host core"}
 
 
+MFMA_F64_PEAK = 78.6e12
+MFMA_BF16_PEAK = 2.5e15
+
+
+def bench_batch(args):
+    """Independent executor runs (no evolver): one step = initialisation and
+    first evaluation of every run, then all generations in one launch, then
+    the float64 best record."""
+    import torch
+    import workloads as W
+    from paper_2502_10470_amd import Batch, metade as M
+
+    wl = W.workload_c4() if args.workload == "c4" else W.workload_c2()
+    prec = M.BF16_REFINE if args.precision == "bf16" else M.FP32
+    b = Batch(wl, precision=prec)
+    evals = wl.evals_per_pass()
+
+    def step():
+        b.reset()
+        b.inner_step(wl.G)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t_before, r_before = b.counters()
+    b.kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    k_ms, k_launches = b.kernel_time()
+    b.kernel_timing(False)
+    t_after, r_after = b.counters()
+    dt = t1 - t0
+    avg_ms = k_ms / max(k_launches, 1)
+    F, CR, bl, br, dn, cs = decode(wl.theta, wl.n_cs)
+    slots = sum(int(wl.N[r]) * wl.G * alg_slots_per_trial(int(wl.N[r]), wl.D_of(r),
+                wl.problems[int(wl.problem[r])].kind, bl[r], br[r], dn[r], cs[r], CR[r])
+                for r in range(wl.n_runs))
+    rot_flops = sum(2.0 * int(wl.N[r]) * wl.D_of(r) ** 2 * wl.G for r in range(wl.n_runs))
+    refine_rate = (r_after - r_before) / max(t_after - t_before, 1)
+    line = {
+        "metric": f"inner-DE individual-evals/sec (runs x N x gens / s) at "
+                  f"{'D=100' if args.workload == 'c4' else 'D in {10,20}'}",
+        "value": evals * args.steps / dt, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1000.0 * dt / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16+f64" if prec == M.BF16_REFINE else "f32", "data": "synthetic",
+        "config": {"workload": wl.name, "runs": wl.n_runs, "gens": wl.G,
+                   "evals_per_step": evals, "precision": args.precision,
+                   "refine_rate": refine_rate if prec == M.BF16_REFINE else None},
+        "roofline": {"bound": "alu", "achieved": slots / (avg_ms * 1e-3) / 1e12,
+                     "peak": VALU_PEAK_SLOTS / 1e12, "unit": "Tslot/s",
+                     "frac": slots / (avg_ms * 1e-3) / VALU_PEAK_SLOTS, "traffic": None,
+                     "kernel": "k_generations_mfma" if args.workload == "c4" else "k_generations",
+                     "avg_launch_ms": avg_ms, "launches": k_launches,
+                     "rotation_tflops": rot_flops / (avg_ms * 1e-3) / 1e12,
+                     "occupied_cu_frac": min(wl.n_runs, 256) / 256.0},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c3", choices=["c3"])
+    ap.add_argument("--workload", default="c3", choices=["c3", "c4", "c2"],
+                    help="c3: full MetaDE at D=20 (default); c4: 128 runs x N=256 at D=100, "
+                         "500 generations; c2: uneven batch of 256 runs, 200 generations")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"],
+                    help="fitness contraction: plain (float64-accumulated) or bf16 matrix cores "
+                         "with plain re-evaluation of near ties")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
@@ -163,6 +232,8 @@ def main():
     import workloads as W
     from paper_2502_10470_amd import Batch
 
+    if args.workload != "c3":
+        return bench_batch(args)
     wl = W.workload_c3()
     P, gens, G, pu = wl.outer["P"], wl.outer["gens"], wl.G, wl.outer["power_up"]
     b = Batch(wl)

@@ -41,7 +41,10 @@ struct metade_ctx {
   float *theta_d = nullptr;
   float *pend_d = nullptr;
   size_t pop_floats = 0, fit_n = 0, bx_n = 0, pend_floats = 0;
-  uint32_t lds_bytes = 0, init_lds_bytes = 0;
+  uint32_t lds_bytes = 0, init_lds_bytes = 0, mfma_lds_bytes = 0;
+  uint32_t n_lane = 0, n_mfma = 0;
+  uint32_t *lane_list_d = nullptr, *mfma_list_d = nullptr;
+  unsigned long long *counters_d = nullptr;
   uint32_t gen = 0;
   // evolver
   float *Xo = nullptr, *Uo = nullptr, *bxo = nullptr;
@@ -77,7 +80,8 @@ struct Plan {
   std::vector<RunDev> runs;
   std::vector<ProbDev> probs;
   size_t tab_bytes = 0;
-  uint32_t init_lds_bytes = 0;
+  uint32_t init_lds_bytes = 0, mfma_lds_bytes = 0;
+  std::vector<uint32_t> lane_list, mfma_list;
   size_t pop_floats = 0, fit_n = 0, bx_n = 0, pend_floats = 0;
   uint32_t lds_bytes = 0;
 };
@@ -91,8 +95,8 @@ metade_status plan_config(const metade_config *cfg, Plan &pl, std::string &msg) 
     msg = "search box must satisfy lb < ub and |lb|, |ub| <= 1e30"; return METADE_EINVAL;
   }
   if (cfg->n_cs != 2 && cfg->n_cs != 3) { msg = "n_cs must be 2 or 3"; return METADE_EINVAL; }
-  if (cfg->precision != METADE_FP32) {
-    msg = "precision: only METADE_FP32 is available in this build"; return METADE_EINVAL;
+  if (cfg->precision != METADE_FP32 && cfg->precision != METADE_BF16_REFINE) {
+    msg = "precision must be METADE_FP32 or METADE_BF16_REFINE"; return METADE_EINVAL;
   }
   pl.probs.resize(cfg->n_problems);
   const double zs = mde::SCHWEFEL_ZSTAR;
@@ -156,19 +160,32 @@ metade_status plan_config(const metade_config *cfg, Plan &pl, std::string &msg) 
     // lanes per part: whole waves covering N; parts: as many as fit the block
     d.Np = ((N + 63u) / 64u) * 64u;
     d.L = std::max<uint32_t>(1, std::min<uint32_t>(8, mde::GEN_CONSUMERS / d.Np));
-    d.t_lds = mde::lds_layout(N, d.Dp, d.L, d.Np, true).total <= mde::LDS_BUDGET ? 1u : 0u;
-    const uint32_t bytes = mde::lds_layout(N, d.Dp, d.L, d.Np, d.t_lds != 0).total;
-    if (bytes > mde::LDS_BUDGET) {
-      msg = "run " + std::to_string(r) + ": population does not fit in LDS"; return METADE_EINVAL;
+    d.Dk = ((D + 31u) / 32u) * 32u;
+    d.NCT = (D + 15u) / 16u;
+    const bool rosen = pl.probs[d.prob].kind == mde::FN_ROSENBROCK;
+    const uint32_t lane_bytes = mde::lds_layout(N, d.Dp, d.L, d.Np, true).total;
+    const uint32_t mf_bytes = mde::mfma_layout(N, d.Dp, d.Dk, d.L, d.Np, d.NCT, rosen).total;
+    if (cfg->precision == METADE_FP32 && lane_bytes <= mde::LDS_BUDGET) {
+      d.kern = 0;
+      d.t_lds = 1;
+      pl.lds_bytes = std::max(pl.lds_bytes, lane_bytes);
+      pl.lane_list.push_back(r);
+    } else if (mf_bytes <= mde::LDS_BUDGET) {
+      d.kern = 1;
+      d.t_lds = 0;
+      pl.mfma_lds_bytes = std::max(pl.mfma_lds_bytes, mf_bytes);
+      pl.mfma_list.push_back(r);
+    } else {
+      msg = "run " + std::to_string(r) + ": population does not fit in LDS (N*D too large)";
+      return METADE_EINVAL;
     }
-    pl.lds_bytes = std::max(pl.lds_bytes, bytes);
     pl.init_lds_bytes = std::max(pl.init_lds_bytes, mde::init_lds_bytes(N, d.Dp, d.Np));
     d.pop_off = pl.pop_floats;
     d.pend_off = pl.pend_floats;
     d.fit_off = (uint32_t)pl.fit_n;
     d.bx_off = (uint32_t)pl.bx_n;
+    if (d.kern == 1) pl.pend_floats += (size_t)N * d.Dk;
     pl.pop_floats += (size_t)N * D;
-    if (!d.t_lds) pl.pend_floats += (size_t)N * D;
     pl.fit_n += N;
     pl.bx_n += D;
     d.F = 0.5f;
@@ -191,6 +208,7 @@ LaunchArgs largs(metade_ctx *c) {
   a.n_runs = c->n_runs;
   a.lds_bytes = c->lds_bytes;
   a.init_lds_bytes = c->init_lds_bytes;
+  a.mfma_lds_bytes = c->mfma_lds_bytes;
   a.k0 = (uint32_t)(c->seed & 0xFFFFFFFFu);
   a.k1 = (uint32_t)(c->seed >> 32);
   a.stream = c->stream;
@@ -205,7 +223,10 @@ metade_status run_generations(metade_ctx *c, uint32_t n, mde::TraceArgs tr) {
     HIP_TRY(c, hipEventCreate(&ev.b));
     HIP_TRY(c, hipEventRecord(ev.a, c->stream));
   }
-  HIP_TRY(c, mde::launch_generations(largs(c), c->gen, n, c->lb, c->ub, tr));
+  HIP_TRY(c, mde::launch_generations(largs(c), c->lane_list_d, c->n_lane, c->gen, n, c->lb, c->ub, tr));
+  HIP_TRY(c, mde::launch_generations_mfma(largs(c), c->mfma_list_d, c->n_mfma,
+                                          c->precision == METADE_BF16_REFINE, c->gen, n, c->lb,
+                                          c->ub, c->counters_d, tr));
   if (c->timing) {
     HIP_TRY(c, hipEventRecord(ev.b, c->stream));
     c->events.push_back(ev);
@@ -292,6 +313,9 @@ metade_status metade_init(const metade_config *cfg, metade_ctx **out) {
   c->pend_floats = pl.pend_floats;
   c->lds_bytes = pl.lds_bytes;
   c->init_lds_bytes = pl.init_lds_bytes;
+  c->mfma_lds_bytes = pl.mfma_lds_bytes;
+  c->n_lane = (uint32_t)pl.lane_list.size();
+  c->n_mfma = (uint32_t)pl.mfma_list.size();
   auto bail = [&](metade_status st) {
     g_init_error = c->err;
     metade_destroy(c);
@@ -324,6 +348,17 @@ metade_status metade_init(const metade_config *cfg, metade_ctx **out) {
   if ((st = dalloc(c, &c->yt, c->n_runs)) != METADE_OK) return bail(st);
   if ((st = dalloc(c, &c->bxo, c->bx_n)) != METADE_OK) return bail(st);
   if ((st = dalloc(c, &c->bidx, 4)) != METADE_OK) return bail(st);
+  if ((st = dalloc(c, &c->counters_d, 1)) != METADE_OK) return bail(st);
+  if ((st = dalloc(c, &c->lane_list_d, pl.lane_list.size())) != METADE_OK) return bail(st);
+  if ((st = dalloc(c, &c->mfma_list_d, pl.mfma_list.size())) != METADE_OK) return bail(st);
+  {
+    hipError_t e5 = hipMemset(c->counters_d, 0, sizeof(unsigned long long));
+    if (e5 == hipSuccess && !pl.lane_list.empty())
+      e5 = hipMemcpy(c->lane_list_d, pl.lane_list.data(), pl.lane_list.size() * 4, hipMemcpyHostToDevice);
+    if (e5 == hipSuccess && !pl.mfma_list.empty())
+      e5 = hipMemcpy(c->mfma_list_d, pl.mfma_list.data(), pl.mfma_list.size() * 4, hipMemcpyHostToDevice);
+    if (e5 != hipSuccess) { c->err = std::string("run lists: ") + hipGetErrorString(e5); return bail(METADE_EDEVICE); }
+  }
   for (size_t k = 0; k < c->probs_h.size(); ++k) {
     // per-output element tables: elliptic weights cond^(idx/(n-1)) and, for
     // the hybrid, the block each rotated output falls in after permutation
@@ -415,6 +450,8 @@ metade_status metade_trace_sizes(metade_ctx *c, size_t *u_bytes, size_t *fu_byte
 
 metade_status metade_inner_step_trace(metade_ctx *c, float *u, float *fu, int32_t *desc) {
   if (!c || !u || !fu || !desc) return fail(c, METADE_EINVAL, "ctx and all trace buffers are required");
+  if (c->precision != METADE_FP32)
+    return fail(c, METADE_EINVAL, "tracing is available for METADE_FP32 contexts only");
   TRY(run_generations(c, 1, mde::TraceArgs{u, fu, desc}));
   return finalize(c);
 }
@@ -612,7 +649,11 @@ metade_status metade_get_counters(metade_ctx *c, uint64_t *trials, uint64_t *ref
   if (!c) return fail(nullptr, METADE_EINVAL, "ctx is NULL");
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   if (trials) *trials = c->trials;
-  if (refined) *refined = c->refined;
+  if (refined) {
+    unsigned long long r = 0;
+    HIP_TRY(c, hipMemcpy(&r, c->counters_d, sizeof(r), hipMemcpyDeviceToHost));
+    *refined = r;
+  }
   return METADE_OK;
 }
 
@@ -639,6 +680,9 @@ void metade_destroy(metade_ctx *c) {
   (void)hipFree(c->bxo);
   (void)hipFree(c->bidx);
   (void)hipFree(c->tab);
+  (void)hipFree(c->counters_d);
+  (void)hipFree(c->lane_list_d);
+  (void)hipFree(c->mfma_list_d);
   delete c;
 }
 

@@ -40,9 +40,10 @@ struct RunDev {
   uint32_t N, D, Dp, prob;      // Dp = D rounded up to a multiple of 4
   uint32_t stream, kp;          // kp = top-p count
   uint32_t L, Np;               // lanes per trial (parts) and lanes per part (multiple of 64)
-  uint32_t t_lds, pad0;         // trial rows in LDS (1) or in the global trial buffer (0)
+  uint32_t t_lds, kern;         // trial rows in LDS (1) or global (0); kernel: 0 lanes, 1 matrix cores
+  uint32_t Dk, NCT;             // matrix-core kernel: D rounded up to 32; 16-wide output tiles
   uint64_t pop_off;             // float offset of the run in pop (N*D packing)
-  uint64_t pend_off;            // float offset in the global trial buffer (D*N packing)
+  uint64_t pend_off;            // float offset in the global trial buffer
   uint32_t fit_off, bx_off;     // offsets in fit / best_x
   float F, CR;
   int32_t bl, br, dn, cs;
@@ -162,6 +163,41 @@ __host__ __device__ inline Lds lds_layout(uint32_t N, uint32_t Dp, uint32_t L, u
   l.msk = o;  o += al16(N * (Dp / 4));
   l.dsc = o;  o += al16(N * 16);
   l.T = o;    o += t_lds ? al16(Dp * Np * 4) : 0u;
+  l.total = o;
+  return l;
+}
+
+// Matrix-core generation kernel (runs whose trial rows do not fit in LDS, and
+// the bf16 precision mode; 512 consumer + 256 producer lanes): trial rows live in a global buffer [N][Dk]
+// (Dk = D rounded up to 32, zero padding); LDS holds the population, ranking
+// state, the producers' mask nibbles and packed draws, per (output tile,
+// trial) partial sums and bounds, Rosenbrock boundary values, the shift, the
+// candidate list of the bf16 mode and per-wave counts.
+constexpr uint32_t MF_THREADS = 768;
+constexpr uint32_t MF_CONSUMERS = 512;
+
+struct MLds {
+  uint32_t pop, key, fit, topk, rk, msk, dsc, ps, pb, zf, zl, oc, cl, cnt, total;
+};
+
+__host__ __device__ inline MLds mfma_layout(uint32_t N, uint32_t Dp, uint32_t Dk, uint32_t L,
+                                            uint32_t Np, uint32_t NCT, bool rosen) {
+  MLds l;
+  uint32_t o = 0;
+  l.pop = o;  o += al16(N * Dp * 4);
+  l.key = o;  o += al16(N * 8);
+  l.fit = o;  o += al16(N * 4);
+  l.topk = o; o += al16(MAX_KP * 4);
+  l.rk = o;   o += al16(L * Np * 4);
+  l.msk = o;  o += al16(N * (Dp / 4));
+  l.dsc = o;  o += al16(N * 16);
+  l.ps = o;   o += al16(NCT * N * 8);
+  l.pb = o;   o += al16(NCT * N * 4);
+  l.zf = o;   o += rosen ? al16(NCT * N * 4) : 0u;
+  l.zl = o;   o += rosen ? al16(NCT * N * 4) : 0u;
+  l.oc = o;   o += al16(Dk * 4);
+  l.cl = o;   o += al16(N * 4);
+  l.cnt = o;  o += al16(16 * 4);
   l.total = o;
   return l;
 }

@@ -24,6 +24,7 @@ struct LaunchArgs {
   uint32_t n_runs;
   uint32_t lds_bytes;
   uint32_t init_lds_bytes;
+  uint32_t mfma_lds_bytes;
   uint32_t k0, k1;
   hipStream_t stream;
 };
@@ -31,8 +32,12 @@ struct LaunchArgs {
 hipError_t set_lds_limits();
 hipError_t launch_rot_t64(const float *R, double *Rt, uint32_t D, hipStream_t s);
 hipError_t launch_init(const LaunchArgs &a, double lb, double ub);
-hipError_t launch_generations(const LaunchArgs &a, uint32_t g0, uint32_t n_gens, float lb,
-                              float ub, TraceArgs tr);
+hipError_t launch_generations(const LaunchArgs &a, const uint32_t *list, uint32_t n,
+                              uint32_t g0, uint32_t n_gens, float lb, float ub, TraceArgs tr);
+hipError_t set_lds_limits_mfma();
+hipError_t launch_generations_mfma(const LaunchArgs &a, const uint32_t *list, uint32_t n,
+                                   bool bf16, uint32_t g0, uint32_t n_gens, float lb, float ub,
+                                   unsigned long long *counters, TraceArgs tr);
 hipError_t launch_finalize(const LaunchArgs &a, double *best_y, float *best_x);
 hipError_t launch_decode(RunDev *runs, float *theta, uint32_t n, uint32_t n_cs, hipStream_t s);
 hipError_t launch_outer_init(float *X, double *y, uint32_t P, uint32_t stream, uint32_t k0,

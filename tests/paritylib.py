@@ -155,3 +155,32 @@ def trajectory_parity(batch, wl, G, stats=None, check_desc=True):
             out["compared"] += 1
     out["runs"] = runs
     return out
+
+
+def state_parity(batch, wl, G):
+    """Compare the populations after each of G generations (one launch each)
+    with the oracle's trajectory, without tracing: for paths that do not
+    trace (the bf16 mode).  Runs stop being compared at an oracle near-tie."""
+    runs = [OracleRun(wl, r) for r in range(wl.n_runs)]
+    pop, fit = batch.host_state()
+    out = {"compared": 0, "diverged": 0, "max_fit_rel": 0.0}
+    for o in runs:
+        assert np.array_equal(batch.run_pop(pop, o.r), o.pop), f"run {o.r}: initial population"
+    for g in range(G):
+        batch.inner_step(1)
+        pop, fit = batch.host_state()
+        for o in runs:
+            if o.diverged:
+                continue
+            s = o.step()
+            if s["amb_rank"] or np.any(s["amb_sel"]):
+                o.diverged = True
+                out["diverged"] += 1
+                continue
+            r = o.r
+            assert np.array_equal(batch.run_pop(pop, r), o.pop), f"run {r} g={g} theta={o.th}: population differs"
+            e = rel_err(batch.run_fit(fit, r), evaluate(o.pop, o.prob))
+            assert e.max() <= FIT_RTOL, f"run {r} g={g}: fitness error {e.max():.3g}"
+            out["max_fit_rel"] = max(out["max_fit_rel"], float(e.max()))
+            out["compared"] += 1
+    return out
