@@ -88,23 +88,28 @@ def unflatten_policy(w, n_in, hidden, n_out):
     return layers
 
 
-def lqr_mlp(w, prob):
+def lqr_mlp(w, prob, dtype=np.float64):
     """Mean over rollouts of J = sum_t x_t^T Q x_t + c ||u_t||^2 with Q = I,
-    u_t = tanh-MLP(x_t), x_{t+1} = A x_t + B u_t, for t = 0 .. steps-1."""
-    w = np.asarray(w, dtype=np.float32).astype(np.float64)
+    u_t = tanh-MLP(x_t), x_{t+1} = A x_t + B u_t, for t = 0 .. steps-1.
+
+    ``dtype`` is the working precision (float64, or numpy's extended
+    longdouble to estimate how well float64 determines J: the closed loop of
+    a policy can amplify rounding differences by many orders of magnitude)."""
+    w = np.asarray(w, dtype=np.float32).astype(dtype)
     lead = w.shape[:-1]
-    A = prob.A.astype(np.float64)
-    B = prob.B.astype(np.float64)
-    x0 = prob.x0.astype(np.float64)                     # [E, obs]
+    A = prob.A.astype(dtype)
+    B = prob.B.astype(dtype)
+    x0 = prob.x0.astype(dtype)                          # [E, obs]
+    cw = dtype(prob.ctrl_weight)
     layers = unflatten_policy(w, A.shape[0], prob.hidden, B.shape[1])
     x = np.broadcast_to(x0, (*lead, *x0.shape)).copy()  # [..., E, obs]
-    J = np.zeros((*lead, x0.shape[0]))
+    J = np.zeros((*lead, x0.shape[0]), dtype=dtype)
     for _ in range(prob.steps):
         h = x
         for W, b in layers:
             h = np.tanh(np.einsum("...oi,...ei->...eo", W, h) + b[..., None, :])
-        J += np.sum(x * x, axis=-1) + prob.ctrl_weight * np.sum(h * h, axis=-1)
-        x = x @ A.T + h @ B.T
+        J += np.sum(x * x, axis=-1) + cw * np.sum(h * h, axis=-1)
+        x = np.einsum("ji,...ei->...ej", A, x) + np.einsum("ja,...ea->...ej", B, h)
     return J.mean(axis=-1)
 
 

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmetade.so")
-SOURCES = ["kernels.hip", "kernels_mfma.hip", "api.hip"]
+SOURCES = ["kernels.hip", "kernels_mfma.hip", "kernels_ctrl.hip", "api.hip"]
 ARCH = os.environ.get("METADE_OFFLOAD_ARCH", "gfx950")
 
 HIP_FLAGS = [

@@ -42,8 +42,10 @@ struct metade_ctx {
   float *pend_d = nullptr;
   size_t pop_floats = 0, fit_n = 0, bx_n = 0, pend_floats = 0;
   uint32_t lds_bytes = 0, init_lds_bytes = 0, mfma_lds_bytes = 0;
-  uint32_t n_lane = 0, n_mfma = 0;
-  uint32_t *lane_list_d = nullptr, *mfma_list_d = nullptr;
+  uint32_t n_lane = 0, n_mfma = 0, n_ctrl = 0, ctrl_max_n = 0;
+  uint32_t *lane_list_d = nullptr, *mfma_list_d = nullptr, *ctrl_list_d = nullptr;
+  uint32_t *order_d = nullptr, *cacc_d = nullptr;  // control runs: top-p lists, decisions
+  float *cfu_d = nullptr;                          // control runs: trial fitness
   unsigned long long *counters_d = nullptr;
   uint32_t gen = 0;
   // evolver
@@ -81,7 +83,8 @@ struct Plan {
   std::vector<ProbDev> probs;
   size_t tab_bytes = 0;
   uint32_t init_lds_bytes = 0, mfma_lds_bytes = 0;
-  std::vector<uint32_t> lane_list, mfma_list;
+  std::vector<uint32_t> lane_list, mfma_list, ctrl_list;
+  uint32_t ctrl_max_n = 0;
   size_t pop_floats = 0, fit_n = 0, bx_n = 0, pend_floats = 0;
   uint32_t lds_bytes = 0;
 };
@@ -111,9 +114,43 @@ metade_status plan_config(const metade_config *cfg, Plan &pl, std::string &msg) 
     p.cs_d = cs;
     p.cs_f = (float)cs;
     const double cond = q.cond > 0 ? (double)q.cond : 1e6;
-    if (q.kind < METADE_FN_RASTRIGIN || q.kind > METADE_FN_HYBRID) {
+    if (q.kind < METADE_FN_RASTRIGIN || q.kind > METADE_FN_LQR_MLP) {
       msg = "problem " + std::to_string(k) + ": unsupported kind " + std::to_string(q.kind);
       return METADE_EINVAL;
+    }
+    auto take = [&](size_t bytes) {
+      const uint64_t off = pl.tab_bytes;
+      pl.tab_bytes += (bytes + 255) & ~(size_t)255;
+      return off;
+    };
+    if (q.kind == METADE_FN_LQR_MLP) {
+      const std::string pk = "problem " + std::to_string(k) + ": ";
+      if (q.hidden1 != (uint32_t)mde::CT_H || q.hidden2 != (uint32_t)mde::CT_H) {
+        msg = pk + "control policy hidden layers must have 64 units"; return METADE_EINVAL;
+      }
+      if (q.obs < 1 || q.obs > (uint32_t)mde::CT_MAX_OBS || q.act < 1 || q.act > (uint32_t)mde::CT_MAX_ACT) {
+        msg = pk + "control workload needs 1 <= obs <= 24 and 1 <= act <= 8"; return METADE_EINVAL;
+      }
+      if (q.steps < 1 || q.n_rollouts < 1) { msg = pk + "steps and n_rollouts must be >= 1"; return METADE_EINVAL; }
+      if (!q.A || !q.B || !q.x0) { msg = pk + "A, B and x0 are required"; return METADE_EINVAL; }
+      if (!std::isfinite(q.ctrl_weight)) { msg = pk + "ctrl_weight must be finite"; return METADE_EINVAL; }
+      const uint64_t Dm = (uint64_t)mde::CT_H * q.obs + mde::CT_H + (uint64_t)mde::CT_H * mde::CT_H +
+                          mde::CT_H + (uint64_t)mde::CT_H * q.act + q.act;
+      if (q.D != Dm) {
+        msg = pk + "D must equal the policy's weight count " + std::to_string(Dm); return METADE_EINVAL;
+      }
+      p.obs = q.obs;
+      p.act = q.act;
+      p.h1 = q.hidden1;
+      p.h2 = q.hidden2;
+      p.steps = q.steps;
+      p.nroll = q.n_rollouts;
+      p.cw = q.ctrl_weight;
+      p.A_off = take((size_t)q.obs * q.obs * sizeof(float));
+      p.B_off = take((size_t)q.obs * q.act * sizeof(float));
+      p.x0_off = take((size_t)q.n_rollouts * q.obs * sizeof(float));
+      pl.probs[k] = p;
+      continue;
     }
     if (q.D == 0 || q.D > (uint32_t)mde::MAX_D) {
       msg = "problem " + std::to_string(k) + ": D must be in 1..128"; return METADE_EINVAL;
@@ -126,11 +163,6 @@ metade_status plan_config(const metade_config *cfg, Plan &pl, std::string &msg) 
     }
     (void)cond;
     // read-only table layout of this problem
-    auto take = [&](size_t bytes) {
-      const uint64_t off = pl.tab_bytes;
-      pl.tab_bytes += (bytes + 255) & ~(size_t)255;
-      return off;
-    };
     p.o_off = take((size_t)q.D * sizeof(float));
     p.r64t_off = take((size_t)q.D * mde::rt_stride(q.D) * sizeof(double));
     p.ew_off = take((size_t)q.D * sizeof(float));
@@ -147,6 +179,35 @@ metade_status plan_config(const metade_config *cfg, Plan &pl, std::string &msg) 
       msg = "run " + std::to_string(r) + ": problem index out of range"; return METADE_EINVAL;
     }
     const uint32_t D = pl.probs[cfg->problem[r]].D;
+    if (pl.probs[cfg->problem[r]].kind == mde::FN_LQR_MLP) {
+      if (N < 10 || N > (uint32_t)mde::CT_MAX_N) {
+        msg = "run " + std::to_string(r) + ": N must be in 10..1024 for the control workload";
+        return METADE_EINVAL;
+      }
+      d.N = N;
+      d.D = D;
+      d.Dp = round4(D);
+      d.prob = cfg->problem[r];
+      d.stream = cfg->stream_id[r];
+      d.kp = std::max<uint32_t>(1, (N * 10 + 99) / 100);
+      d.kern = 2;
+      d.pop_off = pl.pop_floats;
+      d.pend_off = pl.pend_floats;
+      d.fit_off = (uint32_t)pl.fit_n;
+      d.bx_off = (uint32_t)pl.bx_n;
+      pl.pend_floats += (size_t)N * D;
+      pl.pop_floats += (size_t)N * D;
+      pl.fit_n += N;
+      pl.bx_n += D;
+      pl.ctrl_list.push_back(r);
+      pl.ctrl_max_n = std::max(pl.ctrl_max_n, N);
+      d.F = 0.5f;
+      d.CR = 0.9f;
+      d.bl = d.br = mde::RAND;
+      d.dn = 1;
+      d.cs = mde::BIN;
+      continue;
+    }
     if (N < 10 || N > (uint32_t)mde::MAX_N) {
       msg = "run " + std::to_string(r) + ": N must be in 10..256 (9 distinct draws plus the target)";
       return METADE_EINVAL;
@@ -215,6 +276,10 @@ LaunchArgs largs(metade_ctx *c) {
   return a;
 }
 
+mde::CtrlArgs cargs(metade_ctx *c) {
+  return mde::CtrlArgs{c->ctrl_list_d, c->n_ctrl, c->ctrl_max_n, c->order_d, c->cfu_d, c->cacc_d};
+}
+
 metade_status run_generations(metade_ctx *c, uint32_t n, mde::TraceArgs tr) {
   if (n == 0) return METADE_OK;
   EventPair ev{nullptr, nullptr};
@@ -227,6 +292,7 @@ metade_status run_generations(metade_ctx *c, uint32_t n, mde::TraceArgs tr) {
   HIP_TRY(c, mde::launch_generations_mfma(largs(c), c->mfma_list_d, c->n_mfma,
                                           c->precision == METADE_BF16_REFINE, c->gen, n, c->lb,
                                           c->ub, c->counters_d, tr));
+  HIP_TRY(c, mde::launch_ctrl_generations(largs(c), cargs(c), c->gen, n, c->lb, c->ub, tr));
   if (c->timing) {
     HIP_TRY(c, hipEventRecord(ev.b, c->stream));
     c->events.push_back(ev);
@@ -238,12 +304,14 @@ metade_status run_generations(metade_ctx *c, uint32_t n, mde::TraceArgs tr) {
 
 metade_status reinit(metade_ctx *c) {
   HIP_TRY(c, mde::launch_init(largs(c), (double)c->lb, (double)c->ub));
+  HIP_TRY(c, mde::launch_ctrl_init(largs(c), cargs(c), (double)c->lb, (double)c->ub));
   c->gen = 0;
   return METADE_OK;
 }
 
 metade_status finalize(metade_ctx *c) {
   HIP_TRY(c, mde::launch_finalize(largs(c), c->best_y, c->best_x));
+  HIP_TRY(c, mde::launch_ctrl_finalize(largs(c), cargs(c), c->best_y, c->best_x));
   return METADE_OK;
 }
 
@@ -281,6 +349,8 @@ metade_status metade_query_sizes(const metade_config *cfg, size_t *pop_bytes, si
                      pl.pend_floats * sizeof(float) + (size_t)cfg->n_runs * (6 * 4 * 2 + 16) +
                      pl.bx_n * sizeof(float) + 16;
   if (scratch_bytes) *scratch_bytes += pl.tab_bytes;
+  if (scratch_bytes && !pl.ctrl_list.empty())
+    *scratch_bytes += pl.fit_n * 12 + pl.ctrl_list.size() * 4;
   return METADE_OK;
 }
 
@@ -316,6 +386,8 @@ metade_status metade_init(const metade_config *cfg, metade_ctx **out) {
   c->mfma_lds_bytes = pl.mfma_lds_bytes;
   c->n_lane = (uint32_t)pl.lane_list.size();
   c->n_mfma = (uint32_t)pl.mfma_list.size();
+  c->n_ctrl = (uint32_t)pl.ctrl_list.size();
+  c->ctrl_max_n = pl.ctrl_max_n;
   auto bail = [&](metade_status st) {
     g_init_error = c->err;
     metade_destroy(c);
@@ -351,12 +423,20 @@ metade_status metade_init(const metade_config *cfg, metade_ctx **out) {
   if ((st = dalloc(c, &c->counters_d, 1)) != METADE_OK) return bail(st);
   if ((st = dalloc(c, &c->lane_list_d, pl.lane_list.size())) != METADE_OK) return bail(st);
   if ((st = dalloc(c, &c->mfma_list_d, pl.mfma_list.size())) != METADE_OK) return bail(st);
+  if ((st = dalloc(c, &c->ctrl_list_d, pl.ctrl_list.size())) != METADE_OK) return bail(st);
+  if (c->n_ctrl) {
+    if ((st = dalloc(c, &c->order_d, c->fit_n)) != METADE_OK) return bail(st);
+    if ((st = dalloc(c, &c->cfu_d, c->fit_n)) != METADE_OK) return bail(st);
+    if ((st = dalloc(c, &c->cacc_d, c->fit_n)) != METADE_OK) return bail(st);
+  }
   {
     hipError_t e5 = hipMemset(c->counters_d, 0, sizeof(unsigned long long));
     if (e5 == hipSuccess && !pl.lane_list.empty())
       e5 = hipMemcpy(c->lane_list_d, pl.lane_list.data(), pl.lane_list.size() * 4, hipMemcpyHostToDevice);
     if (e5 == hipSuccess && !pl.mfma_list.empty())
       e5 = hipMemcpy(c->mfma_list_d, pl.mfma_list.data(), pl.mfma_list.size() * 4, hipMemcpyHostToDevice);
+    if (e5 == hipSuccess && !pl.ctrl_list.empty())
+      e5 = hipMemcpy(c->ctrl_list_d, pl.ctrl_list.data(), pl.ctrl_list.size() * 4, hipMemcpyHostToDevice);
     if (e5 != hipSuccess) { c->err = std::string("run lists: ") + hipGetErrorString(e5); return bail(METADE_EDEVICE); }
   }
   for (size_t k = 0; k < c->probs_h.size(); ++k) {
@@ -364,6 +444,15 @@ metade_status metade_init(const metade_config *cfg, metade_ctx **out) {
     // the hybrid, the block each rotated output falls in after permutation
     const ProbDev &p = c->probs_h[k];
     const metade_problem &q = cfg->problems[k];
+    if (p.kind == mde::FN_LQR_MLP) {
+      // plant and initial states, copied so that the context does not depend on them
+      unsigned char *t = c->tab;
+      hipError_t e6 = hipMemcpy(t + p.A_off, q.A, (size_t)p.obs * p.obs * sizeof(float), hipMemcpyDeviceToDevice);
+      if (e6 == hipSuccess) e6 = hipMemcpy(t + p.B_off, q.B, (size_t)p.obs * p.act * sizeof(float), hipMemcpyDeviceToDevice);
+      if (e6 == hipSuccess) e6 = hipMemcpy(t + p.x0_off, q.x0, (size_t)p.nroll * p.obs * sizeof(float), hipMemcpyDeviceToDevice);
+      if (e6 != hipSuccess) { c->err = std::string("control tables: ") + hipGetErrorString(e6); return bail(METADE_EDEVICE); }
+      continue;
+    }
     const double cond = q.cond > 0 ? (double)q.cond : 1e6;
     std::vector<float> ew(p.D, 0.0f);
     std::vector<double> ew64(p.D, 0.0);
@@ -683,6 +772,10 @@ void metade_destroy(metade_ctx *c) {
   (void)hipFree(c->counters_d);
   (void)hipFree(c->lane_list_d);
   (void)hipFree(c->mfma_list_d);
+  (void)hipFree(c->ctrl_list_d);
+  (void)hipFree(c->order_d);
+  (void)hipFree(c->cfu_d);
+  (void)hipFree(c->cacc_d);
   delete c;
 }
 

@@ -31,6 +31,11 @@ constexpr int MAX_N = 256;     // LDS-resident kernel: indices fit in 8 bits
 constexpr int MAX_D = 128;
 constexpr int MAX_KP = 32;     // top-p set size for N <= 256 is at most 26
 constexpr uint32_t LDS_BUDGET = 160 * 1024;
+// control workload: one hidden unit per lane, bounded observation / action sizes
+constexpr int CT_H = 64;
+constexpr int CT_MAX_OBS = 24;
+constexpr int CT_MAX_ACT = 8;
+constexpr int CT_MAX_N = 1024;
 constexpr float SCHWEFEL_ZSTAR = 420.96875f;
 
 // ---------------------------------------------------------------- tables
@@ -40,7 +45,7 @@ struct RunDev {
   uint32_t N, D, Dp, prob;      // Dp = D rounded up to a multiple of 4
   uint32_t stream, kp;          // kp = top-p count
   uint32_t L, Np;               // lanes per trial (parts) and lanes per part (multiple of 64)
-  uint32_t t_lds, kern;         // trial rows in LDS (1) or global (0); kernel: 0 lanes, 1 matrix cores
+  uint32_t t_lds, kern;         // trial rows in LDS (1) or global (0); kernel: 0 lanes, 1 matrix cores, 2 control
   uint32_t Dk, NCT;             // matrix-core kernel: D rounded up to 32; 16-wide output tiles
   uint64_t pop_off;             // float offset of the run in pop (N*D packing)
   uint64_t pend_off;            // float offset in the global trial buffer
@@ -65,7 +70,7 @@ struct ProbDev {
   // control workload
   uint32_t obs, act, h1, h2, steps, nroll;
   float cw, pad0;
-  uint64_t A_off, B_off, x0_off;  // float [obs*obs], [obs*act], [nroll*obs]
+  uint64_t A_off, B_off, x0_off;  // float [obs*obs], [obs*act], [nroll*obs], row-major
 };
 
 // Row stride of the transposed float64 rotation: D plus zero padding for the

@@ -29,6 +29,15 @@ struct LaunchArgs {
   hipStream_t stream;
 };
 
+// Control runs (one wavefront per individual, several launches per generation).
+struct CtrlArgs {
+  const uint32_t *list;   // run ids
+  uint32_t n, max_n;      // number of control runs, their largest N
+  uint32_t *order;        // [sum N] top-p lists at the runs' fitness offsets
+  float *fu;              // [sum N] trial fitness
+  uint32_t *acc;          // [sum N] selection decisions
+};
+
 hipError_t set_lds_limits();
 hipError_t launch_rot_t64(const float *R, double *Rt, uint32_t D, hipStream_t s);
 hipError_t launch_init(const LaunchArgs &a, double lb, double ub);
@@ -38,6 +47,11 @@ hipError_t set_lds_limits_mfma();
 hipError_t launch_generations_mfma(const LaunchArgs &a, const uint32_t *list, uint32_t n,
                                    bool bf16, uint32_t g0, uint32_t n_gens, float lb, float ub,
                                    unsigned long long *counters, TraceArgs tr);
+hipError_t launch_ctrl_init(const LaunchArgs &a, const CtrlArgs &c, double lb, double ub);
+hipError_t launch_ctrl_generations(const LaunchArgs &a, const CtrlArgs &c, uint32_t g0,
+                                   uint32_t n_gens, float lb, float ub, TraceArgs tr);
+hipError_t launch_ctrl_finalize(const LaunchArgs &a, const CtrlArgs &c, double *best_y,
+                                float *best_x);
 hipError_t launch_finalize(const LaunchArgs &a, double *best_y, float *best_x);
 hipError_t launch_decode(RunDev *runs, float *theta, uint32_t n, uint32_t n_cs, hipStream_t s);
 hipError_t launch_outer_init(float *X, double *y, uint32_t P, uint32_t stream, uint32_t k0,

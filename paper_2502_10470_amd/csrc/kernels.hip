@@ -113,7 +113,7 @@ __device__ __forceinline__ void eval_part(const unsigned char *__restrict__ tab,
   s1 = ta.s1;
 }
 
-// ---------------------------------------------------------------- init (Alg. 2, lines 1-2)
+// ---------------------------------------------------------------- init (Alg. 2 initialisation)
 
 __global__ __launch_bounds__(INIT_THREADS) void k_init(const RunDev *__restrict__ runs,
                                                        const ProbDev *__restrict__ probs,
@@ -123,6 +123,7 @@ __global__ __launch_bounds__(INIT_THREADS) void k_init(const RunDev *__restrict_
                                                        uint32_t k1, double lb, double ub) {
   extern __shared__ __align__(16) unsigned char smem[];
   const RunDev run = runs[blockIdx.x];
+  if (run.kern == 2) return;  // control runs have their own initialisation kernel
   const ProbDev p = probs[run.prob];
   const uint32_t N = run.N, D = run.D, Dp = run.Dp, Q = Dp / 4;
   const uint32_t Np = ((N + 63u) / 64u) * 64u, L = init_parts(Np);
@@ -168,7 +169,7 @@ __global__ __launch_bounds__(INIT_THREADS) void k_init(const RunDev *__restrict_
   }
 }
 
-// ---------------------------------------------------------------- generations (Alg. 2, lines 6-12)
+// ---------------------------------------------------------------- generations (Alg. 2 main loop)
 //
 // Consumer lane i of part l works on trial i: it builds genes 4q..4q+3 with
 // q = l mod L and the fitness outputs [l D / L, (l+1) D / L); the parts'
@@ -367,6 +368,7 @@ __global__ __launch_bounds__(FIN_BLOCK) void k_finalize(const RunDev *__restrict
   __shared__ uint32_t sk[FIN_BLOCK], si[FIN_BLOCK];
   __shared__ double z[MAX_D], t0s[MAX_D], t1s[MAX_D];
   const RunDev run = runs[blockIdx.x];
+  if (run.kern == 2) return;  // control runs have their own record kernel
   const ProbDev p = probs[run.prob];
   const uint32_t N = run.N, D = run.D, tid = threadIdx.x;
   uint32_t bk = 0xFFFFFFFFu, bi = 0xFFFFFFFFu;

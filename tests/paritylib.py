@@ -16,10 +16,11 @@ from __future__ import annotations
 import numpy as np
 
 from oracle import pde
-from oracle.fitness import evaluate
+from oracle.fitness import evaluate, lqr_mlp
 
 FIT_RTOL = 1e-5           # float32 fitness vs float64 oracle, relative
 TIE_RTOL = 3e-5           # two values closer than this may be ordered either way
+ILL_RTOL = FIT_RTOL / 10  # float64 vs extended precision: beyond this float64 does not fix f
 
 
 def near(a, b, rtol=TIE_RTOL):
@@ -83,6 +84,21 @@ def rel_err(gpu, ref):
     return np.abs(gpu - ref) / np.maximum(np.abs(ref), 1e-300)
 
 
+def fitness_misses(fg, f64, u, prob):
+    """Trials whose float32 fitness misses the oracle's float64 value by more
+    than FIT_RTOL, split into (well-determined misses, count of trials whose
+    float64 value is itself undetermined).  Only the control workload can
+    have the latter: its closed loop may amplify rounding by many orders of
+    magnitude, which the oracle measures by re-running in extended precision."""
+    e = rel_err(fg, f64)
+    bad = np.flatnonzero(e > FIT_RTOL)
+    if bad.size == 0 or prob.kind != "lqr_mlp":
+        return bad, 0
+    fx = lqr_mlp(u[bad], prob, dtype=np.longdouble).astype(np.float64)
+    ill = rel_err(f64[bad], fx) > ILL_RTOL
+    return bad[~ill], int(ill.sum())
+
+
 def compare_desc(desc_gpu, s, th):
     """Bit-exact comparison of the per-target draws with the oracle's."""
     d = s["desc"]
@@ -107,13 +123,19 @@ def trajectory_parity(batch, wl, G, stats=None, check_desc=True):
     statistics: generations compared, first divergence, max fitness error."""
     runs = [OracleRun(wl, r) for r in range(wl.n_runs)]
     pop, fit = batch.host_state()
-    out = {"compared": 0, "diverged": 0, "max_fit_rel": 0.0, "trials": 0}
+    out = {"compared": 0, "diverged": 0, "max_fit_rel": 0.0, "trials": 0, "ill": 0}
     for o in runs:
         gp = batch.run_pop(pop, o.r)
         assert np.array_equal(gp, o.pop), f"run {o.r}: initial population differs"
-        e = rel_err(batch.run_fit(fit, o.r), o.f64)
-        assert e.max() <= FIT_RTOL, f"run {o.r}: initial fitness error {e.max():.3g}"
-        out["max_fit_rel"] = max(out["max_fit_rel"], float(e.max()))
+        fg = batch.run_fit(fit, o.r)
+        bad, n_ill = fitness_misses(fg, o.f64, o.pop, o.prob)
+        assert bad.size == 0, f"run {o.r}: initial fitness error {rel_err(fg, o.f64).max():.3g}"
+        if n_ill:
+            o.diverged, o.why = True, "initial fitness undetermined in float64"
+            out["diverged"] += 1
+            out["ill"] += n_ill
+            continue
+        out["max_fit_rel"] = max(out["max_fit_rel"], float(rel_err(fg, o.f64).max()))
     for g in range(G):
         u, fu, desc = batch.trace_step()
         pop, fit = batch.host_state()
@@ -137,7 +159,13 @@ def trajectory_parity(batch, wl, G, stats=None, check_desc=True):
             bad = np.argwhere(ug != s["u"])
             assert bad.size == 0, f"run {r} g={g} theta={o.th}: trial vectors differ at {bad[:5].tolist()}"
             e = rel_err(fg, s["fu64"])
-            assert e.max() <= FIT_RTOL, f"run {r} g={g} kind={o.prob.kind}: trial fitness error {e.max():.3g}"
+            miss, n_ill = fitness_misses(fg, s["fu64"], s["u"], o.prob)
+            assert miss.size == 0, f"run {r} g={g} kind={o.prob.kind}: trial fitness error {e[miss].max():.3g}"
+            if n_ill:
+                o.diverged, o.why = True, f"trial fitness undetermined in float64 at g={g}"
+                out["diverged"] += 1
+                out["ill"] += n_ill
+                continue
             out["max_fit_rel"] = max(out["max_fit_rel"], float(e.max()))
             out["trials"] += len(fg)
             acc_g = dg[:, 15].astype(bool)

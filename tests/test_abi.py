@@ -99,11 +99,62 @@ def test_query_sizes_packing():
     ({"D": 129}, "D must be"),
     ({"lb": 1.0, "ub": 1.0}, "lb < ub"),
     ({"n_cs": 4}, "n_cs"),
-    ({"kind": "lqr_mlp"}, "unsupported kind"),
 ])
 def test_validation_rejects(kw, msg):
     M = _lib()
     cfg, keep = _cfg(M, **kw)
+    with pytest.raises(M.MetadeError) as ei:
+        M.metade_query_sizes(cfg)
+    assert "status -1" in str(ei.value) and msg in str(ei.value)
+
+
+def test_unknown_kind_rejected():
+    M = _lib()
+    cfg, keep = _cfg(M)
+    keep["probs"][0].kind = 99
+    with pytest.raises(M.MetadeError) as ei:
+        M.metade_query_sizes(cfg)
+    assert "unsupported kind" in str(ei.value)
+
+
+def _ctrl_cfg(M, N=(256,), obs=17, act=6, hidden=(64, 64), D=None, steps=200, plant=True):
+    """Control-workload configuration; D defaults to the policy's weight count."""
+    h1, h2 = hidden
+    if D is None:
+        D = h1 * obs + h1 + h2 * h1 + h2 + act * h2 + act
+    cfg, keep = _cfg(M, N=N, D=D, kind="lqr_mlp", lb=-1.0, ub=1.0)
+    q = keep["probs"][0]
+    q.o = q.R = None
+    q.bias = 0.0
+    q.obs, q.act, q.hidden1, q.hidden2 = obs, act, h1, h2
+    q.steps, q.n_rollouts, q.ctrl_weight = steps, 1, 0.01
+    if plant:
+        q.A, q.B, q.x0 = 0x1000, 0x2000, 0x3000   # never dereferenced by size queries
+    return cfg, keep
+
+
+def test_control_query_sizes():
+    M = _lib()
+    cfg, keep = _ctrl_cfg(M, N=(256, 100))
+    pop, fit, by, bx, scratch = M.metade_query_sizes(cfg)
+    D = 5702   # 17 -> 64 -> 64 -> 6 tanh policy (weights and biases)
+    assert pop == 4 * D * 356 and fit == 4 * 356 and by == 16 and bx == 8 * D
+    assert scratch >= 4 * D * 356   # pending trial rows
+
+
+@pytest.mark.parametrize("kw,msg", [
+    ({"hidden": (32, 32)}, "64 units"),
+    ({"obs": 25}, "obs"),
+    ({"act": 9}, "act"),
+    ({"D": 5701}, "weight count"),
+    ({"plant": False}, "A, B and x0"),
+    ({"steps": 0}, "steps"),
+    ({"N": (1025,)}, "10..1024"),
+    ({"N": (9,)}, "10..1024"),
+])
+def test_control_validation_rejects(kw, msg):
+    M = _lib()
+    cfg, keep = _ctrl_cfg(M, **kw)
     with pytest.raises(M.MetadeError) as ei:
         M.metade_query_sizes(cfg)
     assert "status -1" in str(ei.value) and msg in str(ei.value)

@@ -1,0 +1,123 @@
+"""GPU parity of the control workload: tanh policies scored by a rollout of a
+linear system (the paper's neural-control setting, Sec. IV-D, on a synthetic
+plant), against the oracle's trajectory on the same seeded inputs.
+
+Trial vectors, draws, crossover and selection are compared bit for bit; the
+float32 fitness (a float64 rollout rounded once) within the relative
+tolerance of the float64 oracle.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import pde
+from oracle.fitness import evaluate
+from paritylib import FIT_RTOL, rel_err, trajectory_parity
+
+pytestmark = pytest.mark.gpu
+
+
+def _batch(wl):
+    from paper_2502_10470_amd import Batch
+    return Batch(wl)
+
+
+def _strategy_grid(runs, n_cs, seed):
+    """Theta rows covering every base pair, difference count and crossover scheme."""
+    rng = np.random.default_rng(seed)
+    th = np.empty((runs, 6), np.float32)
+    for r in range(runs):
+        th[r, 0] = rng.uniform(0.05, 1.0)
+        th[r, 1] = rng.uniform(0.0, 1.0)
+        th[r, 2] = 1 + (r % 4) + 0.5
+        th[r, 3] = 1 + ((r // 4) % 4) + 0.5
+        th[r, 4] = 1 + ((r + r // 4) % 4) + 0.5
+        th[r, 5] = 1 + (r % n_cs) + 0.5
+    return th
+
+
+@pytest.mark.parametrize("obs,act,steps,n_roll,n_cs", [
+    (5, 3, 20, 2, 3),     # odd D (4739): unaligned rows, several rollouts, arithmetic crossover
+    (17, 6, 200, 1, 2),   # the policy and horizon of the full workload
+    (24, 8, 12, 1, 3),    # largest observation / action sizes
+    (1, 1, 30, 3, 2),     # smallest
+])
+def test_control_follows_oracle(obs, act, steps, n_roll, n_cs):
+    Ns = [10, 17, 33, 64, 65, 40, 12, 20]
+    th = _strategy_grid(len(Ns), n_cs, seed=obs * 100 + act)
+    wl = W.control_batch(11 + obs, Ns, obs=obs, act=act, steps=steps, n_rollouts=n_roll,
+                         theta=th, n_cs=n_cs)
+    b = _batch(wl)
+    out = trajectory_parity(b, wl, G=3)
+    print(f"obs={obs} act={act}: compared {out['compared']} diverged {out['diverged']} (undetermined {out['ill']}) "
+          f"max fitness rel err {out['max_fit_rel']:.3g}")
+    assert out["compared"] >= 2 * len(Ns)
+
+
+def test_control_full_size_two_generations():
+    """16 runs x N=256, D=5702, 200-step horizon: two traced generations."""
+    wl = W.workload_c5()
+    b = _batch(wl)
+    out = trajectory_parity(b, wl, G=2)
+    print(f"c5: compared {out['compared']} diverged {out['diverged']} "
+          f"max fitness rel err {out['max_fit_rel']:.3g}")
+    assert out["compared"] >= 24
+
+
+def test_control_best_record_float64():
+    wl = W.control_batch(3, [24, 30, 16], steps=50, G=4)
+    b = _batch(wl)
+    b.inner_step(4)
+    y = b.get_best()
+    pop, fit = b.host_state()
+    bx = b.best_x.cpu().numpy()
+    for r in range(wl.n_runs):
+        f = b.run_fit(fit, r)
+        i = int(np.lexsort((np.arange(len(f)), pde.order_key(f)))[0])
+        x = b.run_pop(pop, r)[i]
+        assert np.array_equal(b.run_bx(bx, r), x)
+        ref = float(evaluate(x, wl.problems[r]))
+        assert abs(y[r] - ref) <= 1e-9 * abs(ref), (r, y[r], ref)
+        assert abs(float(f[i]) - ref) <= FIT_RTOL * abs(ref)
+
+
+def test_control_mixed_with_shifted_runs():
+    """Control and shifted-rotated runs in one context, sharing the search box."""
+    ctrl = W.control_batch(8, [20, 33], obs=4, act=2, steps=25)
+    rast = W.make_problem("rastrigin", 10, 8, 5)
+    ell = W.make_problem("elliptic", 100, 8, 6)
+    probs = [rast, ctrl.problems[0], ell, ctrl.problems[1]]
+    theta = np.concatenate([ctrl.theta, ctrl.theta], 0)
+    wl = W.Workload(name="mixed", seed=8, lb=-0.25, ub=0.25, n_cs=2,
+                    N=np.array([32, 20, 40, 33], np.uint32), problem=np.arange(4, dtype=np.uint32),
+                    stream=np.arange(4, dtype=np.uint32), problems=probs, G=3, theta=theta)
+    b = _batch(wl)
+    out = trajectory_parity(b, wl, G=3)
+    assert out["compared"] >= 8
+
+
+def test_control_deterministic_and_resumable():
+    wl = W.control_batch(9, [16, 24], steps=30)
+    b1 = _batch(wl)
+    b1.inner_step(2)
+    blob = b1.get_state()
+    b1.inner_step(2)
+    p1, f1 = b1.host_state()
+    b2 = _batch(wl)
+    b2.set_state(blob)
+    b2.inner_step(2)
+    p2, f2 = b2.host_state()
+    assert np.array_equal(p1, p2) and np.array_equal(f1, f2)
+
+
+def test_control_selection_invariants():
+    """Per-individual fitness never increases; trials stay in the box."""
+    wl = W.control_batch(10, [32, 48], steps=40)
+    b = _batch(wl)
+    _, f0 = b.host_state()
+    for _ in range(5):
+        b.inner_step(1)
+        pop, f = b.host_state()
+        assert np.all(f <= f0)
+        assert pop.min() >= wl.lb and pop.max() <= wl.ub
+        f0 = f

@@ -165,3 +165,22 @@ def test_lqr_flatten_order():
     assert W1.shape == (64, 17) and W1[1, 0] == 17 and b1[0] == 64 * 17
     W3, b3 = layers[2]
     assert W3.shape == (6, 64) and b3[-1] == 5701
+
+
+def test_lqr_extended_precision_agrees_when_well_conditioned():
+    """The extended-precision rollout reproduces the zero-policy closed form and
+    agrees with float64 on policies from the workload's weight box."""
+    p = W.make_problem("lqr_mlp", 5702, 4, 0)
+    x = p.x0[0].astype(np.float64)
+    A = p.A.astype(np.float64)
+    ref = 0.0
+    for _ in range(p.steps):
+        ref += x @ x
+        x = A @ x
+    J80 = float(fitness.lqr_mlp(np.zeros(5702, np.float32), p, dtype=np.longdouble))
+    assert J80 == pytest.approx(ref, rel=1e-12)
+    rng = np.random.default_rng(3)
+    w = rng.uniform(-0.25, 0.25, (8, 5702)).astype(np.float32)
+    J64 = fitness.lqr_mlp(w, p)
+    J80 = fitness.lqr_mlp(w, p, dtype=np.longdouble).astype(np.float64)
+    assert np.all(np.abs(J64 - J80) <= 1e-12 * J80)

@@ -29,6 +29,11 @@ LQR_ACT = 6
 LQR_HIDDEN = (64, 64)
 LQR_STEPS = 200
 LQR_CTRL_WEIGHT = 0.01
+# Weight box of the control workload: 1/sqrt(obs) rounded to 0.25 (the usual
+# fan-in scale of a first layer).  With [-1, 1] most random policies make the
+# closed loop chaotic, and their cost is then not determined by float64
+# arithmetic (it moves by percent against extended precision).
+CTRL_BOX = 0.25
 
 
 def mlp_param_count(n_in: int, hidden, n_out: int) -> int:
@@ -111,21 +116,23 @@ def make_rotation(rng: np.random.Generator, D: int) -> np.ndarray:
 
 
 def make_problem(kind: str, D: int, seed: int, run: int, identity_rotation: bool = False,
-                 bias: float = 100.0, n_rollouts: int = 1) -> Problem:
-    """One seeded instance of a shifted-rotated function (or the control system)."""
+                 bias: float = 100.0, n_rollouts: int = 1, obs: int = LQR_OBS,
+                 act: int = LQR_ACT, steps: int = LQR_STEPS) -> Problem:
+    """One seeded instance of a shifted-rotated function (or the control system:
+    A = 0.95 G / rho(G) with G Gaussian, B Gaussian / sqrt(obs), x0 ~ N(0, I))."""
     if kind not in KINDS:
         raise ValueError(f"unknown problem kind {kind!r}")
     rng = _rng(seed, run, _KIND_TAG[kind])
     if kind == "lqr_mlp":
-        g = rng.standard_normal((LQR_OBS, LQR_OBS))
+        g = rng.standard_normal((obs, obs))
         rho = np.max(np.abs(np.linalg.eigvals(g)))
         A = (0.95 * g / rho).astype(np.float32)
-        B = (rng.standard_normal((LQR_OBS, LQR_ACT)) / np.sqrt(LQR_OBS)).astype(np.float32)
-        x0 = rng.standard_normal((n_rollouts, LQR_OBS)).astype(np.float32)
-        Dm = mlp_param_count(LQR_OBS, LQR_HIDDEN, LQR_ACT)
+        B = (rng.standard_normal((obs, act)) / np.sqrt(obs)).astype(np.float32)
+        x0 = rng.standard_normal((n_rollouts, obs)).astype(np.float32)
+        Dm = mlp_param_count(obs, LQR_HIDDEN, act)
         if D != Dm:
             raise ValueError(f"control workload has D={Dm}, got {D}")
-        return Problem(kind=kind, D=D, bias=0.0, A=A, B=B, x0=x0)
+        return Problem(kind=kind, D=D, bias=0.0, A=A, B=B, x0=x0, steps=steps)
     o = rng.uniform(-80.0, 80.0, size=D).astype(np.float32)
     R = np.eye(D, dtype=np.float32) if identity_rotation else make_rotation(rng, D)
     p = Problem(kind=kind, D=D, bias=bias, o=o, R=R)
@@ -202,7 +209,7 @@ def workload_c5(runs: int = 16, N: int = 256, G: int = 100, n_rollouts: int = 1)
     theta = _sample_theta(rng, runs, 2)
     D = mlp_param_count(LQR_OBS, LQR_HIDDEN, LQR_ACT)
     problems = [make_problem("lqr_mlp", D, seed, r, n_rollouts=n_rollouts) for r in range(runs)]
-    return Workload(name="c5_control_mlp", seed=seed, lb=-1.0, ub=1.0, n_cs=2,
+    return Workload(name="c5_control_mlp", seed=seed, lb=-CTRL_BOX, ub=CTRL_BOX, n_cs=2,
                     N=np.full(runs, N, np.uint32), problem=np.arange(runs, dtype=np.uint32),
                     stream=np.arange(runs, dtype=np.uint32), problems=problems, G=G, theta=theta)
 
@@ -221,6 +228,22 @@ def small_batch(seed: int, kinds, Ns, Ds, G: int = 3, n_cs: int = 2, theta=None,
     return Workload(name=f"small_{seed}", seed=seed, lb=lb, ub=ub, n_cs=n_cs,
                     N=np.asarray(Ns, np.uint32), problem=np.arange(runs, dtype=np.uint32),
                     stream=stream, problems=problems, G=G, theta=np.asarray(theta, np.float32))
+
+
+def control_batch(seed: int, Ns, obs: int = LQR_OBS, act: int = LQR_ACT, steps: int = LQR_STEPS,
+                  n_rollouts: int = 1, theta=None, n_cs: int = 2, G: int = 3) -> Workload:
+    """A small batch of control runs (one plant per run) for parity tests."""
+    runs = len(Ns)
+    rng = _rng(seed, 0xC7)
+    if theta is None:
+        theta = _sample_theta(rng, runs, n_cs)
+    D = mlp_param_count(obs, LQR_HIDDEN, act)
+    problems = [make_problem("lqr_mlp", D, seed, r, n_rollouts=n_rollouts, obs=obs, act=act,
+                             steps=steps) for r in range(runs)]
+    return Workload(name=f"control_{seed}", seed=seed, lb=-CTRL_BOX, ub=CTRL_BOX, n_cs=n_cs,
+                    N=np.asarray(Ns, np.uint32), problem=np.arange(runs, dtype=np.uint32),
+                    stream=np.arange(runs, dtype=np.uint32), problems=problems, G=G,
+                    theta=np.asarray(theta, np.float32))
 
 
 def workload_by_name(name: str) -> Workload:
