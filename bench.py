@@ -90,6 +90,19 @@ def alg_slots_per_trial(N, D, kind, bl, br, dn, cs, CR):
     return rng + sampler + mutation + cross + clip_shift + rotation + elem + ranking + 2
 
 
+def ctrl_slots_per_trial(prob, bl, br, dn, cs, CR):
+    """Lane-slots of one control trial: the DE part as for the other kinds plus
+    the rollout's multiply-adds (float64 FMAs issue at the full rate), with the
+    tanh evaluations not counted."""
+    D, O, A, H1, H2 = prob.D, prob.A.shape[0], prob.B.shape[1], prob.hidden[0], prob.hidden[1]
+    m = int(1 in (bl, br)) + 2 * dn
+    calls = 3 + (math.ceil(D / 4) if cs == 1 else 1)
+    rng = calls * PHILOX_SLOTS + 3 * (m + 3 + (D if cs == 1 else 0))
+    de = D * (2 * dn + 1 + (3 if bl != br else 0)) + D * 3 + 2 * D
+    macs = prob.steps * prob.x0.shape[0] * (H1 * O + H2 * H1 + A * H2 + O * O + O * A)
+    return rng + m * (m + 5) + de + macs
+
+
 def launch_slots(wl, theta, G):
     F, CR, bl, br, dn, cs = decode(theta, wl.n_cs)
     tot = 0.0
@@ -146,7 +159,7 @@ def bench_batch(args):
     import workloads as W
     from paper_2502_10470_amd import Batch, metade as M
 
-    wl = W.workload_c4() if args.workload == "c4" else W.workload_c2()
+    wl = {"c4": W.workload_c4, "c2": W.workload_c2, "c5": W.workload_c5}[args.workload]()
     prec = M.BF16_REFINE if args.precision == "bf16" else M.FP32
     b = Batch(wl, precision=prec)
     evals = wl.evals_per_pass()
@@ -172,28 +185,37 @@ def bench_batch(args):
     dt = t1 - t0
     avg_ms = k_ms / max(k_launches, 1)
     F, CR, bl, br, dn, cs = decode(wl.theta, wl.n_cs)
-    slots = sum(int(wl.N[r]) * wl.G * alg_slots_per_trial(int(wl.N[r]), wl.D_of(r),
-                wl.problems[int(wl.problem[r])].kind, bl[r], br[r], dn[r], cs[r], CR[r])
-                for r in range(wl.n_runs))
-    rot_flops = sum(2.0 * int(wl.N[r]) * wl.D_of(r) ** 2 * wl.G for r in range(wl.n_runs))
+    ctrl = args.workload == "c5"
+    if ctrl:
+        slots = sum(int(wl.N[r]) * wl.G * ctrl_slots_per_trial(wl.problems[int(wl.problem[r])],
+                    bl[r], br[r], dn[r], cs[r], CR[r]) for r in range(wl.n_runs))
+    else:
+        slots = sum(int(wl.N[r]) * wl.G * alg_slots_per_trial(int(wl.N[r]), wl.D_of(r),
+                    wl.problems[int(wl.problem[r])].kind, bl[r], br[r], dn[r], cs[r], CR[r])
+                    for r in range(wl.n_runs))
+    rot_flops = 0.0 if ctrl else sum(2.0 * int(wl.N[r]) * wl.D_of(r) ** 2 * wl.G
+                                     for r in range(wl.n_runs))
     refine_rate = (r_after - r_before) / max(t_after - t_before, 1)
+    at = {"c4": "D=100", "c2": "D in {10,20}", "c5": "D=5702 (control)"}[args.workload]
+    kern = {"c4": "k_generations_mfma", "c2": "k_generations",
+            "c5": "k_ctrl_eval (timed with k_ctrl_rank, k_ctrl_trials, k_ctrl_commit)"}[args.workload]
     line = {
-        "metric": f"inner-DE individual-evals/sec (runs x N x gens / s) at "
-                  f"{'D=100' if args.workload == 'c4' else 'D in {10,20}'}",
+        "metric": f"inner-DE individual-evals/sec (runs x N x gens / s) at {at}",
         "value": evals * args.steps / dt, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1000.0 * dt / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": "bf16+f64" if prec == M.BF16_REFINE else "f32", "data": "synthetic",
+        "dtype": "f32+f64" if ctrl else ("bf16+f64" if prec == M.BF16_REFINE else "f32"),
+        "data": "synthetic",
         "config": {"workload": wl.name, "runs": wl.n_runs, "gens": wl.G,
                    "evals_per_step": evals, "precision": args.precision,
                    "refine_rate": refine_rate if prec == M.BF16_REFINE else None},
         "roofline": {"bound": "alu", "achieved": slots / (avg_ms * 1e-3) / 1e12,
                      "peak": VALU_PEAK_SLOTS / 1e12, "unit": "Tslot/s",
                      "frac": slots / (avg_ms * 1e-3) / VALU_PEAK_SLOTS, "traffic": None,
-                     "kernel": "k_generations_mfma" if args.workload == "c4" else "k_generations",
+                     "kernel": kern,
                      "avg_launch_ms": avg_ms, "launches": k_launches,
                      "rotation_tflops": rot_flops / (avg_ms * 1e-3) / 1e12,
-                     "occupied_cu_frac": min(wl.n_runs, 256) / 256.0},
+                     "occupied_cu_frac": (1.0 if ctrl else min(wl.n_runs, 256) / 256.0)},
     }
     print(json.dumps(line), flush=True)
 
@@ -203,9 +225,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c3", choices=["c3", "c4", "c2"],
+    ap.add_argument("--workload", default="c3", choices=["c3", "c4", "c2", "c5"],
                     help="c3: full MetaDE at D=20 (default); c4: 128 runs x N=256 at D=100, "
-                         "500 generations; c2: uneven batch of 256 runs, 200 generations")
+                         "500 generations; c2: uneven batch of 256 runs, 200 generations; "
+                         "c5: control workload, 16 runs x N=256 tanh policies (D=5702), "
+                         "200-step rollouts, 100 generations")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"],
                     help="fitness contraction: plain (float64-accumulated) or bf16 matrix cores "
                          "with plain re-evaluation of near ties")

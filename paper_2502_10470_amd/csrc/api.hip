@@ -129,7 +129,7 @@ metade_status plan_config(const metade_config *cfg, Plan &pl, std::string &msg) 
         msg = pk + "control policy hidden layers must have 64 units"; return METADE_EINVAL;
       }
       if (q.obs < 1 || q.obs > (uint32_t)mde::CT_MAX_OBS || q.act < 1 || q.act > (uint32_t)mde::CT_MAX_ACT) {
-        msg = pk + "control workload needs 1 <= obs <= 24 and 1 <= act <= 8"; return METADE_EINVAL;
+        msg = pk + "control workload needs 1 <= obs <= 20 and 1 <= act <= 8"; return METADE_EINVAL;
       }
       if (q.steps < 1 || q.n_rollouts < 1) { msg = pk + "steps and n_rollouts must be >= 1"; return METADE_EINVAL; }
       if (!q.A || !q.B || !q.x0) { msg = pk + "A, B and x0 are required"; return METADE_EINVAL; }
@@ -195,7 +195,7 @@ metade_status plan_config(const metade_config *cfg, Plan &pl, std::string &msg) 
       d.pend_off = pl.pend_floats;
       d.fit_off = (uint32_t)pl.fit_n;
       d.bx_off = (uint32_t)pl.bx_n;
-      pl.pend_floats += (size_t)N * D;
+      pl.pend_floats += (size_t)N * d.Dp;   // pending trial rows, 16-byte aligned
       pl.pop_floats += (size_t)N * D;
       pl.fit_n += N;
       pl.bx_n += D;

@@ -33,7 +33,7 @@ constexpr int MAX_KP = 32;     // top-p set size for N <= 256 is at most 26
 constexpr uint32_t LDS_BUDGET = 160 * 1024;
 // control workload: one hidden unit per lane, bounded observation / action sizes
 constexpr int CT_H = 64;
-constexpr int CT_MAX_OBS = 24;
+constexpr int CT_MAX_OBS = 20;
 constexpr int CT_MAX_ACT = 8;
 constexpr int CT_MAX_N = 1024;
 constexpr float SCHWEFEL_ZSTAR = 420.96875f;

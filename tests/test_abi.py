@@ -144,7 +144,7 @@ def test_control_query_sizes():
 
 @pytest.mark.parametrize("kw,msg", [
     ({"hidden": (32, 32)}, "64 units"),
-    ({"obs": 25}, "obs"),
+    ({"obs": 21}, "obs"),
     ({"act": 9}, "act"),
     ({"D": 5701}, "weight count"),
     ({"plant": False}, "A, B and x0"),

@@ -39,7 +39,7 @@ def _strategy_grid(runs, n_cs, seed):
 @pytest.mark.parametrize("obs,act,steps,n_roll,n_cs", [
     (5, 3, 20, 2, 3),     # odd D (4739): unaligned rows, several rollouts, arithmetic crossover
     (17, 6, 200, 1, 2),   # the policy and horizon of the full workload
-    (24, 8, 12, 1, 3),    # largest observation / action sizes
+    (20, 8, 12, 1, 3),    # largest observation / action sizes
     (1, 1, 30, 3, 2),     # smallest
 ])
 def test_control_follows_oracle(obs, act, steps, n_roll, n_cs):
