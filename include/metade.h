@@ -59,9 +59,18 @@ typedef enum {
   METADE_ESTATE = -4    /* call out of order (e.g. outer step before outer reset) */
 } metade_status;
 
+/* Precision of the rotation z = R (u - o) of the shifted-rotated kinds.  The
+ * control kind ignores it (its rollout is always float64).
+ *   FP32: z accumulated in float64 (exact products), rounded once to float32;
+ *         fitness terms in float32, sums in float64.
+ *   BF16_REFINE: z from bf16 splits on the matrix cores with float32
+ *         accumulation and a certified bound E on the fitness error; a trial
+ *         whose approximate fitness minus E exceeds its target's is rejected
+ *         at once, every other trial is re-evaluated as in FP32 and decided
+ *         from that value, so decisions equal those of FP32. */
 typedef enum {
-  METADE_FP32 = 0,        /* fitness contraction in float32 (plain path) */
-  METADE_BF16_REFINE = 1  /* bf16 matrix-core contraction, float32 re-evaluation of near ties */
+  METADE_FP32 = 0,
+  METADE_BF16_REFINE = 1
 } metade_precision;
 
 /* Objective functions: z = R (u - o) [+ c], f = g(z) + bias (textbook base
@@ -128,9 +137,14 @@ metade_status metade_query_sizes(const metade_config *cfg, size_t *pop_bytes, si
  * evaluation; x = lb + (ub - lb) (w >> 8) 2^-24 in float64, rounded once).
  * Rejected with METADE_EINVAL: n_runs = 0, N_r < 10 (the largest index draw,
  * 1 + 2 * 4 distinct indices plus the target), N_r > 256 or D_r > 128 for the
- * shifted-rotated kinds, N_r > 1024 for LQR_MLP, lb >= ub, |lb| or |ub|
- * > 1e30, n_cs not in {2, 3}, a problem index out of range, a missing device
- * pointer, an unknown kind.  On success *out owns the context. */
+ * shifted-rotated kinds, lb >= ub, |lb| or |ub| > 1e30, n_cs not in {2, 3},
+ * a precision not in metade_precision, a problem index out of range, a
+ * missing device pointer, a hybrid permutation that is not one, an unknown
+ * kind; for LQR_MLP: N_r > 1024, hidden1 or hidden2 != 64, obs not in 1..20,
+ * act not in 1..8, steps or n_rollouts = 0, a non-finite ctrl_weight, D not
+ * equal to the policy's weight count.  A run is also rejected when its
+ * population and draws do not fit in the 160 KB of LDS of its generation
+ * kernel.  On success *out owns the context. */
 metade_status metade_init(const metade_config *cfg, metade_ctx **out);
 
 /* Re-run the initialisation and first evaluation of every run and reset the
@@ -162,7 +176,8 @@ metade_status metade_trace_sizes(metade_ctx *ctx, size_t *u_bytes, size_t *fu_by
  *   desc int32 [sum_r N_r][16]: 0 base-left index, 1 base-right index,
  *        2..9 difference pairs (a1,b1,..,a4,b4; -1 unused), 10 j_rand or n,
  *        11 L (exponential) or -1, 12 pbest rank, 13 rand index or -1,
- *        14 K bits (float32) , 15 accept flag. */
+ *        14 K bits (float32) , 15 accept flag.
+ * Available for METADE_FP32 contexts only (METADE_EINVAL otherwise). */
 metade_status metade_inner_step_trace(metade_ctx *ctx, float *u, float *fu, int32_t *desc);
 
 /* Evolver (Alg. 3).  The context's runs are the P = n_runs executors of one
@@ -209,8 +224,8 @@ metade_status metade_set_state(metade_ctx *ctx, const void *blob, size_t bytes);
 metade_status metade_kernel_timing(metade_ctx *ctx, int enable);
 metade_status metade_kernel_time(metade_ctx *ctx, double *ms, uint64_t *launches);
 
-/* Counters of the last metade_inner_step / outer step (synchronises):
- * trials evaluated, trials re-evaluated in float32 (BF16_REFINE only). */
+/* Counters since metade_init (synchronises): trials evaluated, and trials
+ * re-evaluated exactly by the BF16_REFINE mode (0 otherwise). */
 metade_status metade_get_counters(metade_ctx *ctx, uint64_t *trials, uint64_t *refined);
 
 /* Readable message of the last error on ctx (or of the last failed

@@ -5,8 +5,10 @@
 // run; lanes 0..511 are consumers, 512..767 producers of the next
 // generation's random draws (as in the lane-per-trial kernel).  The rotation
 // z = R (u - o) of all trials of a generation is a [N x D] x [D x D] product
-// done on the matrix cores: consumer wave w owns the 16-wide output tile w
-// and keeps its slice of R in registers for the whole launch.
+// done on the matrix cores: consumer wave w owns the 16-wide output tile w.
+// The bf16 mode keeps that tile's slice of R (split in bf16 parts) in
+// registers for the whole launch; the plain mode reads its float64
+// coefficients from the table for every block of k.
 //
 // Plain mode: v_mfma_f64_16x16x4 on y = u - o in float64 (exact), the same
 // accuracy as the lane kernel's float64 accumulation.
@@ -32,8 +34,11 @@ typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 constexpr int KS64 = 32;      // float64 k-steps of 4 (D <= 128)
 constexpr int KSB = 4;        // bf16 k-steps of 32 (D <= 128)
 // |z_hat - z| <= E_COEF * ||u - o||_2 for the three-product bf16 split with
-// float32 accumulation (2^-15 split residue + 384 * 2^-24 accumulation +
-// 2^-24 for rounding u - o to float32, doubled for safety).
+// float32 accumulation: the residues of the two splits and the dropped
+// lo * lo product give 3 * 2^-16 sum_k |R_jk| |y_k|, float32 accumulation of
+// 3 * 128 products 384 * 2^-24 of the same sum, rounding u - o to float32
+// 2^-24; the sum is at most ||y||_2 (rows of R have unit norm), so the total
+// is below 7e-5 ||y||_2 and 2^-13 leaves a margin of 1.7.
 constexpr float E_COEF = 1.2207031e-4f;  // 2^-13
 
 // ---------------------------------------------------------------- rotation tiles
@@ -43,12 +48,12 @@ constexpr float E_COEF = 1.2207031e-4f;  // 2^-13
 // of four steps: lane l feeds steps 4b..4b+3 with k = 16 b + 4 (l/16) + 0..3,
 // one contiguous float4 of its trial row.  Result element v is
 // z[16 rt + l/16 + 4v][16 ct + l%16].
-// Four row tiles at once (rows given per tile), four independent accumulator
-// chains sharing the B loads: the matrix core's latency is hidden by the
-// other chains instead of stalling each step.
+// RT row tiles at once (rows given per tile): RT independent accumulator
+// chains sharing the B loads, so that consecutive matrix-core instructions
+// do not wait on each other's results.
 constexpr int RT = 2;
 
-__device__ __forceinline__ void tile4_f64(const float *__restrict__ Tg, uint32_t Dk, uint32_t D,
+__device__ __forceinline__ void tiles_f64(const float *__restrict__ Tg, uint32_t Dk, uint32_t D,
                                           const float *oc, const bool (&row_ok)[RT],
                                           const uint32_t (&row_trial)[RT],
                                           const double *__restrict__ Rt, uint32_t Dr, uint32_t j,
@@ -85,7 +90,7 @@ __device__ __forceinline__ void tile4_f64(const float *__restrict__ Tg, uint32_t
 // bf16 mode.  Lane l: A row 16 rt + l%16, k = 32 s + 8 (l/16) + e; result
 // element v is z_hat[16 rt + 4 (l/16) + v][16 ct + l%16].  ysq returns the
 // lane's share of ||y||^2 of its A row.
-__device__ __forceinline__ void tile4_bf16(const float *__restrict__ Tg, uint32_t Dk,
+__device__ __forceinline__ void tiles_bf16(const float *__restrict__ Tg, uint32_t Dk,
                                            const float *oc, const bool (&row_ok)[RT],
                                            const uint32_t (&row_trial)[RT],
                                            const bf8v (&bhi)[KSB], const bf8v (&blo)[KSB],
@@ -422,7 +427,7 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
         if (BF16) {
           f4v acc[RT];
           float ysq[RT];
-          tile4_bf16(Tg, Dk, oc, rok, rtr, bhi, blo, lane, acc, ysq);
+          tiles_bf16(Tg, Dk, oc, rok, rtr, bhi, blo, lane, acc, ysq);
 #pragma unroll
           for (int r = 0; r < RT; ++r) {
             // ||y|| of A row (lane & 15): reduce the four k-quarters
@@ -445,7 +450,7 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
           }
         } else {
           d4v acc[RT];
-          tile4_f64(Tg, Dk, D, oc, rok, rtr, Rt, Dr, jcol, lane, acc);
+          tiles_f64(Tg, Dk, D, oc, rok, rtr, Rt, Dr, jcol, lane, acc);
 #pragma unroll
           for (int r = 0; r < RT; ++r) {
             float z[4], e[4];
@@ -518,7 +523,7 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
             rtr[r] = rok[r] ? cl[srow] : 0u;
           }
           d4v acc[RT];
-          tile4_f64(Tg, Dk, D, oc, rok, rtr, Rt, Dr, jcol, lane, acc);
+          tiles_f64(Tg, Dk, D, oc, rok, rtr, Rt, Dr, jcol, lane, acc);
 #pragma unroll
           for (int r = 0; r < RT; ++r) {
             float z[4], e[4];
