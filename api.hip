@@ -1,0 +1,782 @@
+// C ABI of the MetaDE inner-DE library: validation, device tables, launch
+// sequencing of the executor and evolver kernels, checkpointing and timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/metade.h"
+#include "device.h"
+#include "kernels.h"
+
+using mde::LaunchArgs;
+using mde::ProbDev;
+using mde::RunDev;
+
+namespace {
+
+thread_local std::string g_init_error = "no error";
+
+struct EventPair {
+  hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct metade_ctx {
+  hipStream_t stream = nullptr;
+  uint32_t n_runs = 0, n_cs = 2, precision = 0;
+  uint64_t seed = 0;
+  float lb = 0, ub = 0;
+  float *pop = nullptr, *fit = nullptr, *best_x = nullptr;
+  double *best_y = nullptr;
+  std::vector<RunDev> runs_h;
+  std::vector<ProbDev> probs_h;
+  RunDev *runs_d = nullptr;
+  ProbDev *probs_d = nullptr;
+  float *theta_d = nullptr;
+  float *pend_d = nullptr;
+  size_t pop_floats = 0, fit_n = 0, bx_n = 0, pend_floats = 0;
+  uint32_t lds_bytes = 0, init_lds_bytes = 0, mfma_lds_bytes = 0;
+  uint32_t n_lane = 0, n_mfma = 0, n_ctrl = 0, ctrl_max_n = 0;
+  uint32_t *lane_list_d = nullptr, *mfma_list_d = nullptr, *ctrl_list_d = nullptr;
+  uint32_t *order_d = nullptr, *cacc_d = nullptr;  // control runs: top-p lists, decisions
+  float *cfu_d = nullptr;                          // control runs: trial fitness
+  unsigned long long *counters_d = nullptr;
+  uint32_t gen = 0;
+  // evolver
+  float *Xo = nullptr, *Uo = nullptr, *bxo = nullptr;
+  double *yo = nullptr, *yt = nullptr;
+  int32_t *bidx = nullptr;
+  unsigned char *tab = nullptr; // read-only problem tables (shift, float64 rotation, weights)
+  uint32_t outer_gen = 0;
+  bool outer_ready = false;
+  // measurement
+  bool timing = false;
+  std::vector<EventPair> events;
+  uint64_t trials = 0, refined = 0;
+  std::string err = "no error";
+};
+
+namespace {
+
+metade_status fail(metade_ctx *c, metade_status s, const std::string &msg) {
+  if (c) c->err = msg; else g_init_error = msg;
+  return s;
+}
+
+#define HIP_TRY(ctx, expr)                                                              \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail((ctx), METADE_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+uint32_t round4(uint32_t d) { return (d + 3u) & ~3u; }
+
+struct Plan {
+  std::vector<RunDev> runs;
+  std::vector<ProbDev> probs;
+  size_t tab_bytes = 0;
+  uint32_t init_lds_bytes = 0, mfma_lds_bytes = 0;
+  std::vector<uint32_t> lane_list, mfma_list, ctrl_list;
+  uint32_t ctrl_max_n = 0;
+  size_t pop_floats = 0, fit_n = 0, bx_n = 0, pend_floats = 0;
+  uint32_t lds_bytes = 0;
+};
+
+metade_status plan_config(const metade_config *cfg, Plan &pl, std::string &msg) {
+  if (!cfg) { msg = "cfg is NULL"; return METADE_EINVAL; }
+  if (cfg->n_runs == 0) { msg = "n_runs must be >= 1"; return METADE_EINVAL; }
+  if (!cfg->N || !cfg->problem || !cfg->stream_id) { msg = "N, problem and stream_id host arrays are required"; return METADE_EINVAL; }
+  if (cfg->n_problems == 0 || !cfg->problems) { msg = "at least one problem is required"; return METADE_EINVAL; }
+  if (!(cfg->lb < cfg->ub) || std::fabs(cfg->lb) > 1e30f || std::fabs(cfg->ub) > 1e30f) {
+    msg = "search box must satisfy lb < ub and |lb|, |ub| <= 1e30"; return METADE_EINVAL;
+  }
+  if (cfg->n_cs != 2 && cfg->n_cs != 3) { msg = "n_cs must be 2 or 3"; return METADE_EINVAL; }
+  if (cfg->precision != METADE_FP32 && cfg->precision != METADE_BF16_REFINE) {
+    msg = "precision must be METADE_FP32 or METADE_BF16_REFINE"; return METADE_EINVAL;
+  }
+  pl.probs.resize(cfg->n_problems);
+  const double zs = mde::SCHWEFEL_ZSTAR;
+  const double cs = zs * std::sin(std::sqrt(zs));
+  for (uint32_t k = 0; k < cfg->n_problems; ++k) {
+    const metade_problem &q = cfg->problems[k];
+    ProbDev p;
+    std::memset(&p, 0, sizeof(p));
+    p.kind = q.kind;
+    p.D = q.D;
+    p.bias = q.bias;
+    p.cs_d = cs;
+    p.cs_f = (float)cs;
+    const double cond = q.cond > 0 ? (double)q.cond : 1e6;
+    if (q.kind < METADE_FN_RASTRIGIN || q.kind > METADE_FN_LQR_MLP) {
+      msg = "problem " + std::to_string(k) + ": unsupported kind " + std::to_string(q.kind);
+      return METADE_EINVAL;
+    }
+    auto take = [&](size_t bytes) {
+      const uint64_t off = pl.tab_bytes;
+      pl.tab_bytes += (bytes + 255) & ~(size_t)255;
+      return off;
+    };
+    if (q.kind == METADE_FN_LQR_MLP) {
+      const std::string pk = "problem " + std::to_string(k) + ": ";
+      if (q.hidden1 != (uint32_t)mde::CT_H || q.hidden2 != (uint32_t)mde::CT_H) {
+        msg = pk + "control policy hidden layers must have 64 units"; return METADE_EINVAL;
+      }
+      if (q.obs < 1 || q.obs > (uint32_t)mde::CT_MAX_OBS || q.act < 1 || q.act > (uint32_t)mde::CT_MAX_ACT) {
+        msg = pk + "control workload needs 1 <= obs <= 20 and 1 <= act <= 8"; return METADE_EINVAL;
+      }
+      if (q.steps < 1 || q.n_rollouts < 1) { msg = pk + "steps and n_rollouts must be >= 1"; return METADE_EINVAL; }
+      if (!q.A || !q.B || !q.x0) { msg = pk + "A, B and x0 are required"; return METADE_EINVAL; }
+      if (!std::isfinite(q.ctrl_weight)) { msg = pk + "ctrl_weight must be finite"; return METADE_EINVAL; }
+      const uint64_t Dm = (uint64_t)mde::CT_H * q.obs + mde::CT_H + (uint64_t)mde::CT_H * mde::CT_H +
+                          mde::CT_H + (uint64_t)mde::CT_H * q.act + q.act;
+      if (q.D != Dm) {
+        msg = pk + "D must equal the policy's weight count " + std::to_string(Dm); return METADE_EINVAL;
+      }
+      p.obs = q.obs;
+      p.act = q.act;
+      p.h1 = q.hidden1;
+      p.h2 = q.hidden2;
+      p.steps = q.steps;
+      p.nroll = q.n_rollouts;
+      p.cw = q.ctrl_weight;
+      p.A_off = take((size_t)q.obs * q.obs * sizeof(float));
+      p.B_off = take((size_t)q.obs * q.act * sizeof(float));
+      p.x0_off = take((size_t)q.n_rollouts * q.obs * sizeof(float));
+      pl.probs[k] = p;
+      continue;
+    }
+    if (q.D == 0 || q.D > (uint32_t)mde::MAX_D) {
+      msg = "problem " + std::to_string(k) + ": D must be in 1..128"; return METADE_EINVAL;
+    }
+    if (!q.o || !q.R) { msg = "problem " + std::to_string(k) + ": o and R are required"; return METADE_EINVAL; }
+    if (q.kind == METADE_FN_HYBRID &&
+        (!q.perm || (uint64_t)q.split[0] + q.split[1] + q.split[2] != q.D)) {
+      msg = "problem " + std::to_string(k) + ": hybrid needs perm and split summing to D";
+      return METADE_EINVAL;
+    }
+    (void)cond;
+    // read-only table layout of this problem
+    p.o_off = take((size_t)q.D * sizeof(float));
+    p.r64t_off = take((size_t)q.D * mde::rt_stride(q.D) * sizeof(double));
+    p.ew_off = take((size_t)q.D * sizeof(float));
+    p.ew64_off = take((size_t)q.D * sizeof(double));
+    p.ek_off = take((size_t)q.D * sizeof(uint32_t));
+    pl.probs[k] = p;
+  }
+  pl.runs.resize(cfg->n_runs);
+  for (uint32_t r = 0; r < cfg->n_runs; ++r) {
+    RunDev &d = pl.runs[r];
+    std::memset(&d, 0, sizeof(d));
+    const uint32_t N = cfg->N[r];
+    if (cfg->problem[r] >= cfg->n_problems) {
+      msg = "run " + std::to_string(r) + ": problem index out of range"; return METADE_EINVAL;
+    }
+    const uint32_t D = pl.probs[cfg->problem[r]].D;
+    if (pl.probs[cfg->problem[r]].kind == mde::FN_LQR_MLP) {
+      if (N < 10 || N > (uint32_t)mde::CT_MAX_N) {
+        msg = "run " + std::to_string(r) + ": N must be in 10..1024 for the control workload";
+        return METADE_EINVAL;
+      }
+      d.N = N;
+      d.D = D;
+      d.Dp = round4(D);
+      d.prob = cfg->problem[r];
+      d.stream = cfg->stream_id[r];
+      d.kp = std::max<uint32_t>(1, (N * 10 + 99) / 100);
+      d.kern = 2;
+      d.pop_off = pl.pop_floats;
+      d.pend_off = pl.pend_floats;
+      d.fit_off = (uint32_t)pl.fit_n;
+      d.bx_off = (uint32_t)pl.bx_n;
+      pl.pend_floats += (size_t)N * d.Dp;   // pending trial rows, 16-byte aligned
+      pl.pop_floats += (size_t)N * D;
+      pl.fit_n += N;
+      pl.bx_n += D;
+      pl.ctrl_list.push_back(r);
+      pl.ctrl_max_n = std::max(pl.ctrl_max_n, N);
+      d.F = 0.5f;
+      d.CR = 0.9f;
+      d.bl = d.br = mde::RAND;
+      d.dn = 1;
+      d.cs = mde::BIN;
+      continue;
+    }
+    if (N < 10 || N > (uint32_t)mde::MAX_N) {
+      msg = "run " + std::to_string(r) + ": N must be in 10..256 (9 distinct draws plus the target)";
+      return METADE_EINVAL;
+    }
+    d.N = N;
+    d.D = D;
+    d.Dp = round4(D);
+    d.prob = cfg->problem[r];
+    d.stream = cfg->stream_id[r];
+    d.kp = std::max<uint32_t>(1, (N * 10 + 99) / 100);
+    // lanes per part: whole waves covering N; parts: as many as fit the block
+    d.Np = ((N + 63u) / 64u) * 64u;
+    d.L = std::max<uint32_t>(1, std::min<uint32_t>(8, mde::GEN_CONSUMERS / d.Np));
+    d.Dk = ((D + 31u) / 32u) * 32u;
+    d.NCT = (D + 15u) / 16u;
+    const bool rosen = pl.probs[d.prob].kind == mde::FN_ROSENBROCK;
+    const uint32_t lane_bytes = mde::lds_layout(N, d.Dp, d.L, d.Np, true).total;
+    const uint32_t mf_bytes = mde::mfma_layout(N, d.Dp, d.Dk, d.L, d.Np, d.NCT, rosen).total;
+    if (cfg->precision == METADE_FP32 && lane_bytes <= mde::LDS_BUDGET) {
+      d.kern = 0;
+      d.t_lds = 1;
+      pl.lds_bytes = std::max(pl.lds_bytes, lane_bytes);
+      pl.lane_list.push_back(r);
+    } else if (mf_bytes <= mde::LDS_BUDGET) {
+      d.kern = 1;
+      d.t_lds = 0;
+      pl.mfma_lds_bytes = std::max(pl.mfma_lds_bytes, mf_bytes);
+      pl.mfma_list.push_back(r);
+    } else {
+      msg = "run " + std::to_string(r) + ": population does not fit in LDS (N*D too large)";
+      return METADE_EINVAL;
+    }
+    pl.init_lds_bytes = std::max(pl.init_lds_bytes, mde::init_lds_bytes(N, d.Dp, d.Np));
+    d.pop_off = pl.pop_floats;
+    d.pend_off = pl.pend_floats;
+    d.fit_off = (uint32_t)pl.fit_n;
+    d.bx_off = (uint32_t)pl.bx_n;
+    if (d.kern == 1) pl.pend_floats += (size_t)N * d.Dk;
+    pl.pop_floats += (size_t)N * D;
+    pl.fit_n += N;
+    pl.bx_n += D;
+    d.F = 0.5f;
+    d.CR = 0.9f;
+    d.bl = d.br = mde::RAND;
+    d.dn = 1;
+    d.cs = mde::BIN;
+  }
+  return METADE_OK;
+}
+
+LaunchArgs largs(metade_ctx *c) {
+  LaunchArgs a;
+  a.runs = c->runs_d;
+  a.probs = c->probs_d;
+  a.tab = c->tab;
+  a.pop = c->pop;
+  a.fit = c->fit;
+  a.pending = c->pend_d;
+  a.n_runs = c->n_runs;
+  a.lds_bytes = c->lds_bytes;
+  a.init_lds_bytes = c->init_lds_bytes;
+  a.mfma_lds_bytes = c->mfma_lds_bytes;
+  a.k0 = (uint32_t)(c->seed & 0xFFFFFFFFu);
+  a.k1 = (uint32_t)(c->seed >> 32);
+  a.stream = c->stream;
+  return a;
+}
+
+mde::CtrlArgs cargs(metade_ctx *c) {
+  return mde::CtrlArgs{c->ctrl_list_d, c->n_ctrl, c->ctrl_max_n, c->order_d, c->cfu_d, c->cacc_d};
+}
+
+metade_status run_generations(metade_ctx *c, uint32_t n, mde::TraceArgs tr) {
+  if (n == 0) return METADE_OK;
+  EventPair ev{nullptr, nullptr};
+  if (c->timing) {
+    HIP_TRY(c, hipEventCreate(&ev.a));
+    HIP_TRY(c, hipEventCreate(&ev.b));
+    HIP_TRY(c, hipEventRecord(ev.a, c->stream));
+  }
+  HIP_TRY(c, mde::launch_generations(largs(c), c->lane_list_d, c->n_lane, c->gen, n, c->lb, c->ub, tr));
+  HIP_TRY(c, mde::launch_generations_mfma(largs(c), c->mfma_list_d, c->n_mfma,
+                                          c->precision == METADE_BF16_REFINE, c->gen, n, c->lb,
+                                          c->ub, c->counters_d, tr));
+  HIP_TRY(c, mde::launch_ctrl_generations(largs(c), cargs(c), c->gen, n, c->lb, c->ub, tr));
+  if (c->timing) {
+    HIP_TRY(c, hipEventRecord(ev.b, c->stream));
+    c->events.push_back(ev);
+  }
+  c->gen += n;
+  for (const RunDev &r : c->runs_h) c->trials += (uint64_t)r.N * n;
+  return METADE_OK;
+}
+
+metade_status reinit(metade_ctx *c) {
+  HIP_TRY(c, mde::launch_init(largs(c), (double)c->lb, (double)c->ub));
+  HIP_TRY(c, mde::launch_ctrl_init(largs(c), cargs(c), (double)c->lb, (double)c->ub));
+  c->gen = 0;
+  return METADE_OK;
+}
+
+metade_status finalize(metade_ctx *c) {
+  HIP_TRY(c, mde::launch_finalize(largs(c), c->best_y, c->best_x));
+  HIP_TRY(c, mde::launch_ctrl_finalize(largs(c), cargs(c), c->best_y, c->best_x));
+  return METADE_OK;
+}
+
+template <typename T>
+metade_status dalloc(metade_ctx *c, T **p, size_t n) {
+  if (n == 0) { *p = nullptr; return METADE_OK; }
+  hipError_t e = hipMalloc((void **)p, n * sizeof(T));
+  if (e != hipSuccess) return fail(c, METADE_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  return METADE_OK;
+}
+
+#define TRY(expr)                       \
+  do {                                  \
+    metade_status s_ = (expr);          \
+    if (s_ != METADE_OK) return s_;     \
+  } while (0)
+
+}  // namespace
+
+extern "C" {
+
+metade_status metade_query_sizes(const metade_config *cfg, size_t *pop_bytes, size_t *fit_bytes,
+                                 size_t *best_y_bytes, size_t *best_x_bytes,
+                                 size_t *scratch_bytes) {
+  Plan pl;
+  std::string msg;
+  metade_status s = plan_config(cfg, pl, msg);
+  if (s != METADE_OK) return fail(nullptr, s, msg);
+  if (pop_bytes) *pop_bytes = pl.pop_floats * sizeof(float);
+  if (fit_bytes) *fit_bytes = pl.fit_n * sizeof(float);
+  if (best_y_bytes) *best_y_bytes = (size_t)cfg->n_runs * sizeof(double);
+  if (best_x_bytes) *best_x_bytes = pl.bx_n * sizeof(float);
+  if (scratch_bytes)
+    *scratch_bytes = pl.runs.size() * sizeof(RunDev) + pl.probs.size() * sizeof(ProbDev) +
+                     pl.pend_floats * sizeof(float) + (size_t)cfg->n_runs * (6 * 4 * 2 + 16) +
+                     pl.bx_n * sizeof(float) + 16;
+  if (scratch_bytes) *scratch_bytes += pl.tab_bytes;
+  if (scratch_bytes && !pl.ctrl_list.empty())
+    *scratch_bytes += pl.fit_n * 12 + pl.ctrl_list.size() * 4;
+  return METADE_OK;
+}
+
+metade_status metade_init(const metade_config *cfg, metade_ctx **out) {
+  if (!out) return fail(nullptr, METADE_EINVAL, "out is NULL");
+  *out = nullptr;
+  Plan pl;
+  std::string msg;
+  metade_status s = plan_config(cfg, pl, msg);
+  if (s != METADE_OK) return fail(nullptr, s, msg);
+  if (!cfg->pop || !cfg->fit || !cfg->best_y || !cfg->best_x)
+    return fail(nullptr, METADE_EINVAL, "pop, fit, best_y and best_x device buffers are required");
+  metade_ctx *c = new metade_ctx();
+  c->stream = (hipStream_t)cfg->stream;
+  c->n_runs = cfg->n_runs;
+  c->n_cs = cfg->n_cs;
+  c->precision = cfg->precision;
+  c->seed = cfg->seed;
+  c->lb = cfg->lb;
+  c->ub = cfg->ub;
+  c->pop = cfg->pop;
+  c->fit = cfg->fit;
+  c->best_y = cfg->best_y;
+  c->best_x = cfg->best_x;
+  c->runs_h = pl.runs;
+  c->probs_h = pl.probs;
+  c->pop_floats = pl.pop_floats;
+  c->fit_n = pl.fit_n;
+  c->bx_n = pl.bx_n;
+  c->pend_floats = pl.pend_floats;
+  c->lds_bytes = pl.lds_bytes;
+  c->init_lds_bytes = pl.init_lds_bytes;
+  c->mfma_lds_bytes = pl.mfma_lds_bytes;
+  c->n_lane = (uint32_t)pl.lane_list.size();
+  c->n_mfma = (uint32_t)pl.mfma_list.size();
+  c->n_ctrl = (uint32_t)pl.ctrl_list.size();
+  c->ctrl_max_n = pl.ctrl_max_n;
+  auto bail = [&](metade_status st) {
+    g_init_error = c->err;
+    metade_destroy(c);
+    return st;
+  };
+  metade_status st;
+  std::vector<std::vector<uint32_t>> perms(c->probs_h.size());
+  for (size_t k = 0; k < c->probs_h.size(); ++k) {
+    const metade_problem &q = cfg->problems[k];
+    if (q.kind != METADE_FN_HYBRID) continue;
+    // the element tables are built from the permutation: it must be one
+    std::vector<uint32_t> &perm = perms[k];
+    perm.resize(q.D);
+    hipError_t e = hipMemcpy(perm.data(), q.perm, q.D * sizeof(uint32_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) { c->err = std::string("reading hybrid permutation: ") + hipGetErrorString(e); return bail(METADE_EDEVICE); }
+    std::vector<char> seen(q.D, 0);
+    for (uint32_t v : perm) {
+      if (v >= q.D || seen[v]) { c->err = "problem " + std::to_string(k) + ": perm is not a permutation of 0..D-1"; return bail(METADE_EINVAL); }
+      seen[v] = 1;
+    }
+  }
+  if ((st = dalloc(c, &c->tab, pl.tab_bytes)) != METADE_OK) return bail(st);
+  if ((st = dalloc(c, &c->runs_d, c->n_runs)) != METADE_OK) return bail(st);
+  if ((st = dalloc(c, &c->probs_d, c->probs_h.size())) != METADE_OK) return bail(st);
+  if ((st = dalloc(c, &c->theta_d, (size_t)c->n_runs * 6)) != METADE_OK) return bail(st);
+  if ((st = dalloc(c, &c->pend_d, c->pend_floats)) != METADE_OK) return bail(st);
+  if ((st = dalloc(c, &c->Xo, (size_t)c->n_runs * 6)) != METADE_OK) return bail(st);
+  if ((st = dalloc(c, &c->Uo, (size_t)c->n_runs * 6)) != METADE_OK) return bail(st);
+  if ((st = dalloc(c, &c->yo, c->n_runs)) != METADE_OK) return bail(st);
+  if ((st = dalloc(c, &c->yt, c->n_runs)) != METADE_OK) return bail(st);
+  if ((st = dalloc(c, &c->bxo, c->bx_n)) != METADE_OK) return bail(st);
+  if ((st = dalloc(c, &c->bidx, 4)) != METADE_OK) return bail(st);
+  if ((st = dalloc(c, &c->counters_d, 1)) != METADE_OK) return bail(st);
+  if ((st = dalloc(c, &c->lane_list_d, pl.lane_list.size())) != METADE_OK) return bail(st);
+  if ((st = dalloc(c, &c->mfma_list_d, pl.mfma_list.size())) != METADE_OK) return bail(st);
+  if ((st = dalloc(c, &c->ctrl_list_d, pl.ctrl_list.size())) != METADE_OK) return bail(st);
+  if (c->n_ctrl) {
+    if ((st = dalloc(c, &c->order_d, c->fit_n)) != METADE_OK) return bail(st);
+    if ((st = dalloc(c, &c->cfu_d, c->fit_n)) != METADE_OK) return bail(st);
+    if ((st = dalloc(c, &c->cacc_d, c->fit_n)) != METADE_OK) return bail(st);
+  }
+  {
+    hipError_t e5 = hipMemset(c->counters_d, 0, sizeof(unsigned long long));
+    if (e5 == hipSuccess && !pl.lane_list.empty())
+      e5 = hipMemcpy(c->lane_list_d, pl.lane_list.data(), pl.lane_list.size() * 4, hipMemcpyHostToDevice);
+    if (e5 == hipSuccess && !pl.mfma_list.empty())
+      e5 = hipMemcpy(c->mfma_list_d, pl.mfma_list.data(), pl.mfma_list.size() * 4, hipMemcpyHostToDevice);
+    if (e5 == hipSuccess && !pl.ctrl_list.empty())
+      e5 = hipMemcpy(c->ctrl_list_d, pl.ctrl_list.data(), pl.ctrl_list.size() * 4, hipMemcpyHostToDevice);
+    if (e5 != hipSuccess) { c->err = std::string("run lists: ") + hipGetErrorString(e5); return bail(METADE_EDEVICE); }
+  }
+  for (size_t k = 0; k < c->probs_h.size(); ++k) {
+    // per-output element tables: elliptic weights cond^(idx/(n-1)) and, for
+    // the hybrid, the block each rotated output falls in after permutation
+    const ProbDev &p = c->probs_h[k];
+    const metade_problem &q = cfg->problems[k];
+    if (p.kind == mde::FN_LQR_MLP) {
+      // plant and initial states, copied so that the context does not depend on them
+      unsigned char *t = c->tab;
+      hipError_t e6 = hipMemcpy(t + p.A_off, q.A, (size_t)p.obs * p.obs * sizeof(float), hipMemcpyDeviceToDevice);
+      if (e6 == hipSuccess) e6 = hipMemcpy(t + p.B_off, q.B, (size_t)p.obs * p.act * sizeof(float), hipMemcpyDeviceToDevice);
+      if (e6 == hipSuccess) e6 = hipMemcpy(t + p.x0_off, q.x0, (size_t)p.nroll * p.obs * sizeof(float), hipMemcpyDeviceToDevice);
+      if (e6 != hipSuccess) { c->err = std::string("control tables: ") + hipGetErrorString(e6); return bail(METADE_EDEVICE); }
+      continue;
+    }
+    const double cond = q.cond > 0 ? (double)q.cond : 1e6;
+    std::vector<float> ew(p.D, 0.0f);
+    std::vector<double> ew64(p.D, 0.0);
+    std::vector<uint32_t> ek(p.D, 0);
+    if (p.kind == mde::FN_ELLIPTIC) {
+      for (uint32_t j = 0; j < p.D; ++j) {
+        ew64[j] = p.D > 1 ? std::pow(cond, (double)j / (double)(p.D - 1)) : 1.0;
+        ew[j] = (float)ew64[j];
+      }
+    } else if (p.kind == mde::FN_HYBRID) {
+      const uint32_t n1 = q.split[0], n2 = q.split[1], n3 = q.split[2];
+      for (uint32_t pos = 0; pos < p.D; ++pos) {
+        const uint32_t j = perms[k][pos];
+        if (pos < n1) {
+          ek[j] = 0;
+        } else if (pos < n1 + n2) {
+          ek[j] = 1;
+        } else {
+          ek[j] = 2;
+          const uint32_t idx = pos - n1 - n2;
+          ew64[j] = n3 > 1 ? std::pow(cond, (double)idx / (double)(n3 - 1)) : 1.0;
+          ew[j] = (float)ew64[j];
+        }
+      }
+    }
+    unsigned char *t = c->tab;
+    hipError_t e4 = hipMemcpy(t + p.ew_off, ew.data(), p.D * sizeof(float), hipMemcpyHostToDevice);
+    if (e4 == hipSuccess) e4 = hipMemcpy(t + p.ew64_off, ew64.data(), p.D * sizeof(double), hipMemcpyHostToDevice);
+    if (e4 == hipSuccess) e4 = hipMemcpy(t + p.ek_off, ek.data(), p.D * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e4 == hipSuccess) e4 = hipMemcpy(t + p.o_off, q.o, p.D * sizeof(float), hipMemcpyDeviceToDevice);
+    if (e4 == hipSuccess)
+      e4 = mde::launch_rot_t64(q.R, reinterpret_cast<double *>(t + p.r64t_off), p.D, c->stream);
+    if (e4 != hipSuccess) { c->err = std::string("problem tables: ") + hipGetErrorString(e4); return bail(METADE_EDEVICE); }
+  }
+  hipError_t e = mde::set_lds_limits();
+  if (e != hipSuccess) { c->err = std::string("set_lds_limits: ") + hipGetErrorString(e); return bail(METADE_EDEVICE); }
+  e = hipMemcpyAsync(c->runs_d, c->runs_h.data(), c->n_runs * sizeof(RunDev), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->probs_d, c->probs_h.data(), c->probs_h.size() * sizeof(ProbDev), hipMemcpyHostToDevice, c->stream);
+  if (e != hipSuccess) { c->err = std::string("table upload: ") + hipGetErrorString(e); return bail(METADE_EDEVICE); }
+  std::vector<float> th((size_t)c->n_runs * 6);
+  for (uint32_t r = 0; r < c->n_runs; ++r) {
+    const float d[6] = {0.5f, 0.9f, 1.0f, 1.0f, 1.0f, 1.0f};
+    std::memcpy(&th[(size_t)r * 6], d, sizeof(d));
+  }
+  e = hipMemcpyAsync(c->theta_d, th.data(), th.size() * sizeof(float), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) { c->err = std::string("theta upload: ") + hipGetErrorString(e); return bail(METADE_EDEVICE); }
+  if ((st = reinit(c)) != METADE_OK) return bail(st);
+  if ((st = finalize(c)) != METADE_OK) return bail(st);
+  *out = c;
+  return METADE_OK;
+}
+
+metade_status metade_reset(metade_ctx *c) {
+  if (!c) return fail(nullptr, METADE_EINVAL, "ctx is NULL");
+  TRY(reinit(c));
+  return finalize(c);
+}
+
+metade_status metade_set_theta(metade_ctx *c, const float *theta) {
+  if (!c || !theta) return fail(c, METADE_EINVAL, "ctx and theta are required");
+  HIP_TRY(c, hipMemcpyAsync(c->theta_d, theta, (size_t)c->n_runs * 6 * sizeof(float),
+                            hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, mde::launch_decode(c->runs_d, c->theta_d, c->n_runs, c->n_cs, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return METADE_OK;
+}
+
+metade_status metade_inner_step(metade_ctx *c, uint32_t n) {
+  if (!c) return fail(nullptr, METADE_EINVAL, "ctx is NULL");
+  TRY(run_generations(c, n, mde::TraceArgs{nullptr, nullptr, nullptr}));
+  return finalize(c);
+}
+
+metade_status metade_trace_sizes(metade_ctx *c, size_t *u_bytes, size_t *fu_bytes,
+                                 size_t *desc_bytes) {
+  if (!c) return fail(nullptr, METADE_EINVAL, "ctx is NULL");
+  if (u_bytes) *u_bytes = c->pop_floats * sizeof(float);
+  if (fu_bytes) *fu_bytes = c->fit_n * sizeof(float);
+  if (desc_bytes) *desc_bytes = c->fit_n * 16 * sizeof(int32_t);
+  return METADE_OK;
+}
+
+metade_status metade_inner_step_trace(metade_ctx *c, float *u, float *fu, int32_t *desc) {
+  if (!c || !u || !fu || !desc) return fail(c, METADE_EINVAL, "ctx and all trace buffers are required");
+  if (c->precision != METADE_FP32)
+    return fail(c, METADE_EINVAL, "tracing is available for METADE_FP32 contexts only");
+  TRY(run_generations(c, 1, mde::TraceArgs{u, fu, desc}));
+  return finalize(c);
+}
+
+metade_status metade_outer_reset(metade_ctx *c) {
+  if (!c) return fail(nullptr, METADE_EINVAL, "ctx is NULL");
+  if (c->n_runs < 4) return fail(c, METADE_EINVAL, "the evolver needs at least 4 individuals");
+  HIP_TRY(c, mde::launch_outer_init(c->Xo, c->yo, c->n_runs, c->runs_h[0].stream,
+                                    (uint32_t)(c->seed & 0xFFFFFFFFu), (uint32_t)(c->seed >> 32),
+                                    c->n_cs, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->bxo, 0, c->bx_n * sizeof(float), c->stream));
+  c->outer_gen = 0;
+  c->outer_ready = true;
+  return METADE_OK;
+}
+
+metade_status metade_outer_step(metade_ctx *c, uint32_t G_inner, uint32_t power_up) {
+  if (!c) return fail(nullptr, METADE_EINVAL, "ctx is NULL");
+  if (!c->outer_ready) return fail(c, METADE_ESTATE, "metade_outer_reset must come first");
+  const uint32_t G = G_inner * (power_up > 1 ? power_up : 1);
+  HIP_TRY(c, mde::launch_outer_trial(c->Xo, c->Uo, c->runs_d, c->n_runs, c->outer_gen,
+                                     c->runs_h[0].stream, (uint32_t)(c->seed & 0xFFFFFFFFu),
+                                     (uint32_t)(c->seed >> 32), c->n_cs, c->stream));
+  TRY(reinit(c));
+  TRY(run_generations(c, G, mde::TraceArgs{nullptr, nullptr, nullptr}));
+  TRY(finalize(c));
+  HIP_TRY(c, mde::launch_outer_select(c->Xo, c->yo, c->Uo, c->best_y, c->yt, c->bxo, c->best_x,
+                                      c->runs_d, c->n_runs, c->stream));
+  ++c->outer_gen;
+  return METADE_OK;
+}
+
+metade_status metade_get_outer(metade_ctx *c, float *X, double *y, float *U, double *y_trial) {
+  if (!c) return fail(nullptr, METADE_EINVAL, "ctx is NULL");
+  if (!c->outer_ready) return fail(c, METADE_ESTATE, "evolver not initialised");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const size_t n6 = (size_t)c->n_runs * 6;
+  if (X) HIP_TRY(c, hipMemcpy(X, c->Xo, n6 * sizeof(float), hipMemcpyDeviceToHost));
+  if (y) HIP_TRY(c, hipMemcpy(y, c->yo, c->n_runs * sizeof(double), hipMemcpyDeviceToHost));
+  if (U) HIP_TRY(c, hipMemcpy(U, c->Uo, n6 * sizeof(float), hipMemcpyDeviceToHost));
+  if (y_trial) HIP_TRY(c, hipMemcpy(y_trial, c->yt, c->n_runs * sizeof(double), hipMemcpyDeviceToHost));
+  return METADE_OK;
+}
+
+metade_status metade_set_outer(metade_ctx *c, const float *X, const double *y, uint32_t gen) {
+  if (!c || !X || !y) return fail(c, METADE_EINVAL, "ctx, X and y are required");
+  HIP_TRY(c, hipMemcpyAsync(c->Xo, X, (size_t)c->n_runs * 6 * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->yo, y, c->n_runs * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->outer_gen = gen;
+  c->outer_ready = true;
+  return METADE_OK;
+}
+
+metade_status metade_run(metade_ctx *c, uint32_t outer_gens, uint32_t G_inner, uint32_t power_up,
+                         double *best_y, float *best_theta, float *best_x) {
+  if (!c) return fail(nullptr, METADE_EINVAL, "ctx is NULL");
+  if (outer_gens == 0) return fail(c, METADE_EINVAL, "outer_gens must be >= 1");
+  TRY(metade_outer_reset(c));
+  for (uint32_t g = 0; g < outer_gens; ++g)
+    TRY(metade_outer_step(c, G_inner, g + 1 == outer_gens ? power_up : 1));
+  HIP_TRY(c, mde::launch_outer_best(c->yo, c->n_runs, c->bidx, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  int32_t b = 0;
+  HIP_TRY(c, hipMemcpy(&b, c->bidx, sizeof(b), hipMemcpyDeviceToHost));
+  if (best_y) HIP_TRY(c, hipMemcpy(best_y, c->yo + b, sizeof(double), hipMemcpyDeviceToHost));
+  if (best_theta) HIP_TRY(c, hipMemcpy(best_theta, c->Xo + (size_t)b * 6, 6 * sizeof(float), hipMemcpyDeviceToHost));
+  if (best_x)
+    HIP_TRY(c, hipMemcpy(best_x, c->bxo + c->runs_h[b].bx_off, c->runs_h[b].D * sizeof(float),
+                         hipMemcpyDeviceToHost));
+  return METADE_OK;
+}
+
+metade_status metade_get_best(metade_ctx *c, double *y) {
+  if (!c || !y) return fail(c, METADE_EINVAL, "ctx and y are required");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  HIP_TRY(c, hipMemcpy(y, c->best_y, c->n_runs * sizeof(double), hipMemcpyDeviceToHost));
+  return METADE_OK;
+}
+
+namespace {
+constexpr uint32_t STATE_MAGIC = 0x3145444Du;  // "MDE1"
+struct StateHeader {
+  uint32_t magic, n_runs, gen, outer_gen, outer_ready, pad;
+  uint64_t pop_floats, fit_n, bx_n;
+};
+}  // namespace
+
+metade_status metade_get_state(metade_ctx *c, void *blob, size_t *bytes) {
+  if (!c || !bytes) return fail(c, METADE_EINVAL, "ctx and bytes are required");
+  const size_t n = c->n_runs;
+  const size_t need = sizeof(StateHeader) + c->pop_floats * 4 + c->fit_n * 4 + n * 6 * 4 +
+                      n * sizeof(RunDev) + n * 8 + c->bx_n * 4 + n * 6 * 4 * 2 + n * 8 * 2 +
+                      c->bx_n * 4;
+  if (!blob) { *bytes = need; return METADE_OK; }
+  if (*bytes < need) return fail(c, METADE_EINVAL, "state buffer too small");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  unsigned char *p = (unsigned char *)blob;
+  StateHeader h{STATE_MAGIC, c->n_runs, c->gen, c->outer_gen, c->outer_ready ? 1u : 0u, 0,
+                c->pop_floats, c->fit_n, c->bx_n};
+  std::memcpy(p, &h, sizeof(h));
+  p += sizeof(h);
+  auto d2h = [&](const void *src, size_t nb) -> hipError_t {
+    hipError_t e = nb ? hipMemcpy(p, src, nb, hipMemcpyDeviceToHost) : hipSuccess;
+    p += nb;
+    return e;
+  };
+  HIP_TRY(c, d2h(c->pop, c->pop_floats * 4));
+  HIP_TRY(c, d2h(c->fit, c->fit_n * 4));
+  HIP_TRY(c, d2h(c->theta_d, n * 6 * 4));
+  HIP_TRY(c, d2h(c->runs_d, n * sizeof(RunDev)));
+  HIP_TRY(c, d2h(c->best_y, n * 8));
+  HIP_TRY(c, d2h(c->best_x, c->bx_n * 4));
+  HIP_TRY(c, d2h(c->Xo, n * 6 * 4));
+  HIP_TRY(c, d2h(c->Uo, n * 6 * 4));
+  HIP_TRY(c, d2h(c->yo, n * 8));
+  HIP_TRY(c, d2h(c->yt, n * 8));
+  HIP_TRY(c, d2h(c->bxo, c->bx_n * 4));
+  *bytes = need;
+  return METADE_OK;
+}
+
+metade_status metade_set_state(metade_ctx *c, const void *blob, size_t bytes) {
+  if (!c || !blob) return fail(c, METADE_EINVAL, "ctx and blob are required");
+  size_t need = 0;
+  TRY(metade_get_state(c, nullptr, &need));
+  if (bytes != need) return fail(c, METADE_EINVAL, "state size does not match this context");
+  const unsigned char *p = (const unsigned char *)blob;
+  StateHeader h;
+  std::memcpy(&h, p, sizeof(h));
+  if (h.magic != STATE_MAGIC || h.n_runs != c->n_runs || h.pop_floats != c->pop_floats ||
+      h.fit_n != c->fit_n || h.bx_n != c->bx_n)
+    return fail(c, METADE_EINVAL, "state blob does not belong to this configuration");
+  p += sizeof(h);
+  const size_t n = c->n_runs;
+  // run layout fields must agree; only the decoded theta is taken from the blob
+  std::vector<RunDev> runs(n);
+  std::memcpy(runs.data(), p + c->pop_floats * 4 + c->fit_n * 4 + n * 6 * 4, n * sizeof(RunDev));
+  for (size_t r = 0; r < n; ++r) {
+    const RunDev &a = runs[r], &b = c->runs_h[r];
+    if (a.N != b.N || a.D != b.D || a.pop_off != b.pop_off || a.fit_off != b.fit_off ||
+        a.stream != b.stream || a.prob != b.prob)
+      return fail(c, METADE_EINVAL, "state blob run table differs from this configuration");
+  }
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  auto h2d = [&](void *dst, size_t nb) -> hipError_t {
+    hipError_t e = nb ? hipMemcpy(dst, p, nb, hipMemcpyHostToDevice) : hipSuccess;
+    p += nb;
+    return e;
+  };
+  HIP_TRY(c, h2d(c->pop, c->pop_floats * 4));
+  HIP_TRY(c, h2d(c->fit, c->fit_n * 4));
+  HIP_TRY(c, h2d(c->theta_d, n * 6 * 4));
+  HIP_TRY(c, h2d(c->runs_d, n * sizeof(RunDev)));
+  HIP_TRY(c, h2d(c->best_y, n * 8));
+  HIP_TRY(c, h2d(c->best_x, c->bx_n * 4));
+  HIP_TRY(c, h2d(c->Xo, n * 6 * 4));
+  HIP_TRY(c, h2d(c->Uo, n * 6 * 4));
+  HIP_TRY(c, h2d(c->yo, n * 8));
+  HIP_TRY(c, h2d(c->yt, n * 8));
+  HIP_TRY(c, h2d(c->bxo, c->bx_n * 4));
+  c->gen = h.gen;
+  c->outer_gen = h.outer_gen;
+  c->outer_ready = h.outer_ready != 0;
+  return METADE_OK;
+}
+
+metade_status metade_kernel_timing(metade_ctx *c, int enable) {
+  if (!c) return fail(nullptr, METADE_EINVAL, "ctx is NULL");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (EventPair &ev : c->events) {
+    (void)hipEventDestroy(ev.a);
+    (void)hipEventDestroy(ev.b);
+  }
+  c->events.clear();
+  c->timing = enable != 0;
+  return METADE_OK;
+}
+
+metade_status metade_kernel_time(metade_ctx *c, double *ms, uint64_t *launches) {
+  if (!c) return fail(nullptr, METADE_EINVAL, "ctx is NULL");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  double total = 0.0;
+  for (EventPair &ev : c->events) {
+    float t = 0.0f;
+    HIP_TRY(c, hipEventElapsedTime(&t, ev.a, ev.b));
+    total += t;
+  }
+  if (ms) *ms = total;
+  if (launches) *launches = c->events.size();
+  return METADE_OK;
+}
+
+metade_status metade_get_counters(metade_ctx *c, uint64_t *trials, uint64_t *refined) {
+  if (!c) return fail(nullptr, METADE_EINVAL, "ctx is NULL");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (trials) *trials = c->trials;
+  if (refined) {
+    unsigned long long r = 0;
+    HIP_TRY(c, hipMemcpy(&r, c->counters_d, sizeof(r), hipMemcpyDeviceToHost));
+    *refined = r;
+  }
+  return METADE_OK;
+}
+
+const char *metade_last_error(const metade_ctx *c) {
+  return c ? c->err.c_str() : g_init_error.c_str();
+}
+
+void metade_destroy(metade_ctx *c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  for (EventPair &ev : c->events) {
+    (void)hipEventDestroy(ev.a);
+    (void)hipEventDestroy(ev.b);
+  }
+  (void)hipFree(c->runs_d);
+  (void)hipFree(c->probs_d);
+  (void)hipFree(c->theta_d);
+  (void)hipFree(c->pend_d);
+  (void)hipFree(c->Xo);
+  (void)hipFree(c->Uo);
+  (void)hipFree(c->yo);
+  (void)hipFree(c->yt);
+  (void)hipFree(c->bxo);
+  (void)hipFree(c->bidx);
+  (void)hipFree(c->tab);
+  (void)hipFree(c->counters_d);
+  (void)hipFree(c->lane_list_d);
+  (void)hipFree(c->mfma_list_d);
+  (void)hipFree(c->ctrl_list_d);
+  (void)hipFree(c->order_d);
+  (void)hipFree(c->cfu_d);
+  (void)hipFree(c->cacc_d);
+  delete c;
+}
+
+}  // extern "C"

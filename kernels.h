@@ -1,0 +1,67 @@
+// Host-side launch interface of the gfx950 kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device.h"
+
+namespace mde {
+
+struct TraceArgs {
+  float *u;        // [sum N*D] trial vectors, or null
+  float *fu;       // [sum N] trial fitness, or null
+  int32_t *desc;   // [sum N][16] descriptors, or null
+};
+
+struct LaunchArgs {
+  const RunDev *runs;
+  const ProbDev *probs;
+  const unsigned char *tab;
+  float *pop;
+  float *fit;
+  float *pending;
+  uint32_t n_runs;
+  uint32_t lds_bytes;
+  uint32_t init_lds_bytes;
+  uint32_t mfma_lds_bytes;
+  uint32_t k0, k1;
+  hipStream_t stream;
+};
+
+// Control runs (one wavefront per individual, several launches per generation).
+struct CtrlArgs {
+  const uint32_t *list;   // run ids
+  uint32_t n, max_n;      // number of control runs, their largest N
+  uint32_t *order;        // [sum N] top-p lists at the runs' fitness offsets
+  float *fu;              // [sum N] trial fitness
+  uint32_t *acc;          // [sum N] selection decisions
+};
+
+hipError_t set_lds_limits();
+hipError_t launch_rot_t64(const float *R, double *Rt, uint32_t D, hipStream_t s);
+hipError_t launch_init(const LaunchArgs &a, double lb, double ub);
+hipError_t launch_generations(const LaunchArgs &a, const uint32_t *list, uint32_t n,
+                              uint32_t g0, uint32_t n_gens, float lb, float ub, TraceArgs tr);
+hipError_t set_lds_limits_mfma();
+hipError_t launch_generations_mfma(const LaunchArgs &a, const uint32_t *list, uint32_t n,
+                                   bool bf16, uint32_t g0, uint32_t n_gens, float lb, float ub,
+                                   unsigned long long *counters, TraceArgs tr);
+hipError_t launch_ctrl_init(const LaunchArgs &a, const CtrlArgs &c, double lb, double ub);
+hipError_t launch_ctrl_generations(const LaunchArgs &a, const CtrlArgs &c, uint32_t g0,
+                                   uint32_t n_gens, float lb, float ub, TraceArgs tr);
+hipError_t launch_ctrl_finalize(const LaunchArgs &a, const CtrlArgs &c, double *best_y,
+                                float *best_x);
+hipError_t launch_finalize(const LaunchArgs &a, double *best_y, float *best_x);
+hipError_t launch_decode(RunDev *runs, float *theta, uint32_t n, uint32_t n_cs, hipStream_t s);
+hipError_t launch_outer_init(float *X, double *y, uint32_t P, uint32_t stream, uint32_t k0,
+                             uint32_t k1, uint32_t n_cs, hipStream_t s);
+hipError_t launch_outer_trial(const float *X, float *U, RunDev *runs, uint32_t P, uint32_t g_o,
+                              uint32_t stream, uint32_t k0, uint32_t k1, uint32_t n_cs,
+                              hipStream_t s);
+hipError_t launch_outer_select(float *X, double *y, const float *U, const double *y_run,
+                               double *y_trial, float *bxo, const float *best_x,
+                               const RunDev *runs, uint32_t P, hipStream_t s);
+hipError_t launch_outer_best(const double *y, uint32_t P, int32_t *out, hipStream_t s);
+
+}  // namespace mde

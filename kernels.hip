@@ -1,0 +1,665 @@
+// HIP kernels of the MetaDE inner-DE path for gfx950.
+//
+// One workgroup owns one executor run for the whole launch: its population,
+// fitness, ranking and trial descriptors live in LDS, and the generation loop
+// of Alg. 2 runs inside the kernel (no grid-wide synchronisation).  Trials are
+// built and evaluated in chunks of C rows when the whole trial matrix does
+// not fit beside the population; accepted rows of earlier chunks then wait in
+// a global buffer until the synchronous commit at the end of the generation.
+#include "device.h"
+#include "gen_common.h"
+#include "kernels.h"
+
+namespace mde {
+__device__ unsigned long long g_prof[8 * 1024];
+
+// ---------------------------------------------------------------- fitness of one row, split by output
+
+// acc[q] = sum_k R[jc+q][k] (u_k - o_k) in float64 for q < J, from the
+// transposed rotation Rt[k][j]: the J coefficients of one k are contiguous
+// and wave-uniform, so they arrive by wide scalar loads and feed the FMAs as
+// scalar operands.  u_k = t[k*ts] is the lane's own trial.  Outputs past D
+// read the padding columns of Rt (zero) and are not used.
+template <int J, typename TP>
+__device__ __forceinline__ void rot_block(const double *__restrict__ Rt, uint32_t D, uint32_t Dr,
+                                          uint32_t jc, TP t, uint32_t ts,
+                                          const float *__restrict__ o, double (&acc)[J]) {
+#pragma unroll
+  for (int q = 0; q < J; ++q) acc[q] = 0.0;
+  const double *col = Rt + jc;
+  uint32_t k = 0;
+  for (; k + 8 <= D; k += 8) {
+    float tv[8];
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) tv[kk] = t[(k + kk) * ts];
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+      const double yk = (double)tv[kk] - (double)o[k + kk];
+      const double *c = col + (size_t)(k + kk) * Dr;
+#pragma unroll
+      for (int q = 0; q < J; ++q) acc[q] = fma(c[q], yk, acc[q]);
+    }
+  }
+  for (; k < D; ++k) {
+    const double yk = (double)t[k * ts] - (double)o[k];
+    const double *c = col + (size_t)k * Dr;
+#pragma unroll
+    for (int q = 0; q < J; ++q) acc[q] = fma(c[q], yk, acc[q]);
+  }
+}
+
+struct TermAcc {
+  double s0, s1;
+  float prevz;
+  bool have;
+};
+
+template <int J>
+__device__ __forceinline__ void consume(const unsigned char *tab, const ProbDev &p,
+                                        const double (&a)[J], uint32_t jc, uint32_t n,
+                                        uint32_t j1, TermAcc &ta) {
+#pragma unroll
+  for (int q = 0; q < J; ++q) {
+    if ((uint32_t)q < n) {
+      const float z = (float)a[q];
+      const uint32_t j = jc + q;
+      if (p.kind == FN_ROSENBROCK) {
+        if (ta.have && j - 1 < j1) ta.s0 += (double)h_rosenbrock<float>(ta.prevz, z);
+        ta.prevz = z;
+        ta.have = true;
+      } else {
+        float t0, t1;
+        elem_term<float>(tab, p, j, z, t0, t1);
+        ta.s0 += (double)t0;
+        ta.s1 += (double)t1;
+      }
+    }
+  }
+}
+
+// Sum of the element terms of outputs [j0, j1) of the row at t (gene stride
+// ts).  Plain path: z = R (u - o) accumulated in float64 -- y is exact, so a
+// small z_j that cancels between large products keeps its relative accuracy --
+// z rounded once to float32, element terms in float32, sums in float64.
+template <typename TP>
+__device__ __forceinline__ void eval_part(const unsigned char *__restrict__ tab, const ProbDev &p,
+                                          uint32_t D, uint32_t j0, uint32_t j1, TP t, uint32_t ts,
+                                          double &s0, double &s1) {
+  const double *Rt = tab_ptr<double>(tab, p.r64t_off);
+  const uint32_t Dr = rt_stride(D);
+  const float *o = tab_ptr<float>(tab, p.o_off);
+  TermAcc ta{0.0, 0.0, 0.0f, false};
+  const uint32_t jend = p.kind == FN_ROSENBROCK ? min(j1 + 1, D) : j1;
+  uint32_t jc = j0;
+  while (jc < jend) {
+    const uint32_t rem = jend - jc;
+#define MDE_BLOCK(JJ)                                        \
+  {                                                          \
+    double a[JJ];                                            \
+    rot_block<JJ>(Rt, D, Dr, jc, t, ts, o, a);               \
+    consume<JJ>(tab, p, a, jc, min(rem, (uint32_t)JJ), j1, ta); \
+    jc += JJ;                                                \
+  }
+    if (rem > 12) MDE_BLOCK(16)
+    else if (rem > 10) MDE_BLOCK(12)
+    else if (rem > 8) MDE_BLOCK(10)
+    else if (rem > 6) MDE_BLOCK(8)
+    else if (rem == 6) MDE_BLOCK(6)
+    else if (rem == 5) MDE_BLOCK(5)
+    else if (rem > 2) MDE_BLOCK(4)
+    else MDE_BLOCK(2)
+#undef MDE_BLOCK
+  }
+  s0 = ta.s0;
+  s1 = ta.s1;
+}
+
+// ---------------------------------------------------------------- init (Alg. 2 initialisation)
+
+__global__ __launch_bounds__(INIT_THREADS) void k_init(const RunDev *__restrict__ runs,
+                                                       const ProbDev *__restrict__ probs,
+                                                       const unsigned char *__restrict__ tab,
+                                                       float *__restrict__ pop,
+                                                       float *__restrict__ fit, uint32_t k0,
+                                                       uint32_t k1, double lb, double ub) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const RunDev run = runs[blockIdx.x];
+  if (run.kern == 2) return;  // control runs have their own initialisation kernel
+  const ProbDev p = probs[run.prob];
+  const uint32_t N = run.N, D = run.D, Dp = run.Dp, Q = Dp / 4;
+  const uint32_t Np = ((N + 63u) / 64u) * 64u, L = init_parts(Np);
+  float *pop_s = reinterpret_cast<float *>(smem);
+  double2 *Ps = reinterpret_cast<double2 *>(smem + al16(N * Dp * 4));
+  const uint32_t tid = threadIdx.x;
+  const uint32_t l = __builtin_amdgcn_readfirstlane(tid / Np);
+  const uint32_t i = tid - l * Np;
+  const bool act = l < L && i < N;
+
+  // x = lb + (ub - lb) u0, u0 = (w >> 8) 2^-24, in float64, rounded once.
+  for (uint32_t u = tid; u < N * Q; u += INIT_THREADS) {
+    const uint32_t r = u / Q, q = u - r * Q;
+    const uint4 w = philox(q, r, INIT_PHASE, run.stream, k0, k1);
+    float4 x;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const uint32_t j = 4 * q + t;
+      const double u0 = (double)(word_of(w, t) >> 8) * 0x1p-24;
+      set_comp(x, t, j < D ? (float)(lb + (ub - lb) * u0) : 0.0f);
+    }
+    st4(pop_s, r * Dp + 4 * q, x);
+  }
+  __syncthreads();
+  if (act) {
+    double s0, s1;
+    eval_part(tab, p, D, l * D / L, (l + 1) * D / L, pop_s + i * Dp, 1u, s0, s1);
+    Ps[l * Np + i] = make_double2(s0, s1);
+  }
+  __syncthreads();
+  if (act && l == 0) {
+    double s0 = 0.0, s1 = 0.0;
+    for (uint32_t ll = 0; ll < L; ++ll) {
+      const double2 v = Ps[ll * Np + i];
+      s0 += v.x;
+      s1 += v.y;
+    }
+    fit[run.fit_off + i] = finish_f32(p, s0, s1);
+  }
+  for (uint32_t u = tid; u < N * D; u += INIT_THREADS) {
+    const uint32_t r = u / D, j = u - r * D;
+    pop[run.pop_off + u] = pop_s[r * Dp + j];
+  }
+}
+
+// ---------------------------------------------------------------- generations (Alg. 2 main loop)
+//
+// Consumer lane i of part l works on trial i: it builds genes 4q..4q+3 with
+// q = l mod L and the fitness outputs [l D / L, (l+1) D / L); the parts'
+// partial sums meet in LDS.  Per generation (five barriers):
+//   S0 partial ranks | S1 top-p list | S2 mutation + crossover |
+//   S3 fitness (producers: Philox words of g+1) | S4 selection + commit
+//   (producers: draws of g+1).
+
+template <bool TLDS, bool TRACE>
+__device__ __forceinline__ void gen_body(unsigned char *smem, const RunDev &run, const ProbDev &p,
+                                         const unsigned char *__restrict__ tab,
+                                         float *__restrict__ pop, float *__restrict__ fit,
+                                         uint32_t g0, uint32_t n_gens, uint32_t k0, uint32_t k1,
+                                         float lb, float ub, float *__restrict__ pending,
+                                         const TraceArgs &tr) {
+  const uint32_t N = run.N, D = run.D, Dp = run.Dp, Q = Dp / 4, kp = run.kp, L = run.L,
+                 Np = run.Np;
+  const Lds lay = lds_layout(N, Dp, L, Np, TLDS);
+  float *pop_s = reinterpret_cast<float *>(smem + lay.pop);
+  uint64_t *key_s = reinterpret_cast<uint64_t *>(smem + lay.key);
+  float *fit_s = reinterpret_cast<float *>(smem + lay.fit);
+  uint32_t *topk = reinterpret_cast<uint32_t *>(smem + lay.topk);
+  double2 *Ps = reinterpret_cast<double2 *>(smem + lay.ps);
+  uint32_t *rk = reinterpret_cast<uint32_t *>(smem + lay.rk);
+  uint32_t *wb = reinterpret_cast<uint32_t *>(smem + lay.wb);
+  uint8_t *msk = reinterpret_cast<uint8_t *>(smem + lay.msk);
+  uint4 *dsc = reinterpret_cast<uint4 *>(smem + lay.dsc);
+  float *T = TLDS ? reinterpret_cast<float *>(smem + lay.T) : pending + run.pend_off;
+  const uint32_t ts = TLDS ? Np : N;
+  const uint32_t tid = threadIdx.x;
+  const bool producer = tid >= GEN_CONSUMERS;  // whole waves
+  const uint32_t ptid = tid - GEN_CONSUMERS;
+  const uint32_t l = __builtin_amdgcn_readfirstlane(tid / Np);
+  const uint32_t i = tid - l * Np;
+  const bool act = !producer && l < L && i < N;
+  const uint32_t j0 = l * D / L, j1 = (l + 1) * D / L;
+  const uint32_t kr0 = l * N / L, kr1 = (l + 1) * N / L;
+  const int use_rand = (run.bl == RAND || run.br == RAND) ? 1 : 0;
+
+  for (uint32_t u = tid; u < N * Dp; u += GEN_THREADS) {
+    const uint32_t r = u / Dp, j = u - r * Dp;
+    pop_s[u] = j < D ? pop[run.pop_off + (size_t)r * D + j] : 0.0f;
+  }
+  for (uint32_t r = tid; r < N; r += GEN_THREADS) {
+    const float f = fit[run.fit_off + r];
+    fit_s[r] = f;
+    key_s[r] = mkkey(f, r);
+  }
+  // draws of the first generation
+  if (producer) produce_words(ptid, GEN_CONSUMERS, run, N, Q, g0, k0, k1, wb, msk);
+  __syncthreads();
+  if (producer) produce_desc(ptid, GEN_CONSUMERS, run, N, D, kp, g0, k0, k1, wb, dsc);
+
+  unsigned long long tacc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  unsigned long long tprev = clock64();
+  auto stamp = [&](int k) { const unsigned long long t = clock64(); tacc[k] += t - tprev; tprev = t; };
+  for (uint32_t gg = 0; gg < n_gens; ++gg) {
+    const uint32_t g = g0 + gg;
+    stamp(4);
+    __syncthreads();
+    stamp(5);
+    // S0: rank of individual i among this part's slice of the keys
+    if (act) {
+      const uint64_t ki = key_s[i];
+      uint32_t cnt = 0, j = kr0;
+      for (; j + 8 <= kr1; j += 8) {
+        uint64_t kv[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) kv[q] = key_s[j + q];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) cnt += kv[q] < ki ? 1u : 0u;
+      }
+      for (; j < kr1; ++j) cnt += key_s[j] < ki ? 1u : 0u;
+      rk[l * Np + i] = cnt;
+    }
+    stamp(0);
+    __syncthreads();
+    stamp(5);
+    // S1: the top-p list (first is the best)
+    float fx = 0.0f;
+    if (act) {
+      fx = fit_s[i];
+      if (l == 0) {
+        uint32_t rank = 0;
+        for (uint32_t ll = 0; ll < L; ++ll) rank += rk[ll * Np + i];
+        if (rank < kp) topk[rank] = i;
+      }
+    }
+    stamp(1);
+    __syncthreads();
+    stamp(5);
+    // S2: mutation, crossover, clip -> this part's genes of trial i
+    if (act) {
+      const uint4 d = dsc[i];
+      const uint32_t r0 = byte_of(d.z, 0), pb = byte_of(d.z, 1);
+      const uint32_t ibest = topk[0], ipb = topk[pb];
+      const uint32_t ibl = run.bl == RAND ? r0 : (run.bl == BEST ? ibest : (run.bl == PBEST ? ipb : i));
+      const uint32_t ibr = run.br == RAND ? r0 : (run.br == BEST ? ibest : (run.br == PBEST ? ipb : i));
+      if (TRACE && l == 0) {
+        int32_t *o = tr.desc + (size_t)(run.fit_off + i) * 16;
+        o[0] = (int32_t)ibl;
+        o[1] = (int32_t)ibr;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const uint32_t word = k < 4 ? d.x : d.y;
+          o[2 + k] = (k / 2) < run.dn ? (int32_t)byte_of(word, k & 3) : -1;
+        }
+        o[10] = (int32_t)byte_of(d.z, 2);
+        o[11] = run.cs == EXP ? (int32_t)(d.z >> 24) : -1;
+        o[12] = (int32_t)pb;
+        o[13] = use_rand ? (int32_t)r0 : -1;
+        o[14] = run.cs == ARITH ? (int32_t)d.w : -1;
+        o[15] = 0;
+      }
+      for (uint32_t q = l; q < Q; q += L) {
+        const uint32_t nib = run.cs == BIN ? msk[i * Q + q] : 0u;
+        const float4 uu = trial_quad(pop_s, Dp, D, i, q, ibl, ibr, d, nib, run, lb, ub);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const uint32_t j = 4 * q + t;
+          if (j < D) {
+            T[j * ts + i] = comp(uu, t);
+            if (TRACE) tr.u[run.pop_off + (size_t)i * D + j] = comp(uu, t);
+          }
+        }
+      }
+    }
+    stamp(2);
+    __syncthreads();
+    stamp(5);
+    // S3: this part's share of the fitness; producers draw generation g+1
+    if (act) {
+      double s0, s1;
+      eval_part(tab, p, D, j0, j1, T + i, ts, s0, s1);
+      Ps[l * Np + i] = make_double2(s0, s1);
+    }
+    if (producer) produce_words(ptid, GEN_CONSUMERS, run, N, Q, g + 1, k0, k1, wb, msk);
+    stamp(3);
+    __syncthreads();
+    stamp(5);
+    // S4: greedy selection (every part takes the same decision) and commit
+    if (act) {
+      double s0 = 0.0, s1 = 0.0;
+      for (uint32_t ll = 0; ll < L; ++ll) {
+        const double2 v = Ps[ll * Np + i];
+        s0 += v.x;
+        s1 += v.y;
+      }
+      const float f = finish_f32(p, s0, s1);
+      const bool a = accept_trial(f, fx);
+      if (a) {
+        for (uint32_t q = l; q < Q; q += L) {
+          float4 x;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const uint32_t j = 4 * q + t;
+            set_comp(x, t, j < D ? T[j * ts + i] : 0.0f);
+          }
+          st4(pop_s, i * Dp + 4 * q, x);
+        }
+      }
+      if (l == 0) {
+        if (a) {
+          fit_s[i] = f;
+          key_s[i] = mkkey(f, i);
+        }
+        if (TRACE) {
+          tr.fu[run.fit_off + i] = f;
+          tr.desc[(size_t)(run.fit_off + i) * 16 + 15] = a ? 1 : 0;
+        }
+      }
+    }
+    if (producer) produce_desc(ptid, GEN_CONSUMERS, run, N, D, kp, g + 1, k0, k1, wb, dsc);
+  }
+  stamp(4);
+  if (threadIdx.x == 0 || threadIdx.x == 512) {
+    const int w = threadIdx.x / 512;
+    for (int k = 0; k < 6; ++k) g_prof[(blockIdx.x * 2 + w) * 8 + k] = tacc[k];
+    g_prof[(blockIdx.x * 2 + w) * 8 + 6] = n_gens;
+  }
+  __syncthreads();
+  for (uint32_t u = tid; u < N * D; u += GEN_THREADS) {
+    const uint32_t r = u / D, j = u - r * D;
+    pop[run.pop_off + u] = pop_s[r * Dp + j];
+  }
+  for (uint32_t r = tid; r < N; r += GEN_THREADS) fit[run.fit_off + r] = fit_s[r];
+}
+
+template <bool TRACE>
+__global__ __launch_bounds__(GEN_THREADS) void k_generations(
+    const RunDev *__restrict__ runs, const uint32_t *__restrict__ list,
+    const ProbDev *__restrict__ probs, const unsigned char *__restrict__ tab,
+    float *__restrict__ pop, float *__restrict__ fit, uint32_t g0, uint32_t n_gens, uint32_t k0,
+    uint32_t k1, float lb, float ub, float *__restrict__ pending, TraceArgs tr) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const RunDev run = runs[list[blockIdx.x]];
+  const ProbDev p = probs[run.prob];
+  if (run.t_lds)
+    gen_body<true, TRACE>(smem, run, p, tab, pop, fit, g0, n_gens, k0, k1, lb, ub, pending, tr);
+  else
+    gen_body<false, TRACE>(smem, run, p, tab, pop, fit, g0, n_gens, k0, k1, lb, ub, pending, tr);
+}
+
+// ---------------------------------------------------------------- best record in float64
+
+constexpr int FIN_BLOCK = 128;
+
+__global__ __launch_bounds__(FIN_BLOCK) void k_finalize(const RunDev *__restrict__ runs,
+                                                        const ProbDev *__restrict__ probs,
+                                                        const unsigned char *__restrict__ tab,
+                                                        const float *__restrict__ pop,
+                                                        const float *__restrict__ fit,
+                                                        double *__restrict__ best_y,
+                                                        float *__restrict__ best_x) {
+  __shared__ uint32_t sk[FIN_BLOCK], si[FIN_BLOCK];
+  __shared__ double z[MAX_D], t0s[MAX_D], t1s[MAX_D];
+  const RunDev run = runs[blockIdx.x];
+  if (run.kern == 2) return;  // control runs have their own record kernel
+  const ProbDev p = probs[run.prob];
+  const uint32_t N = run.N, D = run.D, tid = threadIdx.x;
+  uint32_t bk = 0xFFFFFFFFu, bi = 0xFFFFFFFFu;
+  for (uint32_t i = tid; i < N; i += FIN_BLOCK) {
+    const uint32_t k = okey(fit[run.fit_off + i]);
+    if (k < bk || (k == bk && i < bi)) { bk = k; bi = i; }
+  }
+  sk[tid] = bk;
+  si[tid] = bi;
+  __syncthreads();
+  for (int s = FIN_BLOCK / 2; s > 0; s >>= 1) {
+    if (tid < (uint32_t)s) {
+      const uint32_t k2 = sk[tid + s], i2 = si[tid + s];
+      if (k2 < sk[tid] || (k2 == sk[tid] && i2 < si[tid])) { sk[tid] = k2; si[tid] = i2; }
+    }
+    __syncthreads();
+  }
+  const uint32_t b = si[0];
+  const float *x = pop + run.pop_off + (size_t)b * D;
+  const double *Rt = tab_ptr<double>(tab, p.r64t_off);
+  const uint32_t Dr = rt_stride(D);
+  const float *o = tab_ptr<float>(tab, p.o_off);
+  for (uint32_t j = tid; j < D; j += FIN_BLOCK) {
+    double acc = 0.0;
+    for (uint32_t k = 0; k < D; ++k) acc = fma(Rt[(size_t)k * Dr + j], (double)x[k] - (double)o[k], acc);
+    z[j] = acc;
+  }
+  __syncthreads();
+  for (uint32_t j = tid; j < D; j += FIN_BLOCK) {
+    if (p.kind == FN_ROSENBROCK) {
+      t0s[j] = j + 1 < D ? h_rosenbrock<double>(z[j], z[j + 1]) : 0.0;
+      t1s[j] = 0.0;
+    } else {
+      elem_term<double>(tab, p, j, z[j], t0s[j], t1s[j]);
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double s0 = 0.0, s1 = 0.0;
+    for (uint32_t j = 0; j < D; ++j) { s0 += t0s[j]; s1 += t1s[j]; }
+    best_y[blockIdx.x] = fn_finish<double>(p, s0, s1);
+  }
+  for (uint32_t j = tid; j < D; j += FIN_BLOCK) best_x[run.bx_off + j] = x[j];
+}
+
+// ---------------------------------------------------------------- theta decode (Alg. 3 decode step)
+
+__device__ __forceinline__ void theta_box(uint32_t n_cs, int k, float &lo, float &hi) {
+  lo = k < 2 ? 0.0f : 1.0f;
+  hi = k < 2 ? 1.0f : (k < 5 ? 5.0f : 1.0f + (float)n_cs);
+}
+
+__device__ __forceinline__ void decode_into(RunDev &r, const float *t, uint32_t n_cs) {
+  r.F = t[0];
+  r.CR = t[1];
+  r.bl = min((int)floorf(t[2]), 4);
+  r.br = min((int)floorf(t[3]), 4);
+  r.dn = min((int)floorf(t[4]), 4);
+  r.cs = min((int)floorf(t[5]), (int)n_cs);
+}
+
+__global__ void k_decode(RunDev *__restrict__ runs, float *__restrict__ theta, uint32_t n,
+                         uint32_t n_cs) {
+  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  float t[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    float lo, hi;
+    theta_box(n_cs, k, lo, hi);
+    float v = theta[r * 6 + k];
+    if (v != v) v = lo;
+    v = fminf(fmaxf(v, lo), hi);
+    t[k] = v;
+    theta[r * 6 + k] = v;
+  }
+  decode_into(runs[r], t, n_cs);
+}
+
+// ---------------------------------------------------------------- evolver (Alg. 3)
+
+__global__ void k_outer_init(float *__restrict__ X, double *__restrict__ y, uint32_t P,
+                             uint32_t stream, uint32_t k0, uint32_t k1, uint32_t n_cs) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P) return;
+  const uint4 w0 = philox(0, i, INIT_PHASE, stream | OUTER_BIT, k0, k1);
+  const uint4 w1 = philox(1, i, INIT_PHASE, stream | OUTER_BIT, k0, k1);
+  const uint32_t w[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    float lo, hi;
+    theta_box(n_cs, k, lo, hi);
+    const double u0 = (double)(w[k] >> 8) * 0x1p-24;
+    X[i * 6 + k] = (float)((double)lo + ((double)hi - (double)lo) * u0);
+  }
+  y[i] = __longlong_as_double(0x7FF0000000000000ll);
+}
+
+// DE/rand/1/bin trial of the evolver: F = 0.5, CR = 0.9, same word map as an
+// executor with theta = (0.5, 0.9, rand, rand, 1, bin).
+__global__ void k_outer_trial(const float *__restrict__ X, float *__restrict__ U,
+                              RunDev *__restrict__ runs, uint32_t P, uint32_t g_o,
+                              uint32_t stream, uint32_t k0, uint32_t k1, uint32_t n_cs, float F,
+                              float CR) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P) return;
+  const uint32_t st = stream | OUTER_BIT;
+  const uint4 wa = philox(0, i, g_o, st, k0, k1);
+  const uint4 wc = philox(2, i, g_o, st, k0, k1);
+  const uint4 g0w = philox(3, i, g_o, st, k0, k1);
+  const uint4 g1w = philox(4, i, g_o, st, k0, k1);
+  uint32_t w[12] = {wa.x, wa.y, wa.z, wa.w, 0, 0, 0, 0, wc.x, wc.y, wc.z, wc.w};
+  uint32_t dr[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  sample_distinct(w, 3, i, P, dr);
+  const uint32_t jr = lemire(w[W_JRAND], 6);
+  const uint32_t gw[8] = {g0w.x, g0w.y, g0w.z, g0w.w, g1w.x, g1w.y, g1w.z, g1w.w};
+  float t[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const float v = X[dr[0] * 6 + k] + F * (X[dr[1] * 6 + k] - X[dr[2] * 6 + k]);
+    const bool take = (unit_oc(gw[k]) <= CR) || ((uint32_t)k == jr);
+    float u = take ? v : X[i * 6 + k];
+    float lo, hi;
+    theta_box(n_cs, k, lo, hi);
+    u = fminf(fmaxf(u, lo), hi);
+    t[k] = u;
+    U[i * 6 + k] = u;
+  }
+  decode_into(runs[i], t, n_cs);
+}
+
+__global__ void k_outer_select(float *__restrict__ X, double *__restrict__ y,
+                               const float *__restrict__ U, const double *__restrict__ y_run,
+                               double *__restrict__ y_trial, float *__restrict__ bxo,
+                               const float *__restrict__ best_x, const RunDev *__restrict__ runs,
+                               uint32_t P) {
+  const uint32_t i = blockIdx.x;
+  if (i >= P) return;
+  const double yt = y_run[i];
+  const bool acc = accept_trial_d(yt, y[i]);
+  __syncthreads();
+  const RunDev run = runs[i];
+  if (acc) {
+    for (uint32_t j = threadIdx.x; j < run.D; j += blockDim.x) bxo[run.bx_off + j] = best_x[run.bx_off + j];
+    if (threadIdx.x < 6) X[i * 6 + threadIdx.x] = U[i * 6 + threadIdx.x];
+  }
+  if (threadIdx.x == 0) {
+    y_trial[i] = yt;
+    if (acc) y[i] = yt;
+  }
+}
+
+__global__ void k_outer_best(const double *__restrict__ y, uint32_t P, int32_t *__restrict__ out) {
+  __shared__ double sv[256];
+  __shared__ int32_t si[256];
+  const uint32_t tid = threadIdx.x;
+  double bv = __longlong_as_double(0x7FF0000000000000ll);
+  int32_t bi = 0x7FFFFFFF;
+  for (uint32_t i = tid; i < P; i += 256) {
+    double v = y[i];
+    if (v != v) v = __longlong_as_double(0x7FF0000000000000ll);
+    if (v < bv || (v == bv && (int32_t)i < bi)) { bv = v; bi = (int32_t)i; }
+  }
+  sv[tid] = bv;
+  si[tid] = bi;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < (uint32_t)s) {
+      if (sv[tid + s] < sv[tid] || (sv[tid + s] == sv[tid] && si[tid + s] < si[tid])) {
+        sv[tid] = sv[tid + s];
+        si[tid] = si[tid + s];
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) out[0] = si[0] == 0x7FFFFFFF ? 0 : si[0];
+}
+
+// Rt[k][j] = R[j][k] in float64, row stride Dr >= D + 16 (zero padding so a
+// block of 16 outputs starting anywhere below D stays inside the row).
+__global__ void k_rot_t64(const float *__restrict__ R, double *__restrict__ Rt, uint32_t D,
+                          uint32_t Dr) {
+  const uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= D * Dr) return;
+  const uint32_t k = u / Dr, j = u - k * Dr;
+  Rt[u] = j < D ? (double)R[(size_t)j * D + k] : 0.0;
+}
+
+// ---------------------------------------------------------------- launchers
+
+hipError_t launch_rot_t64(const float *R, double *Rt, uint32_t D, hipStream_t s) {
+  const uint32_t n = D * rt_stride(D);
+  hipLaunchKernelGGL(k_rot_t64, dim3((n + 255) / 256), dim3(256), 0, s, R, Rt, D, rt_stride(D));
+  return hipGetLastError();
+}
+
+hipError_t set_lds_limits() {
+  hipError_t e = hipFuncSetAttribute((const void *)k_generations<false>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BUDGET);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void *)k_generations<true>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BUDGET);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void *)k_init, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          LDS_BUDGET);
+  if (e != hipSuccess) return e;
+  return set_lds_limits_mfma();
+}
+
+hipError_t launch_init(const LaunchArgs &a, double lb, double ub) {
+  hipLaunchKernelGGL(k_init, dim3(a.n_runs), dim3(INIT_THREADS), a.init_lds_bytes, a.stream,
+                     a.runs, a.probs, a.tab, a.pop, a.fit, a.k0, a.k1, lb, ub);
+  return hipGetLastError();
+}
+
+hipError_t launch_generations(const LaunchArgs &a, const uint32_t *list, uint32_t n,
+                              uint32_t g0, uint32_t n_gens, float lb, float ub, TraceArgs tr) {
+  if (n == 0) return hipSuccess;
+  if (tr.u)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_generations<true>), dim3(n), dim3(GEN_THREADS),
+                       a.lds_bytes, a.stream, a.runs, list, a.probs, a.tab, a.pop, a.fit, g0,
+                       n_gens, a.k0, a.k1, lb, ub, a.pending, tr);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_generations<false>), dim3(n), dim3(GEN_THREADS),
+                       a.lds_bytes, a.stream, a.runs, list, a.probs, a.tab, a.pop, a.fit, g0,
+                       n_gens, a.k0, a.k1, lb, ub, a.pending, tr);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const LaunchArgs &a, double *best_y, float *best_x) {
+  hipLaunchKernelGGL(k_finalize, dim3(a.n_runs), dim3(FIN_BLOCK), 0, a.stream, a.runs, a.probs,
+                     a.tab, a.pop, a.fit, best_y, best_x);
+  return hipGetLastError();
+}
+
+hipError_t launch_decode(RunDev *runs, float *theta, uint32_t n, uint32_t n_cs,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_decode, dim3((n + 63) / 64), dim3(64), 0, s, runs, theta, n, n_cs);
+  return hipGetLastError();
+}
+
+hipError_t launch_outer_init(float *X, double *y, uint32_t P, uint32_t stream, uint32_t k0,
+                             uint32_t k1, uint32_t n_cs, hipStream_t s) {
+  hipLaunchKernelGGL(k_outer_init, dim3((P + 63) / 64), dim3(64), 0, s, X, y, P, stream, k0, k1,
+                     n_cs);
+  return hipGetLastError();
+}
+
+hipError_t launch_outer_trial(const float *X, float *U, RunDev *runs, uint32_t P, uint32_t g_o,
+                              uint32_t stream, uint32_t k0, uint32_t k1, uint32_t n_cs,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_outer_trial, dim3((P + 63) / 64), dim3(64), 0, s, X, U, runs, P, g_o,
+                     stream, k0, k1, n_cs, 0.5f, 0.9f);
+  return hipGetLastError();
+}
+
+hipError_t launch_outer_select(float *X, double *y, const float *U, const double *y_run,
+                               double *y_trial, float *bxo, const float *best_x,
+                               const RunDev *runs, uint32_t P, hipStream_t s) {
+  hipLaunchKernelGGL(k_outer_select, dim3(P), dim3(64), 0, s, X, y, U, y_run, y_trial, bxo, best_x,
+                     runs, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_outer_best(const double *y, uint32_t P, int32_t *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_outer_best, dim3(1), dim3(256), 0, s, y, P, out);
+  return hipGetLastError();
+}
+
+}  // namespace mde
+
+extern "C" int metade_prof_read(unsigned long long *out, int n) {
+  return (int)hipMemcpyFromSymbol(out, HIP_SYMBOL(mde::g_prof), n * sizeof(unsigned long long));
+}

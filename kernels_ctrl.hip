@@ -1,0 +1,684 @@
+// Control-shaped workload: each individual is the flattened weight vector of
+// a tanh policy obs -> 64 -> 64 -> act, scored by a rollout of a linear
+// system x_{t+1} = A x_t + B u_t with cost sum_t |x_t|^2 + cw |u_t|^2.  This
+// is the paper's neural-control setting (Sec. IV-D, policy MLPs of Table VII)
+// on a synthetic plant, with the PDE generation of Alg. 2 around it.
+//
+// One wavefront evaluates two individuals of one run, 32 lanes each.  Lane l
+// of a half holds, in registers, hidden rows l and l + 32 of W2 (the float32
+// values of the population, widened at use), their biases and a 16-weight
+// slice of W3; its two rows of W1 sit in LDS next to each other.  The
+// activations are exchanged through LDS; with two rows per lane every
+// float64 value read from LDS feeds two FMAs, which halves the LDS traffic
+// per multiply-add.  The rollout is float64: the
+// closed loop of a policy amplifies rounding differences (by orders of
+// magnitude for weights of order one), and on gfx950 a float64 FMA issues at
+// the rate of a non-packed float32 FMA.
+//
+// Per generation four launches: rank (top-p list per run); trials (draws,
+// Eq. 12 mutation, Eqs. 8-10 crossover, clip: one block per trial reading
+// the population rows with coalesced loads and writing the trial to a
+// 16-byte aligned pending row); evaluation (rollout and selection decision);
+// commit (accepted rows replace their targets).
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "gen_common.h"
+#include "kernels.h"
+
+namespace mde {
+
+namespace {
+
+constexpr uint32_t CT_TRIAL_THREADS = 256;       // trial construction: threads per trial
+constexpr uint32_t CT_TRIAL_THREADS_INIT = 256;  // initialisation: threads per individual
+constexpr int CT_LPI = 32;            // lanes per individual
+constexpr int CT_RPL = CT_H / CT_LPI; // hidden rows per lane
+constexpr int CT_W3 = 16;             // W3 weights per lane: lane (a, c) has W3[a][16c .. 16c+15]
+
+// ---------------------------------------------------------------- geometry
+
+struct CtGeom {
+  uint32_t O, A, D;                 // obs, act, decision dimension
+  uint32_t b1, w2, b2, w3, b3;      // flat offsets of the parameter blocks
+};
+
+__device__ __forceinline__ CtGeom ct_geom(const ProbDev &p) {
+  CtGeom g;
+  g.O = p.obs;
+  g.A = p.act;
+  g.b1 = CT_H * g.O;
+  g.w2 = g.b1 + CT_H;
+  g.b2 = g.w2 + CT_H * CT_H;
+  g.w3 = g.b2 + CT_H;
+  g.b3 = g.w3 + CT_H * g.A;
+  g.D = g.b3 + g.A;
+  return g;
+}
+
+// Gene index of each register slot of lane l (0..31 within its half).
+__device__ __forceinline__ uint32_t row_of(uint32_t l, int r) { return l + CT_LPI * r; }
+__device__ __forceinline__ uint32_t w1_gene(const CtGeom &G, uint32_t l, int r, uint32_t k) {
+  return row_of(l, r) * G.O + k;
+}
+__device__ __forceinline__ uint32_t w2_gene(const CtGeom &G, uint32_t l, int r, uint32_t k) {
+  return G.w2 + row_of(l, r) * CT_H + k;
+}
+__device__ __forceinline__ uint32_t w3_gene(const CtGeom &G, uint32_t l, uint32_t s) {
+  return G.w3 + (l >> 2) * CT_H + CT_W3 * (l & 3) + s;
+}
+__device__ __forceinline__ bool w3_owned(const CtGeom &G, uint32_t l) { return (l >> 2) < G.A; }
+__device__ __forceinline__ bool b3_owned(const CtGeom &G, uint32_t l) {
+  return (l >> 2) < G.A && (l & 3) == 0;
+}
+
+// ---------------------------------------------------------------- float64 tanh
+//
+// tanh|x| = 1 - 2 / (e^{2|x|} + 1).  e^y: Cody-Waite reduction y = n ln2 + r
+// with ln2 split in a 32-bit head (n ln2_hi exact for the n that occur) and a
+// tail, |r| <= ln2 / 2, then the Taylor series of e^r to degree 13 (remainder
+// below 1e-17 relative) and a scaling by 2^n.  The reciprocal is the hardware
+// estimate refined by two Newton steps.  The absolute error is a few units of
+// 2^-53, which is what the rollout needs (activations enter sums of O(1)).
+// For |x| >= 20, tanh rounds to +-1 in float64; the argument is clamped there.
+
+constexpr double CT_LN2_HI = 0x1.62e42ff000000p-1;
+constexpr double CT_LN2_LO = -0x1.718432a1b0e26p-35;
+constexpr double CT_LOG2E = 0x1.71547652b82fep+0;
+
+__device__ __forceinline__ double tanh_f64(double x) {
+  const double y = fmin(2.0 * fabs(x), 40.0);
+  const double n = rint(y * CT_LOG2E);
+  double r = fma(-n, CT_LN2_HI, y);
+  r = fma(-n, CT_LN2_LO, r);
+  // sum_{k<=13} r^k / k! by Estrin's scheme (dependency depth 4 instead of 13)
+  const double r2 = r * r, r4 = r2 * r2, r8 = r4 * r4;
+  const double q0 = fma(r, 1.0, 1.0);
+  const double q1 = fma(r, 1.0 / 6.0, 0.5);
+  const double q2 = fma(r, 1.0 / 120.0, 1.0 / 24.0);
+  const double q3 = fma(r, 1.0 / 5040.0, 1.0 / 720.0);
+  const double q4 = fma(r, 1.0 / 362880.0, 1.0 / 40320.0);
+  const double q5 = fma(r, 1.0 / 39916800.0, 1.0 / 3628800.0);
+  const double q6 = fma(r, 1.0 / 6227020800.0, 1.0 / 479001600.0);
+  const double s0 = fma(r2, q1, q0);
+  const double s1 = fma(r2, q3, q2);
+  const double s2 = fma(r2, q5, q4);
+  const double t0 = fma(r4, s1, s0);
+  const double t1 = fma(r4, q6, s2);
+  const double p = fma(r8, t1, t0);
+  const double E = ldexp(p, (int)n);
+  const double d = E + 1.0;
+  double q = __builtin_amdgcn_rcp(d);
+  q = fma(q, fma(-d, q, 1.0), q);
+  q = fma(q, fma(-d, q, 1.0), q);
+  const double t = fma(-2.0, q, 1.0);
+  return copysign(t, x);
+}
+
+// ---------------------------------------------------------------- weights and rollout
+
+// The lane's share of one policy (see the file comment), kept as the float32
+// values the population holds; slots past the geometry are zero so that they
+// contribute nothing.
+struct Wts {
+  float b1[CT_RPL];
+  float w2[CT_RPL][CT_H];
+  float b2[CT_RPL];
+  float w3[CT_W3];
+  float b3;
+};
+
+// LDS of one wavefront: the plant's coefficients by lane (at[k][l] = A[l][k],
+// bt[a][l] = B[l][a], zero for l >= obs; both halves belong to one run) and
+// per half the vectors exchanged between the lanes in a step.
+// The halves' vectors are padded by 16 bytes so that the two addresses of
+// one broadcast read fall in different LDS banks.
+struct CtLds {
+  float2 w1[CT_MAX_OBS][2][CT_LPI];   // (W1[l][k], W1[l + 32][k]) of half h at [k][h][l]
+  float at[CT_MAX_OBS][CT_LPI];
+  float bt[CT_MAX_ACT][CT_LPI];
+  double x[2][CT_MAX_OBS + 2];
+  double h1[2][CT_H + 2];
+  double h2[2][CT_H + 2];
+  double u[2][CT_MAX_ACT + 2];
+};
+
+__device__ __forceinline__ void load_plant(const unsigned char *tab, const ProbDev &p,
+                                           const CtGeom &G, uint32_t lane, CtLds &S) {
+  if (lane >= (uint32_t)CT_LPI) return;
+  const float *A = tab_ptr<float>(tab, p.A_off);
+  const float *B = tab_ptr<float>(tab, p.B_off);
+  const bool own = lane < G.O;
+  for (uint32_t k = 0; k < (uint32_t)CT_MAX_OBS; ++k) S.at[k][lane] = (own && k < G.O) ? A[lane * G.O + k] : 0.0f;
+  for (uint32_t a = 0; a < (uint32_t)CT_MAX_ACT; ++a) S.bt[a][lane] = (own && a < G.A) ? B[lane * G.A + a] : 0.0f;
+}
+
+// Sum over the 32 lanes of a half.
+__device__ __forceinline__ double half_sum(double v) {
+#pragma unroll
+  for (int s = 16; s > 0; s >>= 1) v += __shfl_xor(v, s);
+  return v;
+}
+
+// Mean over the rollouts of J = sum_{t < steps} (|x_t|^2 + cw |u_t|^2),
+// u_t = tanh(W3 tanh(W2 tanh(W1 x_t + b1) + b2) + b3), x_{t+1} = A x_t + B u_t,
+// for the individual of this lane's half.  Called by the whole wavefront (a
+// one-wave block); returns J in every lane of the half.
+__device__ __forceinline__ double rollout(Wts &W, const float *x0, const CtGeom &G,
+                                          uint32_t steps, uint32_t E, double cw, uint32_t lane,
+                                          CtLds &S) {
+  const uint32_t h = lane / CT_LPI, l = lane % CT_LPI;
+  const uint32_t ga = l >> 2, gc = l & 3;
+  double *X = S.x[h], *H1 = S.h1[h], *H2 = S.h2[h], *U = S.u[h];
+  double jx = 0.0, ju = 0.0;
+  for (uint32_t e = 0; e < E; ++e) {
+    __syncthreads();
+    if (l < (uint32_t)CT_MAX_OBS) {
+      const double v = l < G.O ? (double)x0[e * G.O + l] : 0.0;
+      X[l] = v;
+      jx = fma(v, v, jx);
+    }
+    __syncthreads();
+    for (uint32_t t = 0; t < steps; ++t) {
+      // Keep the weights as float32 across steps: an empty asm that "modifies"
+      // them stops the compiler from hoisting the float64 widening out of the
+      // loop (which would double their registers).
+#pragma unroll
+      for (int k = 0; k < CT_H; ++k) asm volatile("" : "+v"(W.w2[0][k]), "+v"(W.w2[1][k]));
+#pragma unroll
+      for (int k = 0; k < CT_W3; ++k) asm volatile("" : "+v"(W.w3[k]));
+      // layer 1 (both rows) and the A x_t part of the plant update
+      double a0 = (double)W.b1[0], a0b = 0.0, a1 = (double)W.b1[1], a1b = 0.0;
+      double ax = 0.0, axb = 0.0;
+#pragma unroll
+      for (int k = 0; k < CT_MAX_OBS; k += 2) {
+        if ((uint32_t)k < G.O) {
+          const double2 xv = *reinterpret_cast<const double2 *>(X + k);
+          const float2 wa = S.w1[k][h][l], wb = S.w1[k + 1][h][l];
+          a0 = fma((double)wa.x, xv.x, a0);
+          a1 = fma((double)wa.y, xv.x, a1);
+          a0b = fma((double)wb.x, xv.y, a0b);
+          a1b = fma((double)wb.y, xv.y, a1b);
+          ax = fma((double)S.at[k][l], xv.x, ax);
+          axb = fma((double)S.at[k + 1][l], xv.y, axb);
+        }
+      }
+      ax += axb;
+      H1[l] = tanh_f64(a0 + a0b);
+      H1[l + CT_LPI] = tanh_f64(a1 + a1b);
+      __syncthreads();
+      // layer 2: two rows, four partial sums each
+      double c0[4], c1[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        c0[q] = q == 0 ? (double)W.b2[0] : 0.0;
+        c1[q] = q == 0 ? (double)W.b2[1] : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < CT_H; k += 2) {
+        const double2 v = *reinterpret_cast<const double2 *>(H1 + k);
+        c0[k & 3] = fma((double)W.w2[0][k], v.x, c0[k & 3]);
+        c1[k & 3] = fma((double)W.w2[1][k], v.x, c1[k & 3]);
+        c0[(k + 1) & 3] = fma((double)W.w2[0][k + 1], v.y, c0[(k + 1) & 3]);
+        c1[(k + 1) & 3] = fma((double)W.w2[1][k + 1], v.y, c1[(k + 1) & 3]);
+      }
+      H2[l] = tanh_f64((c0[0] + c0[1]) + (c0[2] + c0[3]));
+      H2[l + CT_LPI] = tanh_f64((c1[0] + c1[1]) + (c1[2] + c1[3]));
+      __syncthreads();
+      // layer 3: lane (ga, gc) sums W3[ga][16gc .. 16gc+15] h2[...], then 4 lanes combine
+      double pz = 0.0, pzb = 0.0;
+#pragma unroll
+      for (int s = 0; s < CT_W3; s += 2) {
+        const double2 v = *reinterpret_cast<const double2 *>(H2 + CT_W3 * gc + s);
+        pz = fma((double)W.w3[s], v.x, pz);
+        pzb = fma((double)W.w3[s + 1], v.y, pzb);
+      }
+      pz += pzb;
+      pz += __shfl_xor(pz, 1);
+      pz += __shfl_xor(pz, 2);
+      if (gc == 0 && ga < G.A) {
+        const double u = tanh_f64(pz + (double)W.b3);
+        U[ga] = u;
+        ju = fma(u, u, ju);
+      }
+      __syncthreads();
+      // plant update; every lane has finished reading x_t (before the first barrier)
+      double xn = ax;
+#pragma unroll
+      for (int a = 0; a < CT_MAX_ACT; ++a)
+        if ((uint32_t)a < G.A) xn = fma((double)S.bt[a][l], U[a], xn);
+      if (l < G.O) {
+        X[l] = xn;
+        if (t + 1 < steps) jx = fma(xn, xn, jx);
+      }
+      __syncthreads();
+    }
+  }
+  return (half_sum(jx) + cw * half_sum(ju)) / (double)E;
+}
+
+// Component R of a lane's W1 pair in LDS.
+template <int R>
+__device__ __forceinline__ float &w1_slot(CtLds &S, uint32_t k, uint32_t h, uint32_t l) {
+  return R == 0 ? S.w1[k][h][l].x : S.w1[k][h][l].y;
+}
+
+// Fill the lane's slots of hidden row set R from a per-gene function val(j).
+template <int R, typename Val>
+__device__ __forceinline__ void fill_rows(const CtGeom &G, uint32_t h, uint32_t l, Wts &W,
+                                          CtLds &S, Val &val) {
+  for (uint32_t k = 0; k < (uint32_t)CT_MAX_OBS; ++k)
+    w1_slot<R>(S, k, h, l) = k < G.O ? val(w1_gene(G, l, R, k)) : 0.0f;
+  W.b1[R] = val(G.b1 + row_of(l, R));
+#pragma unroll
+  for (int k = 0; k < CT_H; ++k) W.w2[R][k] = val(w2_gene(G, l, R, k));
+  W.b2[R] = val(G.b2 + row_of(l, R));
+}
+
+// Fill the lane's slots from a per-gene function val(j) -> float.
+template <typename Val>
+__device__ __forceinline__ void fill_wts(const CtGeom &G, uint32_t h, uint32_t l, Wts &W, CtLds &S,
+                                         Val val) {
+  fill_rows<0>(G, h, l, W, S, val);
+  fill_rows<1>(G, h, l, W, S, val);
+  const bool o3 = w3_owned(G, l);
+#pragma unroll
+  for (int s = 0; s < CT_W3; ++s) W.w3[s] = o3 ? val(w3_gene(G, l, s)) : 0.0f;
+  W.b3 = b3_owned(G, l) ? val(G.b3 + (l >> 2)) : 0.0f;
+}
+
+// ---------------------------------------------------------------- trial construction
+
+// Genes j0 .. j0+3 of a population row (stride D floats; rows are 8-byte
+// aligned when D is even); genes >= D read as 0.
+__device__ __forceinline__ float4 row_quad(const float *row, uint32_t j0, uint32_t D, bool even) {
+  if (j0 + 4 <= D) {
+    if (even) {
+      const float2 a = *reinterpret_cast<const float2 *>(row + j0);
+      const float2 b = *reinterpret_cast<const float2 *>(row + j0 + 2);
+      return make_float4(a.x, a.y, b.x, b.y);
+    }
+    return make_float4(row[j0], row[j0 + 1], row[j0 + 2], row[j0 + 3]);
+  }
+  float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+    if (j0 + t < D) set_comp(v, t, row[j0 + t]);
+  return v;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- kernels
+
+// Initial population (Alg. 2 initialisation: word j of the INIT phase gives
+// gene j, x = lb + (ub - lb) (w >> 8) 2^-24 in float64 rounded once), written
+// to the population and to the pending row the evaluation kernel reads.  One
+// block per individual, grid (max N, control runs).
+__global__ __launch_bounds__(CT_TRIAL_THREADS_INIT) void k_ctrl_init_pop(
+    const RunDev *__restrict__ runs, const uint32_t *__restrict__ list, float *__restrict__ pop,
+    float *__restrict__ pend, uint32_t k0, uint32_t k1, double lb, double ub) {
+  const RunDev run = runs[list[blockIdx.y]];
+  const uint32_t i = blockIdx.x;
+  if (i >= run.N) return;
+  const uint32_t D = run.D;
+  float *row = pop + run.pop_off + (size_t)i * D;
+  float *Urow = pend + run.pend_off + (size_t)i * run.Dp;
+  for (uint32_t q = threadIdx.x; 4 * q < D; q += CT_TRIAL_THREADS_INIT) {
+    const uint4 w = philox(q, i, INIT_PHASE, run.stream, k0, k1);
+    float4 x;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const double u0 = (double)(word_of(w, t) >> 8) * 0x1p-24;
+      const float v = 4 * q + t < D ? (float)(lb + (ub - lb) * u0) : 0.0f;
+      set_comp(x, t, v);
+      if (4 * q + t < D) row[4 * q + t] = v;
+    }
+    *reinterpret_cast<float4 *>(Urow + 4 * q) = x;
+  }
+}
+
+// Top-p list of every control run: order[fit_off + rank] = individual for
+// rank < kp, ranking by (fitness, index) with NaN as +inf.  One block per run.
+__global__ __launch_bounds__(CT_MAX_N) void k_ctrl_rank(const RunDev *__restrict__ runs,
+                                                        const uint32_t *__restrict__ list,
+                                                        const float *__restrict__ fit,
+                                                        uint32_t *__restrict__ order) {
+  __shared__ uint64_t keys[CT_MAX_N];
+  const RunDev run = runs[list[blockIdx.x]];
+  const uint32_t N = run.N, i = threadIdx.x;
+  if (i < N) keys[i] = mkkey(fit[run.fit_off + i], i);
+  __syncthreads();
+  if (i < N) {
+    const uint64_t ki = keys[i];
+    uint32_t rank = 0;
+    for (uint32_t k = 0; k < N; ++k) rank += keys[k] < ki ? 1u : 0u;
+    if (rank < run.kp) order[run.fit_off + rank] = i;
+  }
+}
+
+// Trial vectors of one generation of every control run: one block per target
+// i, grid (max N, control runs).  Index draws, the pbest rank, j_rand / n, K
+// and the exponential length come from Philox words of (i, g); mutation
+// (Eq. 12, float32, the operation order of the other generation kernels:
+// base = x_bl + F (x_br - x_bl), differences summed left to right,
+// v = base + F d), crossover (Eqs. 8-10) and clip run over gene quads with
+// coalesced loads.  The trial goes to its pending row (stride Dp).
+
+template <bool TRACE>
+__global__ __launch_bounds__(CT_TRIAL_THREADS) void k_ctrl_trials(
+    const RunDev *__restrict__ runs, const uint32_t *__restrict__ list,
+    const float *__restrict__ pop, float *__restrict__ pend, const uint32_t *__restrict__ order,
+    uint32_t g, float lb, float ub, uint32_t k0, uint32_t k1, TraceArgs tr) {
+  const RunDev run = runs[list[blockIdx.y]];
+  const uint32_t i = blockIdx.x;
+  if (i >= run.N) return;
+  const uint32_t N = run.N, D = run.D, tid = threadIdx.x, lane = tid % 64;
+  const int use_rand = (run.bl == RAND || run.br == RAND) ? 1 : 0;
+  const int dn = run.dn;
+  const int m = use_rand + 2 * dn;
+  uint32_t w[12];
+  {
+    const uint4 a = philox(0, i, g, run.stream, k0, k1);
+    const uint4 b = philox(1, i, g, run.stream, k0, k1);
+    const uint4 c = philox(2, i, g, run.stream, k0, k1);
+    w[0] = a.x; w[1] = a.y; w[2] = a.z; w[3] = a.w;
+    w[4] = b.x; w[5] = b.y; w[6] = b.z; w[7] = b.w;
+    w[8] = c.x; w[9] = c.y; w[10] = c.z; w[11] = c.w;
+  }
+  uint32_t dr[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) dr[k] = 0;
+  sample_distinct(w, m, i, N, dr);
+  const uint32_t r0 = use_rand ? dr[0] : 0u;
+  const uint32_t pbr = lemire(w[W_PBEST], run.kp);
+  const uint32_t jn = lemire(w[W_JRAND], D);
+  const float K = unit_oc(w[W_K]);
+  const float F = run.F, CR = run.CR;
+  // exponential length: 1 + the number of leading uniforms r_0, r_1, ... <= CR,
+  // at most D; every wavefront scans 256 uniforms per round (4 per lane)
+  uint32_t L = 1;
+  if (run.cs == EXP) {
+    L = D;
+    for (uint32_t c = 0; 256 * c + 1 < D; ++c) {
+      const uint4 wr = philox(W_GENE0 / 4 + 64 * c + lane, i, g, run.stream, k0, k1);
+      uint32_t first = 4;
+#pragma unroll
+      for (int t = 3; t >= 0; --t)
+        if (unit_oc(word_of(wr, t)) > CR) first = (uint32_t)t;
+      const uint64_t fail = __ballot(first < 4);
+      if (fail) {
+        const uint32_t fl = __ffsll((unsigned long long)fail) - 1;
+        const uint32_t ft = __shfl(first, (int)fl);
+        L = min(D, 4 * (64 * c + fl) + ft + 1);
+        break;
+      }
+    }
+  }
+  const uint32_t ibest = order[run.fit_off], ipb = order[run.fit_off + pbr];
+  auto pick = [&](int code) {
+    return code == RAND ? r0 : (code == BEST ? ibest : (code == PBEST ? ipb : i));
+  };
+  const uint32_t ibl = pick(run.bl), ibr = pick(run.br);
+  if (TRACE && tid == 0) {
+    int32_t *o = tr.desc + (size_t)(run.fit_off + i) * 16;
+    o[0] = (int32_t)ibl;
+    o[1] = (int32_t)ibr;
+    for (int k = 0; k < 8; ++k) o[2 + k] = (k / 2) < dn ? (int32_t)dr[use_rand + k] : -1;
+    o[10] = (int32_t)jn;
+    o[11] = run.cs == EXP ? (int32_t)L : -1;
+    o[12] = (int32_t)pbr;
+    o[13] = use_rand ? (int32_t)r0 : -1;
+    o[14] = run.cs == ARITH ? (int32_t)__float_as_uint(K) : -1;
+    o[15] = 0;
+  }
+  const float *P0 = pop + run.pop_off;
+  const float *xi = P0 + (size_t)i * D, *xb = P0 + (size_t)ibl * D, *xr = P0 + (size_t)ibr * D;
+  const float *pa[4], *pb[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    pa[k] = P0 + (size_t)(k < dn ? dr[use_rand + 2 * k] : 0u) * D;
+    pb[k] = P0 + (size_t)(k < dn ? dr[use_rand + 2 * k + 1] : 0u) * D;
+  }
+  // float2 loads when every row is 8-byte aligned
+  const bool even = ((reinterpret_cast<uintptr_t>(P0) & 7u) == 0) && (D & 1u) == 0;
+  const bool two_base = run.bl != run.br;
+  float *Urow = pend + run.pend_off + (size_t)i * run.Dp;
+  float *Ut = TRACE ? tr.u + run.pop_off + (size_t)i * D : nullptr;
+  for (uint32_t q = tid; 4 * q < D; q += CT_TRIAL_THREADS) {
+    const uint32_t j0 = 4 * q;
+    const float4 x = row_quad(xi, j0, D, even);
+    const float4 b = row_quad(xb, j0, D, even);
+    float4 base = b;
+    if (two_base) {
+      const float4 rr = row_quad(xr, j0, D, even);
+      base.x = b.x + F * (rr.x - b.x);
+      base.y = b.y + F * (rr.y - b.y);
+      base.z = b.z + F * (rr.z - b.z);
+      base.w = b.w + F * (rr.w - b.w);
+    }
+    float4 d;
+    {
+      const float4 a0 = row_quad(pa[0], j0, D, even), b0 = row_quad(pb[0], j0, D, even);
+      d.x = a0.x - b0.x; d.y = a0.y - b0.y; d.z = a0.z - b0.z; d.w = a0.w - b0.w;
+    }
+#pragma unroll
+    for (int k = 1; k < 4; ++k) {
+      if (k < dn) {
+        const float4 ak = row_quad(pa[k], j0, D, even), bk = row_quad(pb[k], j0, D, even);
+        d.x = d.x + (ak.x - bk.x);
+        d.y = d.y + (ak.y - bk.y);
+        d.z = d.z + (ak.z - bk.z);
+        d.w = d.w + (ak.w - bk.w);
+      }
+    }
+    float4 v;
+    v.x = base.x + F * d.x;
+    v.y = base.y + F * d.y;
+    v.z = base.z + F * d.z;
+    v.w = base.w + F * d.w;
+    float4 u;
+    if (run.cs == ARITH) {
+      u.x = x.x + K * (v.x - x.x);
+      u.y = x.y + K * (v.y - x.y);
+      u.z = x.z + K * (v.z - x.z);
+      u.w = x.w + K * (v.w - x.w);
+    } else if (run.cs == BIN) {
+      // words 12 + j0 .. 12 + j0 + 3 are exactly Philox block 3 + q
+      const uint4 wr = philox(W_GENE0 / 4 + q, i, g, run.stream, k0, k1);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const bool take = unit_oc(word_of(wr, t)) <= CR || j0 + t == jn;
+        set_comp(u, t, take ? comp(v, t) : comp(x, t));
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const uint32_t off = (j0 + t + D - jn) % D;
+        set_comp(u, t, off < L ? comp(v, t) : comp(x, t));
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      set_comp(u, t, j0 + t < D ? fminf(fmaxf(comp(u, t), lb), ub) : 0.0f);
+    *reinterpret_cast<float4 *>(Urow + j0) = u;
+    if (TRACE) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (j0 + t < D) Ut[j0 + t] = comp(u, t);
+    }
+  }
+}
+
+// Rollout and selection decision of every control trial (INIT: the first
+// evaluation of the initial population, written as its fitness).  Grid
+// (ceil(max N / 2), control runs), one wavefront per two targets; each lane
+// loads its weight slots from the pending row (float4 where aligned).
+template <bool TRACE, bool INIT>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_ctrl_eval(
+    const RunDev *__restrict__ runs, const uint32_t *__restrict__ list,
+    const ProbDev *__restrict__ probs, const unsigned char *__restrict__ tab,
+    float *__restrict__ fit, const float *__restrict__ pend, float *__restrict__ fu_out,
+    uint32_t *__restrict__ acc_out, TraceArgs tr) {
+  __shared__ CtLds S;
+  const RunDev run = runs[list[blockIdx.y]];
+  const uint32_t lane = threadIdx.x, h = lane / CT_LPI, l = lane % CT_LPI;
+  const uint32_t i0 = 2 * blockIdx.x;
+  if (i0 >= run.N) return;
+  const uint32_t N = run.N;
+  const uint32_t i = min(i0 + h, N - 1);   // an odd N duplicates the last target
+  const bool writer = i0 + h < N;
+  const ProbDev p = probs[run.prob];
+  const CtGeom G = ct_geom(p);
+  const float *U = pend + run.pend_off + (size_t)i * run.Dp;
+  Wts W;
+  // W1 rows (stride obs, not aligned in general) into LDS, biases
+#pragma unroll
+  for (int r = 0; r < CT_RPL; ++r) {
+    for (uint32_t k = 0; k < (uint32_t)CT_MAX_OBS; ++k) {
+      const float v = k < G.O ? U[w1_gene(G, l, r, k)] : 0.0f;
+      if (r == 0) S.w1[k][h][l].x = v; else S.w1[k][h][l].y = v;
+    }
+    W.b1[r] = U[G.b1 + row_of(l, r)];
+    W.b2[r] = U[G.b2 + row_of(l, r)];
+  }
+  // W2 rows: 16-byte aligned (pending rows are, and the block starts at 64 obs + 64)
+#pragma unroll
+  for (int k = 0; k < CT_H; k += 4) {
+    const float4 a = *reinterpret_cast<const float4 *>(U + w2_gene(G, l, 0, k));
+    const float4 b = *reinterpret_cast<const float4 *>(U + w2_gene(G, l, 1, k));
+    W.w2[0][k] = a.x; W.w2[0][k + 1] = a.y; W.w2[0][k + 2] = a.z; W.w2[0][k + 3] = a.w;
+    W.w2[1][k] = b.x; W.w2[1][k + 1] = b.y; W.w2[1][k + 2] = b.z; W.w2[1][k + 3] = b.w;
+  }
+  const bool o3 = w3_owned(G, l);
+#pragma unroll
+  for (int t = 0; t < CT_W3; t += 4) {
+    float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (o3) a = *reinterpret_cast<const float4 *>(U + w3_gene(G, l, t));
+    W.w3[t] = a.x; W.w3[t + 1] = a.y; W.w3[t + 2] = a.z; W.w3[t + 3] = a.w;
+  }
+  W.b3 = b3_owned(G, l) ? U[G.b3 + (l >> 2)] : 0.0f;
+
+  load_plant(tab, p, G, lane, S);
+  const double J = rollout(W, tab_ptr<float>(tab, p.x0_off), G, p.steps, p.nroll, (double)p.cw,
+                           lane, S);
+  if (writer && l == 0) {
+    const float f = (float)J;
+    if (INIT) {
+      fit[run.fit_off + i] = f;
+    } else {
+      const float fx = fit[run.fit_off + i];
+      const bool a = accept_trial(f, fx);
+      fu_out[run.fit_off + i] = f;
+      acc_out[run.fit_off + i] = a ? 1u : 0u;
+      if (TRACE) {
+        tr.fu[run.fit_off + i] = f;
+        tr.desc[(size_t)(run.fit_off + i) * 16 + 15] = a ? 1 : 0;
+      }
+    }
+  }
+}
+
+// Greedy selection commit: accepted pending rows replace their targets.
+// Grid (max N, control runs).
+__global__ __launch_bounds__(256) void k_ctrl_commit(const RunDev *__restrict__ runs,
+                                                     const uint32_t *__restrict__ list,
+                                                     float *__restrict__ pop, float *__restrict__ fit,
+                                                     const float *__restrict__ pend,
+                                                     const float *__restrict__ fu,
+                                                     const uint32_t *__restrict__ acc) {
+  const RunDev run = runs[list[blockIdx.y]];
+  const uint32_t i = blockIdx.x;
+  if (i >= run.N || !acc[run.fit_off + i]) return;
+  const uint32_t D = run.D;
+  const float *src = pend + run.pend_off + (size_t)i * run.Dp;
+  float *dst = pop + run.pop_off + (size_t)i * D;
+  for (uint32_t j = threadIdx.x; j < D; j += 256) dst[j] = src[j];
+  if (threadIdx.x == 0) fit[run.fit_off + i] = fu[run.fit_off + i];
+}
+
+// Best record of every control run: the first individual in (fitness, index)
+// order, its float64 cost (the rollout is float64 already) and its weights.
+// Both halves of the wavefront evaluate it; the first writes.
+__global__ __launch_bounds__(64) void k_ctrl_finalize(const RunDev *__restrict__ runs,
+                                                      const uint32_t *__restrict__ list,
+                                                      const ProbDev *__restrict__ probs,
+                                                      const unsigned char *__restrict__ tab,
+                                                      const float *__restrict__ pop,
+                                                      const float *__restrict__ fit,
+                                                      double *__restrict__ best_y,
+                                                      float *__restrict__ best_x) {
+  __shared__ CtLds S;
+  const uint32_t r = list[blockIdx.x];
+  const RunDev run = runs[r];
+  const ProbDev p = probs[run.prob];
+  const CtGeom G = ct_geom(p);
+  const uint32_t lane = threadIdx.x, h = lane / CT_LPI, l = lane % CT_LPI;
+  uint64_t best = ~0ull;
+  for (uint32_t i = lane; i < run.N; i += 64) best = min(best, mkkey(fit[run.fit_off + i], i));
+#pragma unroll
+  for (int s = 32; s > 0; s >>= 1) {
+    const uint64_t o = __shfl_xor(best, s);
+    best = min(best, o);
+  }
+  const uint32_t b = (uint32_t)(best & 0xFFFFFFFFu);
+  const float *x = pop + run.pop_off + (size_t)b * G.D;
+  for (uint32_t j = lane; j < G.D; j += 64) best_x[run.bx_off + j] = x[j];
+  Wts W;
+  fill_wts(G, h, l, W, S, [&](uint32_t j) { return x[j]; });
+  load_plant(tab, p, G, lane, S);
+  const double J = rollout(W, tab_ptr<float>(tab, p.x0_off), G, p.steps, p.nroll, (double)p.cw,
+                           lane, S);
+  if (lane == 0) best_y[r] = J;
+}
+
+// ---------------------------------------------------------------- launchers
+
+hipError_t launch_ctrl_init(const LaunchArgs &a, const CtrlArgs &c, double lb, double ub) {
+  if (c.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ctrl_init_pop, dim3(c.max_n, c.n), dim3(CT_TRIAL_THREADS_INIT), 0, a.stream,
+                     a.runs, c.list, a.pop, a.pending, a.k0, a.k1, lb, ub);
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ctrl_eval<false, true>), dim3((c.max_n + 1) / 2, c.n),
+                     dim3(64), 0, a.stream, a.runs, c.list, a.probs, a.tab, a.fit, a.pending, c.fu,
+                     c.acc, TraceArgs{nullptr, nullptr, nullptr});
+  return hipGetLastError();
+}
+
+hipError_t launch_ctrl_generations(const LaunchArgs &a, const CtrlArgs &c, uint32_t g0,
+                                   uint32_t n_gens, float lb, float ub, TraceArgs tr) {
+  if (c.n == 0) return hipSuccess;
+  const dim3 tgrid(c.max_n, c.n), egrid((c.max_n + 1) / 2, c.n);
+  for (uint32_t g = g0; g < g0 + n_gens; ++g) {
+    hipLaunchKernelGGL(k_ctrl_rank, dim3(c.n), dim3(CT_MAX_N), 0, a.stream, a.runs, c.list, a.fit,
+                       c.order);
+    if (tr.u) {
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ctrl_trials<true>), tgrid, dim3(CT_TRIAL_THREADS), 0,
+                         a.stream, a.runs, c.list, a.pop, a.pending, c.order, g, lb, ub, a.k0,
+                         a.k1, tr);
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ctrl_eval<true, false>), egrid, dim3(64), 0, a.stream, a.runs,
+                         c.list, a.probs, a.tab, a.fit, a.pending, c.fu, c.acc, tr);
+    } else {
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ctrl_trials<false>), tgrid, dim3(CT_TRIAL_THREADS), 0,
+                         a.stream, a.runs, c.list, a.pop, a.pending, c.order, g, lb, ub, a.k0,
+                         a.k1, tr);
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ctrl_eval<false, false>), egrid, dim3(64), 0, a.stream, a.runs,
+                         c.list, a.probs, a.tab, a.fit, a.pending, c.fu, c.acc, tr);
+    }
+    hipLaunchKernelGGL(k_ctrl_commit, dim3(c.max_n, c.n), dim3(256), 0, a.stream, a.runs, c.list,
+                       a.pop, a.fit, a.pending, c.fu, c.acc);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_ctrl_finalize(const LaunchArgs &a, const CtrlArgs &c, double *best_y,
+                                float *best_x) {
+  if (c.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ctrl_finalize, dim3(c.n), dim3(64), 0, a.stream, a.runs, c.list, a.probs,
+                     a.tab, a.pop, a.fit, best_y, best_x);
+  return hipGetLastError();
+}
+
+}  // namespace mde

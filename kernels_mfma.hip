@@ -1,0 +1,613 @@
+// Matrix-core generation kernel of the MetaDE inner-DE path (gfx950).
+//
+// Used for runs whose trial rows do not fit in LDS next to the population
+// (large D) and for the bf16 precision mode.  One workgroup of 768 lanes per
+// run; lanes 0..511 are consumers, 512..767 producers of the next
+// generation's random draws (as in the lane-per-trial kernel).  The rotation
+// z = R (u - o) of all trials of a generation is a [N x D] x [D x D] product
+// done on the matrix cores: consumer wave w owns the 16-wide output tile w.
+// The bf16 mode keeps that tile's slice of R (split in bf16 parts) in
+// registers for the whole launch; the plain mode reads its float64
+// coefficients from the table for every block of k.
+//
+// Plain mode: v_mfma_f64_16x16x4 on y = u - o in float64 (exact), the same
+// accuracy as the lane kernel's float64 accumulation.
+// bf16 mode: the product is formed from bf16 splits, y R ~ y_hi R_hi +
+// y_hi R_lo + y_lo R_hi with v_mfma_f32_16x16x32_bf16 and float32
+// accumulation.  Each trial gets a certified bound E on |f_hat - f|; a trial
+// with f_hat - E > f(target) would be rejected by the plain evaluation too, so
+// it is rejected at once; every other trial is re-evaluated in plain mode (on
+// compacted row tiles) and decided from that value.  Decisions -- hence
+// trajectories -- are those of the plain mode as long as the bound holds.
+#include <hip/hip_bf16.h>
+
+#include "device.h"
+#include "gen_common.h"
+#include "kernels.h"
+
+namespace mde {
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+
+constexpr int KS64 = 32;      // float64 k-steps of 4 (D <= 128)
+constexpr int KSB = 4;        // bf16 k-steps of 32 (D <= 128)
+// |z_hat - z| <= E_COEF * ||u - o||_2 for the three-product bf16 split with
+// float32 accumulation: the residues of the two splits and the dropped
+// lo * lo product give 3 * 2^-16 sum_k |R_jk| |y_k|, float32 accumulation of
+// 3 * 128 products 384 * 2^-24 of the same sum, rounding u - o to float32
+// 2^-24; the sum is at most ||y||_2 (rows of R have unit norm), so the total
+// is below 7e-5 ||y||_2 and 2^-13 leaves a margin of 1.7.
+constexpr float E_COEF = 1.2207031e-4f;  // 2^-13
+
+// ---------------------------------------------------------------- rotation tiles
+
+// Plain mode.  Any consistent assignment of the physical k to (step, lane)
+// slots gives the same product, so the k order is permuted inside each block
+// of four steps: lane l feeds steps 4b..4b+3 with k = 16 b + 4 (l/16) + 0..3,
+// one contiguous float4 of its trial row.  Result element v is
+// z[16 rt + l/16 + 4v][16 ct + l%16].
+// RT row tiles at once (rows given per tile): RT independent accumulator
+// chains sharing the B loads, so that consecutive matrix-core instructions
+// do not wait on each other's results.
+constexpr int RT = 2;
+
+__device__ __forceinline__ void tiles_f64(const float *__restrict__ Tg, uint32_t Dk, uint32_t D,
+                                          const float *oc, const bool (&row_ok)[RT],
+                                          const uint32_t (&row_trial)[RT],
+                                          const double *__restrict__ Rt, uint32_t Dr, uint32_t j,
+                                          uint32_t lane, d4v (&acc)[RT]) {
+  const uint32_t kq = lane >> 4;
+  const uint32_t nb = (D + 15) / 16;  // blocks of 16 k (four steps of 4)
+  const bool jok = j < D;
+#pragma unroll
+  for (int r = 0; r < RT; ++r) acc[r] = d4v{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+  for (uint32_t b = 0; b < nb; ++b) {
+    const uint32_t kb = 16 * b + 4 * kq;
+    float4 tv[RT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+      tv[r] = row_ok[r] ? *reinterpret_cast<const float4 *>(Tg + (size_t)row_trial[r] * Dk + kb)
+                        : make_float4(0.f, 0.f, 0.f, 0.f);
+    double bv[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) bv[e] = (jok && kb + e < D) ? Rt[(size_t)(kb + e) * Dr + j] : 0.0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const bool kin = kb + e < D;
+      const double oe = kin ? (double)oc[kb + e] : 0.0;
+#pragma unroll
+      for (int r = 0; r < RT; ++r) {
+        const double a = kin ? (double)comp(tv[r], e) - oe : 0.0;
+        acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv[e], acc[r], 0, 0, 0);
+      }
+    }
+  }
+}
+
+// bf16 mode.  Lane l: A row 16 rt + l%16, k = 32 s + 8 (l/16) + e; result
+// element v is z_hat[16 rt + 4 (l/16) + v][16 ct + l%16].  ysq returns the
+// lane's share of ||y||^2 of its A row.
+__device__ __forceinline__ void tiles_bf16(const float *__restrict__ Tg, uint32_t Dk,
+                                           const float *oc, const bool (&row_ok)[RT],
+                                           const uint32_t (&row_trial)[RT],
+                                           const bf8v (&bhi)[KSB], const bf8v (&blo)[KSB],
+                                           uint32_t lane, f4v (&acc)[RT], float (&ysq)[RT]) {
+  const uint32_t Ksb = Dk / 32;
+#pragma unroll
+  for (int r = 0; r < RT; ++r) {
+    acc[r] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
+    ysq[r] = 0.0f;
+  }
+#pragma unroll
+  for (int s = 0; s < KSB; ++s) {
+    if ((uint32_t)s < Ksb) {
+      const uint32_t k0 = 32 * s + 8 * (lane >> 4);
+      bf8v ah[RT], al[RT];
+#pragma unroll
+      for (int r = 0; r < RT; ++r) {
+        float y[8];
+        if (row_ok[r]) {
+          const float *trow = Tg + (size_t)row_trial[r] * Dk + k0;
+          const float4 t0 = *reinterpret_cast<const float4 *>(trow);
+          const float4 t1 = *reinterpret_cast<const float4 *>(trow + 4);
+          y[0] = t0.x; y[1] = t0.y; y[2] = t0.z; y[3] = t0.w;
+          y[4] = t1.x; y[5] = t1.y; y[6] = t1.z; y[7] = t1.w;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) y[e] = y[e] - oc[k0 + e];
+        } else {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) y[e] = 0.0f;
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          ysq[r] = fmaf(y[e], y[e], ysq[r]);
+          const __bf16 h = (__bf16)y[e];
+          ah[r][e] = h;
+          al[r][e] = (__bf16)(y[e] - (float)h);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < RT; ++r) acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[r], bhi[s], acc[r], 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < RT; ++r) acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[r], blo[s], acc[r], 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < RT; ++r) acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[r], bhi[s], acc[r], 0, 0, 0);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- row-of-16 lane operations (DPP)
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
+// Sum over the 16 lanes of a row: quad_perm [1,0,3,2], quad_perm [2,3,0,1],
+// row_half_mirror, row_mirror.  Lane 0 of the row holds the sum in a fixed
+// order.
+__device__ __forceinline__ float row_sum16(float v) {
+  v += dpp<0xB1>(v);
+  v += dpp<0x4E>(v);
+  v += dpp<0x141>(v);
+  v += dpp<0x140>(v);
+  return v;
+}
+
+// Value of lane i+1 of the row (row_shl:1); lane 15 receives 0.
+__device__ __forceinline__ float row_next(float v) { return dpp<0x101>(v); }
+
+// ---------------------------------------------------------------- element terms and bounds
+
+// Per-column constants of a lane's output j: the element kind (the hybrid's
+// block resolved) and the elliptic weight.
+struct ColInfo {
+  uint32_t kind;
+  float w;
+};
+
+__device__ __forceinline__ ColInfo col_info(const unsigned char *tab, const ProbDev &p, uint32_t j) {
+  ColInfo c{p.kind, 0.0f};
+  if (j >= p.D) return c;
+  if (p.kind == FN_HYBRID) {
+    const uint32_t ek = tab_ptr<uint32_t>(tab, p.ek_off)[j];
+    c.kind = ek == 0 ? FN_SCHWEFEL : (ek == 1 ? FN_RASTRIGIN : FN_ELLIPTIC);
+  }
+  if (c.kind == FN_ELLIPTIC) c.w = tab_ptr<float>(tab, p.ew_off)[j];
+  return c;
+}
+
+// Element term of kind c.kind (Rosenbrock excluded), as elem_term.
+__device__ __forceinline__ void col_term(const ProbDev &p, const ColInfo &c, float v, float &t0,
+                                         float &t1) {
+  t1 = 0.0f;
+  switch (c.kind) {
+    case FN_RASTRIGIN: t0 = h_rastrigin<float>(v); break;
+    case FN_ELLIPTIC: t0 = c.w * (v * v); break;
+    case FN_ACKLEY: t0 = v * v; t1 = Math<float>::cos2pi(v); break;
+    case FN_SCHWEFEL: t0 = h_schwefel<float>(p, v); break;
+    default: t0 = 0.0f;
+  }
+}
+
+// Bound on |h(z_hat) - h(z)| for |z_hat - z| <= e, plus an allowance for the
+// float32 evaluation of the term t.
+__device__ __forceinline__ float term_bound(const ProbDev &p, const ColInfo &c, float zh, float e,
+                                            float t) {
+  const float az = fabsf(zh) + e;
+  float b;
+  switch (c.kind) {
+    case FN_RASTRIGIN: b = (2.0f * az + 62.83186f) * e; break;
+    case FN_ELLIPTIC: b = c.w * e * (2.0f * fabsf(zh) + e); break;
+    case FN_SCHWEFEL: b = (1.0f + 0.5f * sqrtf(fabsf(zh + SCHWEFEL_ZSTAR) + e)) * e; break;
+    case FN_ACKLEY: b = (4.0f * rsqrtf((float)p.D) + 17.1f / (float)p.D) * e; break;
+    default: b = __int_as_float(0x7F800000); break;  // no certified bound: always refine
+  }
+  return b * 1.0001f + 2.4e-7f * (fabsf(t) + 30.0f);
+}
+
+// Terms of the four results of a tile (rows given by trial[v], column j) and
+// their reduction over the 16 lanes of a row group.  Lane l%16 == 0 writes
+// the partial sums (and bounds) of its rows.
+template <bool BOUND>
+__device__ __forceinline__ void tile_epilogue(const ColInfo &ci, const ProbDev &p,
+                                              const float (&z)[4], const uint32_t (&slot)[4],
+                                              const bool (&ok)[4], const float (&e)[4],
+                                              uint32_t j, uint32_t D, uint32_t ct, uint32_t nslot,
+                                              uint32_t lane, float2 *Ps, float *Pb, float *zf,
+                                              float *zl) {
+  const bool rosen = p.kind == FN_ROSENBROCK;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    float t0 = 0.0f, t1 = 0.0f, bd = 0.0f;
+    const bool in = ok[v] && j < D;
+    if (rosen) {
+      const float zn = row_next(z[v]);
+      if (in && (lane & 15) < 15 && j + 1 < D) t0 = h_rosenbrock<float>(z[v], zn);
+      if (in && (lane & 15) == 0) zf[ct * nslot + slot[v]] = z[v];
+      if (in && (lane & 15) == 15) zl[ct * nslot + slot[v]] = z[v];
+      if (BOUND && in) bd = __int_as_float(0x7F800000);
+    } else if (in) {
+      col_term(p, ci, z[v], t0, t1);
+      if (BOUND) bd = term_bound(p, ci, z[v], e[v], t0);
+    }
+    t0 = row_sum16(t0);
+    if (p.kind == FN_ACKLEY) t1 = row_sum16(t1);
+    if (BOUND) bd = row_sum16(bd);
+    if (ok[v] && (lane & 15) == 0) {
+      Ps[ct * nslot + slot[v]] = make_float2(t0, t1);
+      if (BOUND) Pb[ct * nslot + slot[v]] = bd;
+    }
+  }
+}
+
+// Sum of the per-tile partials of slot s (and Rosenbrock's tile-boundary
+// terms); returns the float32 fitness.
+__device__ __forceinline__ float combine(const ProbDev &p, const float2 *Ps, const float *zf,
+                                         const float *zl, uint32_t NCT, uint32_t D, uint32_t nslot,
+                                         uint32_t s) {
+  double s0 = 0.0, s1 = 0.0;
+  for (uint32_t ct = 0; ct < NCT; ++ct) {
+    const float2 v = Ps[ct * nslot + s];
+    s0 += (double)v.x;
+    s1 += (double)v.y;
+  }
+  if (p.kind == FN_ROSENBROCK)
+    for (uint32_t ct = 0; ct + 1 < NCT; ++ct)
+      if (16 * ct + 16 < D) s0 += (double)h_rosenbrock<float>(zl[ct * nslot + s], zf[(ct + 1) * nslot + s]);
+  return finish_f32(p, s0, s1);
+}
+
+// ---------------------------------------------------------------- generation loop
+
+template <bool BF16, bool TRACE>
+__device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run,
+                                          const ProbDev &p, const unsigned char *__restrict__ tab,
+                                          float *__restrict__ pop, float *__restrict__ fit,
+                                          uint32_t g0, uint32_t n_gens, uint32_t k0, uint32_t k1,
+                                          float lb, float ub, float *__restrict__ Tg,
+                                          unsigned long long *__restrict__ counters,
+                                          const TraceArgs &tr) {
+  const uint32_t N = run.N, D = run.D, Dp = run.Dp, Dk = run.Dk, Q = Dp / 4, kp = run.kp,
+                 L = run.L, Np = run.Np, NCT = run.NCT;
+  const uint32_t NRT = (N + 15) / 16;
+  const bool rosen = p.kind == FN_ROSENBROCK;
+  const MLds lay = mfma_layout(N, Dp, Dk, L, Np, NCT, rosen);
+  float *pop_s = reinterpret_cast<float *>(smem + lay.pop);
+  uint64_t *key_s = reinterpret_cast<uint64_t *>(smem + lay.key);
+  float *fit_s = reinterpret_cast<float *>(smem + lay.fit);
+  uint32_t *topk = reinterpret_cast<uint32_t *>(smem + lay.topk);
+  uint32_t *rk = reinterpret_cast<uint32_t *>(smem + lay.rk);
+  uint8_t *msk = reinterpret_cast<uint8_t *>(smem + lay.msk);
+  uint4 *dsc = reinterpret_cast<uint4 *>(smem + lay.dsc);
+  float2 *Ps = reinterpret_cast<float2 *>(smem + lay.ps);
+  float *Pb = reinterpret_cast<float *>(smem + lay.pb);
+  float *zf = reinterpret_cast<float *>(smem + lay.zf);
+  float *zl = reinterpret_cast<float *>(smem + lay.zl);
+  float *oc = reinterpret_cast<float *>(smem + lay.oc);
+  uint32_t *cl = reinterpret_cast<uint32_t *>(smem + lay.cl);
+  uint32_t *cnt = reinterpret_cast<uint32_t *>(smem + lay.cnt);
+  const double *Rt = tab_ptr<double>(tab, p.r64t_off);
+  const uint32_t Dr = rt_stride(D);
+
+  const uint32_t tid = threadIdx.x;
+  const uint32_t lane = tid & 63;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const bool producer = tid >= MF_CONSUMERS;
+  const uint32_t ptid = tid - MF_CONSUMERS;
+  // ranking geometry: L parts of Np lanes
+  const uint32_t l = __builtin_amdgcn_readfirstlane(tid / Np);
+  const uint32_t ir = tid - l * Np;
+  const bool act_r = !producer && l < L && ir < N;
+  const uint32_t kr0 = l * N / L, kr1 = (l + 1) * N / L;
+  // decision lane of trial tid
+  const bool dec = !producer && tid < N;
+  // output tile of this consumer wave
+  const uint32_t ct = wave;
+  const bool has_ct = !producer && ct < NCT;
+  const uint32_t jcol = 16 * ct + (lane & 15);
+  const int use_rand = (run.bl == RAND || run.br == RAND) ? 1 : 0;
+
+  for (uint32_t u = tid; u < N * Dp; u += MF_THREADS) {
+    const uint32_t r = u / Dp, j = u - r * Dp;
+    pop_s[u] = j < D ? pop[run.pop_off + (size_t)r * D + j] : 0.0f;
+  }
+  for (uint32_t r = tid; r < N; r += MF_THREADS) {
+    const float f = fit[run.fit_off + r];
+    fit_s[r] = f;
+    key_s[r] = mkkey(f, r);
+  }
+  const float *og = tab_ptr<float>(tab, p.o_off);
+  for (uint32_t k = tid; k < Dk; k += MF_THREADS) oc[k] = k < D ? og[k] : 0.0f;
+  if (Dk > Dp)
+    for (uint32_t u = tid; u < N * (Dk - Dp); u += MF_THREADS) {
+      const uint32_t r = u / (Dk - Dp);
+      Tg[(size_t)r * Dk + Dp + (u - r * (Dk - Dp))] = 0.0f;
+    }
+  // this wave's slice of R: the bf16 splits stay in registers for the launch;
+  // the float64 slice is read from the table (L1/L2 resident) block by block
+  const ColInfo ci = col_info(tab, p, jcol);
+  bf8v bhi[KSB], blo[KSB];
+  {
+    const uint32_t kq = lane >> 4;
+#pragma unroll
+    for (int s = 0; s < KSB; ++s) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const uint32_t k = 32 * s + 8 * kq + e;
+        const float r = (BF16 && has_ct && k < D && jcol < D) ? (float)Rt[(size_t)k * Dr + jcol] : 0.0f;
+        const __bf16 h = (__bf16)r;
+        bhi[s][e] = h;
+        blo[s][e] = (__bf16)(r - (float)h);
+      }
+    }
+  }
+  if (producer) {
+    produce_masks(ptid, MF_THREADS - MF_CONSUMERS, run, N, Q, g0, k0, k1, msk);
+    produce_desc_direct(ptid, MF_THREADS - MF_CONSUMERS, run, N, D, kp, g0, k0, k1, dsc);
+  }
+  unsigned long long refined = 0;
+
+  for (uint32_t gg = 0; gg < n_gens; ++gg) {
+    const uint32_t g = g0 + gg;
+    __syncthreads();
+    // S0: partial ranks
+    if (act_r) {
+      const uint64_t ki = key_s[ir];
+      uint32_t c = 0, j = kr0;
+      for (; j + 8 <= kr1; j += 8) {
+        uint64_t kv[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) kv[q] = key_s[j + q];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) c += kv[q] < ki ? 1u : 0u;
+      }
+      for (; j < kr1; ++j) c += key_s[j] < ki ? 1u : 0u;
+      rk[l * Np + ir] = c;
+    }
+    __syncthreads();
+    // S1: top-p list; the decision lane keeps its target's fitness
+    float fx = 0.0f;
+    if (dec) fx = fit_s[tid];
+    if (act_r && l == 0) {
+      uint32_t rank = 0;
+      for (uint32_t ll = 0; ll < L; ++ll) rank += rk[ll * Np + ir];
+      if (rank < kp) topk[rank] = ir;
+    }
+    __syncthreads();
+    // S2: trial genes (trial, quad) -> global trial rows
+    if (!producer) {
+      for (uint32_t u = tid; u < N * Q; u += MF_CONSUMERS) {
+        const uint32_t i = u / Q, q = u - i * Q;
+        const uint4 d = dsc[i];
+        const uint32_t r0 = byte_of(d.z, 0), pb = byte_of(d.z, 1);
+        const uint32_t ibest = topk[0], ipb = topk[pb];
+        const uint32_t ibl = run.bl == RAND ? r0 : (run.bl == BEST ? ibest : (run.bl == PBEST ? ipb : i));
+        const uint32_t ibr = run.br == RAND ? r0 : (run.br == BEST ? ibest : (run.br == PBEST ? ipb : i));
+        const uint32_t nib = run.cs == BIN ? msk[i * Q + q] : 0u;
+        const float4 uu = trial_quad(pop_s, Dp, D, i, q, ibl, ibr, d, nib, run, lb, ub);
+        *reinterpret_cast<float4 *>(Tg + (size_t)i * Dk + 4 * q) = uu;
+        if (TRACE) {
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            if (4 * q + t < D) tr.u[run.pop_off + (size_t)i * D + 4 * q + t] = comp(uu, t);
+          if (q == 0) {
+            int32_t *o = tr.desc + (size_t)(run.fit_off + i) * 16;
+            o[0] = (int32_t)ibl;
+            o[1] = (int32_t)ibr;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+              const uint32_t word = k < 4 ? d.x : d.y;
+              o[2 + k] = (k / 2) < run.dn ? (int32_t)byte_of(word, k & 3) : -1;
+            }
+            o[10] = (int32_t)byte_of(d.z, 2);
+            o[11] = run.cs == EXP ? (int32_t)(d.z >> 24) : -1;
+            o[12] = (int32_t)pb;
+            o[13] = use_rand ? (int32_t)r0 : -1;
+            o[14] = run.cs == ARITH ? (int32_t)d.w : -1;
+            o[15] = 0;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // S3: rotation on the matrix cores + element terms; producers: masks of g+1
+    if (has_ct) {
+      for (uint32_t rt0 = 0; rt0 < NRT; rt0 += RT) {
+        bool rok[RT];
+        uint32_t rtr[RT];
+#pragma unroll
+        for (int r = 0; r < RT; ++r) {
+          rtr[r] = 16 * (rt0 + r) + (lane & 15);
+          rok[r] = rtr[r] < N;
+        }
+        if (BF16) {
+          f4v acc[RT];
+          float ysq[RT];
+          tiles_bf16(Tg, Dk, oc, rok, rtr, bhi, blo, lane, acc, ysq);
+#pragma unroll
+          for (int r = 0; r < RT; ++r) {
+            // ||y|| of A row (lane & 15): reduce the four k-quarters
+            float q = ysq[r];
+            q += __shfl_xor(q, 16);
+            q += __shfl_xor(q, 32);
+            const float ny = sqrtf(q) * 1.0001f;
+            float z[4], e[4];
+            uint32_t slot[4];
+            bool ok[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const uint32_t rr = 4 * (lane >> 4) + v;
+              slot[v] = 16 * (rt0 + r) + rr;
+              ok[v] = slot[v] < N;
+              z[v] = acc[r][v];
+              e[v] = E_COEF * __shfl(ny, (int)rr);
+            }
+            tile_epilogue<true>(ci, p, z, slot, ok, e, jcol, D, ct, N, lane, Ps, Pb, zf, zl);
+          }
+        } else {
+          d4v acc[RT];
+          tiles_f64(Tg, Dk, D, oc, rok, rtr, Rt, Dr, jcol, lane, acc);
+#pragma unroll
+          for (int r = 0; r < RT; ++r) {
+            float z[4], e[4];
+            uint32_t slot[4];
+            bool ok[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              slot[v] = 16 * (rt0 + r) + (lane >> 4) + 4 * v;
+              ok[v] = slot[v] < N;
+              z[v] = (float)acc[r][v];
+              e[v] = 0.0f;
+            }
+            tile_epilogue<false>(ci, p, z, slot, ok, e, jcol, D, ct, N, lane, Ps, Pb, zf, zl);
+          }
+        }
+      }
+    }
+    if (producer) produce_masks(ptid, MF_THREADS - MF_CONSUMERS, run, N, Q, g + 1, k0, k1, msk);
+    __syncthreads();
+    // S4: plain mode decides and commits; bf16 mode selects the candidates
+    bool cand = false;
+    float fh = 0.0f;
+    if (dec) {
+      fh = combine(p, Ps, zf, zl, NCT, D, N, tid);
+      if (!BF16) {
+        const bool a = accept_trial(fh, fx);
+        if (a) {
+          const float *trow = Tg + (size_t)tid * Dk;
+          for (uint32_t q = 0; q < Q; ++q)
+            st4(pop_s, tid * Dp + 4 * q, *reinterpret_cast<const float4 *>(trow + 4 * q));
+          fit_s[tid] = fh;
+          key_s[tid] = mkkey(fh, tid);
+        }
+        if (TRACE) {
+          tr.fu[run.fit_off + tid] = fh;
+          tr.desc[(size_t)(run.fit_off + tid) * 16 + 15] = a ? 1 : 0;
+        }
+      } else {
+        double bnd = 0.0;
+        for (uint32_t c2 = 0; c2 < NCT; ++c2) bnd += (double)Pb[c2 * N + tid];
+        bnd += 9.5367e-7 * (double)fabsf(fh);
+        cand = (fh == fh) && !((double)fh - bnd > (double)fx);
+      }
+    }
+    if (BF16) {
+      // deterministic compaction of the candidates (ascending trial index)
+      const unsigned long long bal = __ballot(cand);
+      if (!producer && lane == 0) cnt[wave] = (uint32_t)__popcll(bal);
+      __syncthreads();
+      uint32_t base = 0, total = 0;
+      for (uint32_t w = 0; w < MF_CONSUMERS / 64; ++w) {
+        const uint32_t cw = cnt[w];
+        if (w < wave) base += cw;
+        total += cw;
+      }
+      if (cand) {
+        const uint32_t pos = base + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
+        cl[pos] = tid;
+      }
+      __syncthreads();
+      // S5: plain re-evaluation of the candidates on compacted row tiles
+      if (has_ct) {
+        for (uint32_t rt0 = 0; rt0 < (total + 15) / 16; rt0 += RT) {
+          bool rok[RT];
+          uint32_t rtr[RT];
+#pragma unroll
+          for (int r = 0; r < RT; ++r) {
+            const uint32_t srow = 16 * (rt0 + r) + (lane & 15);
+            rok[r] = srow < total;
+            rtr[r] = rok[r] ? cl[srow] : 0u;
+          }
+          d4v acc[RT];
+          tiles_f64(Tg, Dk, D, oc, rok, rtr, Rt, Dr, jcol, lane, acc);
+#pragma unroll
+          for (int r = 0; r < RT; ++r) {
+            float z[4], e[4];
+            uint32_t slot[4];
+            bool ok[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              slot[v] = 16 * (rt0 + r) + (lane >> 4) + 4 * v;
+              ok[v] = slot[v] < total;
+              z[v] = (float)acc[r][v];
+              e[v] = 0.0f;
+            }
+            tile_epilogue<false>(ci, p, z, slot, ok, e, jcol, D, ct, N, lane, Ps, Pb, zf, zl);
+          }
+        }
+      }
+      __syncthreads();
+      // S6: decisions of the candidates from their plain values, commit
+      if (!producer && tid < total) {
+        const uint32_t t = cl[tid];
+        const float f = combine(p, Ps, zf, zl, NCT, D, N, tid);
+        if (accept_trial(f, fit_s[t])) {
+          const float *trow = Tg + (size_t)t * Dk;
+          for (uint32_t q = 0; q < Q; ++q)
+            st4(pop_s, t * Dp + 4 * q, *reinterpret_cast<const float4 *>(trow + 4 * q));
+          fit_s[t] = f;
+          key_s[t] = mkkey(f, t);
+        }
+      }
+      refined += total;
+    }
+    if (producer) produce_desc_direct(ptid, MF_THREADS - MF_CONSUMERS, run, N, D, kp, g + 1, k0, k1, dsc);
+  }
+  __syncthreads();
+  for (uint32_t u = tid; u < N * D; u += MF_THREADS) {
+    const uint32_t r = u / D, j = u - r * D;
+    pop[run.pop_off + u] = pop_s[r * Dp + j];
+  }
+  for (uint32_t r = tid; r < N; r += MF_THREADS) fit[run.fit_off + r] = fit_s[r];
+  if (BF16 && tid == 0) atomicAdd(counters, refined);
+}
+
+template <bool BF16, bool TRACE>
+__global__ __launch_bounds__(MF_THREADS) void k_generations_mfma(
+    const RunDev *__restrict__ runs, const uint32_t *__restrict__ list,
+    const ProbDev *__restrict__ probs, const unsigned char *__restrict__ tab,
+    float *__restrict__ pop, float *__restrict__ fit, uint32_t g0, uint32_t n_gens, uint32_t k0,
+    uint32_t k1, float lb, float ub, float *__restrict__ tbuf,
+    unsigned long long *__restrict__ counters, TraceArgs tr) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const RunDev run = runs[list[blockIdx.x]];
+  const ProbDev p = probs[run.prob];
+  mfma_body<BF16, TRACE>(smem, run, p, tab, pop, fit, g0, n_gens, k0, k1, lb, ub,
+                         tbuf + run.pend_off, counters, tr);
+}
+
+hipError_t set_lds_limits_mfma() {
+  const void *ks[4] = {(const void *)k_generations_mfma<false, false>,
+                       (const void *)k_generations_mfma<false, true>,
+                       (const void *)k_generations_mfma<true, false>,
+                       (const void *)k_generations_mfma<true, true>};
+  for (const void *k : ks) {
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BUDGET);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_generations_mfma(const LaunchArgs &a, const uint32_t *list, uint32_t n,
+                                   bool bf16, uint32_t g0, uint32_t n_gens, float lb, float ub,
+                                   unsigned long long *counters, TraceArgs tr) {
+  if (n == 0) return hipSuccess;
+  const bool trace = tr.u != nullptr;
+#define MDE_LAUNCH(B, T)                                                                       \
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_generations_mfma<B, T>), dim3(n), dim3(MF_THREADS),     \
+                     a.mfma_lds_bytes, a.stream, a.runs, list, a.probs, a.tab, a.pop, a.fit, g0, \
+                     n_gens, a.k0, a.k1, lb, ub, a.pending, counters, tr)
+  if (bf16) {
+    if (trace) MDE_LAUNCH(true, true); else MDE_LAUNCH(true, false);
+  } else {
+    if (trace) MDE_LAUNCH(false, true); else MDE_LAUNCH(false, false);
+  }
+#undef MDE_LAUNCH
+  return hipGetLastError();
+}
+
+}  // namespace mde
