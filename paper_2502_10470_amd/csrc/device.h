@@ -144,12 +144,12 @@ constexpr uint32_t INIT_THREADS = 256;
 
 // LDS of the generation kernel: population [N][Dp] (row-major, float4 rows
 // for the gathers of the mutation), 64-bit ranking keys, fitness, the top-p
-// list, per-part partial fitness sums and ranks, the producers' Philox words
-// [N][12], binomial mask nibbles [N][Q] and packed draws [N], and -- when it
+// list, per-part partial fitness sums, the producers' binomial mask
+// nibbles [2][N][Q] (two generations) and packed draws [N], and -- when it
 // fits -- the trial rows stored gene-major ([D][Np]) so that lane i reading
 // gene k of its own trial touches consecutive words.
 struct Lds {
-  uint32_t pop, key, fit, topk, ps, rk, wb, msk, dsc, T, total;
+  uint32_t pop, key, fit, topk, ps, msk, dsc, T, total;
 };
 
 __host__ __device__ inline uint32_t al16(uint32_t b) { return (b + 15u) & ~15u; }
@@ -163,9 +163,7 @@ __host__ __device__ inline Lds lds_layout(uint32_t N, uint32_t Dp, uint32_t L, u
   l.fit = o;  o += al16(N * 4);
   l.topk = o; o += al16(MAX_KP * 4);
   l.ps = o;   o += al16(L * Np * 16);
-  l.rk = o;   o += al16(L * Np * 4);
-  l.wb = o;   o += al16(N * 12 * 4);
-  l.msk = o;  o += al16(N * (Dp / 4));
+  l.msk = o;  o += al16(2 * N * (Dp / 4));   // two generations: read g, write g+1
   l.dsc = o;  o += al16(N * 16);
   l.T = o;    o += t_lds ? al16(Dp * Np * 4) : 0u;
   l.total = o;

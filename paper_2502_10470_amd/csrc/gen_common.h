@@ -37,81 +37,6 @@ __device__ __forceinline__ float finish_f32(const ProbDev &p, double s0, double 
 // binomial mask bits are functions of (seed, stream, generation, individual)
 // and theta only.  Producer lanes compute them one generation ahead.
 
-// Philox blocks of generation g: block b < 3 gives words 4b..4b+3 (kept for
-// the draws), block 3 + q gives the binomial uniforms of genes 4q..4q+3
-// (reduced at once to the mask nibble r <= CR).
-__device__ __forceinline__ void produce_words(uint32_t ptid, uint32_t nprod, const RunDev &run,
-                                              uint32_t N, uint32_t Q, uint32_t g, uint32_t k0,
-                                              uint32_t k1, uint32_t *wb, uint8_t *msk) {
-  const int use_rand = (run.bl == RAND || run.br == RAND) ? 1 : 0;
-  const int m = use_rand + 2 * run.dn;
-  const uint32_t NB = 3 + (run.cs == BIN ? Q : 0);
-  for (uint32_t it = ptid; it < N * NB; it += nprod) {
-    const uint32_t i = it / NB, b = it - i * NB;
-    if (b == 1 && m <= 4) continue;
-    const uint32_t blk = b < 3 ? b : W_GENE0 / 4 + (b - 3);
-    const uint4 w = philox(blk, i, g, run.stream, k0, k1);
-    if (b < 3) {
-      *reinterpret_cast<uint4 *>(wb + i * 12 + 4 * b) = w;
-    } else {
-      uint32_t nib = 0;
-#pragma unroll
-      for (int t = 0; t < 4; ++t) nib |= (unit_oc(word_of(w, t)) <= run.CR ? 1u : 0u) << t;
-      msk[i * Q + (b - 3)] = (uint8_t)nib;
-    }
-  }
-}
-
-// Packed draws of one trial: x = a0|b0|a1|b1, y = a2|b2|a3|b3 (difference
-// pairs), z = r0 | pbest rank << 8 | j_rand (or n) << 16 | L << 24, w = K.
-__device__ __forceinline__ void produce_desc(uint32_t ptid, uint32_t nprod, const RunDev &run,
-                                             uint32_t N, uint32_t D, uint32_t kp, uint32_t g,
-                                             uint32_t k0, uint32_t k1, const uint32_t *wb,
-                                             uint4 *dsc) {
-  const int use_rand = (run.bl == RAND || run.br == RAND) ? 1 : 0;
-  const int dn = run.dn;
-  const int m = use_rand + 2 * dn;
-  for (uint32_t i = ptid; i < N; i += nprod) {
-    uint32_t w[12];
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      const uint4 v = *reinterpret_cast<const uint4 *>(wb + i * 12 + 4 * b);
-      w[4 * b] = v.x; w[4 * b + 1] = v.y; w[4 * b + 2] = v.z; w[4 * b + 3] = v.w;
-    }
-    uint32_t dr[9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) dr[k] = 0;
-    sample_distinct(w, m, i, N, dr);
-    uint32_t pr[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) pr[k] = (k < 2 * dn) ? dr[use_rand + k] : 0u;
-    const uint32_t r0 = use_rand ? dr[0] : 0u;
-    const uint32_t pb = lemire(w[W_PBEST], kp);
-    const uint32_t jn = lemire(w[W_JRAND], D);
-    uint32_t Lx = 1;
-    if (run.cs == EXP) {
-      // censored geometric length: continue while uniform t (word 12 + t) <= CR
-      bool go = true;
-      uint32_t blk = W_GENE0 / 4;
-      while (go && Lx < D) {
-        const uint4 wr = philox(blk++, i, g, run.stream, k0, k1);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          if (go && Lx < D) {
-            if (unit_oc(word_of(wr, t)) <= run.CR) ++Lx; else go = false;
-          }
-        }
-      }
-    }
-    uint4 d;
-    d.x = pr[0] | (pr[1] << 8) | (pr[2] << 16) | (pr[3] << 24);
-    d.y = pr[4] | (pr[5] << 8) | (pr[6] << 16) | (pr[7] << 24);
-    d.z = r0 | (pb << 8) | (jn << 16) | (Lx << 24);
-    d.w = __float_as_uint(unit_oc(w[W_K]));
-    dsc[i] = d;
-  }
-}
-
 // Binomial mask nibbles of generation g only (Philox blocks 3 + q).
 __device__ __forceinline__ void produce_masks(uint32_t ptid, uint32_t nprod, const RunDev &run,
                                               uint32_t N, uint32_t Q, uint32_t g, uint32_t k0,

@@ -173,10 +173,11 @@ __global__ __launch_bounds__(INIT_THREADS) void k_init(const RunDev *__restrict_
 //
 // Consumer lane i of part l works on trial i: it builds genes 4q..4q+3 with
 // q = l mod L and the fitness outputs [l D / L, (l+1) D / L); the parts'
-// partial sums meet in LDS.  Per generation (five barriers):
-//   S0 partial ranks | S1 top-p list | S2 mutation + crossover |
-//   S3 fitness (producers: Philox words of g+1) | S4 selection + commit
-//   (producers: draws of g+1).
+// partial sums meet in LDS.  Per generation (four barriers):
+//   S0 ranks and top-p list | S2 mutation + crossover (producers:
+//   binomial masks of g+1, into the other mask buffer) | S3 fitness
+//   (producers: index draws, pbest rank, j_rand, K, L of g+1) |
+//   S4 selection + commit.
 
 template <bool TLDS, bool TRACE>
 __device__ __forceinline__ void gen_body(unsigned char *smem, const RunDev &run, const ProbDev &p,
@@ -193,8 +194,6 @@ __device__ __forceinline__ void gen_body(unsigned char *smem, const RunDev &run,
   float *fit_s = reinterpret_cast<float *>(smem + lay.fit);
   uint32_t *topk = reinterpret_cast<uint32_t *>(smem + lay.topk);
   double2 *Ps = reinterpret_cast<double2 *>(smem + lay.ps);
-  uint32_t *rk = reinterpret_cast<uint32_t *>(smem + lay.rk);
-  uint32_t *wb = reinterpret_cast<uint32_t *>(smem + lay.wb);
   uint8_t *msk = reinterpret_cast<uint8_t *>(smem + lay.msk);
   uint4 *dsc = reinterpret_cast<uint4 *>(smem + lay.dsc);
   float *T = TLDS ? reinterpret_cast<float *>(smem + lay.T) : pending + run.pend_off;
@@ -206,7 +205,6 @@ __device__ __forceinline__ void gen_body(unsigned char *smem, const RunDev &run,
   const uint32_t i = tid - l * Np;
   const bool act = !producer && l < L && i < N;
   const uint32_t j0 = l * D / L, j1 = (l + 1) * D / L;
-  const uint32_t kr0 = l * N / L, kr1 = (l + 1) * N / L;
   const int use_rand = (run.bl == RAND || run.br == RAND) ? 1 : 0;
 
   for (uint32_t u = tid; u < N * Dp; u += GEN_THREADS) {
@@ -219,39 +217,41 @@ __device__ __forceinline__ void gen_body(unsigned char *smem, const RunDev &run,
     key_s[r] = mkkey(f, r);
   }
   // draws of the first generation
-  if (producer) produce_words(ptid, GEN_CONSUMERS, run, N, Q, g0, k0, k1, wb, msk);
-  __syncthreads();
-  if (producer) produce_desc(ptid, GEN_CONSUMERS, run, N, D, kp, g0, k0, k1, wb, dsc);
+  if (producer) {
+    produce_masks(ptid, GEN_THREADS - GEN_CONSUMERS, run, N, Q, g0, k0, k1, msk + (g0 & 1u) * N * Q);
+    produce_desc_direct(ptid, GEN_THREADS - GEN_CONSUMERS, run, N, D, kp, g0, k0, k1, dsc);
+  }
 
   for (uint32_t gg = 0; gg < n_gens; ++gg) {
     const uint32_t g = g0 + gg;
     __syncthreads();
-    // S0: rank of individual i among this part's slice of the keys
-    if (act) {
-      const uint64_t ki = key_s[i];
-      uint32_t cnt = 0, j = kr0;
-      for (; j + 8 <= kr1; j += 8) {
-        uint64_t kv[8];
+    // S0: ranks and the top-p list (first is the best).  Four consumer lanes
+    // per individual each count the keys below it in a quarter of the
+    // population; lane shuffles add the four counts.
+    if (!producer) {
+      for (uint32_t base = 0; base < N; base += GEN_CONSUMERS / 4) {
+        const uint32_t ri = base + (tid >> 2), rq = tid & 3u;
+        uint32_t cnt = 0;
+        if (ri < N) {
+          const uint64_t ki = key_s[ri];
+          const uint32_t a = rq * N / 4, b = (rq + 1) * N / 4;
+          uint32_t j = a;
+          for (; j + 8 <= b; j += 8) {
+            uint64_t kv[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) kv[q] = key_s[j + q];
+            for (int q = 0; q < 8; ++q) kv[q] = key_s[j + q];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) cnt += kv[q] < ki ? 1u : 0u;
+            for (int q = 0; q < 8; ++q) cnt += kv[q] < ki ? 1u : 0u;
+          }
+          for (; j < b; ++j) cnt += key_s[j] < ki ? 1u : 0u;
+        }
+        cnt += __shfl_xor(cnt, 1);
+        cnt += __shfl_xor(cnt, 2);
+        if (ri < N && rq == 0 && cnt < kp) topk[cnt] = ri;
       }
-      for (; j < kr1; ++j) cnt += key_s[j] < ki ? 1u : 0u;
-      rk[l * Np + i] = cnt;
     }
     __syncthreads();
-    // S1: the top-p list (first is the best)
-    float fx = 0.0f;
-    if (act) {
-      fx = fit_s[i];
-      if (l == 0) {
-        uint32_t rank = 0;
-        for (uint32_t ll = 0; ll < L; ++ll) rank += rk[ll * Np + i];
-        if (rank < kp) topk[rank] = i;
-      }
-    }
-    __syncthreads();
+    const float fx = act ? fit_s[i] : 0.0f;
     // S2: mutation, crossover, clip -> this part's genes of trial i
     if (act) {
       const uint4 d = dsc[i];
@@ -275,8 +275,9 @@ __device__ __forceinline__ void gen_body(unsigned char *smem, const RunDev &run,
         o[14] = run.cs == ARITH ? (int32_t)d.w : -1;
         o[15] = 0;
       }
+      const uint8_t *mg = msk + (g & 1u) * N * Q;
       for (uint32_t q = l; q < Q; q += L) {
-        const uint32_t nib = run.cs == BIN ? msk[i * Q + q] : 0u;
+        const uint32_t nib = run.cs == BIN ? mg[i * Q + q] : 0u;
         const float4 uu = trial_quad(pop_s, Dp, D, i, q, ibl, ibr, d, nib, run, lb, ub);
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
@@ -288,6 +289,9 @@ __device__ __forceinline__ void gen_body(unsigned char *smem, const RunDev &run,
         }
       }
     }
+    if (producer)
+      produce_masks(ptid, GEN_THREADS - GEN_CONSUMERS, run, N, Q, g + 1, k0, k1,
+                    msk + ((g + 1) & 1u) * N * Q);
     __syncthreads();
     // S3: this part's share of the fitness; producers draw generation g+1
     if (act) {
@@ -295,7 +299,8 @@ __device__ __forceinline__ void gen_body(unsigned char *smem, const RunDev &run,
       eval_part(tab, p, D, j0, j1, T + i, ts, s0, s1);
       Ps[l * Np + i] = make_double2(s0, s1);
     }
-    if (producer) produce_words(ptid, GEN_CONSUMERS, run, N, Q, g + 1, k0, k1, wb, msk);
+    if (producer)
+      produce_desc_direct(ptid, GEN_THREADS - GEN_CONSUMERS, run, N, D, kp, g + 1, k0, k1, dsc);
     __syncthreads();
     // S4: greedy selection (every part takes the same decision) and commit
     if (act) {
@@ -329,7 +334,6 @@ __device__ __forceinline__ void gen_body(unsigned char *smem, const RunDev &run,
         }
       }
     }
-    if (producer) produce_desc(ptid, GEN_CONSUMERS, run, N, D, kp, g + 1, k0, k1, wb, dsc);
   }
   __syncthreads();
   for (uint32_t u = tid; u < N * D; u += GEN_THREADS) {
