@@ -63,17 +63,30 @@ __device__ __forceinline__ void tiles_f64(const float *__restrict__ Tg, uint32_t
   const bool jok = j < D;
 #pragma unroll
   for (int r = 0; r < RT; ++r) acc[r] = d4v{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 1
-  for (uint32_t b = 0; b < nb; ++b) {
+  // operands of block b: the lane's float4 of each trial row and four R coefficients
+  auto load = [&](uint32_t b, float4 (&tv)[RT], double (&bv)[4]) {
     const uint32_t kb = 16 * b + 4 * kq;
-    float4 tv[RT];
 #pragma unroll
     for (int r = 0; r < RT; ++r)
       tv[r] = row_ok[r] ? *reinterpret_cast<const float4 *>(Tg + (size_t)row_trial[r] * Dk + kb)
                         : make_float4(0.f, 0.f, 0.f, 0.f);
-    double bv[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) bv[e] = (jok && kb + e < D) ? Rt[(size_t)(kb + e) * Dr + j] : 0.0;
+  };
+  float4 tn[RT];
+  double bn[4];
+  load(0, tn, bn);
+#pragma unroll 1
+  for (uint32_t b = 0; b < nb; ++b) {
+    // the next block's loads are in flight while this block's products run
+    float4 tv[RT];
+    double bv[4];
+#pragma unroll
+    for (int r = 0; r < RT; ++r) tv[r] = tn[r];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) bv[e] = bn[e];
+    if (b + 1 < nb) load(b + 1, tn, bn);
+    const uint32_t kb = 16 * b + 4 * kq;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const bool kin = kb + e < D;
