@@ -245,7 +245,9 @@ metade_status plan_config(const metade_config *cfg, Plan &pl, std::string &msg) 
     d.pend_off = pl.pend_floats;
     d.fit_off = (uint32_t)pl.fit_n;
     d.bx_off = (uint32_t)pl.bx_n;
-    if (d.kern == 1) pl.pend_floats += (size_t)N * d.Dk;
+    // matrix-core runs: trial rows [N][Dk] float32, then the bf16 splits of
+    // u - o ([N][Dk] high parts and [N][Dk] low parts, as many bytes again)
+    if (d.kern == 1) pl.pend_floats += (size_t)N * d.Dk * 2;
     pl.pop_floats += (size_t)N * D;
     pl.fit_n += N;
     pl.bx_n += D;

@@ -171,16 +171,19 @@ __host__ __device__ inline Lds lds_layout(uint32_t N, uint32_t Dp, uint32_t L, u
 }
 
 // Matrix-core generation kernel (runs whose trial rows do not fit in LDS, and
-// the bf16 precision mode; 512 consumer + 256 producer lanes): trial rows live in a global buffer [N][Dk]
-// (Dk = D rounded up to 32, zero padding); LDS holds the population, ranking
-// state, the producers' mask nibbles and packed draws, per (output tile,
-// trial) partial sums and bounds, Rosenbrock boundary values, the shift, the
-// candidate list of the bf16 mode and per-wave counts.
+// the bf16 precision mode; 512 consumer + 256 producer lanes): trial rows live
+// in a global buffer [N][Dk] (Dk = D rounded up to 32, zero padding), followed
+// in the bf16 mode by the bf16 splits of y = u - o ([N][Dk] high parts, then
+// low parts); LDS holds the population, ranking state, the producers' mask
+// nibbles and packed draws, per (output tile, trial) partial sums and bounds,
+// Rosenbrock boundary values, the shift, the element kind and elliptic weight
+// of every output, the candidate list of the bf16 mode, per-wave counts and
+// the bf16 mode's ||y||^2 per trial.
 constexpr uint32_t MF_THREADS = 768;
 constexpr uint32_t MF_CONSUMERS = 512;
 
 struct MLds {
-  uint32_t pop, key, fit, topk, rk, msk, dsc, ps, pb, zf, zl, oc, cl, cnt, total;
+  uint32_t pop, key, fit, topk, rk, msk, dsc, ps, pb, zf, zl, oc, ek, ew, cl, cnt, ysq, total;
 };
 
 __host__ __device__ inline MLds mfma_layout(uint32_t N, uint32_t Dp, uint32_t Dk, uint32_t L,
@@ -199,8 +202,11 @@ __host__ __device__ inline MLds mfma_layout(uint32_t N, uint32_t Dp, uint32_t Dk
   l.zf = o;   o += rosen ? al16(NCT * N * 4) : 0u;
   l.zl = o;   o += rosen ? al16(NCT * N * 4) : 0u;
   l.oc = o;   o += al16(Dk * 4);
+  l.ek = o;   o += al16(Dk * 4);
+  l.ew = o;   o += al16(Dk * 4);
   l.cl = o;   o += al16(N * 4);
   l.cnt = o;  o += al16(16 * 4);
+  l.ysq = o;  o += al16(N * 4);
   l.total = o;
   return l;
 }

@@ -43,11 +43,13 @@ constexpr float E_COEF = 1.2207031e-4f;  // 2^-13
 
 // ---------------------------------------------------------------- rotation tiles
 
-// Plain mode.  Any consistent assignment of the physical k to (step, lane)
-// slots gives the same product, so the k order is permuted inside each block
-// of four steps: lane l feeds steps 4b..4b+3 with k = 16 b + 4 (l/16) + 0..3,
-// one contiguous float4 of its trial row.  Result element v is
-// z[16 rt + l/16 + 4v][16 ct + l%16].
+// Plain mode.  The product is formed transposed, z^T = R y^T: the A operand
+// is the wave's 16 rows of R, the B operand 16 trial rows, so that each lane
+// ends with one trial and four of its outputs.  Any consistent assignment of
+// the physical k to (step, lane) slots gives the same product, so the k order
+// is permuted inside each block of four steps: lane l feeds steps 4b..4b+3
+// with k = 16 b + 4 (l/16) + 0..3, one contiguous float4 of its trial row.
+// Result element v is z[trial 16 rt + l%16][output 16 ct + l/16 + 4v].
 // RT row tiles at once (rows given per tile): RT independent accumulator
 // chains sharing the B loads, so that consecutive matrix-core instructions
 // do not wait on each other's results.
@@ -94,26 +96,25 @@ __device__ __forceinline__ void tiles_f64(const float *__restrict__ Tg, uint32_t
 #pragma unroll
       for (int r = 0; r < RT; ++r) {
         const double a = kin ? (double)comp(tv[r], e) - oe : 0.0;
-        acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv[e], acc[r], 0, 0, 0);
+        acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[e], a, acc[r], 0, 0, 0);
       }
     }
   }
 }
 
-// bf16 mode.  Lane l: A row 16 rt + l%16, k = 32 s + 8 (l/16) + e; result
-// element v is z_hat[16 rt + 4 (l/16) + v][16 ct + l%16].  ysq returns the
-// lane's share of ||y||^2 of its A row.
-__device__ __forceinline__ void tiles_bf16(const float *__restrict__ Tg, uint32_t Dk,
-                                           const float *oc, const bool (&row_ok)[RT],
+// bf16 mode, transposed like the plain mode.  Lane l feeds trial 16 rt + l%16
+// with k = 32 s + 8 (l/16) + e; result element v is
+// z_hat[trial 16 rt + l%16][output 16 ct + 4 (l/16) + v].  The trial operands
+// are the bf16 splits of y = u - o written once per trial when it is built.
+__device__ __forceinline__ void tiles_bf16(const __bf16 *__restrict__ Yh,
+                                           const __bf16 *__restrict__ Yl, uint32_t Dk,
+                                           const bool (&row_ok)[RT],
                                            const uint32_t (&row_trial)[RT],
                                            const bf8v (&bhi)[KSB], const bf8v (&blo)[KSB],
-                                           uint32_t lane, f4v (&acc)[RT], float (&ysq)[RT]) {
+                                           uint32_t lane, f4v (&acc)[RT]) {
   const uint32_t Ksb = Dk / 32;
 #pragma unroll
-  for (int r = 0; r < RT; ++r) {
-    acc[r] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
-    ysq[r] = 0.0f;
-  }
+  for (int r = 0; r < RT; ++r) acc[r] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
   for (int s = 0; s < KSB; ++s) {
     if ((uint32_t)s < Ksb) {
@@ -121,62 +122,29 @@ __device__ __forceinline__ void tiles_bf16(const float *__restrict__ Tg, uint32_
       bf8v ah[RT], al[RT];
 #pragma unroll
       for (int r = 0; r < RT; ++r) {
-        float y[8];
+        const size_t off = (size_t)row_trial[r] * Dk + k0;
         if (row_ok[r]) {
-          const float *trow = Tg + (size_t)row_trial[r] * Dk + k0;
-          const float4 t0 = *reinterpret_cast<const float4 *>(trow);
-          const float4 t1 = *reinterpret_cast<const float4 *>(trow + 4);
-          y[0] = t0.x; y[1] = t0.y; y[2] = t0.z; y[3] = t0.w;
-          y[4] = t1.x; y[5] = t1.y; y[6] = t1.z; y[7] = t1.w;
-#pragma unroll
-          for (int e = 0; e < 8; ++e) y[e] = y[e] - oc[k0 + e];
+          ah[r] = *reinterpret_cast<const bf8v *>(Yh + off);
+          al[r] = *reinterpret_cast<const bf8v *>(Yl + off);
         } else {
 #pragma unroll
-          for (int e = 0; e < 8; ++e) y[e] = 0.0f;
-        }
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          ysq[r] = fmaf(y[e], y[e], ysq[r]);
-          const __bf16 h = (__bf16)y[e];
-          ah[r][e] = h;
-          al[r][e] = (__bf16)(y[e] - (float)h);
+          for (int e = 0; e < 8; ++e) ah[r][e] = al[r][e] = (__bf16)0.0f;
         }
       }
 #pragma unroll
-      for (int r = 0; r < RT; ++r) acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[r], bhi[s], acc[r], 0, 0, 0);
+      for (int r = 0; r < RT; ++r) acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bhi[s], al[r], acc[r], 0, 0, 0);
 #pragma unroll
-      for (int r = 0; r < RT; ++r) acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[r], blo[s], acc[r], 0, 0, 0);
+      for (int r = 0; r < RT; ++r) acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(blo[s], ah[r], acc[r], 0, 0, 0);
 #pragma unroll
-      for (int r = 0; r < RT; ++r) acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[r], bhi[s], acc[r], 0, 0, 0);
+      for (int r = 0; r < RT; ++r) acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bhi[s], ah[r], acc[r], 0, 0, 0);
     }
   }
 }
 
-// ---------------------------------------------------------------- row-of-16 lane operations (DPP)
-
-template <int CTRL>
-__device__ __forceinline__ float dpp(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
-}
-
-// Sum over the 16 lanes of a row: quad_perm [1,0,3,2], quad_perm [2,3,0,1],
-// row_half_mirror, row_mirror.  Lane 0 of the row holds the sum in a fixed
-// order.
-__device__ __forceinline__ float row_sum16(float v) {
-  v += dpp<0xB1>(v);
-  v += dpp<0x4E>(v);
-  v += dpp<0x141>(v);
-  v += dpp<0x140>(v);
-  return v;
-}
-
-// Value of lane i+1 of the row (row_shl:1); lane 15 receives 0.
-__device__ __forceinline__ float row_next(float v) { return dpp<0x101>(v); }
-
 // ---------------------------------------------------------------- element terms and bounds
 
-// Per-column constants of a lane's output j: the element kind (the hybrid's
-// block resolved) and the elliptic weight.
+// Constants of output j: the element kind (the hybrid's block resolved) and
+// the elliptic weight.
 struct ColInfo {
   uint32_t kind;
   float w;
@@ -222,38 +190,67 @@ __device__ __forceinline__ float term_bound(const ProbDev &p, const ColInfo &c, 
   return b * 1.0001f + 2.4e-7f * (fabsf(t) + 30.0f);
 }
 
-// Terms of the four results of a tile (rows given by trial[v], column j) and
-// their reduction over the 16 lanes of a row group.  Lane l%16 == 0 writes
-// the partial sums (and bounds) of its rows.
-template <bool BOUND>
-__device__ __forceinline__ void tile_epilogue(const ColInfo &ci, const ProbDev &p,
-                                              const float (&z)[4], const uint32_t (&slot)[4],
-                                              const bool (&ok)[4], const float (&e)[4],
-                                              uint32_t j, uint32_t D, uint32_t ct, uint32_t nslot,
-                                              uint32_t lane, float2 *Ps, float *Pb, float *zf,
-                                              float *zl) {
-  const bool rosen = p.kind == FN_ROSENBROCK;
+// Terms of the four results a lane holds after a transposed tile (one trial,
+// outputs j(v): 16 ct + l/16 + 4 v for the plain tiles (STRIDED), 16 ct +
+// 4 (l/16) + v for the bf16 tiles) and their sum over the tile's 16 outputs:
+// four local terms, then the four lane groups of the trial (lanes l, l+16,
+// l+32, l+48) by two shuffles.  Lanes 0..15 write the trial's partial sum (and
+// bound).  Rosenbrock pairs z_j with z_{j+1}; the pair that crosses into the
+// next output tile is formed from zl / zf when the tiles are combined.
+template <bool BOUND, bool STRIDED>
+__device__ __forceinline__ void tile_epilogue(const ProbDev &p, const uint32_t *ek_s,
+                                              const float *ew_s, const float (&z)[4],
+                                              uint32_t slot, bool ok, float e, uint32_t D,
+                                              uint32_t ct, uint32_t nslot, uint32_t lane,
+                                              float2 *Ps, float *Pb, float *zf, float *zl) {
+  const uint32_t grp = lane >> 4;
+  float t0 = 0.0f, t1 = 0.0f, bd = 0.0f;
+  if (p.kind == FN_ROSENBROCK) {
+    // successor of each element: the next lane group (same v, or v+1 when
+    // wrapping from group 3 to group 0) for STRIDED; the next element, or
+    // element 0 of the next lane group, otherwise
+    float up[4];
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    float t0 = 0.0f, t1 = 0.0f, bd = 0.0f;
-    const bool in = ok[v] && j < D;
-    if (rosen) {
-      const float zn = row_next(z[v]);
-      if (in && (lane & 15) < 15 && j + 1 < D) t0 = h_rosenbrock<float>(z[v], zn);
-      if (in && (lane & 15) == 0) zf[ct * nslot + slot[v]] = z[v];
-      if (in && (lane & 15) == 15) zl[ct * nslot + slot[v]] = z[v];
-      if (BOUND && in) bd = __int_as_float(0x7F800000);
-    } else if (in) {
-      col_term(p, ci, z[v], t0, t1);
-      if (BOUND) bd = term_bound(p, ci, z[v], e[v], t0);
+    for (int v = 0; v < 4; ++v) up[v] = __shfl(z[v], (int)((lane + 16) & 63));
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const uint32_t j = STRIDED ? 16 * ct + grp + 4 * v : 16 * ct + 4 * grp + v;
+      float zn;
+      if (STRIDED) zn = grp < 3 ? up[v] : (v < 3 ? up[v + 1] : 0.0f);
+      else zn = v < 3 ? z[v + 1] : up[0];
+      const bool inner = (j & 15) != 15 && j + 1 < D;
+      if (ok && inner) t0 += h_rosenbrock<float>(z[v], zn);
     }
-    t0 = row_sum16(t0);
-    if (p.kind == FN_ACKLEY) t1 = row_sum16(t1);
-    if (BOUND) bd = row_sum16(bd);
-    if (ok[v] && (lane & 15) == 0) {
-      Ps[ct * nslot + slot[v]] = make_float2(t0, t1);
-      if (BOUND) Pb[ct * nslot + slot[v]] = bd;
+    if (ok && grp == 0) zf[ct * nslot + slot] = z[0];
+    if (ok && grp == 3) zl[ct * nslot + slot] = z[3];
+    if (BOUND && ok) bd = __int_as_float(0x7F800000);
+  } else {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const uint32_t j = STRIDED ? 16 * ct + grp + 4 * v : 16 * ct + 4 * grp + v;
+      if (ok && j < D) {
+        const ColInfo c{ek_s[j], ew_s[j]};
+        float a0, a1;
+        col_term(p, c, z[v], a0, a1);
+        t0 += a0;
+        t1 += a1;
+        if (BOUND) bd += term_bound(p, c, z[v], e, a0);
+      }
     }
+  }
+  t0 += __shfl_xor(t0, 16);
+  t0 += __shfl_xor(t0, 32);
+  if (p.kind == FN_ACKLEY) {
+    t1 += __shfl_xor(t1, 16);
+    t1 += __shfl_xor(t1, 32);
+  }
+  if (BOUND) {
+    bd += __shfl_xor(bd, 16);
+    bd += __shfl_xor(bd, 32);
+  }
+  if (ok && grp == 0) {
+    Ps[ct * nslot + slot] = make_float2(t0, t1);
+    if (BOUND) Pb[ct * nslot + slot] = bd;
   }
 }
 
@@ -301,8 +298,14 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
   float *zf = reinterpret_cast<float *>(smem + lay.zf);
   float *zl = reinterpret_cast<float *>(smem + lay.zl);
   float *oc = reinterpret_cast<float *>(smem + lay.oc);
+  uint32_t *ek_s = reinterpret_cast<uint32_t *>(smem + lay.ek);
+  float *ew_s = reinterpret_cast<float *>(smem + lay.ew);
   uint32_t *cl = reinterpret_cast<uint32_t *>(smem + lay.cl);
   uint32_t *cnt = reinterpret_cast<uint32_t *>(smem + lay.cnt);
+  float *ysq_s = reinterpret_cast<float *>(smem + lay.ysq);
+  // bf16 mode: splits of y = u - o after the trial rows
+  __bf16 *Yh = reinterpret_cast<__bf16 *>(Tg + (size_t)N * Dk);
+  __bf16 *Yl = Yh + (size_t)N * Dk;
   const double *Rt = tab_ptr<double>(tab, p.r64t_off);
   const uint32_t Dr = rt_stride(D);
 
@@ -323,6 +326,9 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
   const bool has_ct = !producer && ct < NCT;
   const uint32_t jcol = 16 * ct + (lane & 15);
   const int use_rand = (run.bl == RAND || run.br == RAND) ? 1 : 0;
+  // trial construction: P lanes per trial, the largest power of two <= 32 with N P <= consumers
+  uint32_t P = 1;
+  while (P < 32 && N * (2 * P) <= MF_CONSUMERS) P *= 2;
 
   for (uint32_t u = tid; u < N * Dp; u += MF_THREADS) {
     const uint32_t r = u / Dp, j = u - r * Dp;
@@ -334,15 +340,24 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
     key_s[r] = mkkey(f, r);
   }
   const float *og = tab_ptr<float>(tab, p.o_off);
-  for (uint32_t k = tid; k < Dk; k += MF_THREADS) oc[k] = k < D ? og[k] : 0.0f;
+  for (uint32_t k = tid; k < Dk; k += MF_THREADS) {
+    oc[k] = k < D ? og[k] : 0.0f;
+    const ColInfo c = col_info(tab, p, k);
+    ek_s[k] = c.kind;
+    ew_s[k] = c.w;
+  }
   if (Dk > Dp)
     for (uint32_t u = tid; u < N * (Dk - Dp); u += MF_THREADS) {
       const uint32_t r = u / (Dk - Dp);
-      Tg[(size_t)r * Dk + Dp + (u - r * (Dk - Dp))] = 0.0f;
+      const size_t at = (size_t)r * Dk + Dp + (u - r * (Dk - Dp));
+      Tg[at] = 0.0f;
+      if (BF16) {
+        Yh[at] = (__bf16)0.0f;
+        Yl[at] = (__bf16)0.0f;
+      }
     }
   // this wave's slice of R: the bf16 splits stay in registers for the launch;
   // the float64 slice is read from the table (L1/L2 resident) block by block
-  const ColInfo ci = col_info(tab, p, jcol);
   bf8v bhi[KSB], blo[KSB];
   {
     const uint32_t kq = lane >> 4;
@@ -391,23 +406,48 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
       if (rank < kp) topk[rank] = ir;
     }
     __syncthreads();
-    // S2: trial genes (trial, quad) -> global trial rows
+    // S2: trial genes -> global trial rows.  P lanes per trial (a power of
+    // two, as many as the consumers allow) take its quads in turn; in the bf16
+    // mode they also write the splits of y = u - o and combine ||y||^2 by shuffles.
     if (!producer) {
-      for (uint32_t u = tid; u < N * Q; u += MF_CONSUMERS) {
-        const uint32_t i = u / Q, q = u - i * Q;
-        const uint4 d = dsc[i];
-        const uint32_t r0 = byte_of(d.z, 0), pb = byte_of(d.z, 1);
-        const uint32_t ibest = topk[0], ipb = topk[pb];
-        const uint32_t ibl = run.bl == RAND ? r0 : (run.bl == BEST ? ibest : (run.bl == PBEST ? ipb : i));
-        const uint32_t ibr = run.br == RAND ? r0 : (run.br == BEST ? ibest : (run.br == PBEST ? ipb : i));
-        const uint32_t nib = run.cs == BIN ? msk[i * Q + q] : 0u;
-        const float4 uu = trial_quad(pop_s, Dp, D, i, q, ibl, ibr, d, nib, run, lb, ub);
-        *reinterpret_cast<float4 *>(Tg + (size_t)i * Dk + 4 * q) = uu;
-        if (TRACE) {
+      const uint32_t lp = tid & (P - 1), per = MF_CONSUMERS / P;
+      for (uint32_t i0 = 0; i0 < N; i0 += per) {
+        const uint32_t i = i0 + tid / P;
+        const bool valid = i < N;
+        float part = 0.0f;
+        if (valid) {
+          const uint4 d = dsc[i];
+          const uint32_t r0 = byte_of(d.z, 0), pb = byte_of(d.z, 1);
+          const uint32_t ibest = topk[0], ipb = topk[pb];
+          const uint32_t ibl = run.bl == RAND ? r0 : (run.bl == BEST ? ibest : (run.bl == PBEST ? ipb : i));
+          const uint32_t ibr = run.br == RAND ? r0 : (run.br == BEST ? ibest : (run.br == PBEST ? ipb : i));
+          for (uint32_t q = lp; q < Q; q += P) {
+            const uint32_t nib = run.cs == BIN ? msk[i * Q + q] : 0u;
+            const float4 uu = trial_quad(pop_s, Dp, D, i, q, ibl, ibr, d, nib, run, lb, ub);
+            *reinterpret_cast<float4 *>(Tg + (size_t)i * Dk + 4 * q) = uu;
+            if (BF16) {
+              uint32_t hb[4], lb16[4];
 #pragma unroll
-          for (int t = 0; t < 4; ++t)
-            if (4 * q + t < D) tr.u[run.pop_off + (size_t)i * D + 4 * q + t] = comp(uu, t);
-          if (q == 0) {
+              for (int t = 0; t < 4; ++t) {
+                const float y = comp(uu, t) - oc[4 * q + t];
+                part = fmaf(y, y, part);
+                const __bf16 h = (__bf16)y;
+                const __bf16 lo = (__bf16)(y - (float)h);
+                hb[t] = __builtin_bit_cast(uint16_t, h);
+                lb16[t] = __builtin_bit_cast(uint16_t, lo);
+              }
+              *reinterpret_cast<uint2 *>(Yh + (size_t)i * Dk + 4 * q) =
+                  make_uint2(hb[0] | (hb[1] << 16), hb[2] | (hb[3] << 16));
+              *reinterpret_cast<uint2 *>(Yl + (size_t)i * Dk + 4 * q) =
+                  make_uint2(lb16[0] | (lb16[1] << 16), lb16[2] | (lb16[3] << 16));
+            }
+            if (TRACE) {
+#pragma unroll
+              for (int t = 0; t < 4; ++t)
+                if (4 * q + t < D) tr.u[run.pop_off + (size_t)i * D + 4 * q + t] = comp(uu, t);
+            }
+          }
+          if (TRACE && lp == 0) {
             int32_t *o = tr.desc + (size_t)(run.fit_off + i) * 16;
             o[0] = (int32_t)ibl;
             o[1] = (int32_t)ibr;
@@ -424,6 +464,10 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
             o[15] = 0;
           }
         }
+        if (BF16) {
+          for (uint32_t sft = 1; sft < P; sft <<= 1) part += __shfl_xor(part, (int)sft);
+          if (valid && lp == 0) ysq_s[i] = part;
+        }
       }
     }
     __syncthreads();
@@ -439,44 +483,23 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
         }
         if (BF16) {
           f4v acc[RT];
-          float ysq[RT];
-          tiles_bf16(Tg, Dk, oc, rok, rtr, bhi, blo, lane, acc, ysq);
+          tiles_bf16(Yh, Yl, Dk, rok, rtr, bhi, blo, lane, acc);
 #pragma unroll
           for (int r = 0; r < RT; ++r) {
-            // ||y|| of A row (lane & 15): reduce the four k-quarters
-            float q = ysq[r];
-            q += __shfl_xor(q, 16);
-            q += __shfl_xor(q, 32);
-            const float ny = sqrtf(q) * 1.0001f;
-            float z[4], e[4];
-            uint32_t slot[4];
-            bool ok[4];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              const uint32_t rr = 4 * (lane >> 4) + v;
-              slot[v] = 16 * (rt0 + r) + rr;
-              ok[v] = slot[v] < N;
-              z[v] = acc[r][v];
-              e[v] = E_COEF * __shfl(ny, (int)rr);
-            }
-            tile_epilogue<true>(ci, p, z, slot, ok, e, jcol, D, ct, N, lane, Ps, Pb, zf, zl);
+            const float z[4] = {acc[r][0], acc[r][1], acc[r][2], acc[r][3]};
+            const float e = rok[r] ? E_COEF * (sqrtf(ysq_s[rtr[r]]) * 1.0001f) : 0.0f;
+            tile_epilogue<true, false>(p, ek_s, ew_s, z, rtr[r], rok[r], e, D, ct, N, lane, Ps,
+                                       Pb, zf, zl);
           }
         } else {
           d4v acc[RT];
           tiles_f64(Tg, Dk, D, oc, rok, rtr, Rt, Dr, jcol, lane, acc);
 #pragma unroll
           for (int r = 0; r < RT; ++r) {
-            float z[4], e[4];
-            uint32_t slot[4];
-            bool ok[4];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              slot[v] = 16 * (rt0 + r) + (lane >> 4) + 4 * v;
-              ok[v] = slot[v] < N;
-              z[v] = (float)acc[r][v];
-              e[v] = 0.0f;
-            }
-            tile_epilogue<false>(ci, p, z, slot, ok, e, jcol, D, ct, N, lane, Ps, Pb, zf, zl);
+            const float z[4] = {(float)acc[r][0], (float)acc[r][1], (float)acc[r][2],
+                                (float)acc[r][3]};
+            tile_epilogue<false, true>(p, ek_s, ew_s, z, rtr[r], rok[r], 0.0f, D, ct, N, lane,
+                                       Ps, Pb, zf, zl);
           }
         }
       }
@@ -539,17 +562,11 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
           tiles_f64(Tg, Dk, D, oc, rok, rtr, Rt, Dr, jcol, lane, acc);
 #pragma unroll
           for (int r = 0; r < RT; ++r) {
-            float z[4], e[4];
-            uint32_t slot[4];
-            bool ok[4];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              slot[v] = 16 * (rt0 + r) + (lane >> 4) + 4 * v;
-              ok[v] = slot[v] < total;
-              z[v] = (float)acc[r][v];
-              e[v] = 0.0f;
-            }
-            tile_epilogue<false>(ci, p, z, slot, ok, e, jcol, D, ct, N, lane, Ps, Pb, zf, zl);
+            const float z[4] = {(float)acc[r][0], (float)acc[r][1], (float)acc[r][2],
+                                (float)acc[r][3]};
+            const uint32_t slot = 16 * (rt0 + r) + (lane & 15);   // position in the candidate list
+            tile_epilogue<false, true>(p, ek_s, ew_s, z, slot, rok[r], 0.0f, D, ct, N, lane, Ps,
+                                       Pb, zf, zl);
           }
         }
       }
