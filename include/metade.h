@@ -73,6 +73,22 @@ typedef enum {
   METADE_BF16_REFINE = 1
 } metade_precision;
 
+/* Evolver of the outer loop.
+ *   DE:  DE/rand/1/bin with F = 0.5, CR = 0.9 (Alg. 3).
+ *   PSO: particle swarm with inertia 0.729 and acceleration 1.49 + 1.49, the
+ *        alternative evolver of the paper's supplement (S.III).  Positions
+ *        start at the DE evolver's initial population with zero velocity; outer
+ *        generation 0 scores them, later generations first move every particle
+ *        (v = w v + c1 r1 (p - x) + c2 r2 (g - x), x = clip(x + v), float32 in
+ *        that order; r1, r2 from Philox words k and 6 + k of (particle, outer
+ *        generation) on the evolver's stream), then score; a personal best is
+ *        replaced iff the new score <= its score.  In metade_get_outer, X and y
+ *        are the personal bests, U and y_trial the current positions and scores. */
+typedef enum {
+  METADE_EVOLVER_DE = 0,
+  METADE_EVOLVER_PSO = 1
+} metade_evolver;
+
 /* Objective functions: z = R (u - o) [+ c], f = g(z) + bias (textbook base
  * functions standing in for the paper's CEC2022 suite, Sec. IV-A). */
 typedef enum {
@@ -123,6 +139,7 @@ typedef struct {
   double *best_y;
   float *best_x;
   void *stream;                    /* hipStream_t (NULL = default stream) */
+  uint32_t evolver;                /* metade_evolver */
 } metade_config;
 
 /* Sizes in bytes of the caller-owned buffers and of the library's internal
@@ -180,16 +197,20 @@ metade_status metade_trace_sizes(metade_ctx *ctx, size_t *u_bytes, size_t *fu_by
  * Available for METADE_FP32 contexts only (METADE_EINVAL otherwise). */
 metade_status metade_inner_step_trace(metade_ctx *ctx, float *u, float *fu, int32_t *desc);
 
-/* Evolver (Alg. 3).  The context's runs are the P = n_runs executors of one
- * outer population.  metade_outer_reset draws the initial population in the
- * theta box on the device and sets every fitness to +inf. */
+/* Evolver (Alg. 3; metade_config.evolver selects DE or PSO).  The context's
+ * runs are the P = n_runs executors of one outer population.
+ * metade_outer_reset draws the initial population in the theta box on the
+ * device and sets every fitness to +inf (PSO: positions = that population,
+ * velocities 0). */
 metade_status metade_outer_reset(metade_ctx *ctx);
 
-/* One outer generation: DE/rand/1/bin trial vectors (F = 0.5, CR = 0.9),
+/* One outer generation: DE/rand/1/bin trial vectors (F = 0.5, CR = 0.9) --
+ * or, for PSO, the moved particle positions (none moved in generation 0) --
  * clipped and decoded into the runs' theta; all executors re-initialised
  * (same streams: one-shot evaluation) and run for G_inner generations
  * (G_inner * power_up if power_up > 1: Sec. III-D); y* of each run; the
- * trial replaces its target iff y*(trial) <= y(target).  Asynchronous. */
+ * trial replaces its target (PSO: the position replaces the personal best)
+ * iff y*(trial) <= y(target).  Asynchronous. */
 metade_status metade_outer_step(metade_ctx *ctx, uint32_t G_inner, uint32_t power_up);
 
 /* Copy the evolver state to host memory (synchronises): X[n_runs][6],

@@ -11,6 +11,7 @@ Restates Alg. 3 and Secs. III-B..III-E of the paper:
   * the last outer generation runs the executors for 5 G' generations
     (power-up, Sec. III-D);
   * selection keeps the trial iff its score <= the target's.
+A particle-swarm evolver (Supplement S.III) is restated below as well.
 
 The evolver draws its random numbers from the executor's Philox layout with
 the stream word's top bit set, so the two never share counters.
@@ -53,18 +54,81 @@ def outer_select(X, y, U, y_trial):
             accept)
 
 
-def run_metade(wl, gens=None, power_up=None, decide="f32", executor=None, log=None):
-    """Alg. 3 on a workload with an outer loop.  Returns the evolver state and
-    the best (theta, y, x) found."""
+# ---------------------------------------------------------------- PSO evolver
+#
+# The paper's supplement (S.III) compares DE with PSO as the evolver, using
+# the recommended inertia w = 0.729 and acceleration c1 = c2 = 1.49.  The
+# particle swarm is the textbook one, restated here:
+#   * positions start where the DE evolver's population starts, velocities at
+#     zero, personal-best scores at +inf;
+#   * outer generation 0 scores the initial positions; from generation 1 on,
+#     every particle first moves:
+#         v <- w v + c1 r1 (p - x) + c2 r2 (g - x),   x <- clip(x + v)
+#     with r1, r2 uniform in [0, 1) per coordinate, p the particle's personal
+#     best and g the best personal best (first in (score, index) order);
+#   * a particle's personal best becomes its position iff the position's score
+#     <= the personal-best score (the rule of the DE evolver's selection).
+# Readings: float32 arithmetic in the order written, one rounding per
+# operation; positions are clipped to the theta box, velocities are not;
+# r1 and r2 of coordinate k are Philox words k and 6 + k of (particle, g_o) on
+# the evolver's stream, mapped to (w >> 8) 2^-24.
+
+PSO_W, PSO_C1, PSO_C2 = np.float32(0.729), np.float32(1.49), np.float32(1.49)
+
+
+def pso_init(P, seed, stream, n_cs):
+    X, y = outer_init(P, seed, stream, n_cs)
+    return {"x": X.copy(), "v": np.zeros_like(X), "p": X.copy(), "py": y}
+
+
+def pso_move(st, g_o, seed, stream, n_cs):
+    """Velocities and positions of outer generation g_o >= 1."""
+    lo, hi = theta_bounds(n_cs)
+    P = st["x"].shape[0]
+    w = philox.words(seed, np.arange(P), g_o, outer_stream(stream), 12)
+    r = ((w >> np.uint64(8)).astype(np.float64) * 2.0 ** -24).astype(np.float32)
+    r1, r2 = r[:, 0:6], r[:, 6:12]
+    gi = int(np.lexsort((np.arange(P), order_key(st["py"])))[0])
+    x, v, p = st["x"], st["v"], st["p"]
+    g = p[gi][None, :]
+    a = (PSO_C1 * r1) * (p - x)
+    b = (PSO_C2 * r2) * (g - x)
+    v = ((PSO_W * v) + a) + b
+    x = np.minimum(np.maximum(x + v, lo), hi)
+    st = dict(st)
+    st["v"] = v.astype(np.float32)
+    st["x"] = x.astype(np.float32)
+    return st
+
+
+def pso_select(st, y_new):
+    better = ~np.isnan(y_new) & (order_key(y_new) <= order_key(st["py"]))
+    st = dict(st)
+    st["p"] = np.where(better[:, None], st["x"], st["p"]).astype(np.float32)
+    st["py"] = np.where(better, y_new, st["py"])
+    return st, better
+
+
+def run_metade(wl, gens=None, power_up=None, decide="f32", executor=None, log=None,
+               evolver="de"):
+    """Alg. 3 on a workload with an outer loop (evolver "de"; "pso" swaps in the
+    particle swarm of the supplement).  Returns the evolver state and the best
+    (theta, y, x) found."""
     o = wl.outer
     P = o["P"]
     gens = o["gens"] if gens is None else gens
     pu = o.get("power_up", 5) if power_up is None else power_up
     stream = int(wl.stream[0])
     X, y = outer_init(P, wl.seed, stream, wl.n_cs)
+    st = pso_init(P, wl.seed, stream, wl.n_cs) if evolver == "pso" else None
     best_x = np.zeros((P, wl.D_of(0)), np.float32)
     for g_o in range(gens):
-        U, _ = outer_trials(X, y, g_o, wl.seed, stream, wl.n_cs, o["F"], o["CR"])
+        if evolver == "pso":
+            if g_o > 0:
+                st = pso_move(st, g_o, wl.seed, stream, wl.n_cs)
+            U = st["x"]
+        else:
+            U, _ = outer_trials(X, y, g_o, wl.seed, stream, wl.n_cs, o["F"], o["CR"])
         dec = decode(U, wl.n_cs)
         G = wl.G * (pu if g_o == gens - 1 else 1)
         ys = np.empty(P)
@@ -79,7 +143,11 @@ def run_metade(wl, gens=None, power_up=None, decide="f32", executor=None, log=No
                                    wl.lb, wl.ub, prob, decide)
             ys[i] = res["y"]
             xs[i] = res["best_x"]
-        X, y, acc = outer_select(X, y, U, ys)
+        if evolver == "pso":
+            st, acc = pso_select(st, ys)
+            X, y = st["p"], st["py"]
+        else:
+            X, y, acc = outer_select(X, y, U, ys)
         best_x = np.where(acc[:, None], xs, best_x)
         if log is not None:
             log.append({"g": g_o, "U": U, "y_trial": ys, "accept": acc})

@@ -29,7 +29,7 @@ struct EventPair {
 
 struct metade_ctx {
   hipStream_t stream = nullptr;
-  uint32_t n_runs = 0, n_cs = 2, precision = 0;
+  uint32_t n_runs = 0, n_cs = 2, precision = 0, evolver = 0;
   uint64_t seed = 0;
   float lb = 0, ub = 0;
   float *pop = nullptr, *fit = nullptr, *best_x = nullptr;
@@ -49,7 +49,7 @@ struct metade_ctx {
   unsigned long long *counters_d = nullptr;
   uint32_t gen = 0;
   // evolver
-  float *Xo = nullptr, *Uo = nullptr, *bxo = nullptr;
+  float *Xo = nullptr, *Uo = nullptr, *Vo = nullptr, *bxo = nullptr;  // Vo: PSO velocities
   double *yo = nullptr, *yt = nullptr;
   int32_t *bidx = nullptr;
   unsigned char *tab = nullptr; // read-only problem tables (shift, float64 rotation, weights)
@@ -100,6 +100,9 @@ metade_status plan_config(const metade_config *cfg, Plan &pl, std::string &msg) 
   if (cfg->n_cs != 2 && cfg->n_cs != 3) { msg = "n_cs must be 2 or 3"; return METADE_EINVAL; }
   if (cfg->precision != METADE_FP32 && cfg->precision != METADE_BF16_REFINE) {
     msg = "precision must be METADE_FP32 or METADE_BF16_REFINE"; return METADE_EINVAL;
+  }
+  if (cfg->evolver != METADE_EVOLVER_DE && cfg->evolver != METADE_EVOLVER_PSO) {
+    msg = "evolver must be METADE_EVOLVER_DE or METADE_EVOLVER_PSO"; return METADE_EINVAL;
   }
   pl.probs.resize(cfg->n_problems);
   const double zs = mde::SCHWEFEL_ZSTAR;
@@ -348,7 +351,7 @@ metade_status metade_query_sizes(const metade_config *cfg, size_t *pop_bytes, si
   if (best_x_bytes) *best_x_bytes = pl.bx_n * sizeof(float);
   if (scratch_bytes)
     *scratch_bytes = pl.runs.size() * sizeof(RunDev) + pl.probs.size() * sizeof(ProbDev) +
-                     pl.pend_floats * sizeof(float) + (size_t)cfg->n_runs * (6 * 4 * 2 + 16) +
+                     pl.pend_floats * sizeof(float) + (size_t)cfg->n_runs * (6 * 4 * 3 + 16) +
                      pl.bx_n * sizeof(float) + 16;
   if (scratch_bytes) *scratch_bytes += pl.tab_bytes;
   if (scratch_bytes && !pl.ctrl_list.empty())
@@ -370,6 +373,7 @@ metade_status metade_init(const metade_config *cfg, metade_ctx **out) {
   c->n_runs = cfg->n_runs;
   c->n_cs = cfg->n_cs;
   c->precision = cfg->precision;
+  c->evolver = cfg->evolver;
   c->seed = cfg->seed;
   c->lb = cfg->lb;
   c->ub = cfg->ub;
@@ -418,6 +422,7 @@ metade_status metade_init(const metade_config *cfg, metade_ctx **out) {
   if ((st = dalloc(c, &c->pend_d, c->pend_floats)) != METADE_OK) return bail(st);
   if ((st = dalloc(c, &c->Xo, (size_t)c->n_runs * 6)) != METADE_OK) return bail(st);
   if ((st = dalloc(c, &c->Uo, (size_t)c->n_runs * 6)) != METADE_OK) return bail(st);
+  if ((st = dalloc(c, &c->Vo, (size_t)c->n_runs * 6)) != METADE_OK) return bail(st);
   if ((st = dalloc(c, &c->yo, c->n_runs)) != METADE_OK) return bail(st);
   if ((st = dalloc(c, &c->yt, c->n_runs)) != METADE_OK) return bail(st);
   if ((st = dalloc(c, &c->bxo, c->bx_n)) != METADE_OK) return bail(st);
@@ -554,6 +559,12 @@ metade_status metade_outer_reset(metade_ctx *c) {
                                     (uint32_t)(c->seed & 0xFFFFFFFFu), (uint32_t)(c->seed >> 32),
                                     c->n_cs, c->stream));
   HIP_TRY(c, hipMemsetAsync(c->bxo, 0, c->bx_n * sizeof(float), c->stream));
+  if (c->evolver == METADE_EVOLVER_PSO) {
+    // particles start at the initial population, at rest
+    HIP_TRY(c, hipMemcpyAsync(c->Uo, c->Xo, (size_t)c->n_runs * 6 * sizeof(float),
+                              hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->Vo, 0, (size_t)c->n_runs * 6 * sizeof(float), c->stream));
+  }
   c->outer_gen = 0;
   c->outer_ready = true;
   return METADE_OK;
@@ -563,9 +574,20 @@ metade_status metade_outer_step(metade_ctx *c, uint32_t G_inner, uint32_t power_
   if (!c) return fail(nullptr, METADE_EINVAL, "ctx is NULL");
   if (!c->outer_ready) return fail(c, METADE_ESTATE, "metade_outer_reset must come first");
   const uint32_t G = G_inner * (power_up > 1 ? power_up : 1);
-  HIP_TRY(c, mde::launch_outer_trial(c->Xo, c->Uo, c->runs_d, c->n_runs, c->outer_gen,
-                                     c->runs_h[0].stream, (uint32_t)(c->seed & 0xFFFFFFFFu),
-                                     (uint32_t)(c->seed >> 32), c->n_cs, c->stream));
+  const uint32_t k0 = (uint32_t)(c->seed & 0xFFFFFFFFu), k1 = (uint32_t)(c->seed >> 32);
+  if (c->evolver == METADE_EVOLVER_PSO) {
+    if (c->outer_gen == 0) {
+      HIP_TRY(c, mde::launch_decode(c->runs_d, c->Uo, c->n_runs, c->n_cs, c->stream));
+    } else {
+      HIP_TRY(c, mde::launch_outer_best(c->yo, c->n_runs, c->bidx, c->stream));
+      HIP_TRY(c, mde::launch_pso_move(c->Uo, c->Vo, c->Xo, c->bidx, c->runs_d, c->n_runs,
+                                      c->outer_gen, c->runs_h[0].stream, k0, k1, c->n_cs,
+                                      c->stream));
+    }
+  } else {
+    HIP_TRY(c, mde::launch_outer_trial(c->Xo, c->Uo, c->runs_d, c->n_runs, c->outer_gen,
+                                       c->runs_h[0].stream, k0, k1, c->n_cs, c->stream));
+  }
   TRY(reinit(c));
   TRY(run_generations(c, G, mde::TraceArgs{nullptr, nullptr, nullptr}));
   TRY(finalize(c));
@@ -635,7 +657,7 @@ metade_status metade_get_state(metade_ctx *c, void *blob, size_t *bytes) {
   if (!c || !bytes) return fail(c, METADE_EINVAL, "ctx and bytes are required");
   const size_t n = c->n_runs;
   const size_t need = sizeof(StateHeader) + c->pop_floats * 4 + c->fit_n * 4 + n * 6 * 4 +
-                      n * sizeof(RunDev) + n * 8 + c->bx_n * 4 + n * 6 * 4 * 2 + n * 8 * 2 +
+                      n * sizeof(RunDev) + n * 8 + c->bx_n * 4 + n * 6 * 4 * 3 + n * 8 * 2 +
                       c->bx_n * 4;
   if (!blob) { *bytes = need; return METADE_OK; }
   if (*bytes < need) return fail(c, METADE_EINVAL, "state buffer too small");
@@ -658,6 +680,7 @@ metade_status metade_get_state(metade_ctx *c, void *blob, size_t *bytes) {
   HIP_TRY(c, d2h(c->best_x, c->bx_n * 4));
   HIP_TRY(c, d2h(c->Xo, n * 6 * 4));
   HIP_TRY(c, d2h(c->Uo, n * 6 * 4));
+  HIP_TRY(c, d2h(c->Vo, n * 6 * 4));
   HIP_TRY(c, d2h(c->yo, n * 8));
   HIP_TRY(c, d2h(c->yt, n * 8));
   HIP_TRY(c, d2h(c->bxo, c->bx_n * 4));
@@ -701,6 +724,7 @@ metade_status metade_set_state(metade_ctx *c, const void *blob, size_t bytes) {
   HIP_TRY(c, h2d(c->best_x, c->bx_n * 4));
   HIP_TRY(c, h2d(c->Xo, n * 6 * 4));
   HIP_TRY(c, h2d(c->Uo, n * 6 * 4));
+  HIP_TRY(c, h2d(c->Vo, n * 6 * 4));
   HIP_TRY(c, h2d(c->yo, n * 8));
   HIP_TRY(c, h2d(c->yt, n * 8));
   HIP_TRY(c, h2d(c->bxo, c->bx_n * 4));
@@ -766,6 +790,7 @@ void metade_destroy(metade_ctx *c) {
   (void)hipFree(c->pend_d);
   (void)hipFree(c->Xo);
   (void)hipFree(c->Uo);
+  (void)hipFree(c->Vo);
   (void)hipFree(c->yo);
   (void)hipFree(c->yt);
   (void)hipFree(c->bxo);

@@ -525,6 +525,44 @@ __global__ void k_outer_select(float *__restrict__ X, double *__restrict__ y,
   }
 }
 
+// Particle-swarm evolver (the paper's supplement, S.III): move every particle
+// from its position U, velocity V, personal best X and the swarm's best X[g],
+// v = w v + c1 r1 (p - x) + c2 r2 (g - x), x = clip(x + v) in float32 in that
+// order; r1, r2 are Philox words k and 6 + k of (particle, g_o).  The new
+// position is decoded into the particle's executor.
+constexpr float PSO_W = 0.729f, PSO_C1 = 1.49f, PSO_C2 = 1.49f;
+
+__global__ void k_pso_move(float *__restrict__ U, float *__restrict__ V,
+                           const float *__restrict__ X, const int32_t *__restrict__ gbest,
+                           RunDev *__restrict__ runs, uint32_t P, uint32_t g_o, uint32_t stream,
+                           uint32_t k0, uint32_t k1, uint32_t n_cs) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P) return;
+  const uint32_t st = stream | OUTER_BIT;
+  const uint4 a = philox(0, i, g_o, st, k0, k1);
+  const uint4 b = philox(1, i, g_o, st, k0, k1);
+  const uint4 c = philox(2, i, g_o, st, k0, k1);
+  const uint32_t w[12] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w};
+  const uint32_t g = (uint32_t)gbest[0];
+  float t[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const float r1 = (float)(w[k] >> 8) * 0x1p-24f;
+    const float r2 = (float)(w[6 + k] >> 8) * 0x1p-24f;
+    const float x = U[i * 6 + k];
+    const float pa = (PSO_C1 * r1) * (X[i * 6 + k] - x);
+    const float ga = (PSO_C2 * r2) * (X[g * 6 + k] - x);
+    const float v = ((PSO_W * V[i * 6 + k]) + pa) + ga;
+    float lo, hi;
+    theta_box(n_cs, k, lo, hi);
+    const float xn = fminf(fmaxf(x + v, lo), hi);
+    V[i * 6 + k] = v;
+    U[i * 6 + k] = xn;
+    t[k] = xn;
+  }
+  decode_into(runs[i], t, n_cs);
+}
+
 __global__ void k_outer_best(const double *__restrict__ y, uint32_t P, int32_t *__restrict__ out) {
   __shared__ double sv[256];
   __shared__ int32_t si[256];
@@ -634,6 +672,14 @@ hipError_t launch_outer_select(float *X, double *y, const float *U, const double
                                const RunDev *runs, uint32_t P, hipStream_t s) {
   hipLaunchKernelGGL(k_outer_select, dim3(P), dim3(64), 0, s, X, y, U, y_run, y_trial, bxo, best_x,
                      runs, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_pso_move(float *U, float *V, const float *X, const int32_t *gbest, RunDev *runs,
+                           uint32_t P, uint32_t g_o, uint32_t stream, uint32_t k0, uint32_t k1,
+                           uint32_t n_cs, hipStream_t s) {
+  hipLaunchKernelGGL(k_pso_move, dim3((P + 63) / 64), dim3(64), 0, s, U, V, X, gbest, runs, P, g_o,
+                     stream, k0, k1, n_cs);
   return hipGetLastError();
 }
 

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(HERE, "libmetade.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE = 0, -1, -2, -3, -4
 FP32, BF16_REFINE = 0, 1
+EVOLVER_DE, EVOLVER_PSO = 0, 1
 FN = {"rastrigin": 1, "rosenbrock": 2, "ackley": 3, "elliptic": 4, "schwefel": 5, "hybrid": 6,
       "lqr_mlp": 7}
 
@@ -44,6 +45,7 @@ class MetadeConfig(ctypes.Structure):
         ("n_problems", _u32), ("problems", _vp), ("seed", ctypes.c_uint64),
         ("lb", ctypes.c_float), ("ub", ctypes.c_float), ("n_cs", _u32), ("precision", _u32),
         ("pop", _vp), ("fit", _vp), ("best_y", _vp), ("best_x", _vp), ("stream", _vp),
+        ("evolver", _u32),
     ]
 
 
@@ -226,7 +228,8 @@ def metade_destroy(ctx):
 class Batch:
     """A batch of executor runs on one GPU, built from a ``workloads.Workload``."""
 
-    def __init__(self, wl, precision: int = FP32, device: str = "cuda:0", stream=None):
+    def __init__(self, wl, precision: int = FP32, device: str = "cuda:0", stream=None,
+                 evolver: int = EVOLVER_DE):
         import torch
         if not torch.cuda.is_available():
             raise MetadeError("no GPU visible: the MetaDE library runs on the GPU only")
@@ -281,6 +284,7 @@ class Batch:
         cfg.ub = float(wl.ub)
         cfg.n_cs = int(wl.n_cs)
         cfg.precision = int(precision)
+        cfg.evolver = int(evolver)
         cfg.stream = self.stream.cuda_stream
         pop_b, fit_b, by_b, bx_b, _ = metade_query_sizes(cfg)
         self.pop = torch.zeros(pop_b // 4, dtype=torch.float32, device=dev)

@@ -166,3 +166,12 @@ def test_init_requires_buffers():
     with pytest.raises(M.MetadeError) as ei:
         M.metade_init(cfg)
     assert "device buffers" in str(ei.value)
+
+
+def test_unknown_evolver_rejected():
+    M = _lib()
+    cfg, keep = _cfg(M)
+    cfg.evolver = 2
+    with pytest.raises(M.MetadeError) as ei:
+        M.metade_query_sizes(cfg)
+    assert "evolver must be" in str(ei.value)

@@ -150,7 +150,7 @@ def test_outer_step_c1():
         Uo, _ = ometa.outer_trials(Xo, yo, g_o, wl.seed, 0, wl.n_cs)
         assert np.array_equal(U, Uo), f"outer trial vectors differ at g_o={g_o}"
         ys = np.empty(8)
-        amb_any = False
+        diverged = False
         for i in range(8):
             o = OracleRun(wl, i, theta_row=Uo[i])
             amb = False
@@ -159,12 +159,12 @@ def test_outer_step_c1():
                 amb |= bool(s["amb_rank"] or np.any(s["amb_sel"]))
             k = int(pde.ranking(o.fit)[0])
             ys[i] = float(evaluate(o.pop[k], o.prob))
-            if not amb:
-                assert abs(yt[i] - ys[i]) <= 1e-12 * abs(ys[i]), f"executor {i} score"
-            else:
-                amb_any = True  # near-tie on the way: either trajectory is valid
-        print("g_o", g_o, "ambiguous executors:", amb_any, flush=True)
-        if amb_any:
+            same = abs(yt[i] - ys[i]) <= 1e-12 * abs(ys[i])
+            # a near-tie on the way allows the other trajectory; otherwise the scores agree
+            assert same or amb, f"executor {i} score"
+            diverged |= not same
+        print("g_o", g_o, "an executor took the other side of a near-tie:", diverged, flush=True)
+        if diverged:
             break  # the two evolvers may now legitimately differ
         Xo, yo, acc = ometa.outer_select(Xo, yo, Uo, ys)
         assert np.array_equal(X2, Xo)

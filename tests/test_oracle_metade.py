@@ -7,6 +7,7 @@ import pytest
 
 import workloads as W
 from oracle import metade, pde
+from oracle import metade as ometa
 
 
 def _f32_round(q: Fraction) -> np.float32:
@@ -79,3 +80,90 @@ def test_c1_metade_deterministic_and_consistent():
     r = pde.run_executor(32, 10, th, 50, wl.seed, 0, -100, 100, wl.problems[0])
     assert r["y"] == a["best_y"]
     assert a["best_y"] >= 100.0
+
+
+# ---------------------------------------------------------------- PSO evolver (Supplement S.III)
+
+def _pso_state(P=6, seed=3, n_cs=2):
+    return ometa.pso_init(P, seed, 0, n_cs)
+
+
+def test_pso_init_matches_de_population_and_is_at_rest():
+    st = _pso_state()
+    X, y = ometa.outer_init(6, 3, 0, 2)
+    assert np.array_equal(st["x"], X) and np.array_equal(st["p"], X)
+    assert np.all(st["v"] == 0) and np.all(np.isinf(st["py"]))
+
+
+def test_pso_fixed_point_when_bests_coincide():
+    """p = g = x and v = 0: every term of the velocity update is zero."""
+    st = _pso_state()
+    x0 = st["x"][2].copy()
+    st["x"][:] = x0
+    st["p"][:] = x0
+    st["py"] = np.arange(6, dtype=np.float64)
+    moved = ometa.pso_move(st, 1, 3, 0, 2)
+    assert np.array_equal(moved["x"], st["x"]) and np.all(moved["v"] == 0)
+
+
+def test_pso_inertia_only():
+    """p = g = x: the new velocity is w v exactly (one rounding) and the
+    position moves by it (clipped to the box)."""
+    st = _pso_state()
+    x0 = np.array([0.5, 0.5, 2.5, 2.5, 2.5, 2.0], np.float32)
+    st["x"][:] = x0
+    st["p"][:] = x0
+    st["py"] = np.zeros(6)
+    st["v"] = np.full((6, 6), 0.25, np.float32)
+    moved = ometa.pso_move(st, 4, 3, 0, 2)
+    w = np.float32(0.729)
+    assert np.all(moved["v"] == w * np.float32(0.25))
+    assert np.all(moved["x"] == x0 + w * np.float32(0.25))
+
+
+def test_pso_attraction_moves_toward_bests_and_stays_in_box():
+    """With v = 0 and p, g on the same side of x, each coordinate moves toward
+    them by less than c1 |p - x| + c2 |g - x|; positions never leave the box."""
+    lo, hi = pde.theta_bounds(2)
+    rng = np.random.default_rng(0)
+    for trial in range(20):
+        st = _pso_state(P=8, seed=trial)
+        st["py"] = rng.permutation(8).astype(np.float64)
+        st["p"] = (lo + (hi - lo) * rng.random((8, 6))).astype(np.float32)
+        gi = int(np.argmin(st["py"]))
+        moved = ometa.pso_move(st, 2 + trial, trial, 0, 2)
+        assert np.all(moved["x"] >= lo) and np.all(moved["x"] <= hi)
+        d = moved["x"] - st["x"]
+        dp, dg = st["p"] - st["x"], st["p"][gi][None, :] - st["x"]
+        same = (np.sign(dp) == np.sign(dg)) & (dp != 0)
+        assert np.all(np.sign(d[same]) * np.sign(dp[same]) >= 0)
+        bound = 1.49 * np.abs(dp) + 1.49 * np.abs(dg) + 1e-6
+        assert np.all(np.abs(d) <= bound)
+
+
+def test_pso_selection_rule():
+    st = _pso_state(P=4)
+    st, acc = ometa.pso_select(st, np.array([1.0, np.nan, 3.0, 2.0]))
+    assert acc.tolist() == [True, False, True, True]       # first scores: every finite one
+    st["x"] = st["x"] + np.float32(0.01)
+    st2, acc = ometa.pso_select(st, np.array([1.0, 0.5, 3.5, np.nan]))
+    assert acc.tolist() == [True, True, False, False]      # <= keeps ties, NaN never
+    assert np.array_equal(st2["p"][0], st["x"][0]) and np.array_equal(st2["p"][2], st["p"][2])
+
+
+def test_pso_converges_on_a_quadratic():
+    """Personal-best scores never increase, and the swarm finds the minimum of
+    a convex function of theta inside the box."""
+    lo, hi = pde.theta_bounds(2)
+    c = np.array([0.3, 0.7, 2.2, 3.1, 1.7, 1.9], np.float32)
+    f = lambda X: np.sum((X.astype(np.float64) - c) ** 2, axis=1)
+    st = ometa.pso_init(16, 5, 0, 2)
+    best = np.inf
+    for g in range(60):
+        if g > 0:
+            st = ometa.pso_move(st, g, 5, 0, 2)
+        prev = st["py"].copy()
+        st, _ = ometa.pso_select(st, f(st["x"]))
+        assert np.all(st["py"] <= prev)
+        best = min(best, st["py"].min())
+    assert best < 1e-3
