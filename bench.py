@@ -220,13 +220,80 @@ def bench_batch(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_c3_repetitions(args, reps=4):
+    """Independent MetaDE repetitions of the default workload run concurrently,
+    one context and one HIP stream each (the paper repeats every experiment;
+    here the repetitions share the GPU, so together they occupy 4 x 64 CUs).
+    Same problem instance, Philox key 2 + 1000 r for repetition r."""
+    import dataclasses
+    import threading
+    import torch
+    import workloads as W
+    from paper_2502_10470_amd import Batch
+
+    base = W.workload_c3()
+    P, gens, G, pu = base.outer["P"], base.outer["gens"], base.G, base.outer["power_up"]
+    streams = [torch.cuda.Stream() for _ in range(reps)]
+    wls = [dataclasses.replace(base, seed=base.seed + 1000 * r) for r in range(reps)]
+    batches = [Batch(wl, stream=st) for wl, st in zip(wls, streams)]
+    evals = base.evals_per_pass() * reps
+
+    thetas = []
+    for b, wl in zip(batches, wls):
+        b.outer_reset()
+        th = []
+        for g in range(gens):
+            b.outer_step(G, pu if g == gens - 1 else 1)
+            th.append(b.get_outer()[2].copy())
+        thetas.append(th)
+    slots = sum(launch_slots(wl, th[g], G * (pu if g == gens - 1 else 1))
+                for wl, th in zip(wls, thetas) for g in range(gens))
+
+    best = [None] * reps
+
+    def one_pass():
+        def work(r):
+            best[r] = batches[r].run(gens, G, pu)
+        ts = [threading.Thread(target=work, args=(r,)) for r in range(reps)]
+        for t in ts:
+            t.start()
+        for t in ts:
+            t.join()
+
+    for _ in range(args.warmup):
+        one_pass()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        one_pass()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    achieved = slots * args.steps / dt
+    line = {
+        "metric": "inner-DE individual-evals/sec (runs x N x gens / s) at D=20",
+        "value": evals * args.steps / dt, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1000.0 * dt / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{reps} independent repetitions of full MetaDE at D=20, run "
+                               "concurrently on one GPU (one context and stream each)",
+                   "runs": P * reps, "N": 100, "D": 20, "inner_gens": G, "outer_gens": gens,
+                   "evals_per_step": evals, "best_y": [b[0] for b in best]},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_SLOTS / 1e12,
+                     "unit": "Tslot/s", "frac": achieved / VALU_PEAK_SLOTS, "traffic": None,
+                     "kernel": "k_generations (concurrent launches; work over the timed region)",
+                     "occupied_cu_frac": min(P * reps, 256) / 256.0},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c3", choices=["c3", "c4", "c2", "c5"],
-                    help="c3: full MetaDE at D=20 (default); c4: 128 runs x N=256 at D=100, "
+    ap.add_argument("--workload", default="c3", choices=["c3", "c3x4", "c4", "c2", "c5"],
+                    help="c3: full MetaDE at D=20 (default); c3x4: four independent "
+                         "repetitions of it, concurrently; c4: 128 runs x N=256 at D=100, "
                          "500 generations; c2: uneven batch of 256 runs, 200 generations; "
                          "c5: control workload, 16 runs x N=256 tanh policies (D=5702), "
                          "200-step rollouts, 100 generations")
@@ -256,6 +323,8 @@ def main():
     import workloads as W
     from paper_2502_10470_amd import Batch
 
+    if args.workload == "c3x4":
+        return bench_c3_repetitions(args)
     if args.workload != "c3":
         return bench_batch(args)
     wl = W.workload_c3()
