@@ -167,6 +167,7 @@ metade_status plan_config(const metade_config *cfg, Plan &pl, std::string &msg) 
     (void)cond;
     // read-only table layout of this problem
     p.o_off = take((size_t)q.D * sizeof(float));
+    p.o64_off = take((size_t)q.D * sizeof(double));
     p.r64t_off = take((size_t)q.D * mde::rt_stride(q.D) * sizeof(double));
     p.ew_off = take((size_t)q.D * sizeof(float));
     p.ew64_off = take((size_t)q.D * sizeof(double));
@@ -491,7 +492,8 @@ metade_status metade_init(const metade_config *cfg, metade_ctx **out) {
     if (e4 == hipSuccess) e4 = hipMemcpy(t + p.ek_off, ek.data(), p.D * sizeof(uint32_t), hipMemcpyHostToDevice);
     if (e4 == hipSuccess) e4 = hipMemcpy(t + p.o_off, q.o, p.D * sizeof(float), hipMemcpyDeviceToDevice);
     if (e4 == hipSuccess)
-      e4 = mde::launch_rot_t64(q.R, reinterpret_cast<double *>(t + p.r64t_off), p.D, c->stream);
+      e4 = mde::launch_tables64(q.R, q.o, reinterpret_cast<double *>(t + p.r64t_off),
+                                reinterpret_cast<double *>(t + p.o64_off), p.D, c->stream);
     if (e4 != hipSuccess) { c->err = std::string("problem tables: ") + hipGetErrorString(e4); return bail(METADE_EDEVICE); }
   }
   hipError_t e = mde::set_lds_limits();

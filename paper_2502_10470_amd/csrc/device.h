@@ -63,6 +63,7 @@ struct ProbDev {
   float bias, cs_f;             // cs = Schwefel constant z* sin(sqrt z*)
   double cs_d;
   uint64_t o_off;               // float  [D]    shift
+  uint64_t o64_off;             // double [D]    same in float64
   uint64_t r64t_off;            // double [D*D]  rotation transposed: element (k, j) = R[j][k]
   uint64_t ew_off;              // float  [D]    elliptic weight of output j
   uint64_t ew64_off;            // double [D]    same in float64
@@ -149,7 +150,7 @@ constexpr uint32_t INIT_THREADS = 256;
 // fits -- the trial rows stored gene-major ([D][Np]) so that lane i reading
 // gene k of its own trial touches consecutive words.
 struct Lds {
-  uint32_t pop, key, fit, topk, ps, msk, dsc, T, total;
+  uint32_t pop, key, fit, fx, topk, ps, msk, dsc, T, total;
 };
 
 __host__ __device__ inline uint32_t al16(uint32_t b) { return (b + 15u) & ~15u; }
@@ -161,6 +162,7 @@ __host__ __device__ inline Lds lds_layout(uint32_t N, uint32_t Dp, uint32_t L, u
   l.pop = o;  o += al16(N * Dp * 4);
   l.key = o;  o += al16(N * 8);
   l.fit = o;  o += al16(N * 4);
+  l.fx = o;   o += al16(N * 4);         // targets' fitness, frozen for the commit
   l.topk = o; o += al16(MAX_KP * 4);
   l.ps = o;   o += al16(L * Np * 16);
   l.msk = o;  o += al16(2 * N * (Dp / 4));   // two generations: read g, write g+1
@@ -253,6 +255,36 @@ __device__ __forceinline__ void sample_distinct(const uint32_t *w, int m, uint32
 
 template <typename T> struct Math;
 
+// sin(x) in float32 for |x| < 2^20 (the Schwefel term takes the sine of a
+// square root, which stays far below that for any finite box of practical
+// size): quadrant k = rint(2x / pi) and r = x - k pi/2 in float64 (|r| <= pi/4,
+// error below 1e-10), then the Taylor series of sin r to degree 13 or of cos r
+// to degree 12 in float64 (truncation below 4e-13) and one rounding.  Compact
+// enough to inline at every output of a fitness block.
+__device__ __forceinline__ float sin_reduced(float xf) {
+  const double x = (double)xf;
+  const double k = rint(x * 0.63661977236758134308);
+  const double r = fma(-k, 1.57079632679489661923, x);
+  const double r2 = r * r;
+  double ps = 1.0 / 6227020800.0;
+  ps = fma(ps, r2, -1.0 / 39916800.0);
+  ps = fma(ps, r2, 1.0 / 362880.0);
+  ps = fma(ps, r2, -1.0 / 5040.0);
+  ps = fma(ps, r2, 1.0 / 120.0);
+  ps = fma(ps, r2, -1.0 / 6.0);
+  const double sv = fma(ps * r2, r, r);
+  double pc = 1.0 / 479001600.0;
+  pc = fma(pc, r2, -1.0 / 3628800.0);
+  pc = fma(pc, r2, 1.0 / 40320.0);
+  pc = fma(pc, r2, -1.0 / 720.0);
+  pc = fma(pc, r2, 1.0 / 24.0);
+  pc = fma(pc, r2, -0.5);
+  const double cv = fma(pc, r2, 1.0);
+  const int q = (int)(int64_t)k & 3;
+  const double v = (q & 1) ? cv : sv;
+  return (float)((q & 2) ? -v : v);
+}
+
 template <> struct Math<float> {
   // cos(2 pi z): exact reduction r = z - rint(z) in [-1/2, 1/2], then the
   // hardware cosine, whose argument is in revolutions
@@ -260,7 +292,7 @@ template <> struct Math<float> {
     const float r = z - rintf(z);
     return __builtin_amdgcn_cosf(r);
   }
-  static __device__ __forceinline__ float sin_(float x) { return sinf(x); }
+  static __device__ __forceinline__ float sin_(float x) { return sin_reduced(x); }
   static __device__ __forceinline__ float sqrt_(float x) { return sqrtf(x); }
   static __device__ __forceinline__ float exp_(float x) { return expf(x); }
   static __device__ __forceinline__ float exp2_(float x) { return exp2f(x); }

@@ -39,7 +39,8 @@ struct CtrlArgs {
 };
 
 hipError_t set_lds_limits();
-hipError_t launch_rot_t64(const float *R, double *Rt, uint32_t D, hipStream_t s);
+hipError_t launch_tables64(const float *R, const float *o, double *Rt, double *o64, uint32_t D,
+                           hipStream_t s);
 hipError_t launch_init(const LaunchArgs &a, double lb, double ub);
 hipError_t launch_generations(const LaunchArgs &a, const uint32_t *list, uint32_t n,
                               uint32_t g0, uint32_t n_gens, float lb, float ub, TraceArgs tr);

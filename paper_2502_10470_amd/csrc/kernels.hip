@@ -22,7 +22,7 @@ namespace mde {
 template <int J, typename TP>
 __device__ __forceinline__ void rot_block(const double *__restrict__ Rt, uint32_t D, uint32_t Dr,
                                           uint32_t jc, TP t, uint32_t ts,
-                                          const float *__restrict__ o, double (&acc)[J]) {
+                                          const double *__restrict__ o, double (&acc)[J]) {
 #pragma unroll
   for (int q = 0; q < J; ++q) acc[q] = 0.0;
   const double *col = Rt + jc;
@@ -33,14 +33,14 @@ __device__ __forceinline__ void rot_block(const double *__restrict__ Rt, uint32_
     for (int kk = 0; kk < 8; ++kk) tv[kk] = t[(k + kk) * ts];
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk) {
-      const double yk = (double)tv[kk] - (double)o[k + kk];
+      const double yk = (double)tv[kk] - o[k + kk];
       const double *c = col + (size_t)(k + kk) * Dr;
 #pragma unroll
       for (int q = 0; q < J; ++q) acc[q] = fma(c[q], yk, acc[q]);
     }
   }
   for (; k < D; ++k) {
-    const double yk = (double)t[k * ts] - (double)o[k];
+    const double yk = (double)t[k * ts] - o[k];
     const double *c = col + (size_t)k * Dr;
 #pragma unroll
     for (int q = 0; q < J; ++q) acc[q] = fma(c[q], yk, acc[q]);
@@ -86,7 +86,7 @@ __device__ __forceinline__ void eval_part(const unsigned char *__restrict__ tab,
                                           double &s0, double &s1) {
   const double *Rt = tab_ptr<double>(tab, p.r64t_off);
   const uint32_t Dr = rt_stride(D);
-  const float *o = tab_ptr<float>(tab, p.o_off);
+  const double *o = tab_ptr<double>(tab, p.o64_off);
   TermAcc ta{0.0, 0.0, 0.0f, false};
   const uint32_t jend = p.kind == FN_ROSENBROCK ? min(j1 + 1, D) : j1;
   uint32_t jc = j0;
@@ -99,8 +99,7 @@ __device__ __forceinline__ void eval_part(const unsigned char *__restrict__ tab,
     consume<JJ>(tab, p, a, jc, min(rem, (uint32_t)JJ), j1, ta); \
     jc += JJ;                                                \
   }
-    if (rem > 12) MDE_BLOCK(16)
-    else if (rem > 10) MDE_BLOCK(12)
+    if (rem > 10) MDE_BLOCK(12)
     else if (rem > 8) MDE_BLOCK(10)
     else if (rem > 6) MDE_BLOCK(8)
     else if (rem == 6) MDE_BLOCK(6)
@@ -192,6 +191,7 @@ __device__ __forceinline__ void gen_body(unsigned char *smem, const RunDev &run,
   float *pop_s = reinterpret_cast<float *>(smem + lay.pop);
   uint64_t *key_s = reinterpret_cast<uint64_t *>(smem + lay.key);
   float *fit_s = reinterpret_cast<float *>(smem + lay.fit);
+  float *fx_s = reinterpret_cast<float *>(smem + lay.fx);
   uint32_t *topk = reinterpret_cast<uint32_t *>(smem + lay.topk);
   double2 *Ps = reinterpret_cast<double2 *>(smem + lay.ps);
   uint8_t *msk = reinterpret_cast<uint8_t *>(smem + lay.msk);
@@ -251,42 +251,56 @@ __device__ __forceinline__ void gen_body(unsigned char *smem, const RunDev &run,
       }
     }
     __syncthreads();
-    const float fx = act ? fit_s[i] : 0.0f;
-    // S2: mutation, crossover, clip -> this part's genes of trial i
-    if (act) {
-      const uint4 d = dsc[i];
-      const uint32_t r0 = byte_of(d.z, 0), pb = byte_of(d.z, 1);
-      const uint32_t ibest = topk[0], ipb = topk[pb];
-      const uint32_t ibl = run.bl == RAND ? r0 : (run.bl == BEST ? ibest : (run.bl == PBEST ? ipb : i));
-      const uint32_t ibr = run.br == RAND ? r0 : (run.br == BEST ? ibest : (run.br == PBEST ? ipb : i));
-      if (TRACE && l == 0) {
-        int32_t *o = tr.desc + (size_t)(run.fit_off + i) * 16;
-        o[0] = (int32_t)ibl;
-        o[1] = (int32_t)ibr;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          const uint32_t word = k < 4 ? d.x : d.y;
-          o[2 + k] = (k / 2) < run.dn ? (int32_t)byte_of(word, k & 3) : -1;
-        }
-        o[10] = (int32_t)byte_of(d.z, 2);
-        o[11] = run.cs == EXP ? (int32_t)(d.z >> 24) : -1;
-        o[12] = (int32_t)pb;
-        o[13] = use_rand ? (int32_t)r0 : -1;
-        o[14] = run.cs == ARITH ? (int32_t)d.w : -1;
-        o[15] = 0;
-      }
+    // S2: mutation, crossover, clip.  Consumer lane c builds quads it = c,
+    // c + 512, ... of the generation's N x Q quads (trial it / Q, genes
+    // 4 (it mod Q) .. +3): every lane has at most one quad more than any
+    // other, and lanes of one trial read neighbouring parts of the same
+    // source rows.  A lane's first quad stays in registers for the commit.
+    float4 keep = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    uint32_t ki = 0, kq = 0;
+    float kfx = 0.0f;
+    if (!producer && tid < N * Q) {
+      ki = tid / Q;
+      kq = tid - ki * Q;
+      kfx = fit_s[ki];
+    }
+    if (!producer) {
       const uint8_t *mg = msk + (g & 1u) * N * Q;
-      for (uint32_t q = l; q < Q; q += L) {
-        const uint32_t nib = run.cs == BIN ? mg[i * Q + q] : 0u;
-        const float4 uu = trial_quad(pop_s, Dp, D, i, q, ibl, ibr, d, nib, run, lb, ub);
+      for (uint32_t it = tid; it < N * Q; it += GEN_CONSUMERS) {
+        const uint32_t ti = it == tid ? ki : it / Q, q = it == tid ? kq : it - (it / Q) * Q;
+        const uint4 d = dsc[ti];
+        const uint32_t r0 = byte_of(d.z, 0), pb = byte_of(d.z, 1);
+        const uint32_t ibest = topk[0], ipb = topk[pb];
+        const uint32_t ibl = run.bl == RAND ? r0 : (run.bl == BEST ? ibest : (run.bl == PBEST ? ipb : ti));
+        const uint32_t ibr = run.br == RAND ? r0 : (run.br == BEST ? ibest : (run.br == PBEST ? ipb : ti));
+        if (TRACE && q == 0) {
+          int32_t *o = tr.desc + (size_t)(run.fit_off + ti) * 16;
+          o[0] = (int32_t)ibl;
+          o[1] = (int32_t)ibr;
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const uint32_t word = k < 4 ? d.x : d.y;
+            o[2 + k] = (k / 2) < run.dn ? (int32_t)byte_of(word, k & 3) : -1;
+          }
+          o[10] = (int32_t)byte_of(d.z, 2);
+          o[11] = run.cs == EXP ? (int32_t)(d.z >> 24) : -1;
+          o[12] = (int32_t)pb;
+          o[13] = use_rand ? (int32_t)r0 : -1;
+          o[14] = run.cs == ARITH ? (int32_t)d.w : -1;
+          o[15] = 0;
+        }
+        if (q == 0) fx_s[ti] = fit_s[ti];
+        const uint32_t nib = run.cs == BIN ? mg[it] : 0u;
+        const float4 uu = trial_quad(pop_s, Dp, D, ti, q, ibl, ibr, d, nib, run, lb, ub);
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           const uint32_t j = 4 * q + t;
           if (j < D) {
-            T[j * ts + i] = comp(uu, t);
-            if (TRACE) tr.u[run.pop_off + (size_t)i * D + j] = comp(uu, t);
+            T[j * ts + ti] = comp(uu, t);
+            if (TRACE) tr.u[run.pop_off + (size_t)ti * D + j] = comp(uu, t);
           }
         }
+        if (it == tid) keep = uu;
       }
     }
     if (producer)
@@ -302,35 +316,41 @@ __device__ __forceinline__ void gen_body(unsigned char *smem, const RunDev &run,
     if (producer)
       produce_desc_direct(ptid, GEN_THREADS - GEN_CONSUMERS, run, N, D, kp, g + 1, k0, k1, dsc);
     __syncthreads();
-    // S4: greedy selection (every part takes the same decision) and commit
-    if (act) {
-      double s0 = 0.0, s1 = 0.0;
-      for (uint32_t ll = 0; ll < L; ++ll) {
-        const double2 v = Ps[ll * Np + i];
-        s0 += v.x;
-        s1 += v.y;
-      }
-      const float f = finish_f32(p, s0, s1);
-      const bool a = accept_trial(f, fx);
-      if (a) {
-        for (uint32_t q = l; q < Q; q += L) {
-          float4 x;
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const uint32_t j = 4 * q + t;
-            set_comp(x, t, j < D ? T[j * ts + i] : 0.0f);
-          }
-          st4(pop_s, i * Dp + 4 * q, x);
+    // S4: greedy selection and commit, by the lanes of S2: each lane sums the
+    // parts of its trial (all lanes of a trial take the same decision) and
+    // writes its quad back; the quad-0 lane updates fitness and key.
+    if (!producer) {
+      for (uint32_t it = tid; it < N * Q; it += GEN_CONSUMERS) {
+        const uint32_t ti = it == tid ? ki : it / Q, q = it == tid ? kq : it - (it / Q) * Q;
+        const float fx = it == tid ? kfx : fx_s[ti];
+        double s0 = 0.0, s1 = 0.0;
+        for (uint32_t ll = 0; ll < L; ++ll) {
+          const double2 v = Ps[ll * Np + ti];
+          s0 += v.x;
+          s1 += v.y;
         }
-      }
-      if (l == 0) {
+        const float f = finish_f32(p, s0, s1);
+        const bool a = accept_trial(f, fx);
         if (a) {
-          fit_s[i] = f;
-          key_s[i] = mkkey(f, i);
+          float4 x = keep;
+          if (it != tid) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+              const uint32_t j = 4 * q + t;
+              set_comp(x, t, j < D ? T[j * ts + ti] : 0.0f);
+            }
+          }
+          st4(pop_s, ti * Dp + 4 * q, x);
         }
-        if (TRACE) {
-          tr.fu[run.fit_off + i] = f;
-          tr.desc[(size_t)(run.fit_off + i) * 16 + 15] = a ? 1 : 0;
+        if (q == 0) {
+          if (a) {
+            fit_s[ti] = f;
+            key_s[ti] = mkkey(f, ti);
+          }
+          if (TRACE) {
+            tr.fu[run.fit_off + ti] = f;
+            tr.desc[(size_t)(run.fit_off + ti) * 16 + 15] = a ? 1 : 0;
+          }
         }
       }
     }
@@ -351,11 +371,29 @@ __global__ __launch_bounds__(GEN_THREADS) void k_generations(
     uint32_t k1, float lb, float ub, float *__restrict__ pending, TraceArgs tr) {
   extern __shared__ __align__(16) unsigned char smem[];
   const RunDev run = runs[list[blockIdx.x]];
-  const ProbDev p = probs[run.prob];
-  if (run.t_lds)
-    gen_body<true, TRACE>(smem, run, p, tab, pop, fit, g0, n_gens, k0, k1, lb, ub, pending, tr);
-  else
-    gen_body<false, TRACE>(smem, run, p, tab, pop, fit, g0, n_gens, k0, k1, lb, ub, pending, tr);
+  ProbDev p = probs[run.prob];
+  // One copy of the generation loop per function kind: inside each case the
+  // kind is a constant, so the loop a workgroup runs holds only its own
+  // fitness code (a far smaller instruction footprint than one loop that
+  // branches over every kind at every output).
+#define MDE_KIND(K)                                                                            \
+  case K:                                                                                      \
+    p.kind = K;                                                                                \
+    if (run.t_lds)                                                                             \
+      gen_body<true, TRACE>(smem, run, p, tab, pop, fit, g0, n_gens, k0, k1, lb, ub, pending, tr); \
+    else                                                                                       \
+      gen_body<false, TRACE>(smem, run, p, tab, pop, fit, g0, n_gens, k0, k1, lb, ub, pending, tr); \
+    break;
+  switch (p.kind) {
+    MDE_KIND(FN_RASTRIGIN)
+    MDE_KIND(FN_ROSENBROCK)
+    MDE_KIND(FN_ACKLEY)
+    MDE_KIND(FN_ELLIPTIC)
+    MDE_KIND(FN_SCHWEFEL)
+    MDE_KIND(FN_HYBRID)
+    default: break;
+  }
+#undef MDE_KIND
 }
 
 // ---------------------------------------------------------------- best record in float64
@@ -591,9 +629,11 @@ __global__ void k_outer_best(const double *__restrict__ y, uint32_t P, int32_t *
 
 // Rt[k][j] = R[j][k] in float64, row stride Dr >= D + 16 (zero padding so a
 // block of 16 outputs starting anywhere below D stays inside the row).
-__global__ void k_rot_t64(const float *__restrict__ R, double *__restrict__ Rt, uint32_t D,
-                          uint32_t Dr) {
+__global__ void k_tables64(const float *__restrict__ R, const float *__restrict__ o,
+                           double *__restrict__ Rt, double *__restrict__ o64, uint32_t D,
+                           uint32_t Dr) {
   const uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u < D) o64[u] = (double)o[u];
   if (u >= D * Dr) return;
   const uint32_t k = u / Dr, j = u - k * Dr;
   Rt[u] = j < D ? (double)R[(size_t)j * D + k] : 0.0;
@@ -601,9 +641,11 @@ __global__ void k_rot_t64(const float *__restrict__ R, double *__restrict__ Rt, 
 
 // ---------------------------------------------------------------- launchers
 
-hipError_t launch_rot_t64(const float *R, double *Rt, uint32_t D, hipStream_t s) {
+hipError_t launch_tables64(const float *R, const float *o, double *Rt, double *o64, uint32_t D,
+                           hipStream_t s) {
   const uint32_t n = D * rt_stride(D);
-  hipLaunchKernelGGL(k_rot_t64, dim3((n + 255) / 256), dim3(256), 0, s, R, Rt, D, rt_stride(D));
+  hipLaunchKernelGGL(k_tables64, dim3((n + 255) / 256), dim3(256), 0, s, R, o, Rt, o64, D,
+                     rt_stride(D));
   return hipGetLastError();
 }
 

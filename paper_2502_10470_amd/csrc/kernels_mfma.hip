@@ -605,9 +605,25 @@ __global__ __launch_bounds__(MF_THREADS) void k_generations_mfma(
     unsigned long long *__restrict__ counters, TraceArgs tr) {
   extern __shared__ __align__(16) unsigned char smem[];
   const RunDev run = runs[list[blockIdx.x]];
-  const ProbDev p = probs[run.prob];
-  mfma_body<BF16, TRACE>(smem, run, p, tab, pop, fit, g0, n_gens, k0, k1, lb, ub,
-                         tbuf + run.pend_off, counters, tr);
+  ProbDev p = probs[run.prob];
+  // one copy of the generation loop per function kind (the kind is a
+  // constant inside each case)
+#define MDE_KIND(K)                                                                     \
+  case K:                                                                               \
+    p.kind = K;                                                                         \
+    mfma_body<BF16, TRACE>(smem, run, p, tab, pop, fit, g0, n_gens, k0, k1, lb, ub,     \
+                           tbuf + run.pend_off, counters, tr);                          \
+    break;
+  switch (p.kind) {
+    MDE_KIND(FN_RASTRIGIN)
+    MDE_KIND(FN_ROSENBROCK)
+    MDE_KIND(FN_ACKLEY)
+    MDE_KIND(FN_ELLIPTIC)
+    MDE_KIND(FN_SCHWEFEL)
+    MDE_KIND(FN_HYBRID)
+    default: break;
+  }
+#undef MDE_KIND
 }
 
 hipError_t set_lds_limits_mfma() {
