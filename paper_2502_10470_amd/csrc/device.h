@@ -45,7 +45,7 @@ struct RunDev {
   uint32_t N, D, Dp, prob;      // Dp = D rounded up to a multiple of 4
   uint32_t stream, kp;          // kp = top-p count
   uint32_t L, Np;               // lanes per trial (parts) and lanes per part (multiple of 64)
-  uint32_t t_lds, kern;         // trial rows in LDS (1) or global (0); kernel: 0 lanes, 1 matrix cores, 2 control
+  uint32_t t_lds, kern;         // trial rows in LDS (1, lane kernel) or global (0); kernel: 0 lanes, 1 matrix cores, 2 control
   uint32_t Dk, NCT;             // matrix-core kernel: D rounded up to 32; 16-wide output tiles
   uint64_t pop_off;             // float offset of the run in pop (N*D packing)
   uint64_t pend_off;            // float offset in the global trial buffer

@@ -1,11 +1,10 @@
 // HIP kernels of the MetaDE inner-DE path for gfx950.
 //
 // One workgroup owns one executor run for the whole launch: its population,
-// fitness, ranking and trial descriptors live in LDS, and the generation loop
-// of Alg. 2 runs inside the kernel (no grid-wide synchronisation).  Trials are
-// built and evaluated in chunks of C rows when the whole trial matrix does
-// not fit beside the population; accepted rows of earlier chunks then wait in
-// a global buffer until the synchronous commit at the end of the generation.
+// fitness, ranking state, random draws and the generation's trial rows live
+// in LDS, and the generation loop of Alg. 2 runs inside the kernel (no
+// grid-wide synchronisation).  Runs whose population and trials do not fit
+// in LDS go to the matrix-core kernel.
 #include "device.h"
 #include "gen_common.h"
 #include "kernels.h"
@@ -170,24 +169,25 @@ __global__ __launch_bounds__(INIT_THREADS) void k_init(const RunDev *__restrict_
 
 // ---------------------------------------------------------------- generations (Alg. 2 main loop)
 //
-// Consumer lane i of part l works on trial i: it builds genes 4q..4q+3 with
-// q = l mod L and the fitness outputs [l D / L, (l+1) D / L); the parts'
-// partial sums meet in LDS.  Per generation (four barriers):
+// Consumer lanes build the trials by (trial, gene quad) items and write them
+// gene-major to LDS; for the fitness, lane i of part l takes outputs
+// [l D / L, (l+1) D / L) of trial i, and the parts' partial sums meet in LDS.
+// Per generation (four barriers):
 //   S0 ranks and top-p list | S2 mutation + crossover (producers:
 //   binomial masks of g+1, into the other mask buffer) | S3 fitness
 //   (producers: index draws, pbest rank, j_rand, K, L of g+1) |
-//   S4 selection + commit.
+//   S4 selection + commit by the items of S2.
 
-template <bool TLDS, bool TRACE>
+template <bool TRACE>
 __device__ __forceinline__ void gen_body(unsigned char *smem, const RunDev &run, const ProbDev &p,
                                          const unsigned char *__restrict__ tab,
                                          float *__restrict__ pop, float *__restrict__ fit,
                                          uint32_t g0, uint32_t n_gens, uint32_t k0, uint32_t k1,
-                                         float lb, float ub, float *__restrict__ pending,
+                                         float lb, float ub,
                                          const TraceArgs &tr) {
   const uint32_t N = run.N, D = run.D, Dp = run.Dp, Q = Dp / 4, kp = run.kp, L = run.L,
                  Np = run.Np;
-  const Lds lay = lds_layout(N, Dp, L, Np, TLDS);
+  const Lds lay = lds_layout(N, Dp, L, Np, true);
   float *pop_s = reinterpret_cast<float *>(smem + lay.pop);
   uint64_t *key_s = reinterpret_cast<uint64_t *>(smem + lay.key);
   float *fit_s = reinterpret_cast<float *>(smem + lay.fit);
@@ -196,8 +196,8 @@ __device__ __forceinline__ void gen_body(unsigned char *smem, const RunDev &run,
   double2 *Ps = reinterpret_cast<double2 *>(smem + lay.ps);
   uint8_t *msk = reinterpret_cast<uint8_t *>(smem + lay.msk);
   uint4 *dsc = reinterpret_cast<uint4 *>(smem + lay.dsc);
-  float *T = TLDS ? reinterpret_cast<float *>(smem + lay.T) : pending + run.pend_off;
-  const uint32_t ts = TLDS ? Np : N;
+  float *T = reinterpret_cast<float *>(smem + lay.T);
+  const uint32_t ts = Np;
   const uint32_t tid = threadIdx.x;
   const bool producer = tid >= GEN_CONSUMERS;  // whole waves
   const uint32_t ptid = tid - GEN_CONSUMERS;
@@ -368,7 +368,7 @@ __global__ __launch_bounds__(GEN_THREADS) void k_generations(
     const RunDev *__restrict__ runs, const uint32_t *__restrict__ list,
     const ProbDev *__restrict__ probs, const unsigned char *__restrict__ tab,
     float *__restrict__ pop, float *__restrict__ fit, uint32_t g0, uint32_t n_gens, uint32_t k0,
-    uint32_t k1, float lb, float ub, float *__restrict__ pending, TraceArgs tr) {
+    uint32_t k1, float lb, float ub, TraceArgs tr) {
   extern __shared__ __align__(16) unsigned char smem[];
   const RunDev run = runs[list[blockIdx.x]];
   ProbDev p = probs[run.prob];
@@ -376,13 +376,10 @@ __global__ __launch_bounds__(GEN_THREADS) void k_generations(
   // kind is a constant, so the loop a workgroup runs holds only its own
   // fitness code (a far smaller instruction footprint than one loop that
   // branches over every kind at every output).
-#define MDE_KIND(K)                                                                            \
-  case K:                                                                                      \
-    p.kind = K;                                                                                \
-    if (run.t_lds)                                                                             \
-      gen_body<true, TRACE>(smem, run, p, tab, pop, fit, g0, n_gens, k0, k1, lb, ub, pending, tr); \
-    else                                                                                       \
-      gen_body<false, TRACE>(smem, run, p, tab, pop, fit, g0, n_gens, k0, k1, lb, ub, pending, tr); \
+#define MDE_KIND(K)                                                                   \
+  case K:                                                                             \
+    p.kind = K;                                                                       \
+    gen_body<TRACE>(smem, run, p, tab, pop, fit, g0, n_gens, k0, k1, lb, ub, tr);     \
     break;
   switch (p.kind) {
     MDE_KIND(FN_RASTRIGIN)
@@ -674,11 +671,11 @@ hipError_t launch_generations(const LaunchArgs &a, const uint32_t *list, uint32_
   if (tr.u)
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_generations<true>), dim3(n), dim3(GEN_THREADS),
                        a.lds_bytes, a.stream, a.runs, list, a.probs, a.tab, a.pop, a.fit, g0,
-                       n_gens, a.k0, a.k1, lb, ub, a.pending, tr);
+                       n_gens, a.k0, a.k1, lb, ub, tr);
   else
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_generations<false>), dim3(n), dim3(GEN_THREADS),
                        a.lds_bytes, a.stream, a.runs, list, a.probs, a.tab, a.pop, a.fit, g0,
-                       n_gens, a.k0, a.k1, lb, ub, a.pending, tr);
+                       n_gens, a.k0, a.k1, lb, ub, tr);
   return hipGetLastError();
 }
 
