@@ -140,6 +140,11 @@ typedef struct {
   float *best_x;
   void *stream;                    /* hipStream_t (NULL = default stream) */
   uint32_t evolver;                /* metade_evolver */
+  uint32_t graph;                  /* nonzero: the generation loop of control runs (four
+                                      launches per generation) is captured once per
+                                      sequence length as a HIP graph on a private stream
+                                      and replayed on `stream`; traced steps always launch
+                                      directly.  Results are identical either way. */
 } metade_config;
 
 /* Sizes in bytes of the caller-owned buffers and of the library's internal

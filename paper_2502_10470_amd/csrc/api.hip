@@ -48,6 +48,12 @@ struct metade_ctx {
   float *cfu_d = nullptr;                          // control runs: trial fitness
   unsigned long long *counters_d = nullptr;
   uint32_t gen = 0;
+  // control runs: device copy of the generation counter, and the generation
+  // loop captured as HIP graphs (one per sequence length, replayed on stream)
+  uint32_t *gen_d = nullptr;
+  bool graph = false;
+  hipStream_t cap_stream = nullptr;
+  std::vector<std::pair<uint32_t, hipGraphExec_t>> graphs;
   // evolver
   float *Xo = nullptr, *Uo = nullptr, *Vo = nullptr, *bxo = nullptr;  // Vo: PSO velocities
   double *yo = nullptr, *yt = nullptr;
@@ -286,6 +292,38 @@ mde::CtrlArgs cargs(metade_ctx *c) {
   return mde::CtrlArgs{c->ctrl_list_d, c->n_ctrl, c->ctrl_max_n, c->order_d, c->cfu_d, c->cacc_d};
 }
 
+// Capture n generations of the control runs (rank, trials, rollouts, commit,
+// then the counter advance) on a private stream and instantiate the graph.
+// Replays read the generation from the device counter, so one graph serves
+// every starting generation.  The sequence holds kernels only.
+metade_status capture_ctrl(metade_ctx *c, uint32_t n, hipGraphExec_t *out) {
+  if (!c->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  mde::LaunchArgs a = largs(c);
+  a.stream = c->cap_stream;
+  HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+  const hipError_t e1 = mde::launch_ctrl_generations(a, cargs(c), c->gen_d, n, c->lb, c->ub,
+                                                     mde::TraceArgs{nullptr, nullptr, nullptr});
+  hipGraph_t gph = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(c->cap_stream, &gph);
+  if (e1 != hipSuccess || e2 != hipSuccess) {
+    if (gph) (void)hipGraphDestroy(gph);
+    return fail(c, METADE_EDEVICE, std::string("capturing the control generations: ") +
+                                       hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+  }
+  hipGraphExec_t ex = nullptr;
+  const hipError_t e3 = hipGraphInstantiate(&ex, gph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(gph);
+  if (e3 != hipSuccess)
+    return fail(c, METADE_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e3));
+  if (c->graphs.size() >= 8) {  // a handful of sequence lengths is all a caller uses
+    (void)hipGraphExecDestroy(c->graphs.front().second);
+    c->graphs.erase(c->graphs.begin());
+  }
+  c->graphs.emplace_back(n, ex);
+  *out = ex;
+  return METADE_OK;
+}
+
 metade_status run_generations(metade_ctx *c, uint32_t n, mde::TraceArgs tr) {
   if (n == 0) return METADE_OK;
   EventPair ev{nullptr, nullptr};
@@ -298,7 +336,18 @@ metade_status run_generations(metade_ctx *c, uint32_t n, mde::TraceArgs tr) {
   HIP_TRY(c, mde::launch_generations_mfma(largs(c), c->mfma_list_d, c->n_mfma,
                                           c->precision == METADE_BF16_REFINE, c->gen, n, c->lb,
                                           c->ub, c->counters_d, tr));
-  HIP_TRY(c, mde::launch_ctrl_generations(largs(c), cargs(c), c->gen, n, c->lb, c->ub, tr));
+  if (c->n_ctrl && c->graph && !tr.u) {
+    hipGraphExec_t ex = nullptr;
+    for (const auto &e : c->graphs)
+      if (e.first == n) ex = e.second;
+    if (!ex) {
+      const metade_status st = capture_ctrl(c, n, &ex);
+      if (st != METADE_OK) return st;
+    }
+    HIP_TRY(c, hipGraphLaunch(ex, c->stream));
+  } else {
+    HIP_TRY(c, mde::launch_ctrl_generations(largs(c), cargs(c), c->gen_d, n, c->lb, c->ub, tr));
+  }
   if (c->timing) {
     HIP_TRY(c, hipEventRecord(ev.b, c->stream));
     c->events.push_back(ev);
@@ -312,6 +361,7 @@ metade_status reinit(metade_ctx *c) {
   HIP_TRY(c, mde::launch_init(largs(c), (double)c->lb, (double)c->ub));
   HIP_TRY(c, mde::launch_ctrl_init(largs(c), cargs(c), (double)c->lb, (double)c->ub));
   c->gen = 0;
+  if (c->n_ctrl) HIP_TRY(c, mde::launch_ctrl_set_gen(c->gen_d, 0, c->stream));
   return METADE_OK;
 }
 
@@ -375,6 +425,7 @@ metade_status metade_init(const metade_config *cfg, metade_ctx **out) {
   c->n_cs = cfg->n_cs;
   c->precision = cfg->precision;
   c->evolver = cfg->evolver;
+  c->graph = cfg->graph != 0;
   c->seed = cfg->seed;
   c->lb = cfg->lb;
   c->ub = cfg->ub;
@@ -429,6 +480,7 @@ metade_status metade_init(const metade_config *cfg, metade_ctx **out) {
   if ((st = dalloc(c, &c->bxo, c->bx_n)) != METADE_OK) return bail(st);
   if ((st = dalloc(c, &c->bidx, 4)) != METADE_OK) return bail(st);
   if ((st = dalloc(c, &c->counters_d, 1)) != METADE_OK) return bail(st);
+  if ((st = dalloc(c, &c->gen_d, 1)) != METADE_OK) return bail(st);
   if ((st = dalloc(c, &c->lane_list_d, pl.lane_list.size())) != METADE_OK) return bail(st);
   if ((st = dalloc(c, &c->mfma_list_d, pl.mfma_list.size())) != METADE_OK) return bail(st);
   if ((st = dalloc(c, &c->ctrl_list_d, pl.ctrl_list.size())) != METADE_OK) return bail(st);
@@ -731,6 +783,7 @@ metade_status metade_set_state(metade_ctx *c, const void *blob, size_t bytes) {
   HIP_TRY(c, h2d(c->yt, n * 8));
   HIP_TRY(c, h2d(c->bxo, c->bx_n * 4));
   c->gen = h.gen;
+  if (c->n_ctrl) HIP_TRY(c, mde::launch_ctrl_set_gen(c->gen_d, c->gen, c->stream));
   c->outer_gen = h.outer_gen;
   c->outer_ready = h.outer_ready != 0;
   return METADE_OK;
@@ -798,7 +851,10 @@ void metade_destroy(metade_ctx *c) {
   (void)hipFree(c->bxo);
   (void)hipFree(c->bidx);
   (void)hipFree(c->tab);
+  for (auto &e : c->graphs) (void)hipGraphExecDestroy(e.second);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   (void)hipFree(c->counters_d);
+  (void)hipFree(c->gen_d);
   (void)hipFree(c->lane_list_d);
   (void)hipFree(c->mfma_list_d);
   (void)hipFree(c->ctrl_list_d);

@@ -49,7 +49,9 @@ hipError_t launch_generations_mfma(const LaunchArgs &a, const uint32_t *list, ui
                                    bool bf16, uint32_t g0, uint32_t n_gens, float lb, float ub,
                                    unsigned long long *counters, TraceArgs tr);
 hipError_t launch_ctrl_init(const LaunchArgs &a, const CtrlArgs &c, double lb, double ub);
-hipError_t launch_ctrl_generations(const LaunchArgs &a, const CtrlArgs &c, uint32_t g0,
+// control runs: generation sequences read and advance the device counter gen
+hipError_t launch_ctrl_set_gen(uint32_t *gen, uint32_t v, hipStream_t s);
+hipError_t launch_ctrl_generations(const LaunchArgs &a, const CtrlArgs &c, uint32_t *gen,
                                    uint32_t n_gens, float lb, float ub, TraceArgs tr);
 hipError_t launch_ctrl_finalize(const LaunchArgs &a, const CtrlArgs &c, double *best_y,
                                 float *best_x);

@@ -370,9 +370,11 @@ template <bool TRACE>
 __global__ __launch_bounds__(CT_TRIAL_THREADS) void k_ctrl_trials(
     const RunDev *__restrict__ runs, const uint32_t *__restrict__ list,
     const float *__restrict__ pop, float *__restrict__ pend, const uint32_t *__restrict__ order,
-    uint32_t g, float lb, float ub, uint32_t k0, uint32_t k1, TraceArgs tr) {
+    const uint32_t *__restrict__ gen, uint32_t gg, float lb, float ub, uint32_t k0, uint32_t k1,
+    TraceArgs tr) {
   const RunDev run = runs[list[blockIdx.y]];
   const uint32_t i = blockIdx.x;
+  const uint32_t g = gen[0] + gg;  // generation counter kept on the device
   if (i >= run.N) return;
   const uint32_t N = run.N, D = run.D, tid = threadIdx.x, lane = tid % 64;
   const int use_rand = (run.bl == RAND || run.br == RAND) ? 1 : 0;
@@ -645,23 +647,38 @@ hipError_t launch_ctrl_init(const LaunchArgs &a, const CtrlArgs &c, double lb, d
   return hipGetLastError();
 }
 
-hipError_t launch_ctrl_generations(const LaunchArgs &a, const CtrlArgs &c, uint32_t g0,
+// Generation counter of the control runs: set from the host's count, and
+// advanced by the last launch of every generation sequence, so that a
+// captured sequence (HIP graph) can be replayed at any starting generation.
+__global__ void k_ctrl_set_gen(uint32_t *gen, uint32_t v) {
+  if (threadIdx.x == 0) gen[0] = v;
+}
+__global__ void k_ctrl_add_gen(uint32_t *gen, uint32_t n) {
+  if (threadIdx.x == 0) gen[0] += n;
+}
+
+hipError_t launch_ctrl_set_gen(uint32_t *gen, uint32_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_ctrl_set_gen, dim3(1), dim3(64), 0, s, gen, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_ctrl_generations(const LaunchArgs &a, const CtrlArgs &c, uint32_t *gen,
                                    uint32_t n_gens, float lb, float ub, TraceArgs tr) {
   if (c.n == 0) return hipSuccess;
   const dim3 tgrid(c.max_n, c.n), egrid((c.max_n + 1) / 2, c.n);
-  for (uint32_t g = g0; g < g0 + n_gens; ++g) {
+  for (uint32_t g = 0; g < n_gens; ++g) {
     hipLaunchKernelGGL(k_ctrl_rank, dim3(c.n), dim3(CT_MAX_N), 0, a.stream, a.runs, c.list, a.fit,
                        c.order);
     if (tr.u) {
       hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ctrl_trials<true>), tgrid, dim3(CT_TRIAL_THREADS), 0,
-                         a.stream, a.runs, c.list, a.pop, a.pending, c.order, g, lb, ub, a.k0,
-                         a.k1, tr);
+                         a.stream, a.runs, c.list, a.pop, a.pending, c.order, gen, g, lb, ub,
+                         a.k0, a.k1, tr);
       hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ctrl_eval<true, false>), egrid, dim3(64), 0, a.stream, a.runs,
                          c.list, a.probs, a.tab, a.fit, a.pending, c.fu, c.acc, tr);
     } else {
       hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ctrl_trials<false>), tgrid, dim3(CT_TRIAL_THREADS), 0,
-                         a.stream, a.runs, c.list, a.pop, a.pending, c.order, g, lb, ub, a.k0,
-                         a.k1, tr);
+                         a.stream, a.runs, c.list, a.pop, a.pending, c.order, gen, g, lb, ub,
+                         a.k0, a.k1, tr);
       hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ctrl_eval<false, false>), egrid, dim3(64), 0, a.stream, a.runs,
                          c.list, a.probs, a.tab, a.fit, a.pending, c.fu, c.acc, tr);
     }
@@ -670,7 +687,8 @@ hipError_t launch_ctrl_generations(const LaunchArgs &a, const CtrlArgs &c, uint3
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  return hipSuccess;
+  hipLaunchKernelGGL(k_ctrl_add_gen, dim3(1), dim3(64), 0, a.stream, gen, n_gens);
+  return hipGetLastError();
 }
 
 hipError_t launch_ctrl_finalize(const LaunchArgs &a, const CtrlArgs &c, double *best_y,

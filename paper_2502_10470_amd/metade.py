@@ -45,7 +45,7 @@ class MetadeConfig(ctypes.Structure):
         ("n_problems", _u32), ("problems", _vp), ("seed", ctypes.c_uint64),
         ("lb", ctypes.c_float), ("ub", ctypes.c_float), ("n_cs", _u32), ("precision", _u32),
         ("pop", _vp), ("fit", _vp), ("best_y", _vp), ("best_x", _vp), ("stream", _vp),
-        ("evolver", _u32),
+        ("evolver", _u32), ("graph", _u32),
     ]
 
 
@@ -229,7 +229,7 @@ class Batch:
     """A batch of executor runs on one GPU, built from a ``workloads.Workload``."""
 
     def __init__(self, wl, precision: int = FP32, device: str = "cuda:0", stream=None,
-                 evolver: int = EVOLVER_DE):
+                 evolver: int = EVOLVER_DE, graph: bool = True):
         import torch
         if not torch.cuda.is_available():
             raise MetadeError("no GPU visible: the MetaDE library runs on the GPU only")
@@ -285,6 +285,7 @@ class Batch:
         cfg.n_cs = int(wl.n_cs)
         cfg.precision = int(precision)
         cfg.evolver = int(evolver)
+        cfg.graph = 1 if graph else 0
         cfg.stream = self.stream.cuda_stream
         pop_b, fit_b, by_b, bx_b, _ = metade_query_sizes(cfg)
         self.pop = torch.zeros(pop_b // 4, dtype=torch.float32, device=dev)
