@@ -291,9 +291,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c3", choices=["c3", "c3x4", "c4", "c2", "c5"],
+    ap.add_argument("--workload", default="c3", choices=["c3", "c3x4", "paper", "c4", "c2", "c5"],
                     help="c3: full MetaDE at D=20 (default); c3x4: four independent "
-                         "repetitions of it, concurrently; c4: 128 runs x N=256 at D=100, "
+                         "repetitions of it, concurrently; paper: MetaDE at the paper's scale "
+                         "(evolver 100, three crossover schemes); c4: 128 runs x N=256 at D=100, "
                          "500 generations; c2: uneven batch of 256 runs, 200 generations; "
                          "c5: control workload, 16 runs x N=256 tanh policies (D=5702), "
                          "200-step rollouts, 100 generations")
@@ -301,6 +302,9 @@ def main():
                     help="fitness contraction: plain (float64-accumulated) or bf16 matrix cores "
                          "with plain re-evaluation of near ties")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--budget-seconds", type=float, default=0.0,
+                    help="c3 / paper only: equal-wall-clock mode, report the function "
+                         "evaluations done within this many seconds")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -325,9 +329,11 @@ def main():
 
     if args.workload == "c3x4":
         return bench_c3_repetitions(args)
-    if args.workload != "c3":
+    if args.workload not in ("c3", "paper"):
         return bench_batch(args)
-    wl = W.workload_c3()
+    wl = W.workload_c3() if args.workload == "c3" else W.workload_paper()
+    if args.budget_seconds:
+        return bench_budget(args, wl)
     P, gens, G, pu = wl.outer["P"], wl.outer["gens"], wl.G, wl.outer["power_up"]
     b = Batch(wl)
     evals = wl.evals_per_pass()
@@ -359,26 +365,73 @@ def main():
     avg_launch_ms = k_ms / max(k_launches, 1)
     slots_per_launch = slots / gens
     achieved = slots_per_launch / (avg_launch_ms * 1e-3)
-
+    D = wl.problems[0].D
+    if args.workload == "c3":
+        desc = ("full MetaDE at D=20 (evolver 64 x 10 gens, executors N=100, 1000 gens, "
+                "power-up 5x, seeded hybrid Schwefel/Rastrigin/elliptic)")
+    else:
+        desc = (f"MetaDE at the paper's scale, D={D} (evolver 100 x {gens} gens, executors "
+                "N=100, 1000 gens, power-up 5x, bin/exp/arith crossover: 192 strategies)")
     line = {
-        "metric": "inner-DE individual-evals/sec (runs x N x gens / s) at D=20",
+        "metric": f"inner-DE individual-evals/sec (runs x N x gens / s) at D={D}",
         "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "full MetaDE at D=20 (evolver 64 x 10 gens, executors N=100, "
-                               "1000 gens, power-up 5x, seeded hybrid Schwefel/Rastrigin/elliptic)",
-                   "runs": P, "N": 100, "D": 20, "inner_gens": G, "outer_gens": gens,
-                   "evals_per_step": evals, "best_y": best[0]},
+        "config": {"workload": desc, "runs": P, "N": 100, "D": D, "inner_gens": G,
+                   "outer_gens": gens, "evals_per_step": evals, "best_y": best[0]},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_SLOTS / 1e12,
                      "unit": "Tslot/s", "frac": achieved / VALU_PEAK_SLOTS,
-                     "traffic": MEASURED_TRAFFIC.get(kernel_source_hash()),
+                     "traffic": (MEASURED_TRAFFIC.get(kernel_source_hash())
+                                 if args.workload == "c3" else None),
                      "kernel": "k_generations", "avg_launch_ms": avg_launch_ms,
                      "launches": k_launches, "slots_per_launch": slots_per_launch,
                      "occupied_cu_frac": min(P, 256) / 256.0},
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "c3":
         line["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(line), flush=True)
+
+
+def bench_budget(args, wl):
+    """Equal-wall-clock mode (the paper compares optimisers at a fixed time
+    budget): outer generations run until the budget is nearly spent, the last
+    one powered up; reports the function evaluations done and the best y."""
+    import torch
+    from paper_2502_10470_amd import Batch
+
+    P, G, pu = wl.outer["P"], wl.G, wl.outer["power_up"]
+    b = Batch(wl)
+    N = int(wl.N[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.outer_reset()
+    fe = 0
+    gens = 0
+    per_gen = None
+    while True:
+        elapsed = time.perf_counter() - t0
+        # room for one more ordinary generation and the powered-up last one?
+        if per_gen is not None and elapsed + per_gen * (1 + pu) > args.budget_seconds:
+            break
+        tg = time.perf_counter()
+        b.outer_step(G, 1)
+        torch.cuda.synchronize()
+        per_gen = time.perf_counter() - tg
+        fe += P * N * (G + 1)   # initial population and G generations of every executor
+        gens += 1
+    b.outer_step(G, pu)
+    torch.cuda.synchronize()
+    fe += P * N * (G * pu + 1)
+    gens += 1
+    dt = time.perf_counter() - t0
+    _, y, _, _ = b.get_outer()
+    best = float(np.nanmin(y))
+    print(json.dumps({
+        "metric": f"function evaluations within a {args.budget_seconds:g} s budget",
+        "value": fe, "unit": "FE", "n_gpus": 1, "higher_is_better": True,
+        "wall_s": dt, "outer_gens": gens, "best_y": best, "data": "synthetic",
+        "config": {"workload": wl.name, "runs": P, "N": N, "D": wl.problems[0].D,
+                   "inner_gens": G, "power_up": pu, "n_cs": wl.n_cs}}), flush=True)
 
 
 if __name__ == "__main__":

@@ -135,23 +135,21 @@ def test_best_record_float64():
         assert abs(y[r] - ref) <= 1e-12 * abs(ref)
 
 
-def test_outer_step_c1():
-    """Evolver (Alg. 3) on the small MetaDE config: initial population,
-    trial vectors, decoded theta, executor scores and selection."""
-    wl = W.workload_c1()
+def _outer_parity(wl, n_outer):
+    P = wl.outer["P"]
     b = _batch(wl)
     b.outer_reset()
     X, y, _, _ = b.get_outer()
-    Xo, yo = ometa.outer_init(8, wl.seed, 0, wl.n_cs)
+    Xo, yo = ometa.outer_init(P, wl.seed, 0, wl.n_cs)
     assert np.array_equal(X, Xo) and np.all(np.isinf(y))
-    for g_o in range(2):
+    for g_o in range(n_outer):
         b.outer_step(wl.G, 1)
         X2, y2, U, yt = b.get_outer()
         Uo, _ = ometa.outer_trials(Xo, yo, g_o, wl.seed, 0, wl.n_cs)
         assert np.array_equal(U, Uo), f"outer trial vectors differ at g_o={g_o}"
-        ys = np.empty(8)
+        ys = np.empty(P)
         diverged = False
-        for i in range(8):
+        for i in range(P):
             o = OracleRun(wl, i, theta_row=Uo[i])
             amb = False
             for _ in range(wl.G):
@@ -171,6 +169,19 @@ def test_outer_step_c1():
         assert np.allclose(y2, yo, rtol=1e-12, atol=0)
         # scores agree to double rounding only; keep the library's exact values
         # out of the oracle: continue from the oracle's own state
+
+
+def test_outer_step_c1():
+    """Evolver (Alg. 3) on the small MetaDE config: initial population,
+    trial vectors, decoded theta, executor scores and selection."""
+    _outer_parity(W.workload_c1(), 2)
+
+
+def test_outer_step_paper_meta_space():
+    """The paper's own configuration shape: executors N=100 at D=20 and the
+    full meta-space with three crossover schemes (192 strategies), on a
+    slice of the evolver population and a few inner generations."""
+    _outer_parity(W.workload_paper(P=12, gens=2, G=4), 2)
 
 
 def test_metade_run_c1_consistency():

@@ -188,6 +188,20 @@ def workload_c3(P: int = 64, gens: int = 10, G: int = 1000) -> Workload:
                     outer={"P": P, "gens": gens, "power_up": 5, "F": 0.5, "CR": 0.9})
 
 
+def workload_paper(D: int = 20, P: int = 100, gens: int = 10, G: int = 1000) -> Workload:
+    """MetaDE at the paper's own scale (Sec. IV-A1): evolver population 100,
+    executors with N=100 and 1000 generations, the last outer generation
+    powered up 5x, and the full meta-space with the three crossover schemes
+    (bin, exp, arith: 4 x 4 x 4 x 3 = 192 strategies).  Seeded hybrid
+    function at D=20 standing in for the paper's benchmark suite."""
+    seed = 5
+    prob = make_problem("hybrid", D, seed, 0)
+    return Workload(name=f"paper_scale_d{D}", seed=seed, lb=-100.0, ub=100.0, n_cs=3,
+                    N=np.full(P, 100, np.uint32), problem=np.zeros(P, np.uint32),
+                    stream=np.zeros(P, np.uint32), problems=[prob], G=G,
+                    outer={"P": P, "gens": gens, "power_up": 5, "F": 0.5, "CR": 0.9})
+
+
 def workload_c4(runs: int = 128, N: int = 256, D: int = 100, G: int = 500) -> Workload:
     """Precision stress at D=100: 128 runs x N=256, 500 generations, half elliptic
     (cond 1e6), half Rastrigin, each with its own shift and dense rotation."""
@@ -248,5 +262,5 @@ def control_batch(seed: int, Ns, obs: int = LQR_OBS, act: int = LQR_ACT, steps: 
 
 def workload_by_name(name: str) -> Workload:
     table = {"c1": workload_c1, "c2": workload_c2, "c3": workload_c3, "c4": workload_c4,
-             "c5": workload_c5}
+             "c5": workload_c5, "paper": workload_paper}
     return table[name]()
