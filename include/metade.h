@@ -83,10 +83,19 @@ typedef enum {
  *        that order; r1, r2 from Philox words k and 6 + k of (particle, outer
  *        generation) on the evolver's stream), then score; a personal best is
  *        replaced iff the new score <= its score.  In metade_get_outer, X and y
- *        are the personal bests, U and y_trial the current positions and scores. */
+ *        are the personal bests, U and y_trial the current positions and scores.
+ *   CSO: competitive swarm (Cheng and Jin's optimiser, also in S.III) without
+ *        the mean-position term; at most 1024 particles.  Same start as PSO;
+ *        from outer generation 1 on the particles are paired by sorting
+ *        Philox word 12 of (particle, outer generation) (index breaks ties);
+ *        in each pair the particle first in (score, index) order stays, the
+ *        other moves v = r1 v + r2 (x_w - x_l), x = clip(x + v) (r1, r2 as for
+ *        PSO); every particle is then scored and takes that score.  X and y
+ *        are the swarm, U and y_trial the positions just scored (the same). */
 typedef enum {
   METADE_EVOLVER_DE = 0,
-  METADE_EVOLVER_PSO = 1
+  METADE_EVOLVER_PSO = 1,
+  METADE_EVOLVER_CSO = 2
 } metade_evolver;
 
 /* Objective functions: z = R (u - o) [+ c], f = g(z) + bias (textbook base

@@ -11,7 +11,8 @@ Restates Alg. 3 and Secs. III-B..III-E of the paper:
   * the last outer generation runs the executors for 5 G' generations
     (power-up, Sec. III-D);
   * selection keeps the trial iff its score <= the target's.
-A particle-swarm evolver (Supplement S.III) is restated below as well.
+Particle-swarm and competitive-swarm evolvers (Supplement S.III) are restated
+below as well.
 
 The evolver draws its random numbers from the executor's Philox layout with
 the stream word's top bit set, so the two never share counters.
@@ -109,10 +110,74 @@ def pso_select(st, y_new):
     return st, better
 
 
+# ---------------------------------------------------------------- CSO evolver
+#
+# The supplement (S.III) also uses the competitive swarm optimiser of Cheng
+# and Jin (IEEE Trans. Cybernetics, 2015) as the evolver.  Restated from that
+# published definition:
+#   * the swarm starts at the DE evolver's initial population, at rest;
+#     outer generation 0 scores the initial positions;
+#   * from generation 1 on, the particles are split into random pairs; in
+#     each pair the particle with the better score (first in (score, index)
+#     order) wins and stays where it is; the loser l learns from the winner w:
+#         v_l <- r1 v_l + r2 (x_w - x_l),   x_l <- clip(x_l + v_l)
+#     with r1, r2 uniform in [0, 1) per coordinate;
+#   * every particle then takes the score of its (new or unchanged) position.
+# Readings: the social term towards the swarm's mean position is left out
+# (its factor is 0, the setting that needs no tuning); all particles are
+# scored every generation (one-shot evaluation gives a winner the score it
+# already had, except in the powered-up last generation, where every
+# particle is scored with the longer run); the pairing sorts the particles
+# by Philox word 12 of (particle, g_o) on the evolver's stream (index breaks
+# ties) and pairs positions 2k and 2k + 1, an odd last particle sitting out;
+# r1, r2 of coordinate k are words k and 6 + k of the loser's (particle,
+# g_o), mapped to (w >> 8) 2^-24; float32 arithmetic in the order written;
+# velocities are not clipped.
+
+
+def cso_init(P, seed, stream, n_cs):
+    X, y = outer_init(P, seed, stream, n_cs)
+    return {"x": X.copy(), "v": np.zeros_like(X), "y": y}
+
+
+def cso_pairs(P, g_o, seed, stream):
+    w = philox.words(seed, np.arange(P), g_o, outer_stream(stream), 13)
+    order = np.lexsort((np.arange(P), w[:, 12].astype(np.uint64)))
+    return [(int(order[2 * k]), int(order[2 * k + 1])) for k in range(P // 2)], w
+
+
+def cso_move(st, g_o, seed, stream, n_cs):
+    """Positions and velocities of outer generation g_o >= 1; also returns the
+    (winner, loser) pairs."""
+    lo, hi = theta_bounds(n_cs)
+    P = st["x"].shape[0]
+    pairs, w = cso_pairs(P, g_o, seed, stream)
+    r = ((w[:, :12] >> np.uint64(8)).astype(np.float64) * 2.0 ** -24).astype(np.float32)
+    x, v = st["x"].copy(), st["v"].copy()
+    key = order_key(st["y"])
+    wl_pairs = []
+    for a, b in pairs:
+        wn, ls = (a, b) if (key[a], a) < (key[b], b) else (b, a)
+        r1, r2 = r[ls, 0:6], r[ls, 6:12]
+        vn = (r1 * v[ls]) + (r2 * (x[wn] - x[ls]))
+        v[ls] = vn
+        x[ls] = np.minimum(np.maximum(x[ls] + vn, lo), hi)
+        wl_pairs.append((wn, ls))
+    st = dict(st)
+    st["x"], st["v"] = x.astype(np.float32), v.astype(np.float32)
+    return st, wl_pairs
+
+
+def cso_select(st, y_new):
+    st = dict(st)
+    st["y"] = np.asarray(y_new, np.float64).copy()
+    return st, np.ones(len(y_new), bool)
+
+
 def run_metade(wl, gens=None, power_up=None, decide="f32", executor=None, log=None,
                evolver="de"):
-    """Alg. 3 on a workload with an outer loop (evolver "de"; "pso" swaps in the
-    particle swarm of the supplement).  Returns the evolver state and the best
+    """Alg. 3 on a workload with an outer loop (evolver "de"; "pso" or "cso"
+    swaps in the particle swarm or competitive swarm of the supplement).  Returns the evolver state and the best
     (theta, y, x) found."""
     o = wl.outer
     P = o["P"]
@@ -120,12 +185,17 @@ def run_metade(wl, gens=None, power_up=None, decide="f32", executor=None, log=No
     pu = o.get("power_up", 5) if power_up is None else power_up
     stream = int(wl.stream[0])
     X, y = outer_init(P, wl.seed, stream, wl.n_cs)
-    st = pso_init(P, wl.seed, stream, wl.n_cs) if evolver == "pso" else None
+    st = (pso_init(P, wl.seed, stream, wl.n_cs) if evolver == "pso" else
+          cso_init(P, wl.seed, stream, wl.n_cs) if evolver == "cso" else None)
     best_x = np.zeros((P, wl.D_of(0)), np.float32)
     for g_o in range(gens):
         if evolver == "pso":
             if g_o > 0:
                 st = pso_move(st, g_o, wl.seed, stream, wl.n_cs)
+            U = st["x"]
+        elif evolver == "cso":
+            if g_o > 0:
+                st, _ = cso_move(st, g_o, wl.seed, stream, wl.n_cs)
             U = st["x"]
         else:
             U, _ = outer_trials(X, y, g_o, wl.seed, stream, wl.n_cs, o["F"], o["CR"])
@@ -146,6 +216,9 @@ def run_metade(wl, gens=None, power_up=None, decide="f32", executor=None, log=No
         if evolver == "pso":
             st, acc = pso_select(st, ys)
             X, y = st["p"], st["py"]
+        elif evolver == "cso":
+            st, acc = cso_select(st, ys)
+            X, y = st["x"], st["y"]
         else:
             X, y, acc = outer_select(X, y, U, ys)
         best_x = np.where(acc[:, None], xs, best_x)

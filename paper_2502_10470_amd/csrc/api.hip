@@ -107,8 +107,13 @@ metade_status plan_config(const metade_config *cfg, Plan &pl, std::string &msg) 
   if (cfg->precision != METADE_FP32 && cfg->precision != METADE_BF16_REFINE) {
     msg = "precision must be METADE_FP32 or METADE_BF16_REFINE"; return METADE_EINVAL;
   }
-  if (cfg->evolver != METADE_EVOLVER_DE && cfg->evolver != METADE_EVOLVER_PSO) {
-    msg = "evolver must be METADE_EVOLVER_DE or METADE_EVOLVER_PSO"; return METADE_EINVAL;
+  if (cfg->evolver != METADE_EVOLVER_DE && cfg->evolver != METADE_EVOLVER_PSO &&
+      cfg->evolver != METADE_EVOLVER_CSO) {
+    msg = "evolver must be METADE_EVOLVER_DE, METADE_EVOLVER_PSO or METADE_EVOLVER_CSO";
+    return METADE_EINVAL;
+  }
+  if (cfg->evolver == METADE_EVOLVER_CSO && cfg->n_runs > 1024) {
+    msg = "the CSO evolver pairs at most 1024 particles (n_runs <= 1024)"; return METADE_EINVAL;
   }
   pl.probs.resize(cfg->n_problems);
   const double zs = mde::SCHWEFEL_ZSTAR;
@@ -613,7 +618,7 @@ metade_status metade_outer_reset(metade_ctx *c) {
                                     (uint32_t)(c->seed & 0xFFFFFFFFu), (uint32_t)(c->seed >> 32),
                                     c->n_cs, c->stream));
   HIP_TRY(c, hipMemsetAsync(c->bxo, 0, c->bx_n * sizeof(float), c->stream));
-  if (c->evolver == METADE_EVOLVER_PSO) {
+  if (c->evolver == METADE_EVOLVER_PSO || c->evolver == METADE_EVOLVER_CSO) {
     // particles start at the initial population, at rest
     HIP_TRY(c, hipMemcpyAsync(c->Uo, c->Xo, (size_t)c->n_runs * 6 * sizeof(float),
                               hipMemcpyDeviceToDevice, c->stream));
@@ -638,6 +643,14 @@ metade_status metade_outer_step(metade_ctx *c, uint32_t G_inner, uint32_t power_
                                       c->outer_gen, c->runs_h[0].stream, k0, k1, c->n_cs,
                                       c->stream));
     }
+  } else if (c->evolver == METADE_EVOLVER_CSO) {
+    if (c->outer_gen == 0) {
+      HIP_TRY(c, mde::launch_decode(c->runs_d, c->Uo, c->n_runs, c->n_cs, c->stream));
+    } else {
+      HIP_TRY(c, mde::launch_cso_move(c->Xo, c->Vo, c->Uo, c->yo, c->runs_d, c->n_runs,
+                                      c->outer_gen, c->runs_h[0].stream, k0, k1, c->n_cs,
+                                      c->stream));
+    }
   } else {
     HIP_TRY(c, mde::launch_outer_trial(c->Xo, c->Uo, c->runs_d, c->n_runs, c->outer_gen,
                                        c->runs_h[0].stream, k0, k1, c->n_cs, c->stream));
@@ -646,7 +659,8 @@ metade_status metade_outer_step(metade_ctx *c, uint32_t G_inner, uint32_t power_
   TRY(run_generations(c, G, mde::TraceArgs{nullptr, nullptr, nullptr}));
   TRY(finalize(c));
   HIP_TRY(c, mde::launch_outer_select(c->Xo, c->yo, c->Uo, c->best_y, c->yt, c->bxo, c->best_x,
-                                      c->runs_d, c->n_runs, c->stream));
+                                      c->runs_d, c->n_runs, c->evolver == METADE_EVOLVER_CSO,
+                                      c->stream));
   ++c->outer_gen;
   return METADE_OK;
 }

@@ -543,11 +543,11 @@ __global__ void k_outer_select(float *__restrict__ X, double *__restrict__ y,
                                const float *__restrict__ U, const double *__restrict__ y_run,
                                double *__restrict__ y_trial, float *__restrict__ bxo,
                                const float *__restrict__ best_x, const RunDev *__restrict__ runs,
-                               uint32_t P) {
+                               uint32_t P, uint32_t take_all) {
   const uint32_t i = blockIdx.x;
   if (i >= P) return;
   const double yt = y_run[i];
-  const bool acc = accept_trial_d(yt, y[i]);
+  const bool acc = take_all != 0 || accept_trial_d(yt, y[i]);
   __syncthreads();
   const RunDev run = runs[i];
   if (acc) {
@@ -594,6 +594,80 @@ __global__ void k_pso_move(float *__restrict__ U, float *__restrict__ V,
     V[i * 6 + k] = v;
     U[i * 6 + k] = xn;
     t[k] = xn;
+  }
+  decode_into(runs[i], t, n_cs);
+}
+
+// Competitive swarm evolver (the paper's supplement, S.III; Cheng and Jin's
+// optimiser without the mean-position term): one workgroup pairs the P
+// particles by sorting Philox word 12 of (particle, g_o) with the index
+// breaking ties, pairing sorted positions 2k and 2k + 1; in each pair the
+// particle first in (score, index) order wins and stays, the loser moves
+// v = r1 v + r2 (x_w - x_l), x = clip(x + v) in float32 in that order (r1, r2:
+// Philox words k and 6 + k of the loser's (particle, g_o)).  Positions X are
+// updated in place, copied to U and decoded into the executors.
+constexpr uint32_t CSO_MAX_P = 1024;
+
+__global__ __launch_bounds__(CSO_MAX_P) void k_cso_move(
+    float *__restrict__ X, float *__restrict__ V, float *__restrict__ U,
+    const double *__restrict__ y, RunDev *__restrict__ runs, uint32_t P, uint32_t g_o,
+    uint32_t stream, uint32_t k0, uint32_t k1, uint32_t n_cs) {
+  __shared__ uint64_t key[CSO_MAX_P];
+  __shared__ uint32_t at[CSO_MAX_P];
+  const uint32_t i = threadIdx.x;
+  const uint32_t st = stream | OUTER_BIT;
+  if (i < P) key[i] = ((uint64_t)philox(3, i, g_o, st, k0, k1).x << 32) | i;
+  __syncthreads();
+  uint32_t pos = 0;
+  if (i < P) {
+    const uint64_t ki = key[i];
+    for (uint32_t j = 0; j < P; ++j) pos += key[j] < ki ? 1u : 0u;
+    at[pos] = i;
+  }
+  __syncthreads();
+  bool loser = false;
+  uint32_t w = 0;
+  if (i < P && (pos ^ 1u) < P && !((P & 1u) && pos == P - 1)) {
+    const uint32_t j = at[pos ^ 1u];
+    double yi = y[i], yj = y[j];
+    if (yi != yi) yi = __longlong_as_double(0x7FF0000000000000LL);
+    if (yj != yj) yj = __longlong_as_double(0x7FF0000000000000LL);
+    loser = yj < yi || (yj == yi && j < i);
+    w = j;
+  }
+  // every thread has read the positions it needs before any loser writes
+  float xw[6];
+  if (i < P) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) xw[k] = X[w * 6 + k];
+  }
+  __syncthreads();
+  if (i >= P) return;
+  float t[6];
+  if (loser) {
+    const uint4 a = philox(0, i, g_o, st, k0, k1);
+    const uint4 b = philox(1, i, g_o, st, k0, k1);
+    const uint4 c = philox(2, i, g_o, st, k0, k1);
+    const uint32_t wd[12] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const float r1 = (float)(wd[k] >> 8) * 0x1p-24f;
+      const float r2 = (float)(wd[6 + k] >> 8) * 0x1p-24f;
+      const float x = X[i * 6 + k];
+      const float v = (r1 * V[i * 6 + k]) + (r2 * (xw[k] - x));
+      float lo, hi;
+      theta_box(n_cs, k, lo, hi);
+      t[k] = fminf(fmaxf(x + v, lo), hi);
+      V[i * 6 + k] = v;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) t[k] = X[i * 6 + k];
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    X[i * 6 + k] = t[k];
+    U[i * 6 + k] = t[k];
   }
   decode_into(runs[i], t, n_cs);
 }
@@ -708,9 +782,9 @@ hipError_t launch_outer_trial(const float *X, float *U, RunDev *runs, uint32_t P
 
 hipError_t launch_outer_select(float *X, double *y, const float *U, const double *y_run,
                                double *y_trial, float *bxo, const float *best_x,
-                               const RunDev *runs, uint32_t P, hipStream_t s) {
+                               const RunDev *runs, uint32_t P, bool take_all, hipStream_t s) {
   hipLaunchKernelGGL(k_outer_select, dim3(P), dim3(64), 0, s, X, y, U, y_run, y_trial, bxo, best_x,
-                     runs, P);
+                     runs, P, take_all ? 1u : 0u);
   return hipGetLastError();
 }
 
@@ -719,6 +793,15 @@ hipError_t launch_pso_move(float *U, float *V, const float *X, const int32_t *gb
                            uint32_t n_cs, hipStream_t s) {
   hipLaunchKernelGGL(k_pso_move, dim3((P + 63) / 64), dim3(64), 0, s, U, V, X, gbest, runs, P, g_o,
                      stream, k0, k1, n_cs);
+  return hipGetLastError();
+}
+
+hipError_t launch_cso_move(float *X, float *V, float *U, const double *y, RunDev *runs,
+                           uint32_t P, uint32_t g_o, uint32_t stream, uint32_t k0, uint32_t k1,
+                           uint32_t n_cs, hipStream_t s) {
+  if (P > CSO_MAX_P) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_cso_move, dim3(1), dim3(((P + 63) / 64) * 64), 0, s, X, V, U, y, runs, P,
+                     g_o, stream, k0, k1, n_cs);
   return hipGetLastError();
 }
 

@@ -171,7 +171,16 @@ def test_init_requires_buffers():
 def test_unknown_evolver_rejected():
     M = _lib()
     cfg, keep = _cfg(M)
-    cfg.evolver = 2
+    cfg.evolver = 7
     with pytest.raises(M.MetadeError) as ei:
         M.metade_query_sizes(cfg)
     assert "evolver must be" in str(ei.value)
+
+
+def test_cso_swarm_size_limit():
+    M = _lib()
+    cfg, keep = _cfg(M, N=(32,) * 1025)
+    cfg.evolver = M.EVOLVER_CSO
+    with pytest.raises(M.MetadeError) as ei:
+        M.metade_query_sizes(cfg)
+    assert "1024" in str(ei.value)

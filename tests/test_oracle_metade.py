@@ -167,3 +167,74 @@ def test_pso_converges_on_a_quadratic():
         assert np.all(st["py"] <= prev)
         best = min(best, st["py"].min())
     assert best < 1e-3
+
+
+# ---------------------------------------------------------------- CSO evolver (Supplement S.III)
+
+def test_cso_pairs_partition_the_swarm():
+    """Every particle is in exactly one pair (even swarm); an odd swarm leaves
+    exactly one particle out; pairings change with the generation."""
+    for P in (8, 9, 64):
+        pairs, _ = ometa.cso_pairs(P, 3, 7, 0)
+        flat = [i for pr in pairs for i in pr]
+        assert len(pairs) == P // 2 and len(set(flat)) == len(flat) == 2 * (P // 2)
+        assert set(flat) <= set(range(P))
+    assert ometa.cso_pairs(16, 1, 7, 0)[0] != ometa.cso_pairs(16, 2, 7, 0)[0]
+
+
+def test_cso_winners_stay_and_losers_learn_from_them():
+    """The better particle of each pair keeps position and velocity; a loser
+    at rest moves toward its winner by a fraction in [0, 1) of the distance
+    per coordinate (before clipping), and stays in the box."""
+    lo, hi = pde.theta_bounds(3)
+    rng = np.random.default_rng(1)
+    for trial in range(10):
+        st = ometa.cso_init(10, trial, 0, 3)
+        st["y"] = rng.permutation(10).astype(np.float64)
+        moved, wl_pairs = ometa.cso_move(st, 1 + trial, trial, 0, 3)
+        for wn, ls in wl_pairs:
+            assert st["y"][wn] < st["y"][ls]
+            assert np.array_equal(moved["x"][wn], st["x"][wn])
+            assert np.array_equal(moved["v"][wn], st["v"][wn])
+            d, gap = moved["x"][ls] - st["x"][ls], st["x"][wn] - st["x"][ls]
+            assert np.all(np.sign(d) * np.sign(gap) >= 0)
+            assert np.all(np.abs(d) <= np.abs(gap))
+            # from rest, the step is the velocity (up to the rounding of x + v)
+            assert np.allclose(moved["v"][ls], d, rtol=0, atol=4e-7 * np.abs(st["x"][ls]).max())
+        assert np.all(moved["x"] >= lo) and np.all(moved["x"] <= hi)
+
+
+def test_cso_ties_go_to_the_lower_index_and_nan_loses():
+    st = ometa.cso_init(6, 2, 0, 2)
+    st["y"] = np.array([1.0, 1.0, 1.0, 1.0, 1.0, 1.0])
+    _, wl_pairs = ometa.cso_move(st, 1, 2, 0, 2)
+    assert all(wn < ls for wn, ls in wl_pairs)
+    st["y"] = np.full(6, np.nan)
+    st["y"][5] = 0.0
+    _, wl_pairs = ometa.cso_move(st, 1, 2, 0, 2)
+    assert all(ls != 5 for _, ls in wl_pairs)
+
+
+def test_cso_coincident_pair_is_a_fixed_point():
+    """Winner and loser at the same place, loser at rest: nothing moves."""
+    st = ometa.cso_init(4, 2, 0, 2)
+    st["x"][:] = st["x"][0]
+    st["y"] = np.arange(4, dtype=np.float64)
+    moved, _ = ometa.cso_move(st, 5, 2, 0, 2)
+    assert np.array_equal(moved["x"], st["x"]) and np.all(moved["v"] == 0)
+
+
+def test_cso_converges_on_a_quadratic():
+    """The swarm's best score never increases and reaches the minimum of a
+    convex function of theta inside the box."""
+    c = np.array([0.3, 0.7, 2.2, 3.1, 1.7, 1.9], np.float32)
+    f = lambda X: np.sum((X.astype(np.float64) - c) ** 2, axis=1)
+    st = ometa.cso_init(32, 5, 0, 2)
+    best = np.inf
+    for g in range(150):
+        if g > 0:
+            st, _ = ometa.cso_move(st, g, 5, 0, 2)
+        st, _ = ometa.cso_select(st, f(st["x"]))
+        assert st["y"].min() <= best
+        best = st["y"].min()
+    assert best < 1e-3
