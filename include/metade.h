@@ -91,11 +91,22 @@ typedef enum {
  *        in each pair the particle first in (score, index) order stays, the
  *        other moves v = r1 v + r2 (x_w - x_l), x = clip(x + v) (r1, r2 as for
  *        PSO); every particle is then scored and takes that score.  X and y
- *        are the swarm, U and y_trial the positions just scored (the same). */
+ *        are the swarm, U and y_trial the positions just scored (the same).
+ *   NES: separable natural evolution strategy (Schaul et al.'s SNES, also in
+ *        S.III); at most 1024 samples.  A Gaussian N(mu, diag sigma^2) starts
+ *        at the centre of the theta box with sigma a quarter of its width;
+ *        every outer generation draws n_runs samples z = mu + sigma s (s by
+ *        Box-Muller from Philox words 2m, 2m + 1 of (sample, outer generation)
+ *        on the evolver's stream, float64; z rounded once to float32 and
+ *        clipped), scores them and moves mu += sigma sum_r u_r s_(r), sigma *=
+ *        exp(eta_sigma / 2 sum_r u_r (s^2 - 1)) with rank utilities u_r and
+ *        eta_sigma = (3 + ln 6) / (5 sqrt 6).  X, y, U and y_trial are the
+ *        generation's samples and scores. */
 typedef enum {
   METADE_EVOLVER_DE = 0,
   METADE_EVOLVER_PSO = 1,
-  METADE_EVOLVER_CSO = 2
+  METADE_EVOLVER_CSO = 2,
+  METADE_EVOLVER_NES = 3
 } metade_evolver;
 
 /* Objective functions: z = R (u - o) [+ c], f = g(z) + bias (textbook base

@@ -11,8 +11,8 @@ Restates Alg. 3 and Secs. III-B..III-E of the paper:
   * the last outer generation runs the executors for 5 G' generations
     (power-up, Sec. III-D);
   * selection keeps the trial iff its score <= the target's.
-Particle-swarm and competitive-swarm evolvers (Supplement S.III) are restated
-below as well.
+Particle-swarm, competitive-swarm and natural-evolution-strategy evolvers
+(Supplement S.III) are restated below as well.
 
 The evolver draws its random numbers from the executor's Philox layout with
 the stream word's top bit set, so the two never share counters.
@@ -174,10 +174,85 @@ def cso_select(st, y_new):
     return st, np.ones(len(y_new), bool)
 
 
+# ---------------------------------------------------------------- NES evolver
+#
+# The supplement (S.III) also uses a natural evolution strategy as the
+# evolver.  Restated here is the separable NES (Schaul, Glasmachers and
+# Schmidhuber, GECCO 2011): a Gaussian search distribution N(mu, diag sigma^2)
+# over theta; every generation draws lambda = P samples z_k = mu + sigma s_k,
+# s_k ~ N(0, I), scores them, ranks them (best first) and moves
+#     mu    <- mu + eta_mu sigma * sum_r u_r s_(r)
+#     sigma <- sigma * exp(eta_sigma / 2 * sum_r u_r (s_(r)^2 - 1))
+# with the rank utilities u_r = max(0, ln(lambda/2 + 1) - ln r) / sum_q max(...)
+# - 1/lambda, eta_mu = 1 and eta_sigma = (3 + ln d) / (5 sqrt d), d = 6.
+# Readings: mu starts at the centre of the theta box and sigma at a quarter
+# of its width; samples are clipped to the box before they are decoded and
+# scored (the update uses the unclipped s); s comes from the Box-Muller
+# transform of Philox words 2m, 2m + 1 of (sample k, g_o) on the evolver's
+# stream (u1 = ((w >> 8) + 1) 2^-24, u2 = (w >> 8) 2^-24; s_2m = rho cos(2 pi
+# u2), s_2m+1 = rho sin(2 pi u2), rho = sqrt(-2 ln u1)); the sampling, the
+# utilities and the update run in float64 with sums in rank order, mu and
+# sigma are kept in float32 between generations, and z is rounded once to
+# float32; ties in score rank by sample index, NaN last.
+
+
+def nes_init(n_cs):
+    lo, hi = theta_bounds(n_cs)
+    return {"mu": ((lo + hi) / np.float32(2)).astype(np.float32),
+            "sigma": ((hi - lo) / np.float32(4)).astype(np.float32)}
+
+
+def nes_normals(P, g_o, seed, stream):
+    """s[k][j] for sample k: Box-Muller of Philox words (float64)."""
+    w = philox.words(seed, np.arange(P), g_o, outer_stream(stream), 6).astype(np.uint64)
+    s = np.empty((P, 6))
+    for m in range(3):
+        u1 = ((w[:, 2 * m] >> np.uint64(8)) + np.uint64(1)).astype(np.float64) * 2.0 ** -24
+        u2 = (w[:, 2 * m + 1] >> np.uint64(8)).astype(np.float64) * 2.0 ** -24
+        rho = np.sqrt(-2.0 * np.log(u1))
+        s[:, 2 * m] = rho * np.cos(2.0 * np.pi * u2)
+        s[:, 2 * m + 1] = rho * np.sin(2.0 * np.pi * u2)
+    return s
+
+
+def nes_samples(st, P, g_o, seed, stream, n_cs):
+    lo, hi = theta_bounds(n_cs)
+    s = nes_normals(P, g_o, seed, stream)
+    z = (st["mu"].astype(np.float64)[None, :] + st["sigma"].astype(np.float64)[None, :] * s)
+    return np.minimum(np.maximum(z.astype(np.float32), lo), hi), s
+
+
+def nes_utilities(lam):
+    a = np.array([max(0.0, np.log(lam / 2.0 + 1.0) - np.log(r)) for r in range(1, lam + 1)])
+    tot = 0.0
+    for v in a:
+        tot = tot + v
+    return a / tot - 1.0 / lam
+
+
+def nes_update(st, y, g_o, seed, stream):
+    P = len(y)
+    s = nes_normals(P, g_o, seed, stream)
+    order = np.lexsort((np.arange(P), order_key(y)))
+    u = nes_utilities(P)
+    gmu = np.zeros(6)
+    gsig = np.zeros(6)
+    for r in range(P):
+        sk = s[order[r]]
+        gmu = gmu + u[r] * sk
+        gsig = gsig + u[r] * (sk * sk - 1.0)
+    eta_sigma = (3.0 + np.log(6.0)) / (5.0 * np.sqrt(6.0))
+    mu = st["mu"].astype(np.float64)
+    sig = st["sigma"].astype(np.float64)
+    return {"mu": (mu + sig * gmu).astype(np.float32),
+            "sigma": (sig * np.exp((eta_sigma / 2.0) * gsig)).astype(np.float32)}
+
+
 def run_metade(wl, gens=None, power_up=None, decide="f32", executor=None, log=None,
                evolver="de"):
-    """Alg. 3 on a workload with an outer loop (evolver "de"; "pso" or "cso"
-    swaps in the particle swarm or competitive swarm of the supplement).  Returns the evolver state and the best
+    """Alg. 3 on a workload with an outer loop (evolver "de"; "pso", "cso" or
+    "nes" swaps in the particle swarm, competitive swarm or separable NES of
+    the supplement).  Returns the evolver state and the best
     (theta, y, x) found."""
     o = wl.outer
     P = o["P"]
@@ -186,7 +261,8 @@ def run_metade(wl, gens=None, power_up=None, decide="f32", executor=None, log=No
     stream = int(wl.stream[0])
     X, y = outer_init(P, wl.seed, stream, wl.n_cs)
     st = (pso_init(P, wl.seed, stream, wl.n_cs) if evolver == "pso" else
-          cso_init(P, wl.seed, stream, wl.n_cs) if evolver == "cso" else None)
+          cso_init(P, wl.seed, stream, wl.n_cs) if evolver == "cso" else
+          nes_init(wl.n_cs) if evolver == "nes" else None)
     best_x = np.zeros((P, wl.D_of(0)), np.float32)
     for g_o in range(gens):
         if evolver == "pso":
@@ -197,6 +273,8 @@ def run_metade(wl, gens=None, power_up=None, decide="f32", executor=None, log=No
             if g_o > 0:
                 st, _ = cso_move(st, g_o, wl.seed, stream, wl.n_cs)
             U = st["x"]
+        elif evolver == "nes":
+            U, _ = nes_samples(st, P, g_o, wl.seed, stream, wl.n_cs)
         else:
             U, _ = outer_trials(X, y, g_o, wl.seed, stream, wl.n_cs, o["F"], o["CR"])
         dec = decode(U, wl.n_cs)
@@ -219,6 +297,9 @@ def run_metade(wl, gens=None, power_up=None, decide="f32", executor=None, log=No
         elif evolver == "cso":
             st, acc = cso_select(st, ys)
             X, y = st["x"], st["y"]
+        elif evolver == "nes":
+            st = nes_update(st, ys, g_o, wl.seed, stream)
+            X, y, acc = U, ys, np.ones(P, bool)
         else:
             X, y, acc = outer_select(X, y, U, ys)
         best_x = np.where(acc[:, None], xs, best_x)

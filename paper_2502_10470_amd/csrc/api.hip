@@ -108,12 +108,16 @@ metade_status plan_config(const metade_config *cfg, Plan &pl, std::string &msg) 
     msg = "precision must be METADE_FP32 or METADE_BF16_REFINE"; return METADE_EINVAL;
   }
   if (cfg->evolver != METADE_EVOLVER_DE && cfg->evolver != METADE_EVOLVER_PSO &&
-      cfg->evolver != METADE_EVOLVER_CSO) {
-    msg = "evolver must be METADE_EVOLVER_DE, METADE_EVOLVER_PSO or METADE_EVOLVER_CSO";
+      cfg->evolver != METADE_EVOLVER_CSO && cfg->evolver != METADE_EVOLVER_NES) {
+    msg = "evolver must be METADE_EVOLVER_DE, METADE_EVOLVER_PSO, METADE_EVOLVER_CSO or "
+          "METADE_EVOLVER_NES";
     return METADE_EINVAL;
   }
   if (cfg->evolver == METADE_EVOLVER_CSO && cfg->n_runs > 1024) {
     msg = "the CSO evolver pairs at most 1024 particles (n_runs <= 1024)"; return METADE_EINVAL;
+  }
+  if (cfg->evolver == METADE_EVOLVER_NES && cfg->n_runs > 1024) {
+    msg = "the NES evolver ranks at most 1024 samples (n_runs <= 1024)"; return METADE_EINVAL;
   }
   pl.probs.resize(cfg->n_problems);
   const double zs = mde::SCHWEFEL_ZSTAR;
@@ -624,6 +628,7 @@ metade_status metade_outer_reset(metade_ctx *c) {
                               hipMemcpyDeviceToDevice, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->Vo, 0, (size_t)c->n_runs * 6 * sizeof(float), c->stream));
   }
+  if (c->evolver == METADE_EVOLVER_NES) HIP_TRY(c, mde::launch_nes_init(c->Vo, c->n_cs, c->stream));
   c->outer_gen = 0;
   c->outer_ready = true;
   return METADE_OK;
@@ -643,6 +648,9 @@ metade_status metade_outer_step(metade_ctx *c, uint32_t G_inner, uint32_t power_
                                       c->outer_gen, c->runs_h[0].stream, k0, k1, c->n_cs,
                                       c->stream));
     }
+  } else if (c->evolver == METADE_EVOLVER_NES) {
+    HIP_TRY(c, mde::launch_nes_sample(c->Uo, c->Vo, c->runs_d, c->n_runs, c->outer_gen,
+                                      c->runs_h[0].stream, k0, k1, c->n_cs, c->stream));
   } else if (c->evolver == METADE_EVOLVER_CSO) {
     if (c->outer_gen == 0) {
       HIP_TRY(c, mde::launch_decode(c->runs_d, c->Uo, c->n_runs, c->n_cs, c->stream));
@@ -659,8 +667,15 @@ metade_status metade_outer_step(metade_ctx *c, uint32_t G_inner, uint32_t power_
   TRY(run_generations(c, G, mde::TraceArgs{nullptr, nullptr, nullptr}));
   TRY(finalize(c));
   HIP_TRY(c, mde::launch_outer_select(c->Xo, c->yo, c->Uo, c->best_y, c->yt, c->bxo, c->best_x,
-                                      c->runs_d, c->n_runs, c->evolver == METADE_EVOLVER_CSO,
+                                      c->runs_d, c->n_runs,
+                                      c->evolver == METADE_EVOLVER_CSO ||
+                                          c->evolver == METADE_EVOLVER_NES,
                                       c->stream));
+  if (c->evolver == METADE_EVOLVER_NES) {
+    const double eta_sigma = (3.0 + std::log(6.0)) / (5.0 * std::sqrt(6.0));
+    HIP_TRY(c, mde::launch_nes_update(c->yt, c->Vo, c->n_runs, c->outer_gen, c->runs_h[0].stream,
+                                      k0, k1, eta_sigma, c->stream));
+  }
   ++c->outer_gen;
   return METADE_OK;
 }

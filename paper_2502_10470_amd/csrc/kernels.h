@@ -68,6 +68,12 @@ hipError_t launch_outer_select(float *X, double *y, const float *U, const double
 hipError_t launch_cso_move(float *X, float *V, float *U, const double *y, RunDev *runs,
                            uint32_t P, uint32_t g_o, uint32_t stream, uint32_t k0, uint32_t k1,
                            uint32_t n_cs, hipStream_t s);
+hipError_t launch_nes_init(float *V, uint32_t n_cs, hipStream_t s);
+hipError_t launch_nes_sample(float *U, const float *V, RunDev *runs, uint32_t P, uint32_t g_o,
+                             uint32_t stream, uint32_t k0, uint32_t k1, uint32_t n_cs,
+                             hipStream_t s);
+hipError_t launch_nes_update(const double *y, float *V, uint32_t P, uint32_t g_o, uint32_t stream,
+                             uint32_t k0, uint32_t k1, double eta_sigma, hipStream_t s);
 hipError_t launch_outer_best(const double *y, uint32_t P, int32_t *out, hipStream_t s);
 hipError_t launch_pso_move(float *U, float *V, const float *X, const int32_t *gbest, RunDev *runs,
                            uint32_t P, uint32_t g_o, uint32_t stream, uint32_t k0, uint32_t k1,

@@ -672,6 +672,109 @@ __global__ __launch_bounds__(CSO_MAX_P) void k_cso_move(
   decode_into(runs[i], t, n_cs);
 }
 
+// Separable natural evolution strategy (the paper's supplement, S.III;
+// Schaul, Glasmachers and Schmidhuber's SNES).  State: mu = V[0..5], sigma =
+// V[6..11] (float32).  Normals s of sample k are the Box-Muller transform of
+// Philox words 2m, 2m + 1 of (k, g_o) on the evolver's stream, in float64;
+// the sample is z = mu + sigma s rounded once to float32, clipped to the
+// theta box and decoded into executor k.  The update ranks the samples by
+// (score, index), weights them with the rank utilities and moves
+// mu += sigma sum_r u_r s_(r), sigma *= exp(eta_sigma / 2 sum_r u_r (s^2 - 1)),
+// all in float64 with the sums taken in rank order by one lane per
+// coordinate.
+constexpr uint32_t NES_MAX_P = 1024;
+
+__device__ __forceinline__ void nes_normals(uint32_t k, uint32_t g_o, uint32_t st, uint32_t k0,
+                                            uint32_t k1, double (&s)[6]) {
+  const uint4 a = philox(0, k, g_o, st, k0, k1);
+  const uint4 b = philox(1, k, g_o, st, k0, k1);
+  const uint32_t w[6] = {a.x, a.y, a.z, a.w, b.x, b.y};
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    const double u1 = (double)((w[2 * m] >> 8) + 1u) * 0x1p-24;
+    const double u2 = (double)(w[2 * m + 1] >> 8) * 0x1p-24;
+    const double rho = sqrt(-2.0 * log(u1));
+    const double ang = (2.0 * 3.141592653589793) * u2;
+    s[2 * m] = rho * cos(ang);
+    s[2 * m + 1] = rho * sin(ang);
+  }
+}
+
+__global__ void k_nes_init(float *__restrict__ V, uint32_t n_cs) {
+  const int k = (int)threadIdx.x;
+  if (k >= 6) return;
+  float lo, hi;
+  theta_box(n_cs, k, lo, hi);
+  V[k] = (lo + hi) / 2.0f;
+  V[6 + k] = (hi - lo) / 4.0f;
+}
+
+__global__ void k_nes_sample(float *__restrict__ U, const float *__restrict__ V,
+                             RunDev *__restrict__ runs, uint32_t P, uint32_t g_o,
+                             uint32_t stream, uint32_t k0, uint32_t k1, uint32_t n_cs) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= P) return;
+  double s[6];
+  nes_normals(k, g_o, stream | OUTER_BIT, k0, k1, s);
+  float t[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const float z = (float)((double)V[j] + (double)V[6 + j] * s[j]);
+    float lo, hi;
+    theta_box(n_cs, j, lo, hi);
+    t[j] = fminf(fmaxf(z, lo), hi);
+    U[k * 6 + j] = t[j];
+  }
+  decode_into(runs[k], t, n_cs);
+}
+
+__global__ __launch_bounds__(NES_MAX_P) void k_nes_update(
+    const double *__restrict__ y, float *__restrict__ V, uint32_t P, uint32_t g_o,
+    uint32_t stream, uint32_t k0, uint32_t k1, double eta_sigma) {
+  __shared__ double s_all[NES_MAX_P * 6];
+  __shared__ double util[NES_MAX_P];
+  __shared__ uint32_t at[NES_MAX_P];
+  const uint32_t k = threadIdx.x;
+  if (k < P) {
+    double s[6];
+    nes_normals(k, g_o, stream | OUTER_BIT, k0, k1, s);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) s_all[k * 6 + j] = s[j];
+    double yk = y[k];
+    if (yk != yk) yk = __longlong_as_double(0x7FF0000000000000LL);
+    uint32_t r = 0;
+    for (uint32_t q = 0; q < P; ++q) {
+      double yq = y[q];
+      if (yq != yq) yq = __longlong_as_double(0x7FF0000000000000LL);
+      r += (yq < yk || (yq == yk && q < k)) ? 1u : 0u;
+    }
+    at[r] = k;
+    // utility weight before normalisation of rank r + 1
+    util[k] = fmax(0.0, log((double)P / 2.0 + 1.0) - log((double)(k + 1)));
+  }
+  __syncthreads();
+  __shared__ double tot;
+  if (k == 0) {
+    double t = 0.0;
+    for (uint32_t q = 0; q < P; ++q) t = t + util[q];
+    tot = t;
+  }
+  __syncthreads();
+  if (k < P) util[k] = util[k] / tot - 1.0 / (double)P;
+  __syncthreads();
+  if (k < 6) {
+    double gmu = 0.0, gsig = 0.0;
+    for (uint32_t r = 0; r < P; ++r) {
+      const double sk = s_all[at[r] * 6 + k];
+      gmu = gmu + util[r] * sk;
+      gsig = gsig + util[r] * (sk * sk - 1.0);
+    }
+    const double mu = (double)V[k], sig = (double)V[6 + k];
+    V[k] = (float)(mu + sig * gmu);
+    V[6 + k] = (float)(sig * exp((eta_sigma / 2.0) * gsig));
+  }
+}
+
 __global__ void k_outer_best(const double *__restrict__ y, uint32_t P, int32_t *__restrict__ out) {
   __shared__ double sv[256];
   __shared__ int32_t si[256];
@@ -793,6 +896,27 @@ hipError_t launch_pso_move(float *U, float *V, const float *X, const int32_t *gb
                            uint32_t n_cs, hipStream_t s) {
   hipLaunchKernelGGL(k_pso_move, dim3((P + 63) / 64), dim3(64), 0, s, U, V, X, gbest, runs, P, g_o,
                      stream, k0, k1, n_cs);
+  return hipGetLastError();
+}
+
+hipError_t launch_nes_init(float *V, uint32_t n_cs, hipStream_t s) {
+  hipLaunchKernelGGL(k_nes_init, dim3(1), dim3(64), 0, s, V, n_cs);
+  return hipGetLastError();
+}
+
+hipError_t launch_nes_sample(float *U, const float *V, RunDev *runs, uint32_t P, uint32_t g_o,
+                             uint32_t stream, uint32_t k0, uint32_t k1, uint32_t n_cs,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_nes_sample, dim3((P + 63) / 64), dim3(64), 0, s, U, V, runs, P, g_o, stream,
+                     k0, k1, n_cs);
+  return hipGetLastError();
+}
+
+hipError_t launch_nes_update(const double *y, float *V, uint32_t P, uint32_t g_o, uint32_t stream,
+                             uint32_t k0, uint32_t k1, double eta_sigma, hipStream_t s) {
+  if (P > NES_MAX_P) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_nes_update, dim3(1), dim3(((P + 63) / 64) * 64), 0, s, y, V, P, g_o, stream,
+                     k0, k1, eta_sigma);
   return hipGetLastError();
 }
 

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(HERE, "libmetade.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE = 0, -1, -2, -3, -4
 FP32, BF16_REFINE = 0, 1
-EVOLVER_DE, EVOLVER_PSO, EVOLVER_CSO = 0, 1, 2
+EVOLVER_DE, EVOLVER_PSO, EVOLVER_CSO, EVOLVER_NES = 0, 1, 2, 3
 FN = {"rastrigin": 1, "rosenbrock": 2, "ackley": 3, "elliptic": 4, "schwefel": 5, "hybrid": 6,
       "lqr_mlp": 7}
 

@@ -171,7 +171,7 @@ def test_init_requires_buffers():
 def test_unknown_evolver_rejected():
     M = _lib()
     cfg, keep = _cfg(M)
-    cfg.evolver = 7
+    cfg.evolver = 9
     with pytest.raises(M.MetadeError) as ei:
         M.metade_query_sizes(cfg)
     assert "evolver must be" in str(ei.value)

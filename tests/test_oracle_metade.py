@@ -238,3 +238,64 @@ def test_cso_converges_on_a_quadratic():
         assert st["y"].min() <= best
         best = st["y"].min()
     assert best < 1e-3
+
+
+# ---------------------------------------------------------------- NES evolver (Supplement S.III)
+
+def test_nes_utilities_are_zero_sum_and_rank_ordered():
+    for lam in (4, 5, 8, 64, 100):
+        u = ometa.nes_utilities(lam)
+        assert abs(u.sum()) < 1e-12
+        assert np.all(np.diff(u) <= 1e-15)
+        # only ranks below lambda/2 + 1 get weight above the baseline -1/lambda
+        r = np.arange(1, lam + 1)
+        assert np.all((u > -1.0 / lam + 1e-15) == (r < lam / 2.0 + 1.0))
+
+
+def test_nes_normals_are_standard_normal():
+    """Moments of 30000 x 6 Box-Muller samples: mean 0, variance 1, no
+    correlation between the pair of one word pair, kurtosis 3."""
+    s = ometa.nes_normals(30000, 1, 3, 0)
+    n = s.shape[0]
+    assert np.all(np.abs(s.mean(0)) < 5 / np.sqrt(n))
+    assert np.all(np.abs(s.var(0) - 1) < 5 * np.sqrt(2 / n))
+    for m in range(3):
+        c = np.corrcoef(s[:, 2 * m], s[:, 2 * m + 1])[0, 1]
+        assert abs(c) < 5 / np.sqrt(n)
+    k = (s ** 4).mean(0) / s.var(0) ** 2
+    assert np.all(np.abs(k - 3) < 0.15)
+
+
+def test_nes_samples_follow_the_distribution_and_stay_in_the_box():
+    lo, hi = pde.theta_bounds(3)
+    st = {"mu": np.array([0.5, 0.5, 3, 3, 3, 2.5], np.float32),
+          "sigma": np.array([0.01, 0.02, 0.1, 0.2, 0.3, 0.05], np.float32)}
+    z, s = ometa.nes_samples(st, 20000, 2, 4, 0, 3)
+    assert np.all(z >= lo) and np.all(z <= hi)
+    assert np.all(np.abs(z.mean(0) - st["mu"]) < 5 * st["sigma"] / np.sqrt(20000))
+    assert np.allclose(z.std(0), st["sigma"], rtol=0.05)
+
+
+def test_nes_moves_downhill_and_shrinks_on_a_quadratic():
+    """mu reaches the minimum of a convex function of theta inside the box,
+    and sigma contracts around it."""
+    c = np.array([0.3, 0.7, 2.2, 3.1, 1.7, 1.9], np.float32)
+    f = lambda X: np.sum((X.astype(np.float64) - c) ** 2, axis=1)
+    st = ometa.nes_init(2)
+    s0 = st["sigma"].copy()
+    for g in range(150):
+        z, _ = ometa.nes_samples(st, 24, g, 5, 0, 2)
+        st = ometa.nes_update(st, f(z), g, 5, 0)
+    assert np.max(np.abs(st["mu"] - c)) < 0.02
+    assert np.all(st["sigma"] < 0.1 * s0)
+
+
+def test_nes_update_ignores_sample_order_and_equal_scores_rank_by_index():
+    """The update depends on the scores only through their ranks."""
+    st = ometa.nes_init(2)
+    y = np.array([3.0, 1.0, 2.0, 0.5, 7.0, 4.0])
+    a = ometa.nes_update(st, y, 1, 2, 0)
+    b = ometa.nes_update(st, np.exp(y), 1, 2, 0)       # same ranks, other values
+    assert np.array_equal(a["mu"], b["mu"]) and np.array_equal(a["sigma"], b["sigma"])
+    c = ometa.nes_update(st, np.where(np.arange(6) == 4, np.nan, y), 1, 2, 0)
+    assert np.array_equal(a["mu"], c["mu"])            # the worst sample stays the worst
