@@ -217,6 +217,17 @@ def bench_batch(args):
                      "rotation_tflops": rot_flops / (avg_ms * 1e-3) / 1e12,
                      "occupied_cu_frac": (1.0 if ctrl else min(wl.n_runs, 256) / 256.0)},
     }
+    if args.workload == "c4":
+        # the D=100 kernel is bound by the rotation on the matrix cores: algorithmic
+        # flops 2 N D^2 per trial (the bf16 mode's three split products and its
+        # re-evaluations are not counted), against the peak of the dtype it runs in
+        peak = MFMA_BF16_PEAK if prec == M.BF16_REFINE else MFMA_F64_PEAK
+        ach = rot_flops / (avg_ms * 1e-3)
+        line["roofline"] = {"bound": "mfma", "achieved": ach / 1e12, "peak": peak / 1e12,
+                            "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
+                            "kernel": kern, "avg_launch_ms": avg_ms, "launches": k_launches,
+                            "alu_frac": slots / (avg_ms * 1e-3) / VALU_PEAK_SLOTS,
+                            "occupied_cu_frac": min(wl.n_runs, 256) / 256.0}
     print(json.dumps(line), flush=True)
 
 
