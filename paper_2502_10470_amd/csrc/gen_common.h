@@ -37,11 +37,14 @@ __device__ __forceinline__ float finish_f32(const ProbDev &p, double s0, double 
 // binomial mask bits are functions of (seed, stream, generation, individual)
 // and theta only.  Producer lanes compute them one generation ahead.
 
-// Binomial mask nibbles of generation g only (Philox blocks 3 + q).
+// Crossover-test nibbles of generation g (Philox blocks 3 + q): bit t of
+// nibble (i, q) is the test r <= CR of gene uniform 4q + t.  Binomial
+// crossover takes gene 4q + t where the bit is set; exponential crossover
+// continues its run while consecutive bits (in test order) are set.
 __device__ __forceinline__ void produce_masks(uint32_t ptid, uint32_t nprod, const RunDev &run,
                                               uint32_t N, uint32_t Q, uint32_t g, uint32_t k0,
                                               uint32_t k1, uint8_t *msk) {
-  if (run.cs != BIN) return;
+  if (run.cs != BIN && run.cs != EXP) return;
   for (uint32_t it = ptid; it < N * Q; it += nprod) {
     const uint32_t i = it / Q, q = it - i * Q;
     const uint4 w = philox(W_GENE0 / 4 + q, i, g, run.stream, k0, k1);
@@ -52,12 +55,14 @@ __device__ __forceinline__ void produce_masks(uint32_t ptid, uint32_t nprod, con
   }
 }
 
-// Packed draws of generation g computed from scratch (Philox blocks 0..2 by
-// the lane itself), same packing as produce_desc.
+// Packed draws of generation g: Philox blocks 0..2 by the lane itself; the
+// exponential length from the test nibbles of generation g (mskg, written by
+// produce_masks and visible to this lane).
 __device__ __forceinline__ void produce_desc_direct(uint32_t ptid, uint32_t nprod,
                                                     const RunDev &run, uint32_t N, uint32_t D,
                                                     uint32_t kp, uint32_t g, uint32_t k0,
-                                                    uint32_t k1, uint4 *dsc) {
+                                                    uint32_t k1, const uint8_t *mskg,
+                                                    uint4 *dsc) {
   const int use_rand = (run.bl == RAND || run.br == RAND) ? 1 : 0;
   const int dn = run.dn;
   const int m = use_rand + 2 * dn;
@@ -83,19 +88,16 @@ __device__ __forceinline__ void produce_desc_direct(uint32_t ptid, uint32_t npro
     const uint32_t r0 = use_rand ? dr[0] : 0u;
     const uint32_t pb = lemire(w[W_PBEST], kp);
     const uint32_t jn = lemire(w[W_JRAND], D);
+    // L = 1 + the number of leading passed continuation tests, at most D
     uint32_t Lx = 1;
     if (run.cs == EXP) {
-      bool go = true;
-      uint32_t blk = W_GENE0 / 4;
-      while (go && Lx < D) {
-        const uint4 wr = philox(blk++, i, g, run.stream, k0, k1);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          if (go && Lx < D) {
-            if (unit_oc(word_of(wr, t)) <= run.CR) ++Lx; else go = false;
-          }
-        }
+      const uint32_t Q = (D + 3) / 4;
+      for (uint32_t q = 0; q < Q && Lx < D; ++q) {
+        const uint32_t ones = (uint32_t)__builtin_ctz(~(uint32_t)mskg[i * Q + q]);
+        Lx += ones;
+        if (ones < 4) break;
       }
+      Lx = min(Lx, D);
     }
     uint4 d;
     d.x = pr[0] | (pr[1] << 8) | (pr[2] << 16) | (pr[3] << 24);

@@ -217,10 +217,12 @@ __device__ __forceinline__ void gen_body(unsigned char *smem, const RunDev &run,
     key_s[r] = mkkey(f, r);
   }
   // draws of the first generation
-  if (producer) {
+  if (producer)
     produce_masks(ptid, GEN_THREADS - GEN_CONSUMERS, run, N, Q, g0, k0, k1, msk + (g0 & 1u) * N * Q);
-    produce_desc_direct(ptid, GEN_THREADS - GEN_CONSUMERS, run, N, D, kp, g0, k0, k1, dsc);
-  }
+  __syncthreads();
+  if (producer)
+    produce_desc_direct(ptid, GEN_THREADS - GEN_CONSUMERS, run, N, D, kp, g0, k0, k1,
+                        msk + (g0 & 1u) * N * Q, dsc);
 
   for (uint32_t gg = 0; gg < n_gens; ++gg) {
     const uint32_t g = g0 + gg;
@@ -314,7 +316,8 @@ __device__ __forceinline__ void gen_body(unsigned char *smem, const RunDev &run,
       Ps[l * Np + i] = make_double2(s0, s1);
     }
     if (producer)
-      produce_desc_direct(ptid, GEN_THREADS - GEN_CONSUMERS, run, N, D, kp, g + 1, k0, k1, dsc);
+      produce_desc_direct(ptid, GEN_THREADS - GEN_CONSUMERS, run, N, D, kp, g + 1, k0, k1,
+                          msk + ((g + 1) & 1u) * N * Q, dsc);
     __syncthreads();
     // S4: greedy selection and commit, by the lanes of S2: each lane sums the
     // parts of its trial (all lanes of a trial take the same decision) and

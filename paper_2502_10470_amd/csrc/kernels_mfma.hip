@@ -373,10 +373,10 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
       }
     }
   }
-  if (producer) {
-    produce_masks(ptid, MF_THREADS - MF_CONSUMERS, run, N, Q, g0, k0, k1, msk);
-    produce_desc_direct(ptid, MF_THREADS - MF_CONSUMERS, run, N, D, kp, g0, k0, k1, dsc);
-  }
+  if (producer) produce_masks(ptid, MF_THREADS - MF_CONSUMERS, run, N, Q, g0, k0, k1, msk);
+  __syncthreads();
+  if (producer)
+    produce_desc_direct(ptid, MF_THREADS - MF_CONSUMERS, run, N, D, kp, g0, k0, k1, msk, dsc);
   unsigned long long refined = 0;
 
   for (uint32_t gg = 0; gg < n_gens; ++gg) {
@@ -585,7 +585,8 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
       }
       refined += total;
     }
-    if (producer) produce_desc_direct(ptid, MF_THREADS - MF_CONSUMERS, run, N, D, kp, g + 1, k0, k1, dsc);
+    if (producer)
+      produce_desc_direct(ptid, MF_THREADS - MF_CONSUMERS, run, N, D, kp, g + 1, k0, k1, msk, dsc);
   }
   __syncthreads();
   for (uint32_t u = tid; u < N * D; u += MF_THREADS) {
