@@ -55,21 +55,23 @@ __device__ __forceinline__ void produce_masks(uint32_t ptid, uint32_t nprod, con
   }
 }
 
-// Packed draws of generation g: Philox blocks 0..2 by the lane itself; the
-// exponential length from the test nibbles of generation g (mskg, written by
-// produce_masks and visible to this lane).
+// Packed draws of generation g: Philox blocks 0..2 by the lane itself (with
+// PRE, block 2 of the lane's one trial comes in wc_pre, drawn in an earlier
+// phase); the exponential length from the test nibbles of generation g (mskg,
+// written by produce_masks and visible to this lane).
+template <bool PRE = false>
 __device__ __forceinline__ void produce_desc_direct(uint32_t ptid, uint32_t nprod,
                                                     const RunDev &run, uint32_t N, uint32_t D,
                                                     uint32_t kp, uint32_t g, uint32_t k0,
                                                     uint32_t k1, const uint8_t *mskg,
-                                                    uint4 *dsc) {
+                                                    uint4 *dsc, uint4 wc_pre = uint4{}) {
   const int use_rand = (run.bl == RAND || run.br == RAND) ? 1 : 0;
   const int dn = run.dn;
   const int m = use_rand + 2 * dn;
   for (uint32_t i = ptid; i < N; i += nprod) {
     uint32_t w[12];
     const uint4 wa = philox(0, i, g, run.stream, k0, k1);
-    const uint4 wc = philox(2, i, g, run.stream, k0, k1);
+    const uint4 wc = PRE ? wc_pre : philox(2, i, g, run.stream, k0, k1);
     w[0] = wa.x; w[1] = wa.y; w[2] = wa.z; w[3] = wa.w;
     if (m > 4) {
       const uint4 wb = philox(1, i, g, run.stream, k0, k1);

@@ -305,9 +305,14 @@ __device__ __forceinline__ void gen_body(unsigned char *smem, const RunDev &run,
         if (it == tid) keep = uu;
       }
     }
-    if (producer)
+    uint4 wc_next = uint4{};
+    if (producer) {
       produce_masks(ptid, GEN_THREADS - GEN_CONSUMERS, run, N, Q, g + 1, k0, k1,
                     msk + ((g + 1) & 1u) * N * Q);
+      // block 2 of the next generation's draws now, the rest in S3 (N <= 256:
+      // one trial per producer lane)
+      if (ptid < N) wc_next = philox(2, ptid, g + 1, run.stream, k0, k1);
+    }
     __syncthreads();
     // S3: this part's share of the fitness; producers draw generation g+1
     if (act) {
@@ -316,8 +321,8 @@ __device__ __forceinline__ void gen_body(unsigned char *smem, const RunDev &run,
       Ps[l * Np + i] = make_double2(s0, s1);
     }
     if (producer)
-      produce_desc_direct(ptid, GEN_THREADS - GEN_CONSUMERS, run, N, D, kp, g + 1, k0, k1,
-                          msk + ((g + 1) & 1u) * N * Q, dsc);
+      produce_desc_direct<true>(ptid, GEN_THREADS - GEN_CONSUMERS, run, N, D, kp, g + 1, k0, k1,
+                                msk + ((g + 1) & 1u) * N * Q, dsc, wc_next);
     __syncthreads();
     // S4: greedy selection and commit, by the lanes of S2: each lane sums the
     // parts of its trial (all lanes of a trial take the same decision) and
