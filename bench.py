@@ -396,7 +396,8 @@ def main():
                                  if args.workload == "c3" else None),
                      "kernel": "k_generations", "avg_launch_ms": avg_launch_ms,
                      "launches": k_launches, "slots_per_launch": slots_per_launch,
-                     "occupied_cu_frac": min(P, 256) / 256.0},
+                     "occupied_cu_frac": min(P, 256) / 256.0,
+                     "frac_of_occupied_cus": achieved / VALU_PEAK_SLOTS / (min(P, 256) / 256.0)},
     }
     if not args.no_cpu_baseline and args.workload == "c3":
         line["cpu_baseline"] = cpu_baseline(wl)
