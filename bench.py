@@ -39,7 +39,7 @@ HBM_PEAK_GBS = 8000.0
 # the copied bytes on this device, WRITE_SIZE 1.0x).  Keyed by a hash of the
 # kernel sources: a changed kernel reports null until measured again.
 KERNEL_SOURCES = ("paper_2502_10470_amd/csrc/kernels.hip", "paper_2502_10470_amd/csrc/device.h")
-MEASURED_TRAFFIC = {"b97102af80e0e0cd": (797.0 * 2.0 + 3854.0 * 1.0) * 1024}
+MEASURED_TRAFFIC = {"4f5fab9e6de5e3ae": (797.0 * 2.0 + 3854.0 * 1.0) * 1024}
 
 PHILOX_SLOTS = 100   # 10 rounds x (2 quarter-rate 32x32->64 multiplies + 2 three-input XORs)
 ELEM_SLOTS = {       # per element of z: square/accumulate + the element function
@@ -50,11 +50,16 @@ ELEM_SLOTS["hybrid"] = (6 * ELEM_SLOTS["schwefel"] + 7 * ELEM_SLOTS["rastrigin"]
 
 
 def kernel_source_hash():
+    """Hash of the kernel sources' code: comments and whitespace are left out,
+    so that only a change of the code itself invalidates a measurement."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"//[^\n]*", "", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -173,9 +173,10 @@ __global__ __launch_bounds__(INIT_THREADS) void k_init(const RunDev *__restrict_
 // gene-major to LDS; for the fitness, lane i of part l takes outputs
 // [l D / L, (l+1) D / L) of trial i, and the parts' partial sums meet in LDS.
 // Per generation (four barriers):
-//   S0 ranks and top-p list | S2 mutation + crossover (producers:
-//   binomial masks of g+1, into the other mask buffer) | S3 fitness
-//   (producers: index draws, pbest rank, j_rand, K, L of g+1) |
+//   S0 ranks and top-p list | S2 mutation + crossover (producers: the
+//   crossover-test nibbles of g+1, into the other buffer, and Philox block 2
+//   of g+1's draws) | S3 fitness (producers: the rest of g+1's draws: index
+//   draws, pbest rank, j_rand, K, exponential length from the nibbles) |
 //   S4 selection + commit by the items of S2.
 
 template <bool TRACE>

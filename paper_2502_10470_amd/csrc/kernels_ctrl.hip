@@ -19,7 +19,9 @@
 // Eq. 12 mutation, Eqs. 8-10 crossover, clip: one block per trial reading
 // the population rows with coalesced loads and writing the trial to a
 // 16-byte aligned pending row); evaluation (rollout and selection decision);
-// commit (accepted rows replace their targets).
+// commit (accepted rows replace their targets).  The trial kernel reads the
+// generation from a device counter that the last launch of a sequence
+// advances, so a captured sequence replays at any starting generation.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
