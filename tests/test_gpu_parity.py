@@ -236,3 +236,55 @@ def test_invariants_long_run():
     y = b.get_best()
     for r in range(wl.n_runs):
         assert abs(y[r] - b.run_fit(f2, r).min()) <= 1e-5 * abs(y[r])
+
+
+def test_run_order_independence():
+    """Runs share a launch but nothing else: the same runs listed in another
+    order (each keeping its problem, stream and theta) end bit-identical, on
+    both generation kernels."""
+    import dataclasses
+    kinds = ["rastrigin", "elliptic", "hybrid", "schwefel", "ackley", "rosenbrock"]
+    Ns = [40, 100, 64, 256, 33, 120]
+    Ds = [10, 20, 20, 100, 7, 64]
+    wl = W.small_batch(31, kinds, Ns, Ds, n_cs=3)
+    perm = np.array([3, 0, 5, 1, 4, 2])
+    wl2 = dataclasses.replace(wl, N=wl.N[perm], problem=wl.problem[perm], stream=wl.stream[perm],
+                              theta=wl.theta[perm], name=wl.name + "_perm")
+    a, b = _batch(wl), _batch(wl2)
+    a.inner_step(12)
+    b.inner_step(12)
+    pa, fa = a.host_state()
+    pb, fb = b.host_state()
+    ya, yb = a.get_best(), b.get_best()
+    for k, r in enumerate(perm):
+        assert np.array_equal(a.run_pop(pa, r), b.run_pop(pb, k)), f"run {r}"
+        assert np.array_equal(a.run_fit(fa, r), b.run_fit(fb, k))
+        assert ya[r] == yb[k]
+
+
+def test_nan_targets_rank_last_and_are_replaced():
+    """A NaN target fitness counts as +inf: it ranks last and any finite trial
+    replaces it (the oracle's step on the same state decides the same way)."""
+    wl = W.small_batch(41, ["rastrigin", "elliptic"], [30, 50], [10, 12], n_cs=2,
+                       theta=np.array([_theta_for(3, 1, 2, 1, CR=0.8),
+                                       _theta_for(2, 3, 1, 2, CR=0.4)], np.float32))
+    b = _batch(wl)
+    pop0, fit0 = b.host_state()
+    fit_nan = fit0.copy()
+    nan_idx = [0, 3, 7, 31, 42, 79]
+    fit_nan[nan_idx] = np.nan
+    b.fit.copy_(b.torch.from_numpy(fit_nan).to(b.fit.device))
+    u, fu, desc = b.trace_step()
+    pop1, fit1 = b.host_state()
+    for r in range(wl.n_runs):
+        o = OracleRun(wl, r)
+        fr = b.run_fit(fit_nan, r)
+        s = pde.step(o.pop, fr.astype(np.float32), o.th, 0, wl.seed, o.stream, wl.lb, wl.ub,
+                     o.prob)
+        assert np.array_equal(b.run_pop(u, r), s["u"]), f"run {r}: trials (NaN ranks last)"
+        acc = desc[b.fit_off[r]:b.fit_off[r + 1], 15].astype(bool)
+        nan_here = np.isnan(fr)
+        assert nan_here.any() and np.all(acc[nan_here]), f"run {r}: NaN targets kept"
+        assert np.all(np.isfinite(b.run_fit(fit1, r)))
+        amb = near(s["fu64"], fr) & ~np.isnan(s["fu64"])
+        assert np.array_equal(acc[~amb], s["accept"][~amb])
