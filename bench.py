@@ -164,7 +164,8 @@ def bench_batch(args):
     import workloads as W
     from paper_2502_10470_amd import Batch, metade as M
 
-    wl = {"c4": W.workload_c4, "c2": W.workload_c2, "c5": W.workload_c5}[args.workload]()
+    wl = {"c4": W.workload_c4, "c2": W.workload_c2, "c5": W.workload_c5,
+          "t7": W.workload_t7}[args.workload]()
     prec = M.BF16_REFINE if args.precision == "bf16" else M.FP32
     b = Batch(wl, precision=prec)
     evals = wl.evals_per_pass()
@@ -190,7 +191,7 @@ def bench_batch(args):
     dt = t1 - t0
     avg_ms = k_ms / max(k_launches, 1)
     F, CR, bl, br, dn, cs = decode(wl.theta, wl.n_cs)
-    ctrl = args.workload == "c5"
+    ctrl = args.workload in ("c5", "t7")
     if ctrl:
         slots = sum(int(wl.N[r]) * wl.G * ctrl_slots_per_trial(wl.problems[int(wl.problem[r])],
                     bl[r], br[r], dn[r], cs[r], CR[r]) for r in range(wl.n_runs))
@@ -201,9 +202,10 @@ def bench_batch(args):
     rot_flops = 0.0 if ctrl else sum(2.0 * int(wl.N[r]) * wl.D_of(r) ** 2 * wl.G
                                      for r in range(wl.n_runs))
     refine_rate = (r_after - r_before) / max(t_after - t_before, 1)
-    at = {"c4": "D=100", "c2": "D in {10,20}", "c5": "D=5702 (control)"}[args.workload]
-    kern = {"c4": "k_generations_mfma", "c2": "k_generations",
-            "c5": "k_ctrl_eval (timed with k_ctrl_rank, k_ctrl_trials, k_ctrl_commit)"}[args.workload]
+    at = {"c4": "D=100", "c2": "D in {10,20}", "c5": "D=5702 (control)",
+          "t7": "D in {1539,1410,1506} (control, Table VII policies)"}[args.workload]
+    ck = "k_ctrl_eval (timed with k_ctrl_rank, k_ctrl_trials, k_ctrl_commit)"
+    kern = {"c4": "k_generations_mfma", "c2": "k_generations", "c5": ck, "t7": ck}[args.workload]
     line = {
         "metric": f"inner-DE individual-evals/sec (runs x N x gens / s) at {at}",
         "value": evals * args.steps / dt, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
@@ -307,13 +309,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c3", choices=["c3", "c3x4", "paper", "c4", "c2", "c5"],
+    ap.add_argument("--workload", default="c3",
+                    choices=["c3", "c3x4", "paper", "c4", "c2", "c5", "t7"],
                     help="c3: full MetaDE at D=20 (default); c3x4: four independent "
                          "repetitions of it, concurrently; paper: MetaDE at the paper's scale "
                          "(evolver 100, three crossover schemes); c4: 128 runs x N=256 at D=100, "
                          "500 generations; c2: uneven batch of 256 runs, 200 generations; "
                          "c5: control workload, 16 runs x N=256 tanh policies (D=5702), "
-                         "200-step rollouts, 100 generations")
+                         "200-step rollouts, 100 generations; t7: the policy MLPs of "
+                         "Table VII (hidden 32 x 32), 96 runs x N=100, 50 generations")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"],
                     help="fitness contraction: plain (float64-accumulated) or bf16 matrix cores "
                          "with plain re-evaluation of near ties")

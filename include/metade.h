@@ -134,7 +134,9 @@ typedef struct {
   /* control workload (LQR_MLP): policy obs -> hidden1 -> hidden2 -> act with
    * tanh on every layer, weights flattened W1 (hidden1 x obs, row-major), b1,
    * W2, b2, W3, b3; cost sum_{t<steps} |x_t|^2 + ctrl_weight |u_t|^2 averaged
-   * over n_rollouts initial states; x_{t+1} = A x_t + B u_t. */
+   * over n_rollouts initial states; x_{t+1} = A x_t + B u_t.  The hidden
+   * layers are both 32 wide (the policy MLPs of Sec. IV-D, Table VII) or both
+   * 64 wide, and all control problems of one context share that width. */
   uint32_t obs, act, hidden1, hidden2, steps, n_rollouts;
   float ctrl_weight;
   const float *A;        /* device [obs*obs] row-major */
@@ -182,7 +184,8 @@ metade_status metade_query_sizes(const metade_config *cfg, size_t *pop_bytes, si
  * shifted-rotated kinds, lb >= ub, |lb| or |ub| > 1e30, n_cs not in {2, 3},
  * a precision not in metade_precision, a problem index out of range, a
  * missing device pointer, a hybrid permutation that is not one, an unknown
- * kind; for LQR_MLP: N_r > 1024, hidden1 or hidden2 != 64, obs not in 1..20,
+ * kind; for LQR_MLP: N_r > 1024, hidden1 != hidden2, a hidden width other
+ * than 32 or 64 or two widths in one context, obs not in 1..20,
  * act not in 1..8, steps or n_rollouts = 0, a non-finite ctrl_weight, D not
  * equal to the policy's weight count.  A run is also rejected when its
  * population and draws do not fit in the 160 KB of LDS of its generation

@@ -42,7 +42,7 @@ struct metade_ctx {
   float *pend_d = nullptr;
   size_t pop_floats = 0, fit_n = 0, bx_n = 0, pend_floats = 0;
   uint32_t lds_bytes = 0, init_lds_bytes = 0, mfma_lds_bytes = 0;
-  uint32_t n_lane = 0, n_mfma = 0, n_ctrl = 0, ctrl_max_n = 0;
+  uint32_t n_lane = 0, n_mfma = 0, n_ctrl = 0, ctrl_max_n = 0, ctrl_hidden = 0;
   uint32_t *lane_list_d = nullptr, *mfma_list_d = nullptr, *ctrl_list_d = nullptr;
   uint32_t *order_d = nullptr, *cacc_d = nullptr;  // control runs: top-p lists, decisions
   float *cfu_d = nullptr;                          // control runs: trial fitness
@@ -90,7 +90,7 @@ struct Plan {
   size_t tab_bytes = 0;
   uint32_t init_lds_bytes = 0, mfma_lds_bytes = 0;
   std::vector<uint32_t> lane_list, mfma_list, ctrl_list;
-  uint32_t ctrl_max_n = 0;
+  uint32_t ctrl_max_n = 0, ctrl_hidden = 0;
   size_t pop_floats = 0, fit_n = 0, bx_n = 0, pend_floats = 0;
   uint32_t lds_bytes = 0;
 };
@@ -143,17 +143,23 @@ metade_status plan_config(const metade_config *cfg, Plan &pl, std::string &msg) 
     };
     if (q.kind == METADE_FN_LQR_MLP) {
       const std::string pk = "problem " + std::to_string(k) + ": ";
-      if (q.hidden1 != (uint32_t)mde::CT_H || q.hidden2 != (uint32_t)mde::CT_H) {
-        msg = pk + "control policy hidden layers must have 64 units"; return METADE_EINVAL;
+      const uint32_t H = q.hidden1;
+      if ((H != (uint32_t)mde::CT_H_SMALL && H != (uint32_t)mde::CT_H) || q.hidden2 != H) {
+        msg = pk + "control policy hidden layers must both have 32 or both 64 units";
+        return METADE_EINVAL;
       }
+      if (pl.ctrl_hidden != 0 && pl.ctrl_hidden != H) {
+        msg = pk + "all control policies of a context must have the same hidden width";
+        return METADE_EINVAL;
+      }
+      pl.ctrl_hidden = H;
       if (q.obs < 1 || q.obs > (uint32_t)mde::CT_MAX_OBS || q.act < 1 || q.act > (uint32_t)mde::CT_MAX_ACT) {
         msg = pk + "control workload needs 1 <= obs <= 20 and 1 <= act <= 8"; return METADE_EINVAL;
       }
       if (q.steps < 1 || q.n_rollouts < 1) { msg = pk + "steps and n_rollouts must be >= 1"; return METADE_EINVAL; }
       if (!q.A || !q.B || !q.x0) { msg = pk + "A, B and x0 are required"; return METADE_EINVAL; }
       if (!std::isfinite(q.ctrl_weight)) { msg = pk + "ctrl_weight must be finite"; return METADE_EINVAL; }
-      const uint64_t Dm = (uint64_t)mde::CT_H * q.obs + mde::CT_H + (uint64_t)mde::CT_H * mde::CT_H +
-                          mde::CT_H + (uint64_t)mde::CT_H * q.act + q.act;
+      const uint64_t Dm = (uint64_t)H * q.obs + H + (uint64_t)H * H + H + (uint64_t)H * q.act + q.act;
       if (q.D != Dm) {
         msg = pk + "D must equal the policy's weight count " + std::to_string(Dm); return METADE_EINVAL;
       }
@@ -298,7 +304,8 @@ LaunchArgs largs(metade_ctx *c) {
 }
 
 mde::CtrlArgs cargs(metade_ctx *c) {
-  return mde::CtrlArgs{c->ctrl_list_d, c->n_ctrl, c->ctrl_max_n, c->order_d, c->cfu_d, c->cacc_d};
+  return mde::CtrlArgs{c->ctrl_list_d, c->n_ctrl,   c->ctrl_max_n, c->ctrl_hidden,
+                       c->order_d,     c->cfu_d,    c->cacc_d};
 }
 
 // Capture n generations of the control runs (rank, trials, rollouts, commit,
@@ -455,6 +462,7 @@ metade_status metade_init(const metade_config *cfg, metade_ctx **out) {
   c->n_mfma = (uint32_t)pl.mfma_list.size();
   c->n_ctrl = (uint32_t)pl.ctrl_list.size();
   c->ctrl_max_n = pl.ctrl_max_n;
+  c->ctrl_hidden = pl.ctrl_hidden;
   auto bail = [&](metade_status st) {
     g_init_error = c->err;
     metade_destroy(c);

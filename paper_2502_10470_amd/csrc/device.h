@@ -31,7 +31,8 @@ constexpr int MAX_N = 256;     // LDS-resident kernel: indices fit in 8 bits
 constexpr int MAX_D = 128;
 constexpr int MAX_KP = 32;     // top-p set size for N <= 256 is at most 26
 constexpr uint32_t LDS_BUDGET = 160 * 1024;
-// control workload: one hidden unit per lane, bounded observation / action sizes
+// control workload: the larger policy hidden width (the smaller one, 32, is
+// declared with the launch interface), bounded observation / action sizes
 constexpr int CT_H = 64;
 constexpr int CT_MAX_OBS = 20;
 constexpr int CT_MAX_ACT = 8;

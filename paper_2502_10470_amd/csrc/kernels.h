@@ -29,10 +29,15 @@ struct LaunchArgs {
   hipStream_t stream;
 };
 
-// Control runs (one wavefront per individual, several launches per generation).
+// Hidden widths of the control policies: 32 (the MLPs of Table VII) or CT_H = 64;
+// both hidden layers have the same width, and all control runs of a context too.
+constexpr int CT_H_SMALL = 32;
+
+// Control runs (two individuals per wavefront, several launches per generation).
 struct CtrlArgs {
   const uint32_t *list;   // run ids
   uint32_t n, max_n;      // number of control runs, their largest N
+  uint32_t hidden;        // hidden width of their policies (CT_H_SMALL or CT_H)
   uint32_t *order;        // [sum N] top-p lists at the runs' fitness offsets
   float *fu;              // [sum N] trial fitness
   uint32_t *acc;          // [sum N] selection decisions

@@ -1,16 +1,17 @@
 // Control-shaped workload: each individual is the flattened weight vector of
-// a tanh policy obs -> 64 -> 64 -> act, scored by a rollout of a linear
-// system x_{t+1} = A x_t + B u_t with cost sum_t |x_t|^2 + cw |u_t|^2.  This
-// is the paper's neural-control setting (Sec. IV-D, policy MLPs of Table VII)
-// on a synthetic plant, with the PDE generation of Alg. 2 around it.
+// a tanh policy obs -> H -> H -> act (H = 32, the MLPs of Table VII, or 64),
+// scored by a rollout of a linear system x_{t+1} = A x_t + B u_t with cost
+// sum_t |x_t|^2 + cw |u_t|^2.  This is the paper's neural-control setting
+// (Sec. IV-D) on a synthetic plant, with the PDE generation of Alg. 2 around
+// it.
 //
 // One wavefront evaluates two individuals of one run, 32 lanes each.  Lane l
-// of a half holds, in registers, hidden rows l and l + 32 of W2 (the float32
-// values of the population, widened at use), their biases and a 16-weight
-// slice of W3; its two rows of W1 sit in LDS next to each other.  The
-// activations are exchanged through LDS; with two rows per lane every
-// float64 value read from LDS feeds two FMAs, which halves the LDS traffic
-// per multiply-add.  The rollout is float64: the
+// of a half holds, in registers, hidden row l of W2 and for H = 64 row l + 32
+// too (the float32 values of the population, widened at use), their biases
+// and an H/4-weight slice of W3; its rows of W1 sit in LDS next to each
+// other.  The activations are exchanged through LDS; with two rows per lane
+// every float64 value read from LDS feeds two FMAs, which halves the LDS
+// traffic per multiply-add.  The rollout is float64: the
 // closed loop of a policy amplifies rounding differences (by orders of
 // magnitude for weights of order one), and on gfx950 a float64 FMA issues at
 // the rate of a non-packed float32 FMA.
@@ -36,8 +37,15 @@ namespace {
 constexpr uint32_t CT_TRIAL_THREADS = 256;       // trial construction: threads per trial
 constexpr uint32_t CT_TRIAL_THREADS_INIT = 256;  // initialisation: threads per individual
 constexpr int CT_LPI = 32;            // lanes per individual
-constexpr int CT_RPL = CT_H / CT_LPI; // hidden rows per lane
-constexpr int CT_W3 = 16;             // W3 weights per lane: lane (a, c) has W3[a][16c .. 16c+15]
+
+// Per hidden width H: hidden rows per lane, and W3 weights per lane (lane
+// (a, c) of a half holds W3[a][c H/4 .. (c+1) H/4 - 1]).
+template <int H>
+struct Ct {
+  static_assert(H == CT_H_SMALL || H == CT_H, "hidden width");
+  static constexpr int RPL = H / CT_LPI;
+  static constexpr int W3 = H / 4;
+};
 
 // ---------------------------------------------------------------- geometry
 
@@ -46,15 +54,16 @@ struct CtGeom {
   uint32_t b1, w2, b2, w3, b3;      // flat offsets of the parameter blocks
 };
 
+template <int H>
 __device__ __forceinline__ CtGeom ct_geom(const ProbDev &p) {
   CtGeom g;
   g.O = p.obs;
   g.A = p.act;
-  g.b1 = CT_H * g.O;
-  g.w2 = g.b1 + CT_H;
-  g.b2 = g.w2 + CT_H * CT_H;
-  g.w3 = g.b2 + CT_H;
-  g.b3 = g.w3 + CT_H * g.A;
+  g.b1 = H * g.O;
+  g.w2 = g.b1 + H;
+  g.b2 = g.w2 + H * H;
+  g.w3 = g.b2 + H;
+  g.b3 = g.w3 + H * g.A;
   g.D = g.b3 + g.A;
   return g;
 }
@@ -64,11 +73,13 @@ __device__ __forceinline__ uint32_t row_of(uint32_t l, int r) { return l + CT_LP
 __device__ __forceinline__ uint32_t w1_gene(const CtGeom &G, uint32_t l, int r, uint32_t k) {
   return row_of(l, r) * G.O + k;
 }
+template <int H>
 __device__ __forceinline__ uint32_t w2_gene(const CtGeom &G, uint32_t l, int r, uint32_t k) {
-  return G.w2 + row_of(l, r) * CT_H + k;
+  return G.w2 + row_of(l, r) * H + k;
 }
+template <int H>
 __device__ __forceinline__ uint32_t w3_gene(const CtGeom &G, uint32_t l, uint32_t s) {
-  return G.w3 + (l >> 2) * CT_H + CT_W3 * (l & 3) + s;
+  return G.w3 + (l >> 2) * H + Ct<H>::W3 * (l & 3) + s;
 }
 __device__ __forceinline__ bool w3_owned(const CtGeom &G, uint32_t l) { return (l >> 2) < G.A; }
 __device__ __forceinline__ bool b3_owned(const CtGeom &G, uint32_t l) {
@@ -123,11 +134,12 @@ __device__ __forceinline__ double tanh_f64(double x) {
 // The lane's share of one policy (see the file comment), kept as the float32
 // values the population holds; slots past the geometry are zero so that they
 // contribute nothing.
+template <int H>
 struct Wts {
-  float b1[CT_RPL];
-  float w2[CT_RPL][CT_H];
-  float b2[CT_RPL];
-  float w3[CT_W3];
+  float b1[Ct<H>::RPL];
+  float w2[Ct<H>::RPL][H];
+  float b2[Ct<H>::RPL];
+  float w3[Ct<H>::W3];
   float b3;
 };
 
@@ -135,19 +147,23 @@ struct Wts {
 // bt[a][l] = B[l][a], zero for l >= obs; both halves belong to one run) and
 // per half the vectors exchanged between the lanes in a step.
 // The halves' vectors are padded by 16 bytes so that the two addresses of
-// one broadcast read fall in different LDS banks.
-struct CtLds {
-  float2 w1[CT_MAX_OBS][2][CT_LPI];   // (W1[l][k], W1[l + 32][k]) of half h at [k][h][l]
+// one broadcast read fall in different LDS banks; every vector starts at a
+// multiple of 16 bytes (they are read in double2).
+template <int H>
+struct alignas(16) CtLds {
+  static constexpr int RPL = Ct<H>::RPL;
+  float w1[CT_MAX_OBS][2][RPL * CT_LPI];  // W1[l + 32 r][k] of half h at [k][h][RPL l + r]
   float at[CT_MAX_OBS][CT_LPI];
   float bt[CT_MAX_ACT][CT_LPI];
   double x[2][CT_MAX_OBS + 2];
-  double h1[2][CT_H + 2];
-  double h2[2][CT_H + 2];
+  double h1[2][H + 2];
+  double h2[2][H + 2];
   double u[2][CT_MAX_ACT + 2];
 };
 
+template <int H>
 __device__ __forceinline__ void load_plant(const unsigned char *tab, const ProbDev &p,
-                                           const CtGeom &G, uint32_t lane, CtLds &S) {
+                                           const CtGeom &G, uint32_t lane, CtLds<H> &S) {
   if (lane >= (uint32_t)CT_LPI) return;
   const float *A = tab_ptr<float>(tab, p.A_off);
   const float *B = tab_ptr<float>(tab, p.B_off);
@@ -167,9 +183,11 @@ __device__ __forceinline__ double half_sum(double v) {
 // u_t = tanh(W3 tanh(W2 tanh(W1 x_t + b1) + b2) + b3), x_{t+1} = A x_t + B u_t,
 // for the individual of this lane's half.  Called by the whole wavefront (a
 // one-wave block); returns J in every lane of the half.
-__device__ __forceinline__ double rollout(Wts &W, const float *x0, const CtGeom &G,
+template <int H>
+__device__ __forceinline__ double rollout(Wts<H> &W, const float *x0, const CtGeom &G,
                                           uint32_t steps, uint32_t E, double cw, uint32_t lane,
-                                          CtLds &S) {
+                                          CtLds<H> &S) {
+  constexpr int RPL = Ct<H>::RPL, W3N = Ct<H>::W3;
   const uint32_t h = lane / CT_LPI, l = lane % CT_LPI;
   const uint32_t ga = l >> 2, gc = l & 3;
   double *X = S.x[h], *H1 = S.h1[h], *H2 = S.h2[h], *U = S.u[h];
@@ -187,52 +205,68 @@ __device__ __forceinline__ double rollout(Wts &W, const float *x0, const CtGeom 
       // them stops the compiler from hoisting the float64 widening out of the
       // loop (which would double their registers).
 #pragma unroll
-      for (int k = 0; k < CT_H; ++k) asm volatile("" : "+v"(W.w2[0][k]), "+v"(W.w2[1][k]));
+      for (int k = 0; k < H; ++k) {
+        if constexpr (RPL == 2) asm volatile("" : "+v"(W.w2[0][k]), "+v"(W.w2[1][k]));
+        else asm volatile("" : "+v"(W.w2[0][k]));
+      }
 #pragma unroll
-      for (int k = 0; k < CT_W3; ++k) asm volatile("" : "+v"(W.w3[k]));
-      // layer 1 (both rows) and the A x_t part of the plant update
-      double a0 = (double)W.b1[0], a0b = 0.0, a1 = (double)W.b1[1], a1b = 0.0;
+      for (int k = 0; k < W3N; ++k) asm volatile("" : "+v"(W.w3[k]));
+      // layer 1 (the lane's rows) and the A x_t part of the plant update
+      double y1[RPL], y1b[RPL];
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) {
+        y1[r] = (double)W.b1[r];
+        y1b[r] = 0.0;
+      }
       double ax = 0.0, axb = 0.0;
 #pragma unroll
       for (int k = 0; k < CT_MAX_OBS; k += 2) {
         if ((uint32_t)k < G.O) {
           const double2 xv = *reinterpret_cast<const double2 *>(X + k);
-          const float2 wa = S.w1[k][h][l], wb = S.w1[k + 1][h][l];
-          a0 = fma((double)wa.x, xv.x, a0);
-          a1 = fma((double)wa.y, xv.x, a1);
-          a0b = fma((double)wb.x, xv.y, a0b);
-          a1b = fma((double)wb.y, xv.y, a1b);
+          if constexpr (RPL == 2) {
+            const float2 wa = *reinterpret_cast<const float2 *>(&S.w1[k][h][2 * l]);
+            const float2 wb = *reinterpret_cast<const float2 *>(&S.w1[k + 1][h][2 * l]);
+            y1[0] = fma((double)wa.x, xv.x, y1[0]);
+            y1[1] = fma((double)wa.y, xv.x, y1[1]);
+            y1b[0] = fma((double)wb.x, xv.y, y1b[0]);
+            y1b[1] = fma((double)wb.y, xv.y, y1b[1]);
+          } else {
+            y1[0] = fma((double)S.w1[k][h][l], xv.x, y1[0]);
+            y1b[0] = fma((double)S.w1[k + 1][h][l], xv.y, y1b[0]);
+          }
           ax = fma((double)S.at[k][l], xv.x, ax);
           axb = fma((double)S.at[k + 1][l], xv.y, axb);
         }
       }
       ax += axb;
-      H1[l] = tanh_f64(a0 + a0b);
-      H1[l + CT_LPI] = tanh_f64(a1 + a1b);
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) H1[l + CT_LPI * r] = tanh_f64(y1[r] + y1b[r]);
       __syncthreads();
-      // layer 2: two rows, four partial sums each
-      double c0[4], c1[4];
+      // layer 2: the lane's rows, four partial sums each
+      double c[RPL][4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        c0[q] = q == 0 ? (double)W.b2[0] : 0.0;
-        c1[q] = q == 0 ? (double)W.b2[1] : 0.0;
-      }
+      for (int r = 0; r < RPL; ++r)
 #pragma unroll
-      for (int k = 0; k < CT_H; k += 2) {
+        for (int q = 0; q < 4; ++q) c[r][q] = q == 0 ? (double)W.b2[r] : 0.0;
+#pragma unroll
+      for (int k = 0; k < H; k += 2) {
         const double2 v = *reinterpret_cast<const double2 *>(H1 + k);
-        c0[k & 3] = fma((double)W.w2[0][k], v.x, c0[k & 3]);
-        c1[k & 3] = fma((double)W.w2[1][k], v.x, c1[k & 3]);
-        c0[(k + 1) & 3] = fma((double)W.w2[0][k + 1], v.y, c0[(k + 1) & 3]);
-        c1[(k + 1) & 3] = fma((double)W.w2[1][k + 1], v.y, c1[(k + 1) & 3]);
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+          c[r][k & 3] = fma((double)W.w2[r][k], v.x, c[r][k & 3]);
+          c[r][(k + 1) & 3] = fma((double)W.w2[r][k + 1], v.y, c[r][(k + 1) & 3]);
+        }
       }
-      H2[l] = tanh_f64((c0[0] + c0[1]) + (c0[2] + c0[3]));
-      H2[l + CT_LPI] = tanh_f64((c1[0] + c1[1]) + (c1[2] + c1[3]));
+#pragma unroll
+      for (int r = 0; r < RPL; ++r)
+        H2[l + CT_LPI * r] = tanh_f64((c[r][0] + c[r][1]) + (c[r][2] + c[r][3]));
       __syncthreads();
-      // layer 3: lane (ga, gc) sums W3[ga][16gc .. 16gc+15] h2[...], then 4 lanes combine
+      // layer 3: lane (ga, gc) sums its H/4 weights of W3 row ga against the
+      // matching slice of h2, then the 4 lanes of the row combine
       double pz = 0.0, pzb = 0.0;
 #pragma unroll
-      for (int s = 0; s < CT_W3; s += 2) {
-        const double2 v = *reinterpret_cast<const double2 *>(H2 + CT_W3 * gc + s);
+      for (int s = 0; s < W3N; s += 2) {
+        const double2 v = *reinterpret_cast<const double2 *>(H2 + W3N * gc + s);
         pz = fma((double)W.w3[s], v.x, pz);
         pzb = fma((double)W.w3[s + 1], v.y, pzb);
       }
@@ -260,33 +294,23 @@ __device__ __forceinline__ double rollout(Wts &W, const float *x0, const CtGeom 
   return (half_sum(jx) + cw * half_sum(ju)) / (double)E;
 }
 
-// Component R of a lane's W1 pair in LDS.
-template <int R>
-__device__ __forceinline__ float &w1_slot(CtLds &S, uint32_t k, uint32_t h, uint32_t l) {
-  return R == 0 ? S.w1[k][h][l].x : S.w1[k][h][l].y;
-}
-
-// Fill the lane's slots of hidden row set R from a per-gene function val(j).
-template <int R, typename Val>
-__device__ __forceinline__ void fill_rows(const CtGeom &G, uint32_t h, uint32_t l, Wts &W,
-                                          CtLds &S, Val &val) {
-  for (uint32_t k = 0; k < (uint32_t)CT_MAX_OBS; ++k)
-    w1_slot<R>(S, k, h, l) = k < G.O ? val(w1_gene(G, l, R, k)) : 0.0f;
-  W.b1[R] = val(G.b1 + row_of(l, R));
-#pragma unroll
-  for (int k = 0; k < CT_H; ++k) W.w2[R][k] = val(w2_gene(G, l, R, k));
-  W.b2[R] = val(G.b2 + row_of(l, R));
-}
-
 // Fill the lane's slots from a per-gene function val(j) -> float.
-template <typename Val>
-__device__ __forceinline__ void fill_wts(const CtGeom &G, uint32_t h, uint32_t l, Wts &W, CtLds &S,
-                                         Val val) {
-  fill_rows<0>(G, h, l, W, S, val);
-  fill_rows<1>(G, h, l, W, S, val);
+template <int H, typename Val>
+__device__ __forceinline__ void fill_wts(const CtGeom &G, uint32_t h, uint32_t l, Wts<H> &W,
+                                         CtLds<H> &S, Val val) {
+  constexpr int RPL = Ct<H>::RPL;
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    for (uint32_t k = 0; k < (uint32_t)CT_MAX_OBS; ++k)
+      S.w1[k][h][RPL * l + r] = k < G.O ? val(w1_gene(G, l, r, k)) : 0.0f;
+    W.b1[r] = val(G.b1 + row_of(l, r));
+#pragma unroll
+    for (int k = 0; k < H; ++k) W.w2[r][k] = val(w2_gene<H>(G, l, r, k));
+    W.b2[r] = val(G.b2 + row_of(l, r));
+  }
   const bool o3 = w3_owned(G, l);
 #pragma unroll
-  for (int s = 0; s < CT_W3; ++s) W.w3[s] = o3 ? val(w3_gene(G, l, s)) : 0.0f;
+  for (int s = 0; s < Ct<H>::W3; ++s) W.w3[s] = o3 ? val(w3_gene<H>(G, l, s)) : 0.0f;
   W.b3 = b3_owned(G, l) ? val(G.b3 + (l >> 2)) : 0.0f;
 }
 
@@ -519,13 +543,14 @@ __global__ __launch_bounds__(CT_TRIAL_THREADS) void k_ctrl_trials(
 // evaluation of the initial population, written as its fitness).  Grid
 // (ceil(max N / 2), control runs), one wavefront per two targets; each lane
 // loads its weight slots from the pending row (float4 where aligned).
-template <bool TRACE, bool INIT>
+template <int H, bool TRACE, bool INIT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_ctrl_eval(
     const RunDev *__restrict__ runs, const uint32_t *__restrict__ list,
     const ProbDev *__restrict__ probs, const unsigned char *__restrict__ tab,
     float *__restrict__ fit, const float *__restrict__ pend, float *__restrict__ fu_out,
     uint32_t *__restrict__ acc_out, TraceArgs tr) {
-  __shared__ CtLds S;
+  constexpr int RPL = Ct<H>::RPL;
+  __shared__ CtLds<H> S;
   const RunDev run = runs[list[blockIdx.y]];
   const uint32_t lane = threadIdx.x, h = lane / CT_LPI, l = lane % CT_LPI;
   const uint32_t i0 = 2 * blockIdx.x;
@@ -534,32 +559,32 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   const uint32_t i = min(i0 + h, N - 1);   // an odd N duplicates the last target
   const bool writer = i0 + h < N;
   const ProbDev p = probs[run.prob];
-  const CtGeom G = ct_geom(p);
+  const CtGeom G = ct_geom<H>(p);
   const float *U = pend + run.pend_off + (size_t)i * run.Dp;
-  Wts W;
+  Wts<H> W;
   // W1 rows (stride obs, not aligned in general) into LDS, biases
 #pragma unroll
-  for (int r = 0; r < CT_RPL; ++r) {
-    for (uint32_t k = 0; k < (uint32_t)CT_MAX_OBS; ++k) {
-      const float v = k < G.O ? U[w1_gene(G, l, r, k)] : 0.0f;
-      if (r == 0) S.w1[k][h][l].x = v; else S.w1[k][h][l].y = v;
-    }
+  for (int r = 0; r < RPL; ++r) {
+    for (uint32_t k = 0; k < (uint32_t)CT_MAX_OBS; ++k)
+      S.w1[k][h][RPL * l + r] = k < G.O ? U[w1_gene(G, l, r, k)] : 0.0f;
     W.b1[r] = U[G.b1 + row_of(l, r)];
     W.b2[r] = U[G.b2 + row_of(l, r)];
   }
-  // W2 rows: 16-byte aligned (pending rows are, and the block starts at 64 obs + 64)
+  // W2 rows: 16-byte aligned (pending rows are, the block starts at H (obs + 1)
+  // and H is a multiple of 4)
 #pragma unroll
-  for (int k = 0; k < CT_H; k += 4) {
-    const float4 a = *reinterpret_cast<const float4 *>(U + w2_gene(G, l, 0, k));
-    const float4 b = *reinterpret_cast<const float4 *>(U + w2_gene(G, l, 1, k));
-    W.w2[0][k] = a.x; W.w2[0][k + 1] = a.y; W.w2[0][k + 2] = a.z; W.w2[0][k + 3] = a.w;
-    W.w2[1][k] = b.x; W.w2[1][k + 1] = b.y; W.w2[1][k + 2] = b.z; W.w2[1][k + 3] = b.w;
+  for (int r = 0; r < RPL; ++r) {
+#pragma unroll
+    for (int k = 0; k < H; k += 4) {
+      const float4 a = *reinterpret_cast<const float4 *>(U + w2_gene<H>(G, l, r, k));
+      W.w2[r][k] = a.x; W.w2[r][k + 1] = a.y; W.w2[r][k + 2] = a.z; W.w2[r][k + 3] = a.w;
+    }
   }
   const bool o3 = w3_owned(G, l);
 #pragma unroll
-  for (int t = 0; t < CT_W3; t += 4) {
+  for (int t = 0; t < Ct<H>::W3; t += 4) {
     float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (o3) a = *reinterpret_cast<const float4 *>(U + w3_gene(G, l, t));
+    if (o3) a = *reinterpret_cast<const float4 *>(U + w3_gene<H>(G, l, t));
     W.w3[t] = a.x; W.w3[t + 1] = a.y; W.w3[t + 2] = a.z; W.w3[t + 3] = a.w;
   }
   W.b3 = b3_owned(G, l) ? U[G.b3 + (l >> 2)] : 0.0f;
@@ -605,6 +630,7 @@ __global__ __launch_bounds__(256) void k_ctrl_commit(const RunDev *__restrict__ 
 // Best record of every control run: the first individual in (fitness, index)
 // order, its float64 cost (the rollout is float64 already) and its weights.
 // Both halves of the wavefront evaluate it; the first writes.
+template <int H>
 __global__ __launch_bounds__(64) void k_ctrl_finalize(const RunDev *__restrict__ runs,
                                                       const uint32_t *__restrict__ list,
                                                       const ProbDev *__restrict__ probs,
@@ -613,11 +639,11 @@ __global__ __launch_bounds__(64) void k_ctrl_finalize(const RunDev *__restrict__
                                                       const float *__restrict__ fit,
                                                       double *__restrict__ best_y,
                                                       float *__restrict__ best_x) {
-  __shared__ CtLds S;
+  __shared__ CtLds<H> S;
   const uint32_t r = list[blockIdx.x];
   const RunDev run = runs[r];
   const ProbDev p = probs[run.prob];
-  const CtGeom G = ct_geom(p);
+  const CtGeom G = ct_geom<H>(p);
   const uint32_t lane = threadIdx.x, h = lane / CT_LPI, l = lane % CT_LPI;
   uint64_t best = ~0ull;
   for (uint32_t i = lane; i < run.N; i += 64) best = min(best, mkkey(fit[run.fit_off + i], i));
@@ -629,8 +655,8 @@ __global__ __launch_bounds__(64) void k_ctrl_finalize(const RunDev *__restrict__
   const uint32_t b = (uint32_t)(best & 0xFFFFFFFFu);
   const float *x = pop + run.pop_off + (size_t)b * G.D;
   for (uint32_t j = lane; j < G.D; j += 64) best_x[run.bx_off + j] = x[j];
-  Wts W;
-  fill_wts(G, h, l, W, S, [&](uint32_t j) { return x[j]; });
+  Wts<H> W;
+  fill_wts<H>(G, h, l, W, S, [&](uint32_t j) { return x[j]; });
   load_plant(tab, p, G, lane, S);
   const double J = rollout(W, tab_ptr<float>(tab, p.x0_off), G, p.steps, p.nroll, (double)p.cw,
                            lane, S);
@@ -639,13 +665,28 @@ __global__ __launch_bounds__(64) void k_ctrl_finalize(const RunDev *__restrict__
 
 // ---------------------------------------------------------------- launchers
 
+namespace {
+
+// Evaluation launch for the context's hidden width.
+template <bool TRACE, bool INIT>
+void launch_eval(const LaunchArgs &a, const CtrlArgs &c, TraceArgs tr) {
+  const dim3 egrid((c.max_n + 1) / 2, c.n);
+  if (c.hidden == (uint32_t)CT_H_SMALL)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ctrl_eval<CT_H_SMALL, TRACE, INIT>), egrid, dim3(64), 0,
+                       a.stream, a.runs, c.list, a.probs, a.tab, a.fit, a.pending, c.fu, c.acc, tr);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ctrl_eval<CT_H, TRACE, INIT>), egrid, dim3(64), 0,
+                       a.stream, a.runs, c.list, a.probs, a.tab, a.fit, a.pending, c.fu, c.acc, tr);
+}
+
+}  // namespace
+
 hipError_t launch_ctrl_init(const LaunchArgs &a, const CtrlArgs &c, double lb, double ub) {
   if (c.n == 0) return hipSuccess;
+  if (c.hidden != (uint32_t)CT_H_SMALL && c.hidden != (uint32_t)CT_H) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_ctrl_init_pop, dim3(c.max_n, c.n), dim3(CT_TRIAL_THREADS_INIT), 0, a.stream,
                      a.runs, c.list, a.pop, a.pending, a.k0, a.k1, lb, ub);
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ctrl_eval<false, true>), dim3((c.max_n + 1) / 2, c.n),
-                     dim3(64), 0, a.stream, a.runs, c.list, a.probs, a.tab, a.fit, a.pending, c.fu,
-                     c.acc, TraceArgs{nullptr, nullptr, nullptr});
+  launch_eval<false, true>(a, c, TraceArgs{nullptr, nullptr, nullptr});
   return hipGetLastError();
 }
 
@@ -667,7 +708,8 @@ hipError_t launch_ctrl_set_gen(uint32_t *gen, uint32_t v, hipStream_t s) {
 hipError_t launch_ctrl_generations(const LaunchArgs &a, const CtrlArgs &c, uint32_t *gen,
                                    uint32_t n_gens, float lb, float ub, TraceArgs tr) {
   if (c.n == 0) return hipSuccess;
-  const dim3 tgrid(c.max_n, c.n), egrid((c.max_n + 1) / 2, c.n);
+  if (c.hidden != (uint32_t)CT_H_SMALL && c.hidden != (uint32_t)CT_H) return hipErrorInvalidValue;
+  const dim3 tgrid(c.max_n, c.n);
   for (uint32_t g = 0; g < n_gens; ++g) {
     hipLaunchKernelGGL(k_ctrl_rank, dim3(c.n), dim3(CT_MAX_N), 0, a.stream, a.runs, c.list, a.fit,
                        c.order);
@@ -675,14 +717,12 @@ hipError_t launch_ctrl_generations(const LaunchArgs &a, const CtrlArgs &c, uint3
       hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ctrl_trials<true>), tgrid, dim3(CT_TRIAL_THREADS), 0,
                          a.stream, a.runs, c.list, a.pop, a.pending, c.order, gen, g, lb, ub,
                          a.k0, a.k1, tr);
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ctrl_eval<true, false>), egrid, dim3(64), 0, a.stream, a.runs,
-                         c.list, a.probs, a.tab, a.fit, a.pending, c.fu, c.acc, tr);
+      launch_eval<true, false>(a, c, tr);
     } else {
       hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ctrl_trials<false>), tgrid, dim3(CT_TRIAL_THREADS), 0,
                          a.stream, a.runs, c.list, a.pop, a.pending, c.order, gen, g, lb, ub,
                          a.k0, a.k1, tr);
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ctrl_eval<false, false>), egrid, dim3(64), 0, a.stream, a.runs,
-                         c.list, a.probs, a.tab, a.fit, a.pending, c.fu, c.acc, tr);
+      launch_eval<false, false>(a, c, tr);
     }
     hipLaunchKernelGGL(k_ctrl_commit, dim3(c.max_n, c.n), dim3(256), 0, a.stream, a.runs, c.list,
                        a.pop, a.fit, a.pending, c.fu, c.acc);
@@ -696,8 +736,14 @@ hipError_t launch_ctrl_generations(const LaunchArgs &a, const CtrlArgs &c, uint3
 hipError_t launch_ctrl_finalize(const LaunchArgs &a, const CtrlArgs &c, double *best_y,
                                 float *best_x) {
   if (c.n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ctrl_finalize, dim3(c.n), dim3(64), 0, a.stream, a.runs, c.list, a.probs,
-                     a.tab, a.pop, a.fit, best_y, best_x);
+  if (c.hidden == (uint32_t)CT_H_SMALL)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ctrl_finalize<CT_H_SMALL>), dim3(c.n), dim3(64), 0,
+                       a.stream, a.runs, c.list, a.probs, a.tab, a.pop, a.fit, best_y, best_x);
+  else if (c.hidden == (uint32_t)CT_H)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ctrl_finalize<CT_H>), dim3(c.n), dim3(64), 0, a.stream,
+                       a.runs, c.list, a.probs, a.tab, a.pop, a.fit, best_y, best_x);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -142,8 +142,46 @@ def test_control_query_sizes():
     assert scratch >= 4 * D * 356   # pending trial rows
 
 
+@pytest.mark.parametrize("obs,act,D", [(11, 3, 1539), (8, 2, 1410), (11, 2, 1506)])
+def test_control_query_sizes_table7_policies(obs, act, D):
+    """The 32 x 32 policies of Table VII are accepted with their weight counts."""
+    M = _lib()
+    cfg, keep = _ctrl_cfg(M, N=(100,), obs=obs, act=act, hidden=(32, 32))
+    pop, fit, by, bx, scratch = M.metade_query_sizes(cfg)
+    assert pop == 4 * D * 100 and fit == 4 * 100 and bx == 4 * D
+    cfg, keep = _ctrl_cfg(M, N=(100,), obs=obs, act=act, hidden=(32, 32), D=D + 1)
+    with pytest.raises(M.MetadeError) as ei:
+        M.metade_query_sizes(cfg)
+    assert "weight count " + str(D) in str(ei.value)
+
+
+def test_control_mixed_hidden_widths_rejected():
+    """All control policies of one context share one hidden width."""
+    M = _lib()
+    cfg, keep = _ctrl_cfg(M, N=(100, 100))
+    probs = (M.MetadeProblem * 2)()
+    ctypes.memmove(ctypes.addressof(probs), ctypes.addressof(keep["probs"]),
+                   ctypes.sizeof(M.MetadeProblem))
+    ctypes.memmove(ctypes.addressof(probs) + ctypes.sizeof(M.MetadeProblem),
+                   ctypes.addressof(keep["probs"]), ctypes.sizeof(M.MetadeProblem))
+    probs[1].hidden1 = probs[1].hidden2 = 32
+    probs[1].D = 32 * 17 + 32 + 32 * 32 + 32 + 32 * 6 + 6
+    keep["probs2"] = probs
+    keep["P"][1] = 1
+    cfg.n_problems = 2
+    cfg.problems = ctypes.addressof(probs)
+    with pytest.raises(M.MetadeError) as ei:
+        M.metade_query_sizes(cfg)
+    assert "status -1" in str(ei.value) and "same hidden width" in str(ei.value)
+    probs[1].hidden1 = probs[1].hidden2 = 64
+    probs[1].D = 5702
+    M.metade_query_sizes(cfg)
+
+
 @pytest.mark.parametrize("kw,msg", [
-    ({"hidden": (32, 32)}, "64 units"),
+    ({"hidden": (48, 48)}, "32 or both 64"),
+    ({"hidden": (32, 64)}, "32 or both 64"),
+    ({"hidden": (64, 32)}, "32 or both 64"),
     ({"obs": 21}, "obs"),
     ({"act": 9}, "act"),
     ({"D": 5701}, "weight count"),

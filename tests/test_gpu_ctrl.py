@@ -152,3 +152,51 @@ def test_control_graph_replays_match_direct_launches():
         pg, fg = bg.host_state()
         pd, fd = bd2.host_state()
         assert np.array_equal(pg, pd) and np.array_equal(fg, fd)
+
+
+@pytest.mark.parametrize("shapes,steps,n_roll,n_cs", [
+    # the three policies of Table VII (hidden 32 x 32: 1539, 1410, 1506 weights)
+    ([(11, 3), (8, 2), (11, 2)] * 3, 200, 1, 2),
+    # odd D (1153), several rollouts, arithmetic crossover; largest obs / act
+    ([(1, 1), (20, 8), (1, 1), (20, 8)], 15, 2, 3),
+])
+def test_control_hidden32_follows_oracle(shapes, steps, n_roll, n_cs):
+    Ns = [10, 17, 33, 64, 65, 40, 12, 20, 100][:len(shapes)]
+    th = _strategy_grid(len(Ns), n_cs, seed=len(shapes) * 10 + steps)
+    wl = W.control_batch(21 + steps, Ns, shapes=shapes, steps=steps, n_rollouts=n_roll,
+                         theta=th, n_cs=n_cs, hidden=W.TABLE7_HIDDEN)
+    assert all(p.hidden == (32, 32) for p in wl.problems)
+    b = _batch(wl)
+    out = trajectory_parity(b, wl, G=3)
+    print(f"hidden 32 {shapes[:3]}: compared {out['compared']} diverged {out['diverged']} "
+          f"(undetermined {out['ill']}) max fitness rel err {out['max_fit_rel']:.3g}")
+    assert out["compared"] >= 2 * len(Ns)
+
+
+def test_control_table7_workload_two_generations():
+    """96 executors (32 per Table VII policy) x N=100, 200-step horizon: two traced
+    generations at the full size."""
+    wl = W.workload_t7()
+    b = _batch(wl)
+    out = trajectory_parity(b, wl, G=2)
+    print(f"t7: compared {out['compared']} diverged {out['diverged']} "
+          f"max fitness rel err {out['max_fit_rel']:.3g}")
+    assert out["compared"] >= 96
+
+
+def test_control_hidden32_best_record_float64():
+    wl = W.control_batch(5, [24, 30, 16], shapes=[(11, 3), (8, 2), (11, 2)], steps=50, G=4,
+                         hidden=W.TABLE7_HIDDEN)
+    b = _batch(wl)
+    b.inner_step(4)
+    y = b.get_best()
+    pop, fit = b.host_state()
+    bx = b.best_x.cpu().numpy()
+    for r in range(wl.n_runs):
+        f = b.run_fit(fit, r)
+        i = int(np.lexsort((np.arange(len(f)), pde.order_key(f)))[0])
+        x = b.run_pop(pop, r)[i]
+        assert np.array_equal(b.run_bx(bx, r), x)
+        ref = float(evaluate(x, wl.problems[r]))
+        assert abs(y[r] - ref) <= 1e-9 * abs(ref), (r, y[r], ref)
+        assert abs(float(f[i]) - ref) <= FIT_RTOL * abs(ref)

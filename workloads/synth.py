@@ -27,6 +27,9 @@ _KIND_TAG = {k: i + 1 for i, k in enumerate(KINDS)}
 LQR_OBS = 17
 LQR_ACT = 6
 LQR_HIDDEN = (64, 64)
+# Policy shapes (obs, act) of the three control tasks of Table VII, hidden 32 x 32
+TABLE7_HIDDEN = (32, 32)
+TABLE7_TASKS = (("hopper", 11, 3), ("swimmer", 8, 2), ("reacher", 11, 2))
 LQR_STEPS = 200
 LQR_CTRL_WEIGHT = 0.01
 # Weight box of the control workload: 1/sqrt(obs) rounded to 0.25 (the usual
@@ -117,7 +120,7 @@ def make_rotation(rng: np.random.Generator, D: int) -> np.ndarray:
 
 def make_problem(kind: str, D: int, seed: int, run: int, identity_rotation: bool = False,
                  bias: float = 100.0, n_rollouts: int = 1, obs: int = LQR_OBS,
-                 act: int = LQR_ACT, steps: int = LQR_STEPS) -> Problem:
+                 act: int = LQR_ACT, steps: int = LQR_STEPS, hidden=LQR_HIDDEN) -> Problem:
     """One seeded instance of a shifted-rotated function (or the control system:
     A = 0.95 G / rho(G) with G Gaussian, B Gaussian / sqrt(obs), x0 ~ N(0, I))."""
     if kind not in KINDS:
@@ -129,10 +132,11 @@ def make_problem(kind: str, D: int, seed: int, run: int, identity_rotation: bool
         A = (0.95 * g / rho).astype(np.float32)
         B = (rng.standard_normal((obs, act)) / np.sqrt(obs)).astype(np.float32)
         x0 = rng.standard_normal((n_rollouts, obs)).astype(np.float32)
-        Dm = mlp_param_count(obs, LQR_HIDDEN, act)
+        Dm = mlp_param_count(obs, hidden, act)
         if D != Dm:
             raise ValueError(f"control workload has D={Dm}, got {D}")
-        return Problem(kind=kind, D=D, bias=0.0, A=A, B=B, x0=x0, steps=steps)
+        return Problem(kind=kind, D=D, bias=0.0, A=A, B=B, x0=x0, steps=steps,
+                       hidden=tuple(hidden))
     o = rng.uniform(-80.0, 80.0, size=D).astype(np.float32)
     R = np.eye(D, dtype=np.float32) if identity_rotation else make_rotation(rng, D)
     p = Problem(kind=kind, D=D, bias=bias, o=o, R=R)
@@ -228,6 +232,27 @@ def workload_c5(runs: int = 16, N: int = 256, G: int = 100, n_rollouts: int = 1)
                     stream=np.arange(runs, dtype=np.uint32), problems=problems, G=G, theta=theta)
 
 
+def workload_t7(runs_per_task: int = 32, N: int = 100, G: int = 50) -> Workload:
+    """The policy MLPs of Table VII (hopper 11->32->32->3, 1539 weights; swimmer
+    8->32->32->2, 1410; reacher 11->32->32->2, 1506), each scored by a 200-step
+    rollout of a seeded stable linear plant of the task's observation / action
+    sizes (standing in for the robot simulator).  32 executors per task with the
+    control experiment's population 100 and 50 generations (Sec. IV-D)."""
+    seed = 7
+    rng = _rng(seed, 0x77)
+    runs = runs_per_task * len(TABLE7_TASKS)
+    theta = _sample_theta(rng, runs, 2)
+    problems = []
+    for r in range(runs):
+        _, obs, act = TABLE7_TASKS[r // runs_per_task]
+        D = mlp_param_count(obs, TABLE7_HIDDEN, act)
+        problems.append(make_problem("lqr_mlp", D, seed, r, obs=obs, act=act,
+                                     hidden=TABLE7_HIDDEN))
+    return Workload(name="t7_control_mlp", seed=seed, lb=-CTRL_BOX, ub=CTRL_BOX, n_cs=2,
+                    N=np.full(runs, N, np.uint32), problem=np.arange(runs, dtype=np.uint32),
+                    stream=np.arange(runs, dtype=np.uint32), problems=problems, G=G, theta=theta)
+
+
 def small_batch(seed: int, kinds, Ns, Ds, G: int = 3, n_cs: int = 2, theta=None,
                 identity_rotation: bool = False, lb: float = -100.0, ub: float = 100.0,
                 streams=None) -> Workload:
@@ -245,15 +270,19 @@ def small_batch(seed: int, kinds, Ns, Ds, G: int = 3, n_cs: int = 2, theta=None,
 
 
 def control_batch(seed: int, Ns, obs: int = LQR_OBS, act: int = LQR_ACT, steps: int = LQR_STEPS,
-                  n_rollouts: int = 1, theta=None, n_cs: int = 2, G: int = 3) -> Workload:
-    """A small batch of control runs (one plant per run) for parity tests."""
+                  n_rollouts: int = 1, theta=None, n_cs: int = 2, G: int = 3,
+                  hidden=LQR_HIDDEN, shapes=None) -> Workload:
+    """A small batch of control runs (one plant per run) for parity tests.  ``shapes``
+    gives each run's (obs, act) in place of the common obs / act."""
     runs = len(Ns)
     rng = _rng(seed, 0xC7)
     if theta is None:
         theta = _sample_theta(rng, runs, n_cs)
-    D = mlp_param_count(obs, LQR_HIDDEN, act)
-    problems = [make_problem("lqr_mlp", D, seed, r, n_rollouts=n_rollouts, obs=obs, act=act,
-                             steps=steps) for r in range(runs)]
+    if shapes is None:
+        shapes = [(obs, act)] * runs
+    problems = [make_problem("lqr_mlp", mlp_param_count(o, hidden, a), seed, r,
+                             n_rollouts=n_rollouts, obs=o, act=a, steps=steps, hidden=hidden)
+                for r, (o, a) in enumerate(shapes)]
     return Workload(name=f"control_{seed}", seed=seed, lb=-CTRL_BOX, ub=CTRL_BOX, n_cs=n_cs,
                     N=np.asarray(Ns, np.uint32), problem=np.arange(runs, dtype=np.uint32),
                     stream=np.arange(runs, dtype=np.uint32), problems=problems, G=G,
@@ -262,5 +291,5 @@ def control_batch(seed: int, Ns, obs: int = LQR_OBS, act: int = LQR_ACT, steps: 
 
 def workload_by_name(name: str) -> Workload:
     table = {"c1": workload_c1, "c2": workload_c2, "c3": workload_c3, "c4": workload_c4,
-             "c5": workload_c5, "paper": workload_paper}
+             "c5": workload_c5, "paper": workload_paper, "t7": workload_t7}
     return table[name]()
