@@ -31,13 +31,17 @@ struct LaunchArgs {
 
 // Hidden widths of the control policies: 32 (the MLPs of Table VII) or CT_H = 64;
 // both hidden layers have the same width, and all control runs of a context too.
+// Lanes per policy in the evaluation: 32, or 16 for width 32 when every control
+// problem has at most CT_OBS_L16 observations.
 constexpr int CT_H_SMALL = 32;
+constexpr int CT_OBS_L16 = 16;
 
 // Control runs (two individuals per wavefront, several launches per generation).
 struct CtrlArgs {
   const uint32_t *list;   // run ids
   uint32_t n, max_n;      // number of control runs, their largest N
   uint32_t hidden;        // hidden width of their policies (CT_H_SMALL or CT_H)
+  uint32_t lanes;         // lanes per policy in the evaluation (32, or 16 for CT_H_SMALL)
   uint32_t *order;        // [sum N] top-p lists at the runs' fitness offsets
   float *fu;              // [sum N] trial fitness
   uint32_t *acc;          // [sum N] selection decisions

@@ -5,13 +5,14 @@
 // (Sec. IV-D) on a synthetic plant, with the PDE generation of Alg. 2 around
 // it.
 //
-// One wavefront evaluates two individuals of one run, 32 lanes each.  Lane l
-// of a half holds, in registers, hidden row l of W2 and for H = 64 row l + 32
-// too (the float32 values of the population, widened at use), their biases
-// and an H/4-weight slice of W3; its rows of W1 sit in LDS next to each
-// other.  The activations are exchanged through LDS; with two rows per lane
-// every float64 value read from LDS feeds two FMAs, which halves the LDS
-// traffic per multiply-add.  The rollout is float64: the
+// One wavefront evaluates 64 / L individuals of one run, L lanes each (L = 32;
+// L = 16 for H = 32 when obs <= 16, which halves the number of wavefronts
+// and keeps two rows per lane).  Lane l of a group holds, in registers,
+// hidden rows l + L r of W2 (r < H / L; the float32 values of the population,
+// widened at use), their biases and a slice of W3; its rows of W1 sit in LDS
+// next to each other.  The activations are exchanged through LDS; with two
+// rows per lane every float64 value read from LDS feeds two FMAs, which
+// halves the LDS traffic per multiply-add.  The rollout is float64: the
 // closed loop of a policy amplifies rounding differences (by orders of
 // magnitude for weights of order one), and on gfx950 a float64 FMA issues at
 // the rate of a non-packed float32 FMA.
@@ -36,15 +37,20 @@ namespace {
 
 constexpr uint32_t CT_TRIAL_THREADS = 256;       // trial construction: threads per trial
 constexpr uint32_t CT_TRIAL_THREADS_INIT = 256;  // initialisation: threads per individual
-constexpr int CT_LPI = 32;            // lanes per individual
 
-// Per hidden width H: hidden rows per lane, and W3 weights per lane (lane
-// (a, c) of a half holds W3[a][c H/4 .. (c+1) H/4 - 1]).
-template <int H>
+// Layout of a policy of hidden width H over L lanes of a wavefront (a group):
+// lane l holds hidden rows l + L r, r < RPL; for layer 3 lane l is part
+// c = l % LPA of output a = l / LPA (LPA = L / 8 lanes per output, so up to 8
+// outputs) and holds W3[a][c W3 .. (c+1) W3 - 1]; observation l of the plant
+// update sits on lane l, so obs <= MAXO.
+template <int H, int L>
 struct Ct {
-  static_assert(H == CT_H_SMALL || H == CT_H, "hidden width");
-  static constexpr int RPL = H / CT_LPI;
-  static constexpr int W3 = H / 4;
+  static_assert((H == CT_H_SMALL || H == CT_H) && (L == 16 || L == 32) && H >= L, "layout");
+  static constexpr int RPL = H / L;    // hidden rows per lane
+  static constexpr int IPW = 64 / L;   // individuals per wavefront
+  static constexpr int LPA = L / 8;    // lanes per output of layer 3
+  static constexpr int W3 = H / LPA;   // W3 weights per lane
+  static constexpr int MAXO = L < CT_MAX_OBS ? L : CT_MAX_OBS;
 };
 
 // ---------------------------------------------------------------- geometry
@@ -68,22 +74,29 @@ __device__ __forceinline__ CtGeom ct_geom(const ProbDev &p) {
   return g;
 }
 
-// Gene index of each register slot of lane l (0..31 within its half).
-__device__ __forceinline__ uint32_t row_of(uint32_t l, int r) { return l + CT_LPI * r; }
+// Gene index of each register slot of lane l (0..L-1 within its group).
+template <int L>
+__device__ __forceinline__ uint32_t row_of(uint32_t l, int r) { return l + L * r; }
+template <int L>
 __device__ __forceinline__ uint32_t w1_gene(const CtGeom &G, uint32_t l, int r, uint32_t k) {
-  return row_of(l, r) * G.O + k;
+  return row_of<L>(l, r) * G.O + k;
 }
-template <int H>
+template <int H, int L>
 __device__ __forceinline__ uint32_t w2_gene(const CtGeom &G, uint32_t l, int r, uint32_t k) {
-  return G.w2 + row_of(l, r) * H + k;
+  return G.w2 + row_of<L>(l, r) * H + k;
 }
-template <int H>
+template <int H, int L>
 __device__ __forceinline__ uint32_t w3_gene(const CtGeom &G, uint32_t l, uint32_t s) {
-  return G.w3 + (l >> 2) * H + Ct<H>::W3 * (l & 3) + s;
+  using C = Ct<H, L>;
+  return G.w3 + (l / C::LPA) * H + C::W3 * (l % C::LPA) + s;
 }
-__device__ __forceinline__ bool w3_owned(const CtGeom &G, uint32_t l) { return (l >> 2) < G.A; }
+template <int H, int L>
+__device__ __forceinline__ bool w3_owned(const CtGeom &G, uint32_t l) {
+  return l / Ct<H, L>::LPA < G.A;
+}
+template <int H, int L>
 __device__ __forceinline__ bool b3_owned(const CtGeom &G, uint32_t l) {
-  return (l >> 2) < G.A && (l & 3) == 0;
+  return l / Ct<H, L>::LPA < G.A && l % Ct<H, L>::LPA == 0;
 }
 
 // ---------------------------------------------------------------- float64 tanh
@@ -134,67 +147,69 @@ __device__ __forceinline__ double tanh_f64(double x) {
 // The lane's share of one policy (see the file comment), kept as the float32
 // values the population holds; slots past the geometry are zero so that they
 // contribute nothing.
-template <int H>
+template <int H, int L>
 struct Wts {
-  float b1[Ct<H>::RPL];
-  float w2[Ct<H>::RPL][H];
-  float b2[Ct<H>::RPL];
-  float w3[Ct<H>::W3];
+  float b1[Ct<H, L>::RPL];
+  float w2[Ct<H, L>::RPL][H];
+  float b2[Ct<H, L>::RPL];
+  float w3[Ct<H, L>::W3];
   float b3;
 };
 
 // LDS of one wavefront: the plant's coefficients by lane (at[k][l] = A[l][k],
-// bt[a][l] = B[l][a], zero for l >= obs; both halves belong to one run) and
-// per half the vectors exchanged between the lanes in a step.
-// The halves' vectors are padded by 16 bytes so that the two addresses of
-// one broadcast read fall in different LDS banks; every vector starts at a
+// bt[a][l] = B[l][a], zero for l >= obs; all groups belong to one run) and
+// per group the vectors exchanged between the lanes in a step.
+// The groups' vectors are padded by 16 bytes so that the addresses of one
+// broadcast read fall in different LDS banks; every vector starts at a
 // multiple of 16 bytes (they are read in double2).
-template <int H>
+template <int H, int L>
 struct alignas(16) CtLds {
-  static constexpr int RPL = Ct<H>::RPL;
-  float w1[CT_MAX_OBS][2][RPL * CT_LPI];  // W1[l + 32 r][k] of half h at [k][h][RPL l + r]
-  float at[CT_MAX_OBS][CT_LPI];
-  float bt[CT_MAX_ACT][CT_LPI];
-  double x[2][CT_MAX_OBS + 2];
-  double h1[2][H + 2];
-  double h2[2][H + 2];
-  double u[2][CT_MAX_ACT + 2];
+  using C = Ct<H, L>;
+  float w1[C::MAXO][C::IPW][C::RPL * L];  // W1[l + L r][k] of group h at [k][h][RPL l + r]
+  float at[C::MAXO][L];
+  float bt[CT_MAX_ACT][L];
+  double x[C::IPW][C::MAXO + 2];
+  double h1[C::IPW][H + 2];
+  double h2[C::IPW][H + 2];
+  double u[C::IPW][CT_MAX_ACT + 2];
 };
 
-template <int H>
+template <int H, int L>
 __device__ __forceinline__ void load_plant(const unsigned char *tab, const ProbDev &p,
-                                           const CtGeom &G, uint32_t lane, CtLds<H> &S) {
-  if (lane >= (uint32_t)CT_LPI) return;
+                                           const CtGeom &G, uint32_t lane, CtLds<H, L> &S) {
+  if (lane >= (uint32_t)L) return;
   const float *A = tab_ptr<float>(tab, p.A_off);
   const float *B = tab_ptr<float>(tab, p.B_off);
   const bool own = lane < G.O;
-  for (uint32_t k = 0; k < (uint32_t)CT_MAX_OBS; ++k) S.at[k][lane] = (own && k < G.O) ? A[lane * G.O + k] : 0.0f;
+  for (uint32_t k = 0; k < (uint32_t)Ct<H, L>::MAXO; ++k) S.at[k][lane] = (own && k < G.O) ? A[lane * G.O + k] : 0.0f;
   for (uint32_t a = 0; a < (uint32_t)CT_MAX_ACT; ++a) S.bt[a][lane] = (own && a < G.A) ? B[lane * G.A + a] : 0.0f;
 }
 
-// Sum over the 32 lanes of a half.
-__device__ __forceinline__ double half_sum(double v) {
+// Sum over the L lanes of a group.
+template <int L>
+__device__ __forceinline__ double group_sum(double v) {
 #pragma unroll
-  for (int s = 16; s > 0; s >>= 1) v += __shfl_xor(v, s);
+  for (int s = L / 2; s > 0; s >>= 1) v += __shfl_xor(v, s);
   return v;
 }
 
 // Mean over the rollouts of J = sum_{t < steps} (|x_t|^2 + cw |u_t|^2),
 // u_t = tanh(W3 tanh(W2 tanh(W1 x_t + b1) + b2) + b3), x_{t+1} = A x_t + B u_t,
-// for the individual of this lane's half.  Called by the whole wavefront (a
-// one-wave block); returns J in every lane of the half.
-template <int H>
-__device__ __forceinline__ double rollout(Wts<H> &W, const float *x0, const CtGeom &G,
+// for the individual of this lane's group.  Called by the whole wavefront (a
+// one-wave block); returns J in every lane of the group.
+template <int H, int L>
+__device__ __forceinline__ double rollout(Wts<H, L> &W, const float *x0, const CtGeom &G,
                                           uint32_t steps, uint32_t E, double cw, uint32_t lane,
-                                          CtLds<H> &S) {
-  constexpr int RPL = Ct<H>::RPL, W3N = Ct<H>::W3;
-  const uint32_t h = lane / CT_LPI, l = lane % CT_LPI;
-  const uint32_t ga = l >> 2, gc = l & 3;
+                                          CtLds<H, L> &S) {
+  using C = Ct<H, L>;
+  constexpr int RPL = C::RPL, W3N = C::W3, LPA = C::LPA, MAXO = C::MAXO;
+  const uint32_t h = lane / L, l = lane % L;
+  const uint32_t ga = l / LPA, gc = l % LPA;
   double *X = S.x[h], *H1 = S.h1[h], *H2 = S.h2[h], *U = S.u[h];
   double jx = 0.0, ju = 0.0;
   for (uint32_t e = 0; e < E; ++e) {
     __syncthreads();
-    if (l < (uint32_t)CT_MAX_OBS) {
+    if (l < (uint32_t)MAXO) {
       const double v = l < G.O ? (double)x0[e * G.O + l] : 0.0;
       X[l] = v;
       jx = fma(v, v, jx);
@@ -220,7 +235,7 @@ __device__ __forceinline__ double rollout(Wts<H> &W, const float *x0, const CtGe
       }
       double ax = 0.0, axb = 0.0;
 #pragma unroll
-      for (int k = 0; k < CT_MAX_OBS; k += 2) {
+      for (int k = 0; k < MAXO; k += 2) {
         if ((uint32_t)k < G.O) {
           const double2 xv = *reinterpret_cast<const double2 *>(X + k);
           if constexpr (RPL == 2) {
@@ -240,7 +255,7 @@ __device__ __forceinline__ double rollout(Wts<H> &W, const float *x0, const CtGe
       }
       ax += axb;
 #pragma unroll
-      for (int r = 0; r < RPL; ++r) H1[l + CT_LPI * r] = tanh_f64(y1[r] + y1b[r]);
+      for (int r = 0; r < RPL; ++r) H1[l + L * r] = tanh_f64(y1[r] + y1b[r]);
       __syncthreads();
       // layer 2: the lane's rows, four partial sums each
       double c[RPL][4];
@@ -259,10 +274,10 @@ __device__ __forceinline__ double rollout(Wts<H> &W, const float *x0, const CtGe
       }
 #pragma unroll
       for (int r = 0; r < RPL; ++r)
-        H2[l + CT_LPI * r] = tanh_f64((c[r][0] + c[r][1]) + (c[r][2] + c[r][3]));
+        H2[l + L * r] = tanh_f64((c[r][0] + c[r][1]) + (c[r][2] + c[r][3]));
       __syncthreads();
-      // layer 3: lane (ga, gc) sums its H/4 weights of W3 row ga against the
-      // matching slice of h2, then the 4 lanes of the row combine
+      // layer 3: lane (ga, gc) sums its W3N weights of W3 row ga against the
+      // matching slice of h2, then the LPA lanes of the row combine
       double pz = 0.0, pzb = 0.0;
 #pragma unroll
       for (int s = 0; s < W3N; s += 2) {
@@ -271,8 +286,8 @@ __device__ __forceinline__ double rollout(Wts<H> &W, const float *x0, const CtGe
         pzb = fma((double)W.w3[s + 1], v.y, pzb);
       }
       pz += pzb;
-      pz += __shfl_xor(pz, 1);
-      pz += __shfl_xor(pz, 2);
+#pragma unroll
+      for (int o = 1; o < LPA; o <<= 1) pz += __shfl_xor(pz, o);
       if (gc == 0 && ga < G.A) {
         const double u = tanh_f64(pz + (double)W.b3);
         U[ga] = u;
@@ -291,27 +306,27 @@ __device__ __forceinline__ double rollout(Wts<H> &W, const float *x0, const CtGe
       __syncthreads();
     }
   }
-  return (half_sum(jx) + cw * half_sum(ju)) / (double)E;
+  return (group_sum<L>(jx) + cw * group_sum<L>(ju)) / (double)E;
 }
 
 // Fill the lane's slots from a per-gene function val(j) -> float.
-template <int H, typename Val>
-__device__ __forceinline__ void fill_wts(const CtGeom &G, uint32_t h, uint32_t l, Wts<H> &W,
-                                         CtLds<H> &S, Val val) {
-  constexpr int RPL = Ct<H>::RPL;
+template <int H, int L, typename Val>
+__device__ __forceinline__ void fill_wts(const CtGeom &G, uint32_t h, uint32_t l, Wts<H, L> &W,
+                                         CtLds<H, L> &S, Val val) {
+  using C = Ct<H, L>;
 #pragma unroll
-  for (int r = 0; r < RPL; ++r) {
-    for (uint32_t k = 0; k < (uint32_t)CT_MAX_OBS; ++k)
-      S.w1[k][h][RPL * l + r] = k < G.O ? val(w1_gene(G, l, r, k)) : 0.0f;
-    W.b1[r] = val(G.b1 + row_of(l, r));
+  for (int r = 0; r < C::RPL; ++r) {
+    for (uint32_t k = 0; k < (uint32_t)C::MAXO; ++k)
+      S.w1[k][h][C::RPL * l + r] = k < G.O ? val(w1_gene<L>(G, l, r, k)) : 0.0f;
+    W.b1[r] = val(G.b1 + row_of<L>(l, r));
 #pragma unroll
-    for (int k = 0; k < H; ++k) W.w2[r][k] = val(w2_gene<H>(G, l, r, k));
-    W.b2[r] = val(G.b2 + row_of(l, r));
+    for (int k = 0; k < H; ++k) W.w2[r][k] = val(w2_gene<H, L>(G, l, r, k));
+    W.b2[r] = val(G.b2 + row_of<L>(l, r));
   }
-  const bool o3 = w3_owned(G, l);
+  const bool o3 = w3_owned<H, L>(G, l);
 #pragma unroll
-  for (int s = 0; s < Ct<H>::W3; ++s) W.w3[s] = o3 ? val(w3_gene<H>(G, l, s)) : 0.0f;
-  W.b3 = b3_owned(G, l) ? val(G.b3 + (l >> 2)) : 0.0f;
+  for (int s = 0; s < C::W3; ++s) W.w3[s] = o3 ? val(w3_gene<H, L>(G, l, s)) : 0.0f;
+  W.b3 = b3_owned<H, L>(G, l) ? val(G.b3 + l / C::LPA) : 0.0f;
 }
 
 // ---------------------------------------------------------------- trial construction
@@ -541,34 +556,36 @@ __global__ __launch_bounds__(CT_TRIAL_THREADS) void k_ctrl_trials(
 
 // Rollout and selection decision of every control trial (INIT: the first
 // evaluation of the initial population, written as its fitness).  Grid
-// (ceil(max N / 2), control runs), one wavefront per two targets; each lane
-// loads its weight slots from the pending row (float4 where aligned).
-template <int H, bool TRACE, bool INIT>
+// (ceil(max N / IPW), control runs), one wavefront per IPW = 64 / L targets
+// (the obs <= MAXO of the layout is checked at set-up); each lane loads its
+// weight slots from the pending row (float4 where aligned).
+template <int H, int L, bool TRACE, bool INIT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_ctrl_eval(
     const RunDev *__restrict__ runs, const uint32_t *__restrict__ list,
     const ProbDev *__restrict__ probs, const unsigned char *__restrict__ tab,
     float *__restrict__ fit, const float *__restrict__ pend, float *__restrict__ fu_out,
     uint32_t *__restrict__ acc_out, TraceArgs tr) {
-  constexpr int RPL = Ct<H>::RPL;
-  __shared__ CtLds<H> S;
+  using C = Ct<H, L>;
+  constexpr int RPL = C::RPL;
+  __shared__ CtLds<H, L> S;
   const RunDev run = runs[list[blockIdx.y]];
-  const uint32_t lane = threadIdx.x, h = lane / CT_LPI, l = lane % CT_LPI;
-  const uint32_t i0 = 2 * blockIdx.x;
+  const uint32_t lane = threadIdx.x, h = lane / L, l = lane % L;
+  const uint32_t i0 = C::IPW * blockIdx.x;
   if (i0 >= run.N) return;
   const uint32_t N = run.N;
-  const uint32_t i = min(i0 + h, N - 1);   // an odd N duplicates the last target
+  const uint32_t i = min(i0 + h, N - 1);   // past the end: a copy of the last target
   const bool writer = i0 + h < N;
   const ProbDev p = probs[run.prob];
   const CtGeom G = ct_geom<H>(p);
   const float *U = pend + run.pend_off + (size_t)i * run.Dp;
-  Wts<H> W;
+  Wts<H, L> W;
   // W1 rows (stride obs, not aligned in general) into LDS, biases
 #pragma unroll
   for (int r = 0; r < RPL; ++r) {
-    for (uint32_t k = 0; k < (uint32_t)CT_MAX_OBS; ++k)
-      S.w1[k][h][RPL * l + r] = k < G.O ? U[w1_gene(G, l, r, k)] : 0.0f;
-    W.b1[r] = U[G.b1 + row_of(l, r)];
-    W.b2[r] = U[G.b2 + row_of(l, r)];
+    for (uint32_t k = 0; k < (uint32_t)C::MAXO; ++k)
+      S.w1[k][h][RPL * l + r] = k < G.O ? U[w1_gene<L>(G, l, r, k)] : 0.0f;
+    W.b1[r] = U[G.b1 + row_of<L>(l, r)];
+    W.b2[r] = U[G.b2 + row_of<L>(l, r)];
   }
   // W2 rows: 16-byte aligned (pending rows are, the block starts at H (obs + 1)
   // and H is a multiple of 4)
@@ -576,20 +593,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   for (int r = 0; r < RPL; ++r) {
 #pragma unroll
     for (int k = 0; k < H; k += 4) {
-      const float4 a = *reinterpret_cast<const float4 *>(U + w2_gene<H>(G, l, r, k));
+      const float4 a = *reinterpret_cast<const float4 *>(U + w2_gene<H, L>(G, l, r, k));
       W.w2[r][k] = a.x; W.w2[r][k + 1] = a.y; W.w2[r][k + 2] = a.z; W.w2[r][k + 3] = a.w;
     }
   }
-  const bool o3 = w3_owned(G, l);
+  const bool o3 = w3_owned<H, L>(G, l);
 #pragma unroll
-  for (int t = 0; t < Ct<H>::W3; t += 4) {
+  for (int t = 0; t < C::W3; t += 4) {
     float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (o3) a = *reinterpret_cast<const float4 *>(U + w3_gene<H>(G, l, t));
+    if (o3) a = *reinterpret_cast<const float4 *>(U + w3_gene<H, L>(G, l, t));
     W.w3[t] = a.x; W.w3[t + 1] = a.y; W.w3[t + 2] = a.z; W.w3[t + 3] = a.w;
   }
-  W.b3 = b3_owned(G, l) ? U[G.b3 + (l >> 2)] : 0.0f;
+  W.b3 = b3_owned<H, L>(G, l) ? U[G.b3 + l / C::LPA] : 0.0f;
 
-  load_plant(tab, p, G, lane, S);
+  load_plant<H, L>(tab, p, G, lane, S);
   const double J = rollout(W, tab_ptr<float>(tab, p.x0_off), G, p.steps, p.nroll, (double)p.cw,
                            lane, S);
   if (writer && l == 0) {
@@ -629,8 +646,8 @@ __global__ __launch_bounds__(256) void k_ctrl_commit(const RunDev *__restrict__ 
 
 // Best record of every control run: the first individual in (fitness, index)
 // order, its float64 cost (the rollout is float64 already) and its weights.
-// Both halves of the wavefront evaluate it; the first writes.
-template <int H>
+// Every group of the wavefront evaluates it; the first writes.
+template <int H, int L>
 __global__ __launch_bounds__(64) void k_ctrl_finalize(const RunDev *__restrict__ runs,
                                                       const uint32_t *__restrict__ list,
                                                       const ProbDev *__restrict__ probs,
@@ -639,12 +656,12 @@ __global__ __launch_bounds__(64) void k_ctrl_finalize(const RunDev *__restrict__
                                                       const float *__restrict__ fit,
                                                       double *__restrict__ best_y,
                                                       float *__restrict__ best_x) {
-  __shared__ CtLds<H> S;
+  __shared__ CtLds<H, L> S;
   const uint32_t r = list[blockIdx.x];
   const RunDev run = runs[r];
   const ProbDev p = probs[run.prob];
   const CtGeom G = ct_geom<H>(p);
-  const uint32_t lane = threadIdx.x, h = lane / CT_LPI, l = lane % CT_LPI;
+  const uint32_t lane = threadIdx.x, h = lane / L, l = lane % L;
   uint64_t best = ~0ull;
   for (uint32_t i = lane; i < run.N; i += 64) best = min(best, mkkey(fit[run.fit_off + i], i));
 #pragma unroll
@@ -655,9 +672,9 @@ __global__ __launch_bounds__(64) void k_ctrl_finalize(const RunDev *__restrict__
   const uint32_t b = (uint32_t)(best & 0xFFFFFFFFu);
   const float *x = pop + run.pop_off + (size_t)b * G.D;
   for (uint32_t j = lane; j < G.D; j += 64) best_x[run.bx_off + j] = x[j];
-  Wts<H> W;
-  fill_wts<H>(G, h, l, W, S, [&](uint32_t j) { return x[j]; });
-  load_plant(tab, p, G, lane, S);
+  Wts<H, L> W;
+  fill_wts<H, L>(G, h, l, W, S, [&](uint32_t j) { return x[j]; });
+  load_plant<H, L>(tab, p, G, lane, S);
   const double J = rollout(W, tab_ptr<float>(tab, p.x0_off), G, p.steps, p.nroll, (double)p.cw,
                            lane, S);
   if (lane == 0) best_y[r] = J;
@@ -667,23 +684,35 @@ __global__ __launch_bounds__(64) void k_ctrl_finalize(const RunDev *__restrict__
 
 namespace {
 
-// Evaluation launch for the context's hidden width.
+// The three layouts: (H, L) = (64, 32), (32, 32), (32, 16).
+bool layout_ok(const CtrlArgs &c) {
+  return (c.hidden == (uint32_t)CT_H && c.lanes == 32) ||
+         (c.hidden == (uint32_t)CT_H_SMALL && (c.lanes == 32 || c.lanes == 16));
+}
+
+// Evaluation launch for the context's layout.
 template <bool TRACE, bool INIT>
 void launch_eval(const LaunchArgs &a, const CtrlArgs &c, TraceArgs tr) {
-  const dim3 egrid((c.max_n + 1) / 2, c.n);
-  if (c.hidden == (uint32_t)CT_H_SMALL)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ctrl_eval<CT_H_SMALL, TRACE, INIT>), egrid, dim3(64), 0,
+  const uint32_t ipw = 64 / c.lanes;
+  const dim3 egrid((c.max_n + ipw - 1) / ipw, c.n);
+  if (c.hidden == (uint32_t)CT_H)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ctrl_eval<CT_H, 32, TRACE, INIT>), egrid, dim3(64), 0,
                        a.stream, a.runs, c.list, a.probs, a.tab, a.fit, a.pending, c.fu, c.acc, tr);
+  else if (c.lanes == 32)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ctrl_eval<CT_H_SMALL, 32, TRACE, INIT>), egrid, dim3(64),
+                       0, a.stream, a.runs, c.list, a.probs, a.tab, a.fit, a.pending, c.fu, c.acc,
+                       tr);
   else
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ctrl_eval<CT_H, TRACE, INIT>), egrid, dim3(64), 0,
-                       a.stream, a.runs, c.list, a.probs, a.tab, a.fit, a.pending, c.fu, c.acc, tr);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ctrl_eval<CT_H_SMALL, 16, TRACE, INIT>), egrid, dim3(64),
+                       0, a.stream, a.runs, c.list, a.probs, a.tab, a.fit, a.pending, c.fu, c.acc,
+                       tr);
 }
 
 }  // namespace
 
 hipError_t launch_ctrl_init(const LaunchArgs &a, const CtrlArgs &c, double lb, double ub) {
   if (c.n == 0) return hipSuccess;
-  if (c.hidden != (uint32_t)CT_H_SMALL && c.hidden != (uint32_t)CT_H) return hipErrorInvalidValue;
+  if (!layout_ok(c)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_ctrl_init_pop, dim3(c.max_n, c.n), dim3(CT_TRIAL_THREADS_INIT), 0, a.stream,
                      a.runs, c.list, a.pop, a.pending, a.k0, a.k1, lb, ub);
   launch_eval<false, true>(a, c, TraceArgs{nullptr, nullptr, nullptr});
@@ -708,7 +737,7 @@ hipError_t launch_ctrl_set_gen(uint32_t *gen, uint32_t v, hipStream_t s) {
 hipError_t launch_ctrl_generations(const LaunchArgs &a, const CtrlArgs &c, uint32_t *gen,
                                    uint32_t n_gens, float lb, float ub, TraceArgs tr) {
   if (c.n == 0) return hipSuccess;
-  if (c.hidden != (uint32_t)CT_H_SMALL && c.hidden != (uint32_t)CT_H) return hipErrorInvalidValue;
+  if (!layout_ok(c)) return hipErrorInvalidValue;
   const dim3 tgrid(c.max_n, c.n);
   for (uint32_t g = 0; g < n_gens; ++g) {
     hipLaunchKernelGGL(k_ctrl_rank, dim3(c.n), dim3(CT_MAX_N), 0, a.stream, a.runs, c.list, a.fit,
@@ -736,14 +765,16 @@ hipError_t launch_ctrl_generations(const LaunchArgs &a, const CtrlArgs &c, uint3
 hipError_t launch_ctrl_finalize(const LaunchArgs &a, const CtrlArgs &c, double *best_y,
                                 float *best_x) {
   if (c.n == 0) return hipSuccess;
-  if (c.hidden == (uint32_t)CT_H_SMALL)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ctrl_finalize<CT_H_SMALL>), dim3(c.n), dim3(64), 0,
+  if (!layout_ok(c)) return hipErrorInvalidValue;
+  if (c.hidden == (uint32_t)CT_H)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ctrl_finalize<CT_H, 32>), dim3(c.n), dim3(64), 0,
                        a.stream, a.runs, c.list, a.probs, a.tab, a.pop, a.fit, best_y, best_x);
-  else if (c.hidden == (uint32_t)CT_H)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ctrl_finalize<CT_H>), dim3(c.n), dim3(64), 0, a.stream,
-                       a.runs, c.list, a.probs, a.tab, a.pop, a.fit, best_y, best_x);
+  else if (c.lanes == 32)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ctrl_finalize<CT_H_SMALL, 32>), dim3(c.n), dim3(64), 0,
+                       a.stream, a.runs, c.list, a.probs, a.tab, a.pop, a.fit, best_y, best_x);
   else
-    return hipErrorInvalidValue;
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ctrl_finalize<CT_H_SMALL, 16>), dim3(c.n), dim3(64), 0,
+                       a.stream, a.runs, c.list, a.probs, a.tab, a.pop, a.fit, best_y, best_x);
   return hipGetLastError();
 }
 
