@@ -294,6 +294,7 @@ def bench_c3_repetitions(args, reps=4):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{reps} independent repetitions of full MetaDE at D=20, run "
                                "concurrently on one GPU (one context and stream each)",
+                   "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4")),
                    "runs": P * reps, "N": 100, "D": 20, "inner_gens": G, "outer_gens": gens,
                    "evals_per_step": evals, "best_y": [b[0] for b in best]},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_SLOTS / 1e12,
@@ -342,6 +343,13 @@ def main():
         print(json.dumps({"error": "this build measures one GPU: the executor batch is not "
                                    "sharded across GPUs (run with --gpus 1)"}))
         sys.exit(2)
+    if args.workload == "c3x4":
+        # The repetitions overlap only if each stream gets a hardware queue of its
+        # own: with HIP's default of 4 queues per process, two of the four streams
+        # share one (the default stream holds another) and their launches run one
+        # after the other.  Set before the HIP runtime starts.
+        if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < 8:
+            os.environ["GPU_MAX_HW_QUEUES"] = "8"
 
     import torch
     import workloads as W
