@@ -108,6 +108,12 @@ def ctrl_slots_per_trial(prob, bl, br, dn, cs, CR):
     return rng + m * (m + 5) + de + macs
 
 
+def ctrl_rollout_macs(prob):
+    """Multiply-adds of one policy's rollouts: layers and plant, every step."""
+    O, A, H1, H2 = prob.A.shape[0], prob.B.shape[1], prob.hidden[0], prob.hidden[1]
+    return prob.steps * prob.x0.shape[0] * (H1 * O + H2 * H1 + A * H2 + O * O + O * A)
+
+
 def launch_slots(wl, theta, G):
     F, CR, bl, br, dn, cs = decode(theta, wl.n_cs)
     tot = 0.0
@@ -165,7 +171,7 @@ def bench_batch(args):
     from paper_2502_10470_amd import Batch, metade as M
 
     wl = {"c4": W.workload_c4, "c2": W.workload_c2, "c5": W.workload_c5,
-          "t7": W.workload_t7}[args.workload]()
+          "t7": W.workload_t7, "c5e16": W.workload_c5e16}[args.workload]()
     prec = M.BF16_REFINE if args.precision == "bf16" else M.FP32
     b = Batch(wl, precision=prec)
     evals = wl.evals_per_pass()
@@ -191,7 +197,7 @@ def bench_batch(args):
     dt = t1 - t0
     avg_ms = k_ms / max(k_launches, 1)
     F, CR, bl, br, dn, cs = decode(wl.theta, wl.n_cs)
-    ctrl = args.workload in ("c5", "t7")
+    ctrl = args.workload in ("c5", "t7", "c5e16")
     if ctrl:
         slots = sum(int(wl.N[r]) * wl.G * ctrl_slots_per_trial(wl.problems[int(wl.problem[r])],
                     bl[r], br[r], dn[r], cs[r], CR[r]) for r in range(wl.n_runs))
@@ -203,9 +209,12 @@ def bench_batch(args):
                                      for r in range(wl.n_runs))
     refine_rate = (r_after - r_before) / max(t_after - t_before, 1)
     at = {"c4": "D=100", "c2": "D in {10,20}", "c5": "D=5702 (control)",
-          "t7": "D in {1539,1410,1506} (control, Table VII policies)"}[args.workload]
+          "t7": "D in {1539,1410,1506} (control, Table VII policies)",
+          "c5e16": "D=5702 (control, 16 rollouts per policy)"}[args.workload]
     ck = "k_ctrl_eval (timed with k_ctrl_rank, k_ctrl_trials, k_ctrl_commit)"
-    kern = {"c4": "k_generations_mfma", "c2": "k_generations", "c5": ck, "t7": ck}[args.workload]
+    kern = {"c4": "k_generations_mfma", "c2": "k_generations", "c5": ck, "t7": ck,
+            "c5e16": "k_ctrl_eval_mx (timed with k_ctrl_rank, k_ctrl_trials, k_ctrl_commit)"
+            }[args.workload]
     line = {
         "metric": f"inner-DE individual-evals/sec (runs x N x gens / s) at {at}",
         "value": evals * args.steps / dt, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
@@ -235,6 +244,18 @@ def bench_batch(args):
                             "kernel": kern, "avg_launch_ms": avg_ms, "launches": k_launches,
                             "alu_frac": slots / (avg_ms * 1e-3) / VALU_PEAK_SLOTS,
                             "occupied_cu_frac": min(wl.n_runs, 256) / 256.0}
+    if args.workload == "c5e16":
+        # 16 rollouts per policy: the layers and the plant are float64 matrix-core
+        # products; algorithmic flops are two per multiply-add of the rollouts
+        # (padding of the tiles not counted), against the float64 matrix peak
+        macs = sum(int(wl.N[r]) * wl.G * ctrl_rollout_macs(wl.problems[int(wl.problem[r])])
+                   for r in range(wl.n_runs))
+        ach = 2.0 * macs / (avg_ms * 1e-3)
+        line["roofline"] = {"bound": "mfma", "achieved": ach / 1e12, "peak": MFMA_F64_PEAK / 1e12,
+                            "unit": "TFLOP/s", "frac": ach / MFMA_F64_PEAK, "traffic": None,
+                            "kernel": kern, "avg_launch_ms": avg_ms, "launches": k_launches,
+                            "alu_frac": slots / (avg_ms * 1e-3) / VALU_PEAK_SLOTS,
+                            "occupied_cu_frac": 1.0}
     print(json.dumps(line), flush=True)
 
 
@@ -311,14 +332,15 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c3",
-                    choices=["c3", "c3x4", "paper", "c4", "c2", "c5", "t7"],
+                    choices=["c3", "c3x4", "paper", "c4", "c2", "c5", "t7", "c5e16"],
                     help="c3: full MetaDE at D=20 (default); c3x4: four independent "
                          "repetitions of it, concurrently; paper: MetaDE at the paper's scale "
                          "(evolver 100, three crossover schemes); c4: 128 runs x N=256 at D=100, "
                          "500 generations; c2: uneven batch of 256 runs, 200 generations; "
                          "c5: control workload, 16 runs x N=256 tanh policies (D=5702), "
                          "200-step rollouts, 100 generations; t7: the policy MLPs of "
-                         "Table VII (hidden 32 x 32), 96 runs x N=100, 50 generations")
+                         "Table VII (hidden 32 x 32), 96 runs x N=100, 50 generations; "
+                         "c5e16: c5 with 16 rollouts per policy, 10 generations")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"],
                     help="fitness contraction: plain (float64-accumulated) or bf16 matrix cores "
                          "with plain re-evaluation of near ties")

@@ -43,6 +43,7 @@ struct metade_ctx {
   size_t pop_floats = 0, fit_n = 0, bx_n = 0, pend_floats = 0;
   uint32_t lds_bytes = 0, init_lds_bytes = 0, mfma_lds_bytes = 0;
   uint32_t n_lane = 0, n_mfma = 0, n_ctrl = 0, ctrl_max_n = 0, ctrl_hidden = 0, ctrl_lanes = 32;
+  uint32_t ctrl_mx = 0;
   uint32_t *lane_list_d = nullptr, *mfma_list_d = nullptr, *ctrl_list_d = nullptr;
   uint32_t *order_d = nullptr, *cacc_d = nullptr;  // control runs: top-p lists, decisions
   float *cfu_d = nullptr;                          // control runs: trial fitness
@@ -91,6 +92,7 @@ struct Plan {
   uint32_t init_lds_bytes = 0, mfma_lds_bytes = 0;
   std::vector<uint32_t> lane_list, mfma_list, ctrl_list;
   uint32_t ctrl_max_n = 0, ctrl_hidden = 0, ctrl_max_obs = 0;
+  bool ctrl_roll16 = true;   // every control problem has a multiple of 16 rollouts
   size_t pop_floats = 0, fit_n = 0, bx_n = 0, pend_floats = 0;
   uint32_t lds_bytes = 0;
 };
@@ -154,6 +156,7 @@ metade_status plan_config(const metade_config *cfg, Plan &pl, std::string &msg) 
       }
       pl.ctrl_hidden = H;
       pl.ctrl_max_obs = std::max(pl.ctrl_max_obs, q.obs);
+      pl.ctrl_roll16 = pl.ctrl_roll16 && q.n_rollouts % 16 == 0;
       if (q.obs < 1 || q.obs > (uint32_t)mde::CT_MAX_OBS || q.act < 1 || q.act > (uint32_t)mde::CT_MAX_ACT) {
         msg = pk + "control workload needs 1 <= obs <= 20 and 1 <= act <= 8"; return METADE_EINVAL;
       }
@@ -305,8 +308,8 @@ LaunchArgs largs(metade_ctx *c) {
 }
 
 mde::CtrlArgs cargs(metade_ctx *c) {
-  return mde::CtrlArgs{c->ctrl_list_d, c->n_ctrl, c->ctrl_max_n, c->ctrl_hidden,
-                       c->ctrl_lanes,  c->order_d, c->cfu_d,      c->cacc_d};
+  return mde::CtrlArgs{c->ctrl_list_d, c->n_ctrl,  c->ctrl_max_n, c->ctrl_hidden, c->ctrl_lanes,
+                       c->ctrl_mx,     c->order_d, c->cfu_d,      c->cacc_d};
 }
 
 // Capture n generations of the control runs (rank, trials, rollouts, commit,
@@ -467,6 +470,8 @@ metade_status metade_init(const metade_config *cfg, metade_ctx **out) {
   // width-32 policies with few observations: 16 lanes each, four per wavefront
   c->ctrl_lanes = (pl.ctrl_hidden == (uint32_t)mde::CT_H_SMALL &&
                    pl.ctrl_max_obs <= (uint32_t)mde::CT_OBS_L16) ? 16u : 32u;
+  // 16 rollouts per policy or a multiple: one policy per wavefront on the matrix cores
+  c->ctrl_mx = (pl.ctrl_hidden != 0 && pl.ctrl_roll16) ? 1u : 0u;
   auto bail = [&](metade_status st) {
     g_init_error = c->err;
     metade_destroy(c);

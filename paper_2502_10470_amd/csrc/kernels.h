@@ -42,6 +42,7 @@ struct CtrlArgs {
   uint32_t n, max_n;      // number of control runs, their largest N
   uint32_t hidden;        // hidden width of their policies (CT_H_SMALL or CT_H)
   uint32_t lanes;         // lanes per policy in the evaluation (32, or 16 for CT_H_SMALL)
+  uint32_t mx;            // 1: every problem has a multiple of 16 rollouts, matrix-core evaluation
   uint32_t *order;        // [sum N] top-p lists at the runs' fitness offsets
   float *fu;              // [sum N] trial fitness
   uint32_t *acc;          // [sum N] selection decisions

@@ -626,6 +626,190 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   }
 }
 
+// ---------------------------------------------------------------- matrix-core evaluation
+//
+// With 16 rollouts per policy (or a multiple of 16, taken 16 at a time) every
+// layer of a step is a product [rows x k] x [k x 16 rollouts], so one
+// wavefront evaluates one policy on v_mfma_f64_16x16x4f64.  That
+// instruction takes A[i][k] from lane i + 16 k and B[k][j] from lane j + 16 k
+// and leaves result element v of lane l at row l/16 + 4 v, column l % 16.  A
+// result tile therefore already holds in every lane what the next product
+// needs as its B operand: k-step s = 4 t + v (rows 4 s + l/16) is element v
+// of tile t.  State, activations and actions stay in registers for the whole
+// rollout (no LDS, no shuffles, no barriers); the weights are the A operands,
+// kept as the float32 values of the population and widened at use.
+
+typedef double ct_d4 __attribute__((ext_vector_type(4)));
+
+constexpr int CT_MX_S1 = (CT_MAX_OBS + 3) / 4;  // k-steps over the observations
+constexpr int CT_MX_SA = (CT_MAX_ACT + 3) / 4;  // k-steps over the actions
+
+__device__ __forceinline__ ct_d4 mx(float a, double b, ct_d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64((double)a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ ct_d4 tanh4(ct_d4 x) {
+  ct_d4 y;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) y[v] = tanh_f64(x[v]);
+  return y;
+}
+
+// Mean cost J of the policy with weights U (D floats) over the problem's
+// rollouts, on the matrix cores; called by a whole wavefront, returns J in
+// every lane.  The problem has obs <= 20, act <= 8 and a multiple of 16
+// rollouts (checked at set-up).
+template <int H>
+__device__ __forceinline__ double rollout_mx(const float *__restrict__ U, const ProbDev &p,
+                                             const unsigned char *__restrict__ tab,
+                                             uint32_t lane) {
+  constexpr int T = H / 16;  // row tiles of a hidden layer
+  constexpr int S = H / 4;   // k-steps over a hidden layer
+  const uint32_t c = lane % 16, g = lane / 16;
+  const CtGeom G = ct_geom<H>(p);
+  const float *Ap = tab_ptr<float>(tab, p.A_off);
+  const float *Bp = tab_ptr<float>(tab, p.B_off);
+  const float *x0 = tab_ptr<float>(tab, p.x0_off);
+  // A operands: W1[16 t + c][4 s + g], W2[16 t + c][4 s + g], W3[c][4 s + g],
+  // plant A[16 t + c][4 s + g] and B[16 t + c][4 s + g] (zero outside);
+  // biases at the lane's result rows 16 t + g + 4 v
+  float w1[T][CT_MX_S1], w2[T][S], w3[S], pa[2][CT_MX_S1], pb[2][CT_MX_SA];
+  float b1[T][4], b2[T][4], b3[4];
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    const uint32_t row = 16 * t + c;
+#pragma unroll
+    for (int s = 0; s < CT_MX_S1; ++s) {
+      const uint32_t col = 4 * s + g;
+      w1[t][s] = col < G.O ? U[row * G.O + col] : 0.0f;
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) w2[t][s] = U[G.w2 + row * H + 4 * s + g];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      b1[t][v] = U[G.b1 + 16 * t + g + 4 * v];
+      b2[t][v] = U[G.b2 + 16 * t + g + 4 * v];
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < S; ++s) w3[s] = c < G.A ? U[G.w3 + c * H + 4 * s + g] : 0.0f;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) b3[v] = g + 4 * v < G.A ? U[G.b3 + g + 4 * v] : 0.0f;
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const uint32_t row = 16 * t + c;
+#pragma unroll
+    for (int s = 0; s < CT_MX_S1; ++s) {
+      const uint32_t col = 4 * s + g;
+      pa[t][s] = (row < G.O && col < G.O) ? Ap[row * G.O + col] : 0.0f;
+    }
+#pragma unroll
+    for (int s = 0; s < CT_MX_SA; ++s) {
+      const uint32_t col = 4 * s + g;
+      pb[t][s] = (row < G.O && col < G.A) ? Bp[row * G.A + col] : 0.0f;
+    }
+  }
+
+  const uint32_t E = p.nroll, steps = p.steps;
+  double jx = 0.0, ju = 0.0;
+  for (uint32_t e0 = 0; e0 < E; e0 += 16) {
+    // state of rollout e0 + c, observations 16 t + g + 4 v (zero past obs)
+    ct_d4 X[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const uint32_t o = 16 * t + g + 4 * v;
+        const double xv = o < G.O ? (double)x0[(e0 + c) * G.O + o] : 0.0;
+        X[t][v] = xv;
+        jx = fma(xv, xv, jx);
+      }
+    for (uint32_t st = 0; st < steps; ++st) {
+      // layer 1: T independent accumulator chains over the observation steps
+      ct_d4 H1[T];
+#pragma unroll
+      for (int t = 0; t < T; ++t)
+        H1[t] = ct_d4{(double)b1[t][0], (double)b1[t][1], (double)b1[t][2], (double)b1[t][3]};
+#pragma unroll
+      for (int s = 0; s < CT_MX_S1; ++s)
+#pragma unroll
+        for (int t = 0; t < T; ++t) H1[t] = mx(w1[t][s], X[s / 4][s % 4], H1[t]);
+#pragma unroll
+      for (int t = 0; t < T; ++t) H1[t] = tanh4(H1[t]);
+      // layer 2
+      ct_d4 H2[T];
+#pragma unroll
+      for (int t = 0; t < T; ++t)
+        H2[t] = ct_d4{(double)b2[t][0], (double)b2[t][1], (double)b2[t][2], (double)b2[t][3]};
+#pragma unroll
+      for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int t = 0; t < T; ++t) H2[t] = mx(w2[t][s], H1[s / 4][s % 4], H2[t]);
+#pragma unroll
+      for (int t = 0; t < T; ++t) H2[t] = tanh4(H2[t]);
+      // layer 3 (rows past act: zero weights and bias, tanh(0) = 0)
+      ct_d4 u = ct_d4{(double)b3[0], (double)b3[1], (double)b3[2], (double)b3[3]};
+#pragma unroll
+      for (int s = 0; s < S; ++s) u = mx(w3[s], H2[s / 4][s % 4], u);
+      u = tanh4(u);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) ju = fma(u[v], u[v], ju);
+      // plant update x <- A x + B u (rows past obs stay zero)
+      ct_d4 Xn[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        Xn[t] = ct_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < CT_MX_S1; ++s) Xn[t] = mx(pa[t][s], X[s / 4][s % 4], Xn[t]);
+#pragma unroll
+        for (int s = 0; s < CT_MX_SA; ++s) Xn[t] = mx(pb[t][s], u[s], Xn[t]);
+      }
+#pragma unroll
+      for (int t = 0; t < 2; ++t) X[t] = Xn[t];
+      if (st + 1 < steps) {
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) jx = fma(X[t][v], X[t][v], jx);
+      }
+    }
+  }
+  double jsum = jx + (double)p.cw * ju;
+#pragma unroll
+  for (int s2 = 32; s2 > 0; s2 >>= 1) jsum += __shfl_xor(jsum, s2);
+  return jsum / (double)E;
+}
+
+// Rollout and selection decision of every control trial, one wavefront per
+// target (INIT: the first evaluation).  Grid (max N, control runs).
+template <int H, bool TRACE, bool INIT>
+__global__ __launch_bounds__(64) void k_ctrl_eval_mx(
+    const RunDev *__restrict__ runs, const uint32_t *__restrict__ list,
+    const ProbDev *__restrict__ probs, const unsigned char *__restrict__ tab,
+    float *__restrict__ fit, const float *__restrict__ pend, float *__restrict__ fu_out,
+    uint32_t *__restrict__ acc_out, TraceArgs tr) {
+  const RunDev run = runs[list[blockIdx.y]];
+  const uint32_t i = blockIdx.x;
+  if (i >= run.N) return;
+  const uint32_t lane = threadIdx.x;
+  const ProbDev p = probs[run.prob];
+  const double J = rollout_mx<H>(pend + run.pend_off + (size_t)i * run.Dp, p, tab, lane);
+  if (lane == 0) {
+    const float f = (float)J;
+    if (INIT) {
+      fit[run.fit_off + i] = f;
+    } else {
+      const float fx = fit[run.fit_off + i];
+      const bool a = accept_trial(f, fx);
+      fu_out[run.fit_off + i] = f;
+      acc_out[run.fit_off + i] = a ? 1u : 0u;
+      if (TRACE) {
+        tr.fu[run.fit_off + i] = f;
+        tr.desc[(size_t)(run.fit_off + i) * 16 + 15] = a ? 1 : 0;
+      }
+    }
+  }
+}
+
 // Greedy selection commit: accepted pending rows replace their targets.
 // Grid (max N, control runs).
 __global__ __launch_bounds__(256) void k_ctrl_commit(const RunDev *__restrict__ runs,
@@ -680,6 +864,35 @@ __global__ __launch_bounds__(64) void k_ctrl_finalize(const RunDev *__restrict__
   if (lane == 0) best_y[r] = J;
 }
 
+// Best record with the matrix-core rollout (runs with a multiple of 16
+// rollouts): as k_ctrl_finalize, one wavefront per run.
+template <int H>
+__global__ __launch_bounds__(64) void k_ctrl_finalize_mx(const RunDev *__restrict__ runs,
+                                                         const uint32_t *__restrict__ list,
+                                                         const ProbDev *__restrict__ probs,
+                                                         const unsigned char *__restrict__ tab,
+                                                         const float *__restrict__ pop,
+                                                         const float *__restrict__ fit,
+                                                         double *__restrict__ best_y,
+                                                         float *__restrict__ best_x) {
+  const uint32_t r = list[blockIdx.x];
+  const RunDev run = runs[r];
+  const ProbDev p = probs[run.prob];
+  const uint32_t lane = threadIdx.x;
+  uint64_t best = ~0ull;
+  for (uint32_t i = lane; i < run.N; i += 64) best = min(best, mkkey(fit[run.fit_off + i], i));
+#pragma unroll
+  for (int s = 32; s > 0; s >>= 1) {
+    const uint64_t o = __shfl_xor(best, s);
+    best = min(best, o);
+  }
+  const uint32_t b = (uint32_t)(best & 0xFFFFFFFFu);
+  const float *x = pop + run.pop_off + (size_t)b * run.D;
+  for (uint32_t j = lane; j < run.D; j += 64) best_x[run.bx_off + j] = x[j];
+  const double J = rollout_mx<H>(x, p, tab, lane);
+  if (lane == 0) best_y[r] = J;
+}
+
 // ---------------------------------------------------------------- launchers
 
 namespace {
@@ -693,6 +906,18 @@ bool layout_ok(const CtrlArgs &c) {
 // Evaluation launch for the context's layout.
 template <bool TRACE, bool INIT>
 void launch_eval(const LaunchArgs &a, const CtrlArgs &c, TraceArgs tr) {
+  if (c.mx) {
+    const dim3 mgrid(c.max_n, c.n);
+    if (c.hidden == (uint32_t)CT_H)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ctrl_eval_mx<CT_H, TRACE, INIT>), mgrid, dim3(64), 0,
+                         a.stream, a.runs, c.list, a.probs, a.tab, a.fit, a.pending, c.fu, c.acc,
+                         tr);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ctrl_eval_mx<CT_H_SMALL, TRACE, INIT>), mgrid, dim3(64),
+                         0, a.stream, a.runs, c.list, a.probs, a.tab, a.fit, a.pending, c.fu,
+                         c.acc, tr);
+    return;
+  }
   const uint32_t ipw = 64 / c.lanes;
   const dim3 egrid((c.max_n + ipw - 1) / ipw, c.n);
   if (c.hidden == (uint32_t)CT_H)
@@ -766,6 +991,15 @@ hipError_t launch_ctrl_finalize(const LaunchArgs &a, const CtrlArgs &c, double *
                                 float *best_x) {
   if (c.n == 0) return hipSuccess;
   if (!layout_ok(c)) return hipErrorInvalidValue;
+  if (c.mx) {
+    if (c.hidden == (uint32_t)CT_H)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ctrl_finalize_mx<CT_H>), dim3(c.n), dim3(64), 0,
+                         a.stream, a.runs, c.list, a.probs, a.tab, a.pop, a.fit, best_y, best_x);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ctrl_finalize_mx<CT_H_SMALL>), dim3(c.n), dim3(64), 0,
+                         a.stream, a.runs, c.list, a.probs, a.tab, a.pop, a.fit, best_y, best_x);
+    return hipGetLastError();
+  }
   if (c.hidden == (uint32_t)CT_H)
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_ctrl_finalize<CT_H, 32>), dim3(c.n), dim3(64), 0,
                        a.stream, a.runs, c.list, a.probs, a.tab, a.pop, a.fit, best_y, best_x);

@@ -200,3 +200,47 @@ def test_control_hidden32_best_record_float64():
         ref = float(evaluate(x, wl.problems[r]))
         assert abs(y[r] - ref) <= 1e-9 * abs(ref), (r, y[r], ref)
         assert abs(float(f[i]) - ref) <= FIT_RTOL * abs(ref)
+
+
+@pytest.mark.parametrize("hidden,shapes,steps,n_roll,n_cs", [
+    ((64, 64), [(17, 6)] * 4, 30, 16, 2),                 # C5's policy, 16 rollouts
+    ((64, 64), [(5, 3)] * 4, 12, 32, 3),                  # odd D, two groups of 16 rollouts
+    ((32, 32), [(11, 3), (8, 2), (11, 2), (20, 8)], 25, 16, 2),  # Table VII, largest obs / act
+    ((32, 32), [(1, 1)] * 3, 10, 16, 3),                  # smallest
+])
+def test_control_16_rollouts_matrix_cores_follow_oracle(hidden, shapes, steps, n_roll, n_cs):
+    """Policies scored over a multiple of 16 rollouts go to the matrix-core
+    evaluation (one policy per wavefront); trajectories follow the oracle."""
+    Ns = [10, 17, 33, 24][:len(shapes)]
+    th = _strategy_grid(len(Ns), n_cs, seed=steps * 7 + n_roll)
+    wl = W.control_batch(31 + steps, Ns, shapes=shapes, steps=steps, n_rollouts=n_roll,
+                         theta=th, n_cs=n_cs, hidden=hidden)
+    b = _batch(wl)
+    out = trajectory_parity(b, wl, G=3)
+    print(f"E={n_roll} hidden {hidden[0]}: compared {out['compared']} diverged {out['diverged']} "
+          f"(undetermined {out['ill']}) max fitness rel err {out['max_fit_rel']:.3g}")
+    assert out["compared"] >= 2 * len(Ns)
+
+
+def test_control_16_rollouts_best_record_and_resume():
+    wl = W.control_batch(6, [20, 12], steps=15, n_rollouts=16, G=3)
+    b1 = _batch(wl)
+    b1.inner_step(2)
+    blob = b1.get_state()
+    b1.inner_step(2)
+    p1, f1 = b1.host_state()
+    y = b1.get_best()
+    bx = b1.best_x.cpu().numpy()
+    for r in range(wl.n_runs):
+        f = b1.run_fit(f1, r)
+        i = int(np.lexsort((np.arange(len(f)), pde.order_key(f)))[0])
+        x = b1.run_pop(p1, r)[i]
+        assert np.array_equal(b1.run_bx(bx, r), x)
+        ref = float(evaluate(x, wl.problems[r]))
+        assert abs(y[r] - ref) <= 1e-9 * abs(ref), (r, y[r], ref)
+        assert abs(float(f[i]) - ref) <= FIT_RTOL * abs(ref)
+    b2 = _batch(wl)
+    b2.set_state(blob)
+    b2.inner_step(2)
+    p2, f2 = b2.host_state()
+    assert np.array_equal(p1, p2) and np.array_equal(f1, f2)

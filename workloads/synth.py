@@ -232,6 +232,15 @@ def workload_c5(runs: int = 16, N: int = 256, G: int = 100, n_rollouts: int = 1)
                     stream=np.arange(runs, dtype=np.uint32), problems=problems, G=G, theta=theta)
 
 
+def workload_c5e16(G: int = 10) -> Workload:
+    """The control workload with 16 rollouts per policy (16 initial states per
+    plant, J averaged): every layer of a step becomes a product with 16 columns.
+    16 runs x N=256 policies 17->64->64->6, 10 generations."""
+    wl = workload_c5(G=G, n_rollouts=16)
+    wl.name = "c5e16_control_mlp_16_rollouts"
+    return wl
+
+
 def workload_t7(runs_per_task: int = 32, N: int = 100, G: int = 50) -> Workload:
     """The policy MLPs of Table VII (hopper 11->32->32->3, 1539 weights; swimmer
     8->32->32->2, 1410; reacher 11->32->32->2, 1506), each scored by a 200-step
@@ -291,5 +300,6 @@ def control_batch(seed: int, Ns, obs: int = LQR_OBS, act: int = LQR_ACT, steps: 
 
 def workload_by_name(name: str) -> Workload:
     table = {"c1": workload_c1, "c2": workload_c2, "c3": workload_c3, "c4": workload_c4,
-             "c5": workload_c5, "paper": workload_paper, "t7": workload_t7}
+             "c5": workload_c5, "paper": workload_paper, "t7": workload_t7,
+             "c5e16": workload_c5e16}
     return table[name]()
