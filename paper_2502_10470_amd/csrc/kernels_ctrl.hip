@@ -637,7 +637,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
 // needs as its B operand: k-step s = 4 t + v (rows 4 s + l/16) is element v
 // of tile t.  State, activations and actions stay in registers for the whole
 // rollout (no LDS, no shuffles, no barriers); the weights are the A operands,
-// kept as the float32 values of the population and widened at use.
+// float32 values of the population widened at use: W1, W3 and the plant in
+// registers, W2 and the hidden biases read from the (L2-resident) row at every
+// step, which leaves room for two wavefronts per SIMD.
 
 typedef double ct_d4 __attribute__((ext_vector_type(4)));
 
@@ -658,7 +660,28 @@ __device__ __forceinline__ ct_d4 tanh4(ct_d4 x) {
 // rollouts, on the matrix cores; called by a whole wavefront, returns J in
 // every lane.  The problem has obs <= 20, act <= 8 and a multiple of 16
 // rollouts (checked at set-up).
+// Physical order of the hidden units: result row p of a hidden layer holds
+// unit (H/4)(p mod 4) + p/4, so that a lane's A operands of the next layer
+// (k-steps s = 0 .. H/4-1 of lane group g: units (H/4) g + s) and its biases
+// (rows 16 t + g + 4 v: units 16 g + 4 t + v for H = 64) are contiguous.
 template <int H>
+__device__ __forceinline__ uint32_t unit_of(uint32_t p) {
+  return (H / 4) * (p % 4) + p / 4;
+}
+
+template <bool VEC>
+__device__ __forceinline__ float4 ld4w(const float *__restrict__ q) {
+  if (VEC) return *reinterpret_cast<const float4 *>(q);
+  return make_float4(q[0], q[1], q[2], q[3]);
+}
+
+// Mean cost J of the policy with weights U (D floats; 16-byte aligned rows
+// when VEC) over the problem's rollouts, on the matrix cores; called by a
+// whole wavefront, returns J in every lane.  The problem has obs <= 20,
+// act <= 8 and a multiple of 16 rollouts (checked at set-up).  W2 and the
+// hidden biases are read from the row at every step (L2-resident), one block
+// of four k-steps ahead; the rest of the weights stay in registers.
+template <int H, bool VEC>
 __device__ __forceinline__ double rollout_mx(const float *__restrict__ U, const ProbDev &p,
                                              const unsigned char *__restrict__ tab,
                                              uint32_t lane) {
@@ -669,29 +692,19 @@ __device__ __forceinline__ double rollout_mx(const float *__restrict__ U, const 
   const float *Ap = tab_ptr<float>(tab, p.A_off);
   const float *Bp = tab_ptr<float>(tab, p.B_off);
   const float *x0 = tab_ptr<float>(tab, p.x0_off);
-  // A operands: W1[16 t + c][4 s + g], W2[16 t + c][4 s + g], W3[c][4 s + g],
-  // plant A[16 t + c][4 s + g] and B[16 t + c][4 s + g] (zero outside);
-  // biases at the lane's result rows 16 t + g + 4 v
-  float w1[T][CT_MX_S1], w2[T][S], w3[S], pa[2][CT_MX_S1], pb[2][CT_MX_SA];
-  float b1[T][4], b2[T][4], b3[4];
+  // registers: W1[unit(16 t + c)][4 s + g], W3[c][unit(4 s + g)], plant A and B
+  float w1[T][CT_MX_S1], w3[S], pa[2][CT_MX_S1], pb[2][CT_MX_SA], b3[4];
 #pragma unroll
   for (int t = 0; t < T; ++t) {
-    const uint32_t row = 16 * t + c;
+    const uint32_t row = unit_of<H>(16 * t + c);
 #pragma unroll
     for (int s = 0; s < CT_MX_S1; ++s) {
       const uint32_t col = 4 * s + g;
       w1[t][s] = col < G.O ? U[row * G.O + col] : 0.0f;
     }
-#pragma unroll
-    for (int s = 0; s < S; ++s) w2[t][s] = U[G.w2 + row * H + 4 * s + g];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      b1[t][v] = U[G.b1 + 16 * t + g + 4 * v];
-      b2[t][v] = U[G.b2 + 16 * t + g + 4 * v];
-    }
   }
 #pragma unroll
-  for (int s = 0; s < S; ++s) w3[s] = c < G.A ? U[G.w3 + c * H + 4 * s + g] : 0.0f;
+  for (int s = 0; s < S; ++s) w3[s] = c < G.A ? U[G.w3 + c * H + (H / 4) * g + s] : 0.0f;
 #pragma unroll
   for (int v = 0; v < 4; ++v) b3[v] = g + 4 * v < G.A ? U[G.b3 + g + 4 * v] : 0.0f;
 #pragma unroll
@@ -708,11 +721,18 @@ __device__ __forceinline__ double rollout_mx(const float *__restrict__ U, const 
       pb[t][s] = (row < G.O && col < G.A) ? Bp[row * G.A + col] : 0.0f;
     }
   }
+  // streamed: row t of the lane's W2 operands (units (H/4) g .. +H/4-1 of row
+  // unit(16 t + c)); biases of the lane's result rows, tile t element v = unit
+  // (H/4) g + 4 t + v: four consecutive floats per tile
+  const float *w2r[T];
+#pragma unroll
+  for (int t = 0; t < T; ++t) w2r[t] = U + G.w2 + unit_of<H>(16 * t + c) * H + (H / 4) * g;
+  const float *b1r = U + G.b1 + (H / 4) * g;
+  const float *b2r = U + G.b2 + (H / 4) * g;
 
   const uint32_t E = p.nroll, steps = p.steps;
   double jx = 0.0, ju = 0.0;
   for (uint32_t e0 = 0; e0 < E; e0 += 16) {
-    // state of rollout e0 + c, observations 16 t + g + 4 v (zero past obs)
     ct_d4 X[2];
 #pragma unroll
     for (int t = 0; t < 2; ++t)
@@ -724,36 +744,71 @@ __device__ __forceinline__ double rollout_mx(const float *__restrict__ U, const 
         jx = fma(xv, xv, jx);
       }
     for (uint32_t st = 0; st < steps; ++st) {
-      // layer 1: T independent accumulator chains over the observation steps
-      ct_d4 H1[T];
+      // keep the register weights as float32 across steps (an empty asm that
+      // "modifies" them stops the widening from being hoisted out of the loop,
+      // which would double their registers)
 #pragma unroll
       for (int t = 0; t < T; ++t)
-        H1[t] = ct_d4{(double)b1[t][0], (double)b1[t][1], (double)b1[t][2], (double)b1[t][3]};
+#pragma unroll
+        for (int s = 0; s < CT_MX_S1; ++s) asm volatile("" : "+v"(w1[t][s]));
+#pragma unroll
+      for (int s = 0; s < S; ++s) asm volatile("" : "+v"(w3[s]));
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+#pragma unroll
+        for (int s = 0; s < CT_MX_S1; ++s) asm volatile("" : "+v"(pa[t][s]));
+#pragma unroll
+        for (int s = 0; s < CT_MX_SA; ++s) asm volatile("" : "+v"(pb[t][s]));
+      }
+      // first W2 block of this step and the biases, in flight during layer 1
+      float4 wb[T];
+#pragma unroll
+      for (int t = 0; t < T; ++t) wb[t] = ld4w<VEC>(w2r[t]);
+      ct_d4 H1[T];
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        const float4 bb = ld4w<VEC>(b1r + 4 * t);
+        H1[t] = ct_d4{(double)bb.x, (double)bb.y, (double)bb.z, (double)bb.w};
+      }
 #pragma unroll
       for (int s = 0; s < CT_MX_S1; ++s)
 #pragma unroll
         for (int t = 0; t < T; ++t) H1[t] = mx(w1[t][s], X[s / 4][s % 4], H1[t]);
 #pragma unroll
       for (int t = 0; t < T; ++t) H1[t] = tanh4(H1[t]);
-      // layer 2
+      // layer 2: blocks j of four k-steps, the next block's loads in flight
       ct_d4 H2[T];
 #pragma unroll
-      for (int t = 0; t < T; ++t)
-        H2[t] = ct_d4{(double)b2[t][0], (double)b2[t][1], (double)b2[t][2], (double)b2[t][3]};
+      for (int t = 0; t < T; ++t) {
+        const float4 bb = ld4w<VEC>(b2r + 4 * t);
+        H2[t] = ct_d4{(double)bb.x, (double)bb.y, (double)bb.z, (double)bb.w};
+      }
 #pragma unroll
-      for (int s = 0; s < S; ++s)
+      for (int j = 0; j < S / 4; ++j) {
+        float4 wn[T];
+        if (j + 1 < S / 4) {
 #pragma unroll
-        for (int t = 0; t < T; ++t) H2[t] = mx(w2[t][s], H1[s / 4][s % 4], H2[t]);
+          for (int t = 0; t < T; ++t) wn[t] = ld4w<VEC>(w2r[t] + 4 * (j + 1));
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int s = 4 * j + e;
+#pragma unroll
+          for (int t = 0; t < T; ++t) H2[t] = mx(comp(wb[t], e), H1[s / 4][s % 4], H2[t]);
+        }
+        if (j + 1 < S / 4) {
+#pragma unroll
+          for (int t = 0; t < T; ++t) wb[t] = wn[t];
+        }
+      }
 #pragma unroll
       for (int t = 0; t < T; ++t) H2[t] = tanh4(H2[t]);
-      // layer 3 (rows past act: zero weights and bias, tanh(0) = 0)
       ct_d4 u = ct_d4{(double)b3[0], (double)b3[1], (double)b3[2], (double)b3[3]};
 #pragma unroll
       for (int s = 0; s < S; ++s) u = mx(w3[s], H2[s / 4][s % 4], u);
       u = tanh4(u);
 #pragma unroll
       for (int v = 0; v < 4; ++v) ju = fma(u[v], u[v], ju);
-      // plant update x <- A x + B u (rows past obs stay zero)
       ct_d4 Xn[2];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
@@ -782,7 +837,7 @@ __device__ __forceinline__ double rollout_mx(const float *__restrict__ U, const 
 // Rollout and selection decision of every control trial, one wavefront per
 // target (INIT: the first evaluation).  Grid (max N, control runs).
 template <int H, bool TRACE, bool INIT>
-__global__ __launch_bounds__(64) void k_ctrl_eval_mx(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_ctrl_eval_mx(
     const RunDev *__restrict__ runs, const uint32_t *__restrict__ list,
     const ProbDev *__restrict__ probs, const unsigned char *__restrict__ tab,
     float *__restrict__ fit, const float *__restrict__ pend, float *__restrict__ fu_out,
@@ -792,7 +847,7 @@ __global__ __launch_bounds__(64) void k_ctrl_eval_mx(
   if (i >= run.N) return;
   const uint32_t lane = threadIdx.x;
   const ProbDev p = probs[run.prob];
-  const double J = rollout_mx<H>(pend + run.pend_off + (size_t)i * run.Dp, p, tab, lane);
+  const double J = rollout_mx<H, true>(pend + run.pend_off + (size_t)i * run.Dp, p, tab, lane);
   if (lane == 0) {
     const float f = (float)J;
     if (INIT) {
@@ -889,7 +944,7 @@ __global__ __launch_bounds__(64) void k_ctrl_finalize_mx(const RunDev *__restric
   const uint32_t b = (uint32_t)(best & 0xFFFFFFFFu);
   const float *x = pop + run.pop_off + (size_t)b * run.D;
   for (uint32_t j = lane; j < run.D; j += 64) best_x[run.bx_off + j] = x[j];
-  const double J = rollout_mx<H>(x, p, tab, lane);
+  const double J = rollout_mx<H, false>(x, p, tab, lane);
   if (lane == 0) best_y[r] = J;
 }
 
