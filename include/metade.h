@@ -136,7 +136,10 @@ typedef struct {
    * W2, b2, W3, b3; cost sum_{t<steps} |x_t|^2 + ctrl_weight |u_t|^2 averaged
    * over n_rollouts initial states; x_{t+1} = A x_t + B u_t.  The hidden
    * layers are both 32 wide (the policy MLPs of Sec. IV-D, Table VII) or both
-   * 64 wide, and all control problems of one context share that width. */
+   * 64 wide, and all control problems of one context share that width.  When
+   * every control problem of a context has a multiple of 16 rollouts, each
+   * policy is evaluated on the float64 matrix cores (16 rollouts per product);
+   * otherwise the rollouts run one after another on the vector units. */
   uint32_t obs, act, hidden1, hidden2, steps, n_rollouts;
   float ctrl_weight;
   const float *A;        /* device [obs*obs] row-major */
