@@ -33,13 +33,23 @@ sys.path.insert(0, ROOT)
 VALU_PEAK_SLOTS = 256 * 64 * 2.4e9
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per generation-kernel launch of the default workload, from two
-# rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE, KiB per dispatch) scaled by
-# what the same counters read for a 2 GiB device copy (FETCH_SIZE reads 0.5x
-# the copied bytes on this device, WRITE_SIZE 1.0x).  Keyed by a hash of the
-# kernel sources: a changed kernel reports null until measured again.
-KERNEL_SOURCES = ("paper_2502_10470_amd/csrc/kernels.hip", "paper_2502_10470_amd/csrc/device.h")
-MEASURED_TRAFFIC = {"4f5fab9e6de5e3ae": (797.0 * 2.0 + 3854.0 * 1.0) * 1024}
+# HBM bytes per launch of a workload's dominant kernel, from two rocprofv3
+# counter runs (FETCH_SIZE, WRITE_SIZE, KiB per dispatch) scaled by what the
+# same counters read for a 2 GiB device copy (FETCH_SIZE reads 0.5x the copied
+# bytes on this device, WRITE_SIZE 1.0x).  Keyed by a hash of the kernel's
+# sources: a changed kernel reports null until measured again.
+KERNEL_SOURCES = {
+    "k_generations": ("paper_2502_10470_amd/csrc/kernels.hip",
+                      "paper_2502_10470_amd/csrc/gen_common.h",
+                      "paper_2502_10470_amd/csrc/device.h"),
+    "k_generations_mfma": ("paper_2502_10470_amd/csrc/kernels_mfma.hip",
+                           "paper_2502_10470_amd/csrc/gen_common.h",
+                           "paper_2502_10470_amd/csrc/device.h"),
+}
+MEASURED_TRAFFIC = {
+    "4cd7f07d5b083480": (797.0 * 2.0 + 3854.0 * 1.0) * 1024,          # k_generations, C3
+    "d6eef48be04b0e82": (105753.2 * 2.0 + 8058403.0 * 1.0) * 1024,    # k_generations_mfma, C4
+}
 
 PHILOX_SLOTS = 100   # 10 rounds x (2 quarter-rate 32x32->64 multiplies + 2 three-input XORs)
 ELEM_SLOTS = {       # per element of z: square/accumulate + the element function
@@ -49,13 +59,13 @@ ELEM_SLOTS["hybrid"] = (6 * ELEM_SLOTS["schwefel"] + 7 * ELEM_SLOTS["rastrigin"]
                         + 7 * ELEM_SLOTS["elliptic"]) / 20.0
 
 
-def kernel_source_hash():
-    """Hash of the kernel sources' code: comments and whitespace are left out,
+def kernel_source_hash(kernel="k_generations"):
+    """Hash of a kernel's sources' code: comments and whitespace are left out,
     so that only a change of the code itself invalidates a measurement."""
     import hashlib
     import re
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, f), encoding="utf-8") as fh:
             text = fh.read()
         text = re.sub(r"//[^\n]*", "", text)
@@ -240,7 +250,9 @@ def bench_batch(args):
         peak = MFMA_BF16_PEAK if prec == M.BF16_REFINE else MFMA_F64_PEAK
         ach = rot_flops / (avg_ms * 1e-3)
         line["roofline"] = {"bound": "mfma", "achieved": ach / 1e12, "peak": peak / 1e12,
-                            "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
+                            "unit": "TFLOP/s", "frac": ach / peak,
+                            "traffic": (MEASURED_TRAFFIC.get(kernel_source_hash(kern))
+                                        if prec == M.FP32 else None),
                             "kernel": kern, "avg_launch_ms": avg_ms, "launches": k_launches,
                             "alu_frac": slots / (avg_ms * 1e-3) / VALU_PEAK_SLOTS,
                             "occupied_cu_frac": min(wl.n_runs, 256) / 256.0}
