@@ -244,3 +244,17 @@ def test_control_16_rollouts_best_record_and_resume():
     b2.inner_step(2)
     p2, f2 = b2.host_state()
     assert np.array_equal(p1, p2) and np.array_equal(f1, f2)
+
+
+@pytest.mark.parametrize("hidden,n_roll", [((64, 64), 1), ((32, 32), 1), ((64, 64), 16)])
+def test_control_largest_population_and_sizes(hidden, n_roll):
+    """N = 1024 (the control maximum) with the largest observation / action sizes,
+    on the vector evaluation (one rollout) and the matrix-core one (16)."""
+    th = _strategy_grid(2, 3, seed=77)
+    wl = W.control_batch(71, [1024, 10], shapes=[(20, 8), (20, 8)], steps=4, n_rollouts=n_roll,
+                         theta=th, n_cs=3, hidden=hidden)
+    b = _batch(wl)
+    out = trajectory_parity(b, wl, G=2)
+    print(f"N=1024 hidden {hidden[0]} E={n_roll}: compared {out['compared']} "
+          f"diverged {out['diverged']} max fitness rel err {out['max_fit_rel']:.3g}")
+    assert out["compared"] >= 2
