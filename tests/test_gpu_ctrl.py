@@ -123,13 +123,15 @@ def test_control_selection_invariants():
         f0 = f
 
 
-def test_control_graph_replays_match_direct_launches():
+@pytest.mark.parametrize("n_roll", [2, 16])
+def test_control_graph_replays_match_direct_launches(n_roll):
     """The control generation loop replayed from HIP graphs gives the same
     populations as direct launches, call after call: replays of one graph at
     later starting generations, a second sequence length, host work and
-    synchronisations in between, and a checkpoint restored mid-way."""
+    synchronisations in between, and a checkpoint restored mid-way (vector
+    evaluation with 2 rollouts, matrix-core evaluation with 16)."""
     from paper_2502_10470_amd import Batch
-    wl = W.control_batch(12, [24, 40, 17], obs=6, act=2, steps=30, n_rollouts=2)
+    wl = W.control_batch(12, [24, 40, 17], obs=6, act=2, steps=30, n_rollouts=n_roll)
     bg = Batch(wl, graph=True)
     bd = Batch(wl, graph=False)
     blob = None
