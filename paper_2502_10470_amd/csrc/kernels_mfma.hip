@@ -75,19 +75,20 @@ __device__ __forceinline__ void tiles_f64(const float *__restrict__ Tg, uint32_t
 #pragma unroll
     for (int e = 0; e < 4; ++e) bv[e] = (jok && kb + e < D) ? Rt[(size_t)(kb + e) * Dr + j] : 0.0;
   };
-  float4 tn[RT];
-  double bn[4];
+  float4 tn[RT], tm[RT];
+  double bn[4], bm[4];
   load(0, tn, bn);
+  if (nb > 1) load(1, tm, bm);
 #pragma unroll 1
   for (uint32_t b = 0; b < nb; ++b) {
-    // the next block's loads are in flight while this block's products run
+    // the loads of the next two blocks are in flight while this block's products run
     float4 tv[RT];
     double bv[4];
 #pragma unroll
-    for (int r = 0; r < RT; ++r) tv[r] = tn[r];
+    for (int r = 0; r < RT; ++r) { tv[r] = tn[r]; tn[r] = tm[r]; }
 #pragma unroll
-    for (int e = 0; e < 4; ++e) bv[e] = bn[e];
-    if (b + 1 < nb) load(b + 1, tn, bn);
+    for (int e = 0; e < 4; ++e) { bv[e] = bn[e]; bn[e] = bm[e]; }
+    if (b + 2 < nb) load(b + 2, tm, bm);
     const uint32_t kb = 16 * b + 4 * kq;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
