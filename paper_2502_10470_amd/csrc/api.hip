@@ -193,7 +193,10 @@ metade_status plan_config(const metade_config *cfg, Plan &pl, std::string &msg) 
     // read-only table layout of this problem
     p.o_off = take((size_t)q.D * sizeof(float));
     p.o64_off = take((size_t)q.D * sizeof(double));
-    p.r64t_off = take((size_t)q.D * mde::rt_stride(q.D) * sizeof(double));
+    // transposed float64 rotation [D][rt_stride], then the row-major float32 one
+    // [D][round4(D)] (zero padded) that the matrix-core kernel reads
+    p.r64t_off = take((size_t)q.D * mde::rt_stride(q.D) * sizeof(double) +
+                      (size_t)q.D * round4(q.D) * sizeof(float));
     p.ew_off = take((size_t)q.D * sizeof(float));
     p.ew64_off = take((size_t)q.D * sizeof(double));
     p.ek_off = take((size_t)q.D * sizeof(uint32_t));
@@ -572,6 +575,14 @@ metade_status metade_init(const metade_config *cfg, metade_ctx **out) {
     if (e4 == hipSuccess)
       e4 = mde::launch_tables64(q.R, q.o, reinterpret_cast<double *>(t + p.r64t_off),
                                 reinterpret_cast<double *>(t + p.o64_off), p.D, c->stream);
+    if (e4 == hipSuccess) {
+      unsigned char *r32 = t + p.r64t_off + (size_t)p.D * mde::rt_stride(p.D) * sizeof(double);
+      const size_t pitch = (size_t)round4(p.D) * sizeof(float);
+      e4 = hipMemsetAsync(r32, 0, (size_t)p.D * pitch, c->stream);
+      if (e4 == hipSuccess)
+        e4 = hipMemcpy2DAsync(r32, pitch, q.R, (size_t)p.D * sizeof(float),
+                              (size_t)p.D * sizeof(float), p.D, hipMemcpyDeviceToDevice, c->stream);
+    }
     if (e4 != hipSuccess) { c->err = std::string("problem tables: ") + hipGetErrorString(e4); return bail(METADE_EDEVICE); }
   }
   hipError_t e = mde::set_lds_limits();

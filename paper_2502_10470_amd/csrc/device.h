@@ -65,7 +65,8 @@ struct ProbDev {
   double cs_d;
   uint64_t o_off;               // float  [D]    shift
   uint64_t o64_off;             // double [D]    same in float64
-  uint64_t r64t_off;            // double [D*D]  rotation transposed: element (k, j) = R[j][k]
+  uint64_t r64t_off;            // double [D][rt_stride] rotation transposed: (k, j) = R[j][k];
+                                //   followed by float [D][round4(D)] row-major R, zero padded
   uint64_t ew_off;              // float  [D]    elliptic weight of output j
   uint64_t ew64_off;            // double [D]    same in float64
   uint64_t ek_off;              // uint32 [D]    hybrid block of output j (0 Schwefel, 1 Rastrigin, 2 elliptic)

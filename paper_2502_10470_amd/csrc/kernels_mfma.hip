@@ -58,36 +58,38 @@ constexpr int RT = 2;
 __device__ __forceinline__ void tiles_f64(const float *__restrict__ Tg, uint32_t Dk, uint32_t D,
                                           const float *oc, const bool (&row_ok)[RT],
                                           const uint32_t (&row_trial)[RT],
-                                          const double *__restrict__ Rt, uint32_t Dr, uint32_t j,
+                                          const float *__restrict__ R32, uint32_t D4, uint32_t j,
                                           uint32_t lane, d4v (&acc)[RT]) {
   const uint32_t kq = lane >> 4;
   const uint32_t nb = (D + 15) / 16;  // blocks of 16 k (four steps of 4)
   const bool jok = j < D;
 #pragma unroll
   for (int r = 0; r < RT; ++r) acc[r] = d4v{0.0, 0.0, 0.0, 0.0};
-  // operands of block b: the lane's float4 of each trial row and four R coefficients
-  auto load = [&](uint32_t b, float4 (&tv)[RT], double (&bv)[4]) {
+  // operands of block b: the lane's float4 of each trial row and the four R
+  // coefficients R[j][kb .. kb+3], one float4 of the row-major float32
+  // rotation (row stride D4, zero padding; the values are the problem's
+  // float32 coefficients, so widening them is exact)
+  auto load = [&](uint32_t b, float4 (&tv)[RT], float4 &bv) {
     const uint32_t kb = 16 * b + 4 * kq;
 #pragma unroll
     for (int r = 0; r < RT; ++r)
       tv[r] = row_ok[r] ? *reinterpret_cast<const float4 *>(Tg + (size_t)row_trial[r] * Dk + kb)
                         : make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-    for (int e = 0; e < 4; ++e) bv[e] = (jok && kb + e < D) ? Rt[(size_t)(kb + e) * Dr + j] : 0.0;
+    bv = (jok && kb < D4) ? *reinterpret_cast<const float4 *>(R32 + (size_t)j * D4 + kb)
+                          : make_float4(0.f, 0.f, 0.f, 0.f);
   };
   float4 tn[RT], tm[RT];
-  double bn[4], bm[4];
+  float4 bn, bm;
   load(0, tn, bn);
   if (nb > 1) load(1, tm, bm);
 #pragma unroll 1
   for (uint32_t b = 0; b < nb; ++b) {
     // the loads of the next two blocks are in flight while this block's products run
     float4 tv[RT];
-    double bv[4];
 #pragma unroll
     for (int r = 0; r < RT; ++r) { tv[r] = tn[r]; tn[r] = tm[r]; }
-#pragma unroll
-    for (int e = 0; e < 4; ++e) { bv[e] = bn[e]; bn[e] = bm[e]; }
+    const float4 bv = bn;
+    bn = bm;
     if (b + 2 < nb) load(b + 2, tm, bm);
     const uint32_t kb = 16 * b + 4 * kq;
 #pragma unroll
@@ -97,7 +99,7 @@ __device__ __forceinline__ void tiles_f64(const float *__restrict__ Tg, uint32_t
 #pragma unroll
       for (int r = 0; r < RT; ++r) {
         const double a = kin ? (double)comp(tv[r], e) - oe : 0.0;
-        acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[e], a, acc[r], 0, 0, 0);
+        acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)comp(bv, e), a, acc[r], 0, 0, 0);
       }
     }
   }
@@ -309,6 +311,9 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
   __bf16 *Yl = Yh + (size_t)N * Dk;
   const double *Rt = tab_ptr<double>(tab, p.r64t_off);
   const uint32_t Dr = rt_stride(D);
+  // row-major float32 rotation [D][D4] stored after the transposed float64 one
+  const uint32_t D4 = (D + 3u) & ~3u;
+  const float *R32 = tab_ptr<float>(tab, p.r64t_off + (uint64_t)D * Dr * sizeof(double));
 
   const uint32_t tid = threadIdx.x;
   const uint32_t lane = tid & 63;
@@ -494,7 +499,7 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
           }
         } else {
           d4v acc[RT];
-          tiles_f64(Tg, Dk, D, oc, rok, rtr, Rt, Dr, jcol, lane, acc);
+          tiles_f64(Tg, Dk, D, oc, rok, rtr, R32, D4, jcol, lane, acc);
 #pragma unroll
           for (int r = 0; r < RT; ++r) {
             const float z[4] = {(float)acc[r][0], (float)acc[r][1], (float)acc[r][2],
@@ -560,7 +565,7 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
             rtr[r] = rok[r] ? cl[srow] : 0u;
           }
           d4v acc[RT];
-          tiles_f64(Tg, Dk, D, oc, rok, rtr, Rt, Dr, jcol, lane, acc);
+          tiles_f64(Tg, Dk, D, oc, rok, rtr, R32, D4, jcol, lane, acc);
 #pragma unroll
           for (int r = 0; r < RT; ++r) {
             const float z[4] = {(float)acc[r][0], (float)acc[r][1], (float)acc[r][2],
