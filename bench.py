@@ -168,6 +168,61 @@ def cpu_baseline(wl, budget_s=12.0):
                       f"theta from the first evolver trial, {dt:.1f} s on one host core"}
 
 
+POOL_WORKERS = 16   # host cores of the measurement machine's share
+
+
+def _pool_run(args):
+    """One executor run of the oracle on one core (worker of the all-cores baseline)."""
+    r, G = args
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(limits=1)
+    except Exception:  # pragma: no cover
+        pass
+    import workloads as W
+    from oracle import metade as ometa
+    from oracle import pde
+    wl = W.workload_c3()
+    X, y = ometa.outer_init(wl.outer["P"], wl.seed, int(wl.stream[0]), wl.n_cs)
+    U, _ = ometa.outer_trials(X, y, 0, wl.seed, int(wl.stream[0]), wl.n_cs)
+    th = pde.decode(U, wl.n_cs)
+    prob = wl.problems[int(wl.problem[r])]
+    t = {k: v[r] for k, v in th.items()}
+    pde.run_executor(int(wl.N[r]), prob.D, t, G, wl.seed, int(wl.stream[r]), wl.lb, wl.ub, prob)
+    return int(wl.N[r]) * G
+
+
+def cpu_baseline_pool_child(G=2000):
+    """All-cores oracle figure: every executor run of the default workload's first
+    evolver generation (its theta, G generations each) on a pool of one-thread
+    worker processes.  Runs in a process of its own that never touches the GPU;
+    prints one JSON object."""
+    import multiprocessing as mp
+    import workloads as W
+    wl = W.workload_c3()
+    workers = min(POOL_WORKERS, os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(workers) as pool:
+        evals = sum(pool.map(_pool_run, [(r, G) for r in range(wl.n_runs)], chunksize=1))
+    dt = time.perf_counter() - t0
+    print(json.dumps({"value": evals / dt, "cores": workers,
+                      "sample": f"{wl.n_runs} executor runs x {G} generations, {dt:.1f} s wall "
+                                f"on {workers} worker processes"}), flush=True)
+
+
+def cpu_baseline_all_cores():
+    """Start the all-cores baseline in a fresh interpreter (before this process
+    starts the GPU runtime) and return its result, or None."""
+    import subprocess
+    code = "import bench; bench.cpu_baseline_pool_child()"
+    try:
+        out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True,
+                             text=True, timeout=300)
+        return json.loads(out.stdout.strip().splitlines()[-1])
+    except Exception:  # pragma: no cover - reported as missing, never fatal
+        return None
+
+
 MFMA_F64_PEAK = 78.6e12
 MFMA_BF16_PEAK = 2.5e15
 
@@ -384,6 +439,11 @@ def main():
         # after the other.  Set before the HIP runtime starts.
         if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < 8:
             os.environ["GPU_MAX_HW_QUEUES"] = "8"
+    # the all-cores oracle figure is taken first, in a separate process, while
+    # this one has not started the GPU runtime
+    pool_baseline = None
+    if (not args.no_cpu_baseline and args.workload == "c3" and not args.budget_seconds):
+        pool_baseline = cpu_baseline_all_cores()
 
     import torch
     import workloads as W
@@ -396,6 +456,7 @@ def main():
     wl = W.workload_c3() if args.workload == "c3" else W.workload_paper()
     if args.budget_seconds:
         return bench_budget(args, wl)
+    args.pool_baseline = pool_baseline
     P, gens, G, pu = wl.outer["P"], wl.outer["gens"], wl.G, wl.outer["power_up"]
     b = Batch(wl)
     evals = wl.evals_per_pass()
@@ -452,6 +513,8 @@ def main():
     }
     if not args.no_cpu_baseline and args.workload == "c3":
         line["cpu_baseline"] = cpu_baseline(wl)
+        if getattr(args, "pool_baseline", None):
+            line["cpu_baseline"]["all_cores"] = args.pool_baseline
     print(json.dumps(line), flush=True)
 
 

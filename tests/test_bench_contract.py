@@ -41,3 +41,5 @@ def test_default_line_fields():
     assert abs(rf["frac"] - rf["achieved"] / rf["peak"]) < 1e-9
     cb = d["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["cores"] >= 1 and cb["value"] > 0 and cb["sample"]
+    ac = cb["all_cores"]   # the oracle on a pool of one-thread worker processes
+    assert ac["cores"] >= 1 and ac["value"] > 0 and ac["sample"]
