@@ -31,7 +31,6 @@ typedef double d4v __attribute__((ext_vector_type(4)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 
-constexpr int KS64 = 32;      // float64 k-steps of 4 (D <= 128)
 constexpr int KSB = 4;        // bf16 k-steps of 32 (D <= 128)
 // |z_hat - z| <= E_COEF * ||u - o||_2 for the three-product bf16 split with
 // float32 accumulation: the residues of the two splits and the dropped
