@@ -184,3 +184,25 @@ def test_lqr_extended_precision_agrees_when_well_conditioned():
     J64 = fitness.lqr_mlp(w, p)
     J80 = fitness.lqr_mlp(w, p, dtype=np.longdouble).astype(np.float64)
     assert np.all(np.abs(J64 - J80) <= 1e-12 * J80)
+
+
+def test_table7_workload_shapes():
+    """The T7 workload holds the three policies of Table VII (hidden 32 x 32) with
+    their weight counts, 32 executors each, and a plant of each task's sizes."""
+    wl = W.workload_t7()
+    assert wl.n_runs == 96 and all(int(n) == 100 for n in wl.N) and wl.G == 50
+    want = {(11, 3): 1539, (8, 2): 1410, (11, 2): 1506}
+    seen = {}
+    for p in wl.problems:
+        obs, act = p.A.shape[0], p.B.shape[1]
+        assert p.hidden == (32, 32) and p.D == want[(obs, act)]
+        assert p.B.shape == (obs, act) and p.x0.shape == (1, obs)
+        seen[(obs, act)] = seen.get((obs, act), 0) + 1
+    assert seen == {k: 32 for k in want}
+
+
+def test_c5e16_workload_has_16_rollouts():
+    wl = W.workload_c5e16()
+    assert wl.G == 10 and wl.n_runs == 16
+    for p in wl.problems:
+        assert p.D == 5702 and p.hidden == (64, 64) and p.x0.shape == (16, 17)
