@@ -288,3 +288,22 @@ def test_nan_targets_rank_last_and_are_replaced():
         assert np.all(np.isfinite(b.run_fit(fit1, r)))
         amb = near(s["fu64"], fr) & ~np.isnan(s["fu64"])
         assert np.array_equal(acc[~amb], s["accept"][~amb])
+
+
+def test_theta_outside_the_box_and_nan():
+    """θ components outside the box are clipped and NaN components take the
+    lower bound when the library decodes θ (the box's upper end maps to the
+    last category); the trajectories follow the oracle run on the clipped θ."""
+    import dataclasses
+    raw = np.array([[1.7, -0.3, 7.2, 0.1, 5.0, 9.0],
+                    [np.nan, 0.6, np.nan, 3.5, np.nan, 2.5],
+                    [0.5, np.nan, 2.5, 9.5, -4.0, np.nan],
+                    [-2.0, 2.0, 4.999, 1.0, 3.9, 1.0]], np.float32)
+    lo, hi = W.theta_box(3)
+    clean = np.where(np.isnan(raw), lo, np.minimum(np.maximum(raw, lo), hi)).astype(np.float32)
+    wl = W.small_batch(61, ["rastrigin", "elliptic"], [24, 30, 17, 40], [10, 13, 7, 20],
+                       theta=clean, n_cs=3)
+    b = _batch(wl)
+    b.set_theta(raw)
+    out = trajectory_parity(b, dataclasses.replace(wl, theta=clean), G=3)
+    assert out["compared"] >= 8
