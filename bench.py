@@ -429,7 +429,7 @@ def main():
         print(json.dumps({"copy_mib": args.copy_calibration_mib, "launches": 3}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU: the executor batch is not "
+        print(json.dumps({"error": "this implementation measures one GPU: the executor batch is not "
                                    "sharded across GPUs (run with --gpus 1)"}))
         sys.exit(2)
     if args.workload == "c3x4":
