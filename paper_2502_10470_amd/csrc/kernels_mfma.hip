@@ -326,7 +326,8 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
   const uint32_t kr0 = l * N / L, kr1 = (l + 1) * N / L;
   // decision lane of trial tid
   const bool dec = !producer && tid < N;
-  // output tile of this consumer wave
+  // output tile of this consumer wave in the bf16 rotation (its bf16 parts of R
+  // stay in registers); the float64 tiles are dealt to the waves as items
   const uint32_t ct = wave;
   const bool has_ct = !producer && ct < NCT;
   const uint32_t jcol = 16 * ct + (lane & 15);
@@ -477,7 +478,8 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
     }
     __syncthreads();
     // S3: rotation on the matrix cores + element terms; producers: masks of g+1
-    if (has_ct) {
+    if (BF16 && has_ct) {
+      // the bf16 parts of R stay in registers: one output tile per wave
       for (uint32_t rt0 = 0; rt0 < NRT; rt0 += RT) {
         bool rok[RT];
         uint32_t rtr[RT];
@@ -486,26 +488,38 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
           rtr[r] = 16 * (rt0 + r) + (lane & 15);
           rok[r] = rtr[r] < N;
         }
-        if (BF16) {
-          f4v acc[RT];
-          tiles_bf16(Yh, Yl, Dk, rok, rtr, bhi, blo, lane, acc);
+        f4v acc[RT];
+        tiles_bf16(Yh, Yl, Dk, rok, rtr, bhi, blo, lane, acc);
 #pragma unroll
-          for (int r = 0; r < RT; ++r) {
-            const float z[4] = {acc[r][0], acc[r][1], acc[r][2], acc[r][3]};
-            const float e = rok[r] ? E_COEF * (sqrtf(ysq_s[rtr[r]]) * 1.0001f) : 0.0f;
-            tile_epilogue<true, false>(p, ek_s, ew_s, z, rtr[r], rok[r], e, D, ct, N, lane, Ps,
-                                       Pb, zf, zl);
-          }
-        } else {
-          d4v acc[RT];
-          tiles_f64(Tg, Dk, D, oc, rok, rtr, R32, D4, jcol, lane, acc);
+        for (int r = 0; r < RT; ++r) {
+          const float z[4] = {acc[r][0], acc[r][1], acc[r][2], acc[r][3]};
+          const float e = rok[r] ? E_COEF * (sqrtf(ysq_s[rtr[r]]) * 1.0001f) : 0.0f;
+          tile_epilogue<true, false>(p, ek_s, ew_s, z, rtr[r], rok[r], e, D, ct, N, lane, Ps,
+                                     Pb, zf, zl);
+        }
+      }
+    } else if (!BF16 && !producer) {
+      // (output tile, group of RT row tiles) items dealt to all consumer waves
+      // in turn, so that no wave idles when D spans fewer output tiles than
+      // there are waves
+      const uint32_t n_items = NCT * ((NRT + RT - 1) / RT);
+      for (uint32_t it = wave; it < n_items; it += MF_CONSUMERS / 64) {
+        const uint32_t ci = it % NCT, rt0 = (it / NCT) * RT;
+        bool rok[RT];
+        uint32_t rtr[RT];
 #pragma unroll
-          for (int r = 0; r < RT; ++r) {
-            const float z[4] = {(float)acc[r][0], (float)acc[r][1], (float)acc[r][2],
-                                (float)acc[r][3]};
-            tile_epilogue<false, true>(p, ek_s, ew_s, z, rtr[r], rok[r], 0.0f, D, ct, N, lane,
-                                       Ps, Pb, zf, zl);
-          }
+        for (int r = 0; r < RT; ++r) {
+          rtr[r] = 16 * (rt0 + r) + (lane & 15);
+          rok[r] = rtr[r] < N;
+        }
+        d4v acc[RT];
+        tiles_f64(Tg, Dk, D, oc, rok, rtr, R32, D4, 16 * ci + (lane & 15), lane, acc);
+#pragma unroll
+        for (int r = 0; r < RT; ++r) {
+          const float z[4] = {(float)acc[r][0], (float)acc[r][1], (float)acc[r][2],
+                              (float)acc[r][3]};
+          tile_epilogue<false, true>(p, ek_s, ew_s, z, rtr[r], rok[r], 0.0f, D, ci, N, lane,
+                                     Ps, Pb, zf, zl);
         }
       }
     }
@@ -552,9 +566,12 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
         cl[pos] = tid;
       }
       __syncthreads();
-      // S5: plain re-evaluation of the candidates on compacted row tiles
-      if (has_ct) {
-        for (uint32_t rt0 = 0; rt0 < (total + 15) / 16; rt0 += RT) {
+      // S5: plain re-evaluation of the candidates on compacted row tiles,
+      // (output tile, row tile group) items dealt to all consumer waves
+      if (!producer) {
+        const uint32_t n_items = NCT * (((total + 15) / 16 + RT - 1) / RT);
+        for (uint32_t it = wave; it < n_items; it += MF_CONSUMERS / 64) {
+          const uint32_t ci = it % NCT, rt0 = (it / NCT) * RT;
           bool rok[RT];
           uint32_t rtr[RT];
 #pragma unroll
@@ -564,13 +581,13 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
             rtr[r] = rok[r] ? cl[srow] : 0u;
           }
           d4v acc[RT];
-          tiles_f64(Tg, Dk, D, oc, rok, rtr, R32, D4, jcol, lane, acc);
+          tiles_f64(Tg, Dk, D, oc, rok, rtr, R32, D4, 16 * ci + (lane & 15), lane, acc);
 #pragma unroll
           for (int r = 0; r < RT; ++r) {
             const float z[4] = {(float)acc[r][0], (float)acc[r][1], (float)acc[r][2],
                                 (float)acc[r][3]};
             const uint32_t slot = 16 * (rt0 + r) + (lane & 15);   // position in the candidate list
-            tile_epilogue<false, true>(p, ek_s, ew_s, z, slot, rok[r], 0.0f, D, ct, N, lane, Ps,
+            tile_epilogue<false, true>(p, ek_s, ew_s, z, slot, rok[r], 0.0f, D, ci, N, lane, Ps,
                                        Pb, zf, zl);
           }
         }
