@@ -51,10 +51,12 @@ def test_every_strategy_small():
 
 
 @pytest.mark.parametrize("N,D", [(10, 2), (33, 7), (64, 20), (100, 20), (200, 37), (256, 64),
-                                 (256, 100), (130, 128)])
+                                 (256, 100), (130, 128), (200, 90)])
 def test_tiles_and_ragged_tails(N, D):
     """Population and dimension sizes spanning several LDS tiles and chunks,
-    with ragged tails (D not a multiple of 4, N not a multiple of a wave)."""
+    with ragged tails (D not a multiple of 4, N not a multiple of a wave).
+    The last three run the matrix-core kernel; at N = 200, D = 90 its 42
+    (output tile, row-tile pair) items fall unevenly on the eight waves."""
     kinds = ["rastrigin", "elliptic", "ackley", "rosenbrock", "schwefel"]
     wl = W.small_batch(N * 1000 + D, kinds, [N] * 5, [D] * 5, n_cs=3)
     b = _batch(wl)
