@@ -48,7 +48,7 @@ KERNEL_SOURCES = {
 }
 MEASURED_TRAFFIC = {
     "4cd7f07d5b083480": (797.0 * 2.0 + 3854.0 * 1.0) * 1024,          # k_generations, C3
-    "62ae697bc60a5429": (17660.8 * 2.0 + 7093979.1 * 1.0) * 1024,     # k_generations_mfma, C4
+    "d60c363f3e1b744e": (21362.5 * 2.0 + 7197942.1 * 1.0) * 1024,     # k_generations_mfma, C4
 }
 
 PHILOX_SLOTS = 100   # 10 rounds x (2 quarter-rate 32x32->64 multiplies + 2 three-input XORs)

@@ -49,44 +49,49 @@ constexpr float E_COEF = 1.2207031e-4f;  // 2^-13
 // is permuted inside each block of four steps: lane l feeds steps 4b..4b+3
 // with k = 16 b + 4 (l/16) + 0..3, one contiguous float4 of its trial row.
 // Result element v is z[trial 16 rt + l%16][output 16 ct + l/16 + 4v].
-// RT row tiles at once (rows given per tile): RT independent accumulator
+// RR row tiles at once (rows given per tile): RR independent accumulator
 // chains sharing the B loads, so that consecutive matrix-core instructions
-// do not wait on each other's results.
+// do not wait on each other's results.  The plain rotation takes four row
+// tiles per item, the bf16 tiles and the bf16 mode's re-evaluation two
+// (measured best for each; more rows per item spill registers in the bf16
+// kernel).
 constexpr int RT = 2;
+constexpr int RT_F64 = 4;
 
+template <int RR>
 __device__ __forceinline__ void tiles_f64(const float *__restrict__ Tg, uint32_t Dk, uint32_t D,
-                                          const float *oc, const bool (&row_ok)[RT],
-                                          const uint32_t (&row_trial)[RT],
+                                          const float *oc, const bool (&row_ok)[RR],
+                                          const uint32_t (&row_trial)[RR],
                                           const float *__restrict__ R32, uint32_t D4, uint32_t j,
-                                          uint32_t lane, d4v (&acc)[RT]) {
+                                          uint32_t lane, d4v (&acc)[RR]) {
   const uint32_t kq = lane >> 4;
   const uint32_t nb = (D + 15) / 16;  // blocks of 16 k (four steps of 4)
   const bool jok = j < D;
 #pragma unroll
-  for (int r = 0; r < RT; ++r) acc[r] = d4v{0.0, 0.0, 0.0, 0.0};
+  for (int r = 0; r < RR; ++r) acc[r] = d4v{0.0, 0.0, 0.0, 0.0};
   // operands of block b: the lane's float4 of each trial row and the four R
   // coefficients R[j][kb .. kb+3], one float4 of the row-major float32
   // rotation (row stride D4, zero padding; the values are the problem's
   // float32 coefficients, so widening them is exact)
-  auto load = [&](uint32_t b, float4 (&tv)[RT], float4 &bv) {
+  auto load = [&](uint32_t b, float4 (&tv)[RR], float4 &bv) {
     const uint32_t kb = 16 * b + 4 * kq;
 #pragma unroll
-    for (int r = 0; r < RT; ++r)
+    for (int r = 0; r < RR; ++r)
       tv[r] = row_ok[r] ? *reinterpret_cast<const float4 *>(Tg + (size_t)row_trial[r] * Dk + kb)
                         : make_float4(0.f, 0.f, 0.f, 0.f);
     bv = (jok && kb < D4) ? *reinterpret_cast<const float4 *>(R32 + (size_t)j * D4 + kb)
                           : make_float4(0.f, 0.f, 0.f, 0.f);
   };
-  float4 tn[RT], tm[RT];
+  float4 tn[RR], tm[RR];
   float4 bn, bm;
   load(0, tn, bn);
   if (nb > 1) load(1, tm, bm);
 #pragma unroll 1
   for (uint32_t b = 0; b < nb; ++b) {
     // the loads of the next two blocks are in flight while this block's products run
-    float4 tv[RT];
+    float4 tv[RR];
 #pragma unroll
-    for (int r = 0; r < RT; ++r) { tv[r] = tn[r]; tn[r] = tm[r]; }
+    for (int r = 0; r < RR; ++r) { tv[r] = tn[r]; tn[r] = tm[r]; }
     const float4 bv = bn;
     bn = bm;
     if (b + 2 < nb) load(b + 2, tm, bm);
@@ -96,7 +101,7 @@ __device__ __forceinline__ void tiles_f64(const float *__restrict__ Tg, uint32_t
       const bool kin = kb + e < D;
       const double oe = kin ? (double)oc[kb + e] : 0.0;
 #pragma unroll
-      for (int r = 0; r < RT; ++r) {
+      for (int r = 0; r < RR; ++r) {
         const double a = kin ? (double)comp(tv[r], e) - oe : 0.0;
         acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)comp(bv, e), a, acc[r], 0, 0, 0);
       }
@@ -499,23 +504,23 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
         }
       }
     } else if (!BF16 && !producer) {
-      // (output tile, group of RT row tiles) items dealt to all consumer waves
+      // (output tile, group of RT_F64 row tiles) items dealt to all consumer waves
       // in turn, so that no wave idles when D spans fewer output tiles than
       // there are waves
-      const uint32_t n_items = NCT * ((NRT + RT - 1) / RT);
+      const uint32_t n_items = NCT * ((NRT + RT_F64 - 1) / RT_F64);
       for (uint32_t it = wave; it < n_items; it += MF_CONSUMERS / 64) {
-        const uint32_t ci = it % NCT, rt0 = (it / NCT) * RT;
-        bool rok[RT];
-        uint32_t rtr[RT];
+        const uint32_t ci = it % NCT, rt0 = (it / NCT) * RT_F64;
+        bool rok[RT_F64];
+        uint32_t rtr[RT_F64];
 #pragma unroll
-        for (int r = 0; r < RT; ++r) {
+        for (int r = 0; r < RT_F64; ++r) {
           rtr[r] = 16 * (rt0 + r) + (lane & 15);
           rok[r] = rtr[r] < N;
         }
-        d4v acc[RT];
+        d4v acc[RT_F64];
         tiles_f64(Tg, Dk, D, oc, rok, rtr, R32, D4, 16 * ci + (lane & 15), lane, acc);
 #pragma unroll
-        for (int r = 0; r < RT; ++r) {
+        for (int r = 0; r < RT_F64; ++r) {
           const float z[4] = {(float)acc[r][0], (float)acc[r][1], (float)acc[r][2],
                               (float)acc[r][3]};
           tile_epilogue<false, true>(p, ek_s, ew_s, z, rtr[r], rok[r], 0.0f, D, ci, N, lane,
