@@ -225,8 +225,22 @@ metade_status metade_trace_sizes(metade_ctx *ctx, size_t *u_bytes, size_t *fu_by
  *        2..9 difference pairs (a1,b1,..,a4,b4; -1 unused), 10 j_rand or n,
  *        11 L (exponential) or -1, 12 pbest rank, 13 rand index or -1,
  *        14 K bits (float32) , 15 accept flag.
- * Available for METADE_FP32 contexts only (METADE_EINVAL otherwise). */
+ * In a METADE_BF16_REFINE context a traced generation re-evaluates every
+ * trial with the plain evaluation (fu is that value; the decisions are the
+ * mode's, which equal the plain ones) and checks each trial's bf16 value
+ * against its bound (see metade_get_bound_check). */
 metade_status metade_inner_step_trace(metade_ctx *ctx, float *u, float *fu, int32_t *desc);
+
+/* Totals since metade_init of the bound check that traced generations of a
+ * METADE_BF16_REFINE context carry out (synchronises; any pointer may be
+ * NULL; all zero in other contexts): trials checked; trials whose bf16
+ * fitness lies farther than its bound from the plain value (a bound
+ * violation: must stay 0); trials the screen alone would have rejected
+ * without re-evaluation; of those, the ones the plain value accepts (a wrong
+ * decision: must stay 0); the largest |f_bf16 - f_plain| / bound seen. */
+metade_status metade_get_bound_check(metade_ctx *ctx, uint64_t *checked, uint64_t *outside,
+                                     uint64_t *screened, uint64_t *screen_wrong,
+                                     double *max_ratio);
 
 /* Evolver (Alg. 3; metade_config.evolver selects DE or PSO).  The context's
  * runs are the P = n_runs executors of one outer population.
@@ -264,8 +278,13 @@ metade_status metade_run(metade_ctx *ctx, uint32_t outer_gens, uint32_t G_inner,
 metade_status metade_get_best(metade_ctx *ctx, double *y);
 
 /* Checkpoint: all state that determines future results (populations,
- * fitness, theta, generation counters, evolver state, best records) as an
- * opaque host blob.  With blob == NULL only *bytes is set.  Synchronises. */
+ * fitness, decoded theta, generation counters, evolver state, best records)
+ * as an opaque host blob.  With blob == NULL only *bytes is set.
+ * Synchronises.  metade_set_state accepts a blob from any context with the
+ * same runs (sizes, packing) and n_cs, whatever its precision: the run layout
+ * always comes from the receiving context.  METADE_EINVAL for a blob of
+ * another size or configuration, or one whose theta lies outside the decoded
+ * domain (F, CR in [0, 1], bl, br, dn in 1..4, cs in 1..n_cs). */
 metade_status metade_get_state(metade_ctx *ctx, void *blob, size_t *bytes);
 metade_status metade_set_state(metade_ctx *ctx, const void *blob, size_t bytes);
 

@@ -223,11 +223,23 @@ def as_decision(f64, decide: str):
     return np.asarray(f64, dtype=np.float64)
 
 
-def step(pop, fit, th, g, seed, stream, lb, ub, prob, decide="f32"):
-    """One PDE generation (Alg. 2 loop body).  Returns a dict of everything."""
+def step(pop, fit, th, g, seed, stream, lb, ub, prob, decide="f32", fitness_override=None):
+    """One PDE generation (Alg. 2 loop body).  Returns a dict of everything.
+
+    ``fitness_override`` (one value per trial) replaces the trials' fitness in
+    the selection step: given another implementation's state before the
+    generation and its trial fitness, the selection rule of Alg. 1 is then
+    applied to exactly the values that implementation decided on, so its
+    decisions can be compared one by one, ties and near-ties included.  The
+    float64 fitness of the trials is still computed and returned as ``fu64``.
+    """
     u, desc = make_trials(pop, fit, th, g, seed, stream, lb, ub)
     fu64 = evaluate(u, prob)
-    fu = as_decision(fu64, decide)
+    if fitness_override is None:
+        fu = as_decision(fu64, decide)
+    else:
+        fu = np.asarray(fitness_override).reshape(fu64.shape)
+        fu = fu.astype(np.float32) if decide == "f32" else fu.astype(np.float64)
     new_pop, new_fit, accept = select(pop, fit, u, fu)
     return {"u": u, "fu64": fu64, "fu": fu, "desc": desc, "pop": new_pop, "fit": new_fit,
             "accept": accept}

@@ -21,6 +21,12 @@ namespace {
 
 thread_local std::string g_init_error = "no error";
 
+// Device counters of a context: [0] trials re-evaluated exactly by the bf16
+// mode; [1..5] the bound check of traced bf16 generations (checked, outside
+// the bound, screened out, screened out but accepted by the exact value, and
+// the largest deviation / bound as double bits).
+constexpr size_t N_COUNTERS = 8;
+
 struct EventPair {
   hipEvent_t a, b;
 };
@@ -508,7 +514,7 @@ metade_status metade_init(const metade_config *cfg, metade_ctx **out) {
   if ((st = dalloc(c, &c->yt, c->n_runs)) != METADE_OK) return bail(st);
   if ((st = dalloc(c, &c->bxo, c->bx_n)) != METADE_OK) return bail(st);
   if ((st = dalloc(c, &c->bidx, 4)) != METADE_OK) return bail(st);
-  if ((st = dalloc(c, &c->counters_d, 1)) != METADE_OK) return bail(st);
+  if ((st = dalloc(c, &c->counters_d, N_COUNTERS)) != METADE_OK) return bail(st);
   if ((st = dalloc(c, &c->gen_d, 1)) != METADE_OK) return bail(st);
   if ((st = dalloc(c, &c->lane_list_d, pl.lane_list.size())) != METADE_OK) return bail(st);
   if ((st = dalloc(c, &c->mfma_list_d, pl.mfma_list.size())) != METADE_OK) return bail(st);
@@ -519,7 +525,7 @@ metade_status metade_init(const metade_config *cfg, metade_ctx **out) {
     if ((st = dalloc(c, &c->cacc_d, c->fit_n)) != METADE_OK) return bail(st);
   }
   {
-    hipError_t e5 = hipMemset(c->counters_d, 0, sizeof(unsigned long long));
+    hipError_t e5 = hipMemset(c->counters_d, 0, N_COUNTERS * sizeof(unsigned long long));
     if (e5 == hipSuccess && !pl.lane_list.empty())
       e5 = hipMemcpy(c->lane_list_d, pl.lane_list.data(), pl.lane_list.size() * 4, hipMemcpyHostToDevice);
     if (e5 == hipSuccess && !pl.mfma_list.empty())
@@ -637,8 +643,6 @@ metade_status metade_trace_sizes(metade_ctx *c, size_t *u_bytes, size_t *fu_byte
 
 metade_status metade_inner_step_trace(metade_ctx *c, float *u, float *fu, int32_t *desc) {
   if (!c || !u || !fu || !desc) return fail(c, METADE_EINVAL, "ctx and all trace buffers are required");
-  if (c->precision != METADE_FP32)
-    return fail(c, METADE_EINVAL, "tracing is available for METADE_FP32 contexts only");
   TRY(run_generations(c, 1, mde::TraceArgs{u, fu, desc}));
   return finalize(c);
 }
@@ -757,10 +761,18 @@ metade_status metade_get_best(metade_ctx *c, double *y) {
 }
 
 namespace {
-constexpr uint32_t STATE_MAGIC = 0x3145444Du;  // "MDE1"
+constexpr uint32_t STATE_MAGIC = 0x3245444Du;  // "MDE2"
 struct StateHeader {
-  uint32_t magic, n_runs, gen, outer_gen, outer_ready, pad;
+  uint32_t magic, n_runs, gen, outer_gen, outer_ready, n_cs;
   uint64_t pop_floats, fit_n, bx_n;
+};
+// The decoded theta of a run: the only part of the run table a checkpoint
+// carries.  Sizes, offsets and the kernel choice always come from the context
+// the blob is restored into (they depend on its precision), so a blob taken
+// from a context of another precision restores safely.
+struct RunTheta {
+  float F, CR;
+  int32_t bl, br, dn, cs;
 };
 }  // namespace
 
@@ -768,14 +780,19 @@ metade_status metade_get_state(metade_ctx *c, void *blob, size_t *bytes) {
   if (!c || !bytes) return fail(c, METADE_EINVAL, "ctx and bytes are required");
   const size_t n = c->n_runs;
   const size_t need = sizeof(StateHeader) + c->pop_floats * 4 + c->fit_n * 4 + n * 6 * 4 +
-                      n * sizeof(RunDev) + n * 8 + c->bx_n * 4 + n * 6 * 4 * 3 + n * 8 * 2 +
+                      n * sizeof(RunTheta) + n * 8 + c->bx_n * 4 + n * 6 * 4 * 3 + n * 8 * 2 +
                       c->bx_n * 4;
   if (!blob) { *bytes = need; return METADE_OK; }
   if (*bytes < need) return fail(c, METADE_EINVAL, "state buffer too small");
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   unsigned char *p = (unsigned char *)blob;
-  StateHeader h{STATE_MAGIC, c->n_runs, c->gen, c->outer_gen, c->outer_ready ? 1u : 0u, 0,
+  StateHeader h{STATE_MAGIC, c->n_runs, c->gen, c->outer_gen, c->outer_ready ? 1u : 0u, c->n_cs,
                 c->pop_floats, c->fit_n, c->bx_n};
+  std::vector<RunDev> runs(n);
+  HIP_TRY(c, hipMemcpy(runs.data(), c->runs_d, n * sizeof(RunDev), hipMemcpyDeviceToHost));
+  std::vector<RunTheta> th(n);
+  for (size_t r = 0; r < n; ++r)
+    th[r] = RunTheta{runs[r].F, runs[r].CR, runs[r].bl, runs[r].br, runs[r].dn, runs[r].cs};
   std::memcpy(p, &h, sizeof(h));
   p += sizeof(h);
   auto d2h = [&](const void *src, size_t nb) -> hipError_t {
@@ -786,7 +803,8 @@ metade_status metade_get_state(metade_ctx *c, void *blob, size_t *bytes) {
   HIP_TRY(c, d2h(c->pop, c->pop_floats * 4));
   HIP_TRY(c, d2h(c->fit, c->fit_n * 4));
   HIP_TRY(c, d2h(c->theta_d, n * 6 * 4));
-  HIP_TRY(c, d2h(c->runs_d, n * sizeof(RunDev)));
+  std::memcpy(p, th.data(), n * sizeof(RunTheta));
+  p += n * sizeof(RunTheta);
   HIP_TRY(c, d2h(c->best_y, n * 8));
   HIP_TRY(c, d2h(c->best_x, c->bx_n * 4));
   HIP_TRY(c, d2h(c->Xo, n * 6 * 4));
@@ -808,18 +826,28 @@ metade_status metade_set_state(metade_ctx *c, const void *blob, size_t bytes) {
   StateHeader h;
   std::memcpy(&h, p, sizeof(h));
   if (h.magic != STATE_MAGIC || h.n_runs != c->n_runs || h.pop_floats != c->pop_floats ||
-      h.fit_n != c->fit_n || h.bx_n != c->bx_n)
+      h.fit_n != c->fit_n || h.bx_n != c->bx_n || h.n_cs != c->n_cs)
     return fail(c, METADE_EINVAL, "state blob does not belong to this configuration");
   p += sizeof(h);
   const size_t n = c->n_runs;
-  // run layout fields must agree; only the decoded theta is taken from the blob
-  std::vector<RunDev> runs(n);
-  std::memcpy(runs.data(), p + c->pop_floats * 4 + c->fit_n * 4 + n * 6 * 4, n * sizeof(RunDev));
+  // only the decoded theta comes from the blob; the run layout (offsets, the
+  // kernel choice and the trial-row area, which depend on the precision) is
+  // this context's own
+  std::vector<RunTheta> th(n);
+  std::memcpy(th.data(), p + c->pop_floats * 4 + c->fit_n * 4 + n * 6 * 4, n * sizeof(RunTheta));
+  std::vector<RunDev> runs = c->runs_h;
   for (size_t r = 0; r < n; ++r) {
-    const RunDev &a = runs[r], &b = c->runs_h[r];
-    if (a.N != b.N || a.D != b.D || a.pop_off != b.pop_off || a.fit_off != b.fit_off ||
-        a.stream != b.stream || a.prob != b.prob)
-      return fail(c, METADE_EINVAL, "state blob run table differs from this configuration");
+    const RunTheta &t = th[r];
+    const bool cat_ok = t.bl >= 1 && t.bl <= 4 && t.br >= 1 && t.br <= 4 && t.dn >= 1 &&
+                        t.dn <= 4 && t.cs >= 1 && t.cs <= (int32_t)c->n_cs;
+    if (!cat_ok || !(t.F >= 0.0f && t.F <= 1.0f) || !(t.CR >= 0.0f && t.CR <= 1.0f))
+      return fail(c, METADE_EINVAL, "state blob holds a theta outside the decoded domain");
+    runs[r].F = t.F;
+    runs[r].CR = t.CR;
+    runs[r].bl = t.bl;
+    runs[r].br = t.br;
+    runs[r].dn = t.dn;
+    runs[r].cs = t.cs;
   }
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   auto h2d = [&](void *dst, size_t nb) -> hipError_t {
@@ -830,7 +858,8 @@ metade_status metade_set_state(metade_ctx *c, const void *blob, size_t bytes) {
   HIP_TRY(c, h2d(c->pop, c->pop_floats * 4));
   HIP_TRY(c, h2d(c->fit, c->fit_n * 4));
   HIP_TRY(c, h2d(c->theta_d, n * 6 * 4));
-  HIP_TRY(c, h2d(c->runs_d, n * sizeof(RunDev)));
+  HIP_TRY(c, hipMemcpy(c->runs_d, runs.data(), n * sizeof(RunDev), hipMemcpyHostToDevice));
+  p += n * sizeof(RunTheta);
   HIP_TRY(c, h2d(c->best_y, n * 8));
   HIP_TRY(c, h2d(c->best_x, c->bx_n * 4));
   HIP_TRY(c, h2d(c->Xo, n * 6 * 4));
@@ -880,6 +909,25 @@ metade_status metade_get_counters(metade_ctx *c, uint64_t *trials, uint64_t *ref
     unsigned long long r = 0;
     HIP_TRY(c, hipMemcpy(&r, c->counters_d, sizeof(r), hipMemcpyDeviceToHost));
     *refined = r;
+  }
+  return METADE_OK;
+}
+
+metade_status metade_get_bound_check(metade_ctx *c, uint64_t *checked, uint64_t *outside,
+                                     uint64_t *screened, uint64_t *screen_wrong,
+                                     double *max_ratio) {
+  if (!c) return fail(nullptr, METADE_EINVAL, "ctx is NULL");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  unsigned long long v[N_COUNTERS];
+  HIP_TRY(c, hipMemcpy(v, c->counters_d, sizeof(v), hipMemcpyDeviceToHost));
+  if (checked) *checked = v[1];
+  if (outside) *outside = v[2];
+  if (screened) *screened = v[3];
+  if (screen_wrong) *screen_wrong = v[4];
+  if (max_ratio) {
+    double r;
+    std::memcpy(&r, &v[5], sizeof(r));
+    *max_ratio = r;
   }
   return METADE_OK;
 }

@@ -280,6 +280,16 @@ __device__ __forceinline__ float combine(const ProbDev &p, const float2 *Ps, con
 
 // ---------------------------------------------------------------- generation loop
 
+// Check of the bf16 screen in traced generations (every trial re-evaluated):
+// trials checked, bf16 values farther than their bound from the plain value,
+// trials the screen alone would have rejected, of those the ones the plain
+// value accepts (a wrong decision the bound should have prevented), and the
+// largest |f_hat - f| / bound seen.
+struct BoundCheck {
+  unsigned long long checked, outside, screened, screen_wrong;
+  double max_ratio;
+};
+
 template <bool BF16, bool TRACE>
 __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run,
                                           const ProbDev &p, const unsigned char *__restrict__ tab,
@@ -389,6 +399,7 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
   if (producer)
     produce_desc_direct(ptid, MF_THREADS - MF_CONSUMERS, run, N, D, kp, g0, k0, k1, msk, dsc);
   unsigned long long refined = 0;
+  BoundCheck chk{0, 0, 0, 0, 0.0};
 
   for (uint32_t gg = 0; gg < n_gens; ++gg) {
     const uint32_t g = g0 + gg;
@@ -531,8 +542,9 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
     if (producer) produce_masks(ptid, MF_THREADS - MF_CONSUMERS, run, N, Q, g + 1, k0, k1, msk);
     __syncthreads();
     // S4: plain mode decides and commits; bf16 mode selects the candidates
-    bool cand = false;
+    bool cand = false, screen = false;
     float fh = 0.0f;
+    double bnd = 0.0;
     if (dec) {
       fh = combine(p, Ps, zf, zl, NCT, D, N, tid);
       if (!BF16) {
@@ -549,10 +561,12 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
           tr.desc[(size_t)(run.fit_off + tid) * 16 + 15] = a ? 1 : 0;
         }
       } else {
-        double bnd = 0.0;
         for (uint32_t c2 = 0; c2 < NCT; ++c2) bnd += (double)Pb[c2 * N + tid];
         bnd += 9.5367e-7 * (double)fabsf(fh);
-        cand = (fh == fh) && !((double)fh - bnd > (double)fx);
+        screen = (fh == fh) && !((double)fh - bnd > (double)fx);
+        // traced generations re-evaluate every trial, so that each bf16 value
+        // can be checked against its bound (the decisions are unchanged)
+        cand = TRACE ? true : screen;
       }
     }
     if (BF16) {
@@ -602,12 +616,29 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
       if (!producer && tid < total) {
         const uint32_t t = cl[tid];
         const float f = combine(p, Ps, zf, zl, NCT, D, N, tid);
-        if (accept_trial(f, fit_s[t])) {
+        const bool a = accept_trial(f, fit_s[t]);
+        if (a) {
           const float *trow = Tg + (size_t)t * Dk;
           for (uint32_t q = 0; q < Q; ++q)
             st4(pop_s, t * Dp + 4 * q, *reinterpret_cast<const float4 *>(trow + 4 * q));
           fit_s[t] = f;
           key_s[t] = mkkey(f, t);
+        }
+        if (TRACE) {
+          // every trial is a candidate here and the list is in trial order,
+          // so t == tid and fh, bnd, screen of this lane belong to trial t
+          tr.fu[run.fit_off + t] = f;
+          tr.desc[(size_t)(run.fit_off + t) * 16 + 15] = a ? 1 : 0;
+          ++chk.checked;
+          if (f == f && fh == fh) {
+            const double dev = fabs((double)fh - (double)f);
+            if (dev > bnd) ++chk.outside;
+            if (bnd > 0.0) chk.max_ratio = fmax(chk.max_ratio, dev / bnd);
+          }
+          if (!screen) {
+            ++chk.screened;
+            if (a) ++chk.screen_wrong;
+          }
         }
       }
       refined += total;
@@ -622,6 +653,15 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
   }
   for (uint32_t r = tid; r < N; r += MF_THREADS) fit[run.fit_off + r] = fit_s[r];
   if (BF16 && tid == 0) atomicAdd(counters, refined);
+  if (BF16 && TRACE) {
+    if (chk.checked) atomicAdd(counters + 1, chk.checked);
+    if (chk.outside) atomicAdd(counters + 2, chk.outside);
+    if (chk.screened) atomicAdd(counters + 3, chk.screened);
+    if (chk.screen_wrong) atomicAdd(counters + 4, chk.screen_wrong);
+    // non-negative doubles order like their bit patterns
+    if (chk.max_ratio > 0.0)
+      atomicMax(counters + 5, (unsigned long long)__double_as_longlong(chk.max_ratio));
+  }
 }
 
 template <bool BF16, bool TRACE>

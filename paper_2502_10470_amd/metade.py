@@ -74,6 +74,8 @@ _SIGS = {
     "metade_kernel_timing": [_vp, ctypes.c_int],
     "metade_kernel_time": [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64)],
     "metade_get_counters": [_vp, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)],
+    "metade_get_bound_check": [_vp] + [ctypes.POINTER(ctypes.c_uint64)] * 4
+                              + [ctypes.POINTER(ctypes.c_double)],
 }
 EXPORTED = tuple(_SIGS) + ("metade_last_error", "metade_destroy")
 
@@ -213,6 +215,14 @@ def metade_get_counters(ctx):
     r = ctypes.c_uint64()
     _check(lib().metade_get_counters(ctx, ctypes.byref(t), ctypes.byref(r)), ctx)
     return int(t.value), int(r.value)
+
+
+def metade_get_bound_check(ctx):
+    """(checked, outside, screened, screen_wrong, max_ratio) of traced bf16 generations."""
+    v = [ctypes.c_uint64() for _ in range(4)]
+    r = ctypes.c_double()
+    _check(lib().metade_get_bound_check(ctx, *[ctypes.byref(x) for x in v], ctypes.byref(r)), ctx)
+    return tuple(int(x.value) for x in v) + (float(r.value),)
 
 
 def metade_last_error(ctx=None) -> str:
@@ -360,6 +370,9 @@ class Batch:
 
     def counters(self):
         return metade_get_counters(self.ctx)
+
+    def bound_check(self):
+        return metade_get_bound_check(self.ctx)
 
     # -- host views (synchronise)
     def host_state(self):

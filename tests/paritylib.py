@@ -1,15 +1,18 @@
-"""Helpers of the GPU parity tests: run the oracle's own trajectory on the same
-seeded inputs and compare it with the library generation by generation.
+"""Helpers of the GPU parity tests: run the oracle on the same seeded inputs
+and compare it with the library generation by generation.
 
 Both sides start from the same workload description (seed, streams, instance
 data).  The library's trial vectors, index draws and crossover masks must
-match the oracle bit for bit; its float32 fitness must be within the stated
-relative tolerance of the oracle's float64 value of the same vector; its
-selection decisions must match.  Selection and ranking are decided in float32
-on both sides, but from values that carry different rounding errors, so a
-decision between two values closer than the tolerance may legitimately go
-either way.  The oracle flags such near-ties; from a flagged generation on
-that run's trajectory is no longer compared (and counted as such).
+match the oracle bit for bit, and its float32 fitness must be within the
+stated relative tolerance of the oracle's float64 value of the same vector.
+
+Selection is compared literally: the oracle's generation step is given the
+library's trial fitness (``fitness_override``) and applies the selection rule
+of Alg. 1 to exactly the values the library decided on, so every decision is
+checked, ties and near-ties included, and both sides keep identical
+populations and fitness values -- the ranking of the next generation then
+starts from identical inputs too.  The fitness values themselves are checked
+against the float64 oracle separately, trial by trial.
 """
 from __future__ import annotations
 
@@ -118,97 +121,101 @@ def compare_desc(desc_gpu, s, th):
         assert np.array_equal(desc_gpu[:, 14].astype(np.int32).view(np.float32), d["K"]), "K"
 
 
-def trajectory_parity(batch, wl, G, stats=None, check_desc=True):
-    """Compare G generations, one traced launch each.  Returns per-run
-    statistics: generations compared, first divergence, max fitness error."""
+def _check_step(prob, r, s, ug, fg, dg, pg, fitg, th, g, out):
+    """One run-generation of the library (trials ug, fitness fg, descriptors
+    dg, population pg and fitness fitg after selection) against the oracle
+    step s taken from the same state with the library's fitness."""
+    bad = np.argwhere(ug != s["u"])
+    assert bad.size == 0, f"run {r} g={g} theta={th}: trial vectors differ at {bad[:5].tolist()}"
+    try:
+        compare_desc(dg, s, th)
+    except AssertionError as exc:
+        raise AssertionError(f"run {r} g={g} theta={th}: {exc}") from None
+    e = rel_err(fg, s["fu64"])
+    miss, n_ill = fitness_misses(fg, s["fu64"], s["u"], prob)
+    assert miss.size == 0, f"run {r} g={g} kind={prob.kind}: trial fitness error {e[miss].max():.3g}"
+    out["ill"] += n_ill
+    ok = rel_err(fg, s["fu64"]) <= FIT_RTOL
+    if np.any(ok):
+        out["max_fit_rel"] = max(out["max_fit_rel"], float(e[ok].max()))
+    acc_g = dg[:, 15].astype(bool)
+    mism = np.flatnonzero(acc_g != s["accept"])
+    if mism.size:
+        i = int(mism[0])
+        raise AssertionError(f"run {r} g={g}: selection of {i} differs (gpu {acc_g[i]}, "
+                             f"oracle rule on the same values {s['accept'][i]}; "
+                             f"f(u)={fg[i]!r} f(x)={s['fx'][i]!r})")
+    assert np.array_equal(pg, s["pop"]), f"run {r} g={g}: population after selection differs"
+    assert np.array_equal(fitg, s["fit"], equal_nan=True), f"run {r} g={g}: fitness after selection differs"
+    out["trials"] += len(fg)
+    out["accepted"] += int(acc_g.sum())
+    # decisions between values closer than the tie tolerance: the hard cases,
+    # checked like every other one
+    fx = s["fx"]
+    out["near_ties"] += int(np.sum(near(fg, fx) & ~np.isnan(fg) & ~np.isnan(fx)))
+    out["exact_ties"] += int(np.sum(fg == fx))
+    out["compared"] += 1
+
+
+def trajectory_parity(batch, wl, G):
+    """Compare G generations, one traced launch each, every run and every
+    trial.  The oracle's trajectory takes the library's fitness values (after
+    checking each against the float64 oracle), so it never leaves the
+    library's: nothing is skipped."""
     runs = [OracleRun(wl, r) for r in range(wl.n_runs)]
     pop, fit = batch.host_state()
-    out = {"compared": 0, "diverged": 0, "max_fit_rel": 0.0, "trials": 0, "ill": 0}
+    out = {"compared": 0, "diverged": 0, "max_fit_rel": 0.0, "trials": 0, "ill": 0,
+           "accepted": 0, "near_ties": 0, "exact_ties": 0}
     for o in runs:
         gp = batch.run_pop(pop, o.r)
         assert np.array_equal(gp, o.pop), f"run {o.r}: initial population differs"
         fg = batch.run_fit(fit, o.r)
         bad, n_ill = fitness_misses(fg, o.f64, o.pop, o.prob)
         assert bad.size == 0, f"run {o.r}: initial fitness error {rel_err(fg, o.f64).max():.3g}"
-        if n_ill:
-            o.diverged, o.why = True, "initial fitness undetermined in float64"
-            out["diverged"] += 1
-            out["ill"] += n_ill
-            continue
-        out["max_fit_rel"] = max(out["max_fit_rel"], float(rel_err(fg, o.f64).max()))
+        out["ill"] += n_ill
+        e0 = rel_err(fg, o.f64)
+        if np.any(e0 <= FIT_RTOL):
+            out["max_fit_rel"] = max(out["max_fit_rel"], float(e0[e0 <= FIT_RTOL].max()))
+        o.fit = fg.copy()   # identical inputs from here on
     for g in range(G):
         u, fu, desc = batch.trace_step()
         pop, fit = batch.host_state()
         for o in runs:
-            if o.diverged:
-                continue
-            s = o.step()
             r = o.r
-            ug = batch.run_pop(u, r)
             fg = batch.run_fit(fu, r)
-            dg = desc[batch.fit_off[r]:batch.fit_off[r + 1]]
-            if s["amb_rank"] and not np.array_equal(ug, s["u"]):
-                o.diverged, o.why = True, f"ranking near-tie at g={g}"
-                out["diverged"] += 1
-                continue
-            if check_desc:
-                try:
-                    compare_desc(dg, s, o.th)
-                except AssertionError as exc:
-                    raise AssertionError(f"run {r} g={g} theta={o.th}: {exc}") from None
-            bad = np.argwhere(ug != s["u"])
-            assert bad.size == 0, f"run {r} g={g} theta={o.th}: trial vectors differ at {bad[:5].tolist()}"
-            e = rel_err(fg, s["fu64"])
-            miss, n_ill = fitness_misses(fg, s["fu64"], s["u"], o.prob)
-            assert miss.size == 0, f"run {r} g={g} kind={o.prob.kind}: trial fitness error {e[miss].max():.3g}"
-            if n_ill:
-                o.diverged, o.why = True, f"trial fitness undetermined in float64 at g={g}"
-                out["diverged"] += 1
-                out["ill"] += n_ill
-                continue
-            out["max_fit_rel"] = max(out["max_fit_rel"], float(e.max()))
-            out["trials"] += len(fg)
-            acc_g = dg[:, 15].astype(bool)
-            mism = acc_g != s["accept"]
-            if np.any(mism & ~s["amb_sel"]):
-                i = int(np.argwhere(mism & ~s["amb_sel"])[0, 0])
-                raise AssertionError(f"run {r} g={g}: selection of {i} differs "
-                                     f"(gpu {acc_g[i]}, oracle {s['accept'][i]})")
-            pg = batch.run_pop(pop, r)
-            if np.any(mism):
-                o.diverged, o.why = True, f"selection near-tie at g={g}"
-                out["diverged"] += 1
-                continue
-            assert np.array_equal(pg, s["pop"]), f"run {r} g={g}: population after selection differs"
-            out["compared"] += 1
+            s = pde.step(o.pop, o.fit, o.th, o.g, wl.seed, o.stream, wl.lb, wl.ub, o.prob,
+                         decide="f32", fitness_override=fg)
+            s["fx"] = o.fit
+            _check_step(o.prob, r, s, batch.run_pop(u, r), fg,
+                        desc[batch.fit_off[r]:batch.fit_off[r + 1]], batch.run_pop(pop, r),
+                        batch.run_fit(fit, r), o.th, g, out)
+            o.pop, o.fit = s["pop"], s["fit"]
+            o.g += 1
     out["runs"] = runs
     return out
 
 
-def state_parity(batch, wl, G):
-    """Compare the populations after each of G generations (one launch each)
-    with the oracle's trajectory, without tracing: for paths that do not
-    trace (the bf16 mode).  Runs stop being compared at an oracle near-tie."""
-    runs = [OracleRun(wl, r) for r in range(wl.n_runs)]
+def resync_parity(batch, wl, g, theta, runs=None):
+    """One traced generation taken from the library's own state after g
+    generations (e.g. deep inside a full-size launch): the oracle steps that
+    state with the library's fitness, and every trial, draw and decision is
+    compared.  ``theta`` holds the runs' theta rows (continuous encoding)."""
     pop, fit = batch.host_state()
-    out = {"compared": 0, "diverged": 0, "max_fit_rel": 0.0}
-    for o in runs:
-        assert np.array_equal(batch.run_pop(pop, o.r), o.pop), f"run {o.r}: initial population"
-    for g in range(G):
-        batch.inner_step(1)
-        pop, fit = batch.host_state()
-        for o in runs:
-            if o.diverged:
-                continue
-            s = o.step()
-            if s["amb_rank"] or np.any(s["amb_sel"]):
-                o.diverged = True
-                out["diverged"] += 1
-                continue
-            r = o.r
-            assert np.array_equal(batch.run_pop(pop, r), o.pop), f"run {r} g={g} theta={o.th}: population differs"
-            e = rel_err(batch.run_fit(fit, r), evaluate(o.pop, o.prob))
-            assert e.max() <= FIT_RTOL, f"run {r} g={g}: fitness error {e.max():.3g}"
-            out["max_fit_rel"] = max(out["max_fit_rel"], float(e.max()))
-            out["compared"] += 1
+    u, fu, desc = batch.trace_step()
+    pop2, fit2 = batch.host_state()
+    out = {"compared": 0, "max_fit_rel": 0.0, "trials": 0, "ill": 0, "accepted": 0,
+           "near_ties": 0, "exact_ties": 0}
+    for r in (range(wl.n_runs) if runs is None else runs):
+        r = int(r)
+        prob = wl.problems[int(wl.problem[r])]
+        th = pde.decode(np.asarray(theta[r], np.float32), wl.n_cs)
+        th = {k: (v.item() if hasattr(v, "item") else v) for k, v in th.items()}
+        fx = batch.run_fit(fit, r).copy()
+        fg = batch.run_fit(fu, r)
+        s = pde.step(batch.run_pop(pop, r).copy(), fx, th, g, wl.seed, int(wl.stream[r]), wl.lb,
+                     wl.ub, prob, decide="f32", fitness_override=fg)
+        s["fx"] = fx
+        _check_step(prob, r, s, batch.run_pop(u, r), fg,
+                    desc[batch.fit_off[r]:batch.fit_off[r + 1]], batch.run_pop(pop2, r),
+                    batch.run_fit(fit2, r), th, g, out)
     return out

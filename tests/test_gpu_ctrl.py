@@ -12,7 +12,7 @@ import pytest
 import workloads as W
 from oracle import pde
 from oracle.fitness import evaluate
-from paritylib import FIT_RTOL, rel_err, trajectory_parity
+from paritylib import FIT_RTOL, rel_err, resync_parity, trajectory_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -59,9 +59,22 @@ def test_control_full_size_two_generations():
     wl = W.workload_c5()
     b = _batch(wl)
     out = trajectory_parity(b, wl, G=2)
-    print(f"c5: compared {out['compared']} diverged {out['diverged']} "
+    print(f"c5: compared {out['compared']} near ties {out['near_ties']} "
           f"max fitness rel err {out['max_fit_rel']:.3g}")
-    assert out["compared"] >= 24
+    assert out["compared"] == 32
+
+
+def test_control_resync_after_50_generations():
+    """The full control workload after 50 generations in one untraced sequence
+    (graph replays): one traced generation from the library's own state,
+    compared with the oracle step on that state for four of the runs --
+    trials, draws and every decision."""
+    wl = W.workload_c5()
+    b = _batch(wl)
+    b.inner_step(50)
+    out = resync_parity(b, wl, 50, wl.theta, runs=[0, 5, 10, 15])
+    print(out, flush=True)
+    assert out["compared"] == 4 and out["trials"] == 4 * 256
 
 
 def test_control_best_record_float64():

@@ -1,5 +1,7 @@
 """Pins of the oracle's objective functions: closed-form optima, textbook
 reductions, rotation orientation, and the control workload's closed form."""
+import math
+
 import numpy as np
 import pytest
 
@@ -206,3 +208,95 @@ def test_c5e16_workload_has_16_rollouts():
     assert wl.G == 10 and wl.n_runs == 16
     for p in wl.problems:
         assert p.D == 5702 and p.hidden == (64, 64) and p.x0.shape == (16, 17)
+
+
+def _sparse_policy_problem(obs, H, act, steps):
+    """A hand-made plant for the closed-form pins below (not a workload instance)."""
+    rng = np.random.default_rng(11)
+    A = np.zeros((obs, obs), np.float32)
+    for k in range(obs):
+        A[k, k] = 0.9 - 0.05 * (k % 4)
+    A[1, 0] = 0.25                     # one off-diagonal coupling, x1 <- x0
+    B = np.zeros((obs, act), np.float32)
+    B[0, 0] = 1.0                      # action 0 drives x0
+    B[obs - 1, act - 1] = 0.5          # the last action drives the last state
+    x0 = rng.uniform(-1.5, 1.5, (1, obs)).astype(np.float32)
+    return W.Problem(kind="lqr_mlp", D=W.mlp_param_count(obs, (H, H), act), bias=0.0,
+                     A=A, B=B, x0=x0, steps=steps, hidden=(H, H))
+
+
+@pytest.mark.parametrize("obs,H,act,steps", [(3, 4, 2, 2), (17, 64, 6, 3), (11, 32, 3, 2)])
+def test_lqr_sparse_policy_closed_form(obs, H, act, steps):
+    """A policy whose only weights are one entry of W1, one OFF-diagonal entry of
+    W2, one entry of W3, plus nonzero biases on every layer.  The signal path is
+    x[q1] -> unit p1 of layer 1 -> unit p2 != p1 of layer 2 -> action m, so J
+    follows from scalar tanh values written out unit by unit (no matrix
+    products).  A transposed W2 (square, so a product would still run) sends
+    h1[p1] to unit p1 of layer 2 instead of p2; a dropped hidden tanh changes
+    every downstream value; a wrong flatten offset moves an entry off the path.
+    Any of these fails here."""
+    p = _sparse_policy_problem(obs, H, act, steps)
+    q1, p1, p2, m = obs - 1, 1, H - 2, act - 1          # p1 != p2: off-diagonal W2 entry
+    a, b, c = 0.8, -1.3, 0.9                            # W1[p1, q1], W2[p2, p1], W3[m, p2]
+    b1 = np.linspace(-0.2, 0.3, H).astype(np.float32)
+    b2 = np.linspace(0.15, -0.25, H).astype(np.float32)
+    b3 = np.linspace(0.1, -0.1, act).astype(np.float32)
+    w = np.zeros(p.D, np.float32)
+    o1 = 0                        # W1 [H][obs]
+    ob1 = o1 + H * obs            # b1 [H]
+    o2 = ob1 + H                  # W2 [H][H]
+    ob2 = o2 + H * H              # b2 [H]
+    o3 = ob2 + H                  # W3 [act][H]
+    ob3 = o3 + act * H            # b3 [act]
+    assert ob3 + act == p.D
+    w[o1 + p1 * obs + q1] = a
+    w[ob1:ob1 + H] = b1
+    w[o2 + p2 * H + p1] = b
+    w[ob2:ob2 + H] = b2
+    w[o3 + m * H + p2] = c
+    w[ob3:ob3 + act] = b3
+    f = lambda v: float(np.float32(v))                  # the stored float32 weights
+    x = [float(v) for v in p.x0[0]]
+    J = 0.0
+    for _ in range(steps):
+        # layer 1: only unit p1 sees the state, every unit has its bias
+        h1 = [math.tanh(f(b1[k]) + (f(a) * x[q1] if k == p1 else 0.0)) for k in range(H)]
+        # layer 2: only unit p2 sees layer 1, and only through unit p1
+        h2 = [math.tanh(f(b2[k]) + (f(b) * h1[p1] if k == p2 else 0.0)) for k in range(H)]
+        # layer 3: only action m sees layer 2, through unit p2
+        u = [math.tanh(f(b3[j]) + (f(c) * h2[p2] if j == m else 0.0)) for j in range(act)]
+        J += sum(v * v for v in x) + p.ctrl_weight * sum(v * v for v in u)
+        xn = []
+        for r in range(obs):
+            s = sum(float(p.A[r, k]) * x[k] for k in range(obs) if p.A[r, k] != 0)
+            s += sum(float(p.B[r, j]) * u[j] for j in range(act) if p.B[r, j] != 0)
+            xn.append(s)
+        x = xn
+    assert fitness.lqr_mlp(w, p) == pytest.approx(J, rel=1e-13)
+    # the same policy with W2's entry mirrored (the transposed reading) differs
+    wt = w.copy()
+    wt[o2 + p2 * H + p1] = 0.0
+    wt[o2 + p1 * H + p2] = b
+    assert abs(fitness.lqr_mlp(wt, p) - J) > 1e-6 * J
+
+
+def test_lqr_sparse_policy_hand_value():
+    """The smallest sparse policy with its cost worked out by hand (to 12 digits):
+    obs = 1, hidden 2 x 2, act = 1, one step from x0 = 1 with A = 0.5, B = 1.
+    W1 = [[0], [1]], b1 = 0; W2 = [[0, 1], [0, 0]] (row 0 reads unit 1), b2 = 0;
+    W3 = [[1, 0]], b3 = 0: u = tanh(tanh(tanh(1))), with tanh(1) = 0.761594155956,
+    tanh(0.761594155956) = 0.642014992012, tanh(0.642014992012) = 0.566269975961;
+    J = x0^2 + 0.01 u^2 = 1.003206616857."""
+    p = W.Problem(kind="lqr_mlp", D=W.mlp_param_count(1, (2, 2), 1), bias=0.0,
+                  A=np.array([[0.5]], np.float32), B=np.array([[1.0]], np.float32),
+                  x0=np.array([[1.0]], np.float32), steps=1, hidden=(2, 2))
+    w = np.zeros(p.D, np.float32)
+    w[1] = 1.0            # W1[1, 0]
+    w[4 + 1] = 1.0        # W2[0, 1]  (W2 starts after W1 (2) and b1 (2))
+    w[4 + 4 + 2] = 1.0    # W3[0, 0]  (after W2 (4) and b2 (2))
+    assert fitness.lqr_mlp(w, p) == pytest.approx(1.003206616857, abs=1e-11)
+    w2 = np.zeros(p.D, np.float32)
+    w2[1] = 1.0
+    w2[4 + 2] = 1.0       # W2[1, 0]: the transposed entry leaves unit 0 of layer 2 dark
+    w2[4 + 4 + 2] = 1.0
+    assert fitness.lqr_mlp(w2, p) == pytest.approx(1.0, abs=1e-12)

@@ -319,3 +319,29 @@ def test_tiny_population_brute_force():
                 better = np.float32(s["fu64"][i]) <= fit[i]
                 assert s["accept"][i] == better
             pop, fit = s["pop"], s["fit"]
+
+
+def test_fitness_override_drives_selection():
+    """step(..., fitness_override=fu) applies Alg. 1's selection rule to the given
+    values: the trials and draws do not change, ties go to the trial, a NaN trial
+    is never taken, and the float64 fitness is still returned for comparison."""
+    p = W.make_problem("rastrigin", 6, 5, 0)
+    N, D = 12, 6
+    pop = pde.init_population(N, D, 5, 0, -100.0, 100.0)
+    fit = evaluate(pop, p).astype(np.float32)
+    th = pde.decode(np.array([0.5, 0.9, 1.5, 1.5, 1.5, 1.5], np.float32), 2)
+    ref = pde.step(pop, fit, th, 0, 5, 0, -100.0, 100.0, p)
+    same = pde.step(pop, fit, th, 0, 5, 0, -100.0, 100.0, p, fitness_override=ref["fu"])
+    assert np.array_equal(same["u"], ref["u"]) and np.array_equal(same["accept"], ref["accept"])
+    fo = fit.copy()                    # every trial ties its target: all taken
+    fo[3] = np.nextafter(fit[3], np.float32(np.inf))   # one just above: kept out
+    fo[5] = np.nan                     # a NaN trial is never taken
+    s = pde.step(pop, fit, th, 0, 5, 0, -100.0, 100.0, p, fitness_override=fo)
+    want = np.ones(N, bool)
+    want[3] = want[5] = False
+    assert np.array_equal(s["accept"], want)
+    assert np.array_equal(s["u"], ref["u"])
+    assert np.array_equal(s["fu64"], ref["fu64"])
+    assert np.array_equal(s["pop"][want], ref["u"][want])
+    assert np.array_equal(s["pop"][~want], pop[~want])
+    assert np.array_equal(s["fit"][want], fo[want]) and np.array_equal(s["fit"][~want], fit[~want])
