@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -17,9 +18,22 @@ using mde::LaunchArgs;
 using mde::ProbDev;
 using mde::RunDev;
 
+// Workspace of metade_inner_step_static: the matrix-core kernel's trial rows
+// (and the bf16 mode's splits) of every run, at the run offsets the context
+// uses for its own trial buffer.  One copy per GPU, held until the process
+// ends.  In host code this name is only a stand-in for the symbol: kernels
+// get the per-device address that hipGetSymbolAddress returns at init.
+static __device__ __align__(256) float scratch[METADE_STATIC_SCRATCH_BYTES / sizeof(float)];
+
 namespace {
 
 thread_local std::string g_init_error = "no error";
+
+// Device address of `scratch` on each GPU, looked up once per device (with
+// that device current) by metade_init.
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_dev[MAX_DEVICES] = {};
 
 // Device counters of a context: [0] trials re-evaluated exactly by the bf16
 // mode; [1..5] the bound check of traced bf16 generations (checked, outside
@@ -54,6 +68,8 @@ struct metade_ctx {
   uint32_t *order_d = nullptr, *cacc_d = nullptr;  // control runs: top-p lists, decisions
   float *cfu_d = nullptr;                          // control runs: trial fitness
   unsigned long long *counters_d = nullptr;
+  int device = 0;
+  float *scratch_d = nullptr;   // this device's copy of the static workspace
   uint32_t gen = 0;
   // control runs: device copy of the generation counter, and the generation
   // loop captured as HIP graphs (one per sequence length, replayed on stream)
@@ -487,6 +503,24 @@ metade_status metade_init(const metade_config *cfg, metade_ctx **out) {
     return st;
   };
   metade_status st;
+  {
+    // the static workspace's address on this device (the current one)
+    hipError_t e0 = hipGetDevice(&c->device);
+    if (e0 == hipSuccess && (c->device < 0 || c->device >= MAX_DEVICES)) e0 = hipErrorInvalidDevice;
+    if (e0 == hipSuccess) {
+      std::lock_guard<std::mutex> lk(g_scratch_mu);
+      if (!g_scratch_dev[c->device]) {
+        void *ptr = nullptr;
+        e0 = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e0 == hipSuccess) g_scratch_dev[c->device] = static_cast<float *>(ptr);
+      }
+      c->scratch_d = g_scratch_dev[c->device];
+    }
+    if (e0 != hipSuccess) {
+      c->err = std::string("static workspace address: ") + hipGetErrorString(e0);
+      return bail(METADE_EDEVICE);
+    }
+  }
   std::vector<std::vector<uint32_t>> perms(c->probs_h.size());
   for (size_t k = 0; k < c->probs_h.size(); ++k) {
     const metade_problem &q = cfg->problems[k];
@@ -629,6 +663,39 @@ metade_status metade_set_theta(metade_ctx *c, const float *theta) {
 metade_status metade_inner_step(metade_ctx *c, uint32_t n) {
   if (!c) return fail(nullptr, METADE_EINVAL, "ctx is NULL");
   TRY(run_generations(c, n, mde::TraceArgs{nullptr, nullptr, nullptr}));
+  return finalize(c);
+}
+
+metade_status metade_inner_step_static(metade_ctx *c, uint32_t n) {
+  if (!c) return fail(nullptr, METADE_EINVAL, "ctx is NULL");
+  if (c->n_ctrl)
+    return fail(c, METADE_EINVAL,
+                "metade_inner_step_static takes no control runs (their pending rows exceed the "
+                "static workspace)");
+  const size_t need = c->pend_floats * sizeof(float);
+  if (need > (size_t)METADE_STATIC_SCRATCH_BYTES)
+    return fail(c, METADE_EINVAL,
+                "the runs' trial rows need " + std::to_string(need) +
+                    " bytes, more than the static workspace's " +
+                    std::to_string((size_t)METADE_STATIC_SCRATCH_BYTES));
+  int dev = -1;
+  HIP_TRY(c, hipGetDevice(&dev));
+  if (dev != c->device)
+    return fail(c, METADE_EINVAL, "call metade_inner_step_static with the context's device current");
+  if (!c->scratch_d) return fail(c, METADE_EDEVICE, "static workspace address unknown");
+  if (n) {
+    // the same kernels as metade_inner_step, with the trial rows in the
+    // static workspace; no events, no graphs, no allocation
+    LaunchArgs a = largs(c);
+    a.pending = c->scratch_d;
+    const mde::TraceArgs none{nullptr, nullptr, nullptr};
+    HIP_TRY(c, mde::launch_generations(a, c->lane_list_d, c->n_lane, c->gen, n, c->lb, c->ub, none));
+    HIP_TRY(c, mde::launch_generations_mfma(a, c->mfma_list_d, c->n_mfma,
+                                            c->precision == METADE_BF16_REFINE, c->gen, n, c->lb,
+                                            c->ub, c->counters_d, none));
+    c->gen += n;
+    for (const RunDev &r : c->runs_h) c->trials += (uint64_t)r.N * n;
+  }
   return finalize(c);
 }
 

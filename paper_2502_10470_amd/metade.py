@@ -61,6 +61,7 @@ _SIGS = {
     "metade_reset": [_vp],
     "metade_set_theta": [_vp, _vp],
     "metade_inner_step": [_vp, _u32],
+    "metade_inner_step_static": [_vp, _u32],
     "metade_trace_sizes": [_vp] + [ctypes.POINTER(ctypes.c_size_t)] * 3,
     "metade_inner_step_trace": [_vp, _vp, _vp, _vp],
     "metade_outer_reset": [_vp],
@@ -135,6 +136,10 @@ def metade_set_theta(ctx, theta: np.ndarray):
 
 def metade_inner_step(ctx, n_generations: int):
     _check(lib().metade_inner_step(ctx, int(n_generations)), ctx)
+
+
+def metade_inner_step_static(ctx, n_generations: int):
+    _check(lib().metade_inner_step_static(ctx, n_generations), ctx)
 
 
 def metade_trace_sizes(ctx):
@@ -327,6 +332,9 @@ class Batch:
 
     def inner_step(self, n):
         metade_inner_step(self.ctx, n)
+
+    def inner_step_static(self, n):
+        metade_inner_step_static(self.ctx, n)
 
     def trace_step(self):
         torch = self.torch
