@@ -48,7 +48,9 @@ KERNEL_SOURCES = {
 }
 MEASURED_TRAFFIC = {
     "4cd7f07d5b083480": (797.0 * 2.0 + 3854.0 * 1.0) * 1024,          # k_generations, C3
-    "d60c363f3e1b744e": (21362.5 * 2.0 + 7197942.1 * 1.0) * 1024,     # k_generations_mfma, C4
+    # k_generations_mfma at D = 100 (key: hash + precision); measured on an earlier
+    # version of the kernel, so it no longer matches and reports null
+    "d60c363f3e1b744e:fp32": (21362.5 * 2.0 + 7197942.1 * 1.0) * 1024,
 }
 
 PHILOX_SLOTS = 100   # 10 rounds x (2 quarter-rate 32x32->64 multiplies + 2 three-input XORs)
@@ -172,8 +174,8 @@ POOL_WORKERS = 16   # host cores of the measurement machine's share
 
 
 def _pool_run(args):
-    """One executor run of the oracle on one core (worker of the all-cores baseline)."""
-    r, G = args
+    """One executor run of the oracle on one core (worker of the all-cores baselines)."""
+    name, r, G = args
     try:
         from threadpoolctl import threadpool_limits
         threadpool_limits(limits=1)
@@ -182,37 +184,43 @@ def _pool_run(args):
     import workloads as W
     from oracle import metade as ometa
     from oracle import pde
-    wl = W.workload_c3()
-    X, y = ometa.outer_init(wl.outer["P"], wl.seed, int(wl.stream[0]), wl.n_cs)
-    U, _ = ometa.outer_trials(X, y, 0, wl.seed, int(wl.stream[0]), wl.n_cs)
-    th = pde.decode(U, wl.n_cs)
+    if name == "c3":
+        wl = W.workload_c3()
+        X, y = ometa.outer_init(wl.outer["P"], wl.seed, int(wl.stream[0]), wl.n_cs)
+        theta, _ = ometa.outer_trials(X, y, 0, wl.seed, int(wl.stream[0]), wl.n_cs)
+    else:
+        wl = W.workload_c4()
+        theta = wl.theta
+    th = pde.decode(theta, wl.n_cs)
     prob = wl.problems[int(wl.problem[r])]
     t = {k: v[r] for k, v in th.items()}
     pde.run_executor(int(wl.N[r]), prob.D, t, G, wl.seed, int(wl.stream[r]), wl.lb, wl.ub, prob)
     return int(wl.N[r]) * G
 
 
-def cpu_baseline_pool_child(G=2000):
-    """All-cores oracle figure: every executor run of the default workload's first
-    evolver generation (its theta, G generations each) on a pool of one-thread
-    worker processes.  Runs in a process of its own that never touches the GPU;
-    prints one JSON object."""
+def cpu_baseline_pool_child(G3=2000, G4=30):
+    """All-cores oracle figures: every executor run of the default workload's first
+    evolver generation (its theta, G3 generations each) and every run of the D = 100
+    workload (G4 generations each), on a pool of one-thread worker processes.  Runs in
+    a process of its own that never touches the GPU; prints one JSON object."""
     import multiprocessing as mp
     import workloads as W
-    wl = W.workload_c3()
     workers = min(POOL_WORKERS, os.cpu_count() or 1)
-    t0 = time.perf_counter()
+    res = {}
     with mp.get_context("fork").Pool(workers) as pool:
-        evals = sum(pool.map(_pool_run, [(r, G) for r in range(wl.n_runs)], chunksize=1))
-    dt = time.perf_counter() - t0
-    print(json.dumps({"value": evals / dt, "cores": workers,
-                      "sample": f"{wl.n_runs} executor runs x {G} generations, {dt:.1f} s wall "
-                                f"on {workers} worker processes"}), flush=True)
+        for name, wl, G in (("c3", W.workload_c3(), G3), ("c4", W.workload_c4(), G4)):
+            t0 = time.perf_counter()
+            evals = sum(pool.map(_pool_run, [(name, r, G) for r in range(wl.n_runs)], chunksize=1))
+            dt = time.perf_counter() - t0
+            res[name] = {"value": evals / dt, "cores": workers,
+                         "sample": f"{wl.n_runs} executor runs x {G} generations, {dt:.1f} s wall "
+                                   f"on {workers} worker processes"}
+    print(json.dumps(res), flush=True)
 
 
 def cpu_baseline_all_cores():
-    """Start the all-cores baseline in a fresh interpreter (before this process
-    starts the GPU runtime) and return its result, or None."""
+    """Start the all-cores baselines in a fresh interpreter (before this process
+    starts the GPU runtime) and return {"c3": ..., "c4": ...}, or None."""
     import subprocess
     code = "import bench; bench.cpu_baseline_pool_child()"
     try:
@@ -223,21 +231,45 @@ def cpu_baseline_all_cores():
         return None
 
 
+def cpu_baseline_c4(wl, budget_s=10.0, G=40):
+    """The oracle (untuned) on a bounded sample of the D = 100 workload, one core."""
+    try:
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(limits=1)
+    except Exception:  # pragma: no cover
+        limiter = None
+    from oracle import pde
+    th = pde.decode(wl.theta, wl.n_cs)
+    evals = runs = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s and runs < wl.n_runs:
+        r = runs
+        prob = wl.problems[int(wl.problem[r])]
+        t = {k: v[r] for k, v in th.items()}
+        pde.run_executor(int(wl.N[r]), prob.D, t, G, wl.seed, int(wl.stream[r]), wl.lb, wl.ub,
+                         prob)
+        evals += int(wl.N[r]) * G
+        runs += 1
+    dt = time.perf_counter() - t0
+    if limiter is not None and hasattr(limiter, "unregister"):
+        limiter.unregister()
+    return {"value": evals / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"{runs} executor runs of the workload (N=256, D=100, elliptic and "
+                      f"Rastrigin), {G} generations each, {dt:.1f} s on one host core"}
+
+
 MFMA_F64_PEAK = 78.6e12
 MFMA_BF16_PEAK = 2.5e15
 
 
-def bench_batch(args):
+def measure_batch(wl, name, precision, steps, warmup):
     """Independent executor runs (no evolver): one step = initialisation and
     first evaluation of every run, then all generations in one launch, then
-    the float64 best record."""
+    the float64 best record.  Returns the bench line's fields."""
     import torch
-    import workloads as W
     from paper_2502_10470_amd import Batch, metade as M
 
-    wl = {"c4": W.workload_c4, "c2": W.workload_c2, "c5": W.workload_c5,
-          "t7": W.workload_t7, "c5e16": W.workload_c5e16}[args.workload]()
-    prec = M.BF16_REFINE if args.precision == "bf16" else M.FP32
+    prec = M.BF16_REFINE if precision == "bf16" else M.FP32
     b = Batch(wl, precision=prec)
     evals = wl.evals_per_pass()
 
@@ -245,24 +277,25 @@ def bench_batch(args):
         b.reset()
         b.inner_step(wl.G)
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
     t_before, r_before = b.counters()
     b.kernel_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     k_ms, k_launches = b.kernel_time()
     b.kernel_timing(False)
     t_after, r_after = b.counters()
+    b.close()
     dt = t1 - t0
     avg_ms = k_ms / max(k_launches, 1)
     F, CR, bl, br, dn, cs = decode(wl.theta, wl.n_cs)
-    ctrl = args.workload in ("c5", "t7", "c5e16")
+    ctrl = name in ("c5", "t7", "c5e16")
     if ctrl:
         slots = sum(int(wl.N[r]) * wl.G * ctrl_slots_per_trial(wl.problems[int(wl.problem[r])],
                     bl[r], br[r], dn[r], cs[r], CR[r]) for r in range(wl.n_runs))
@@ -275,20 +308,20 @@ def bench_batch(args):
     refine_rate = (r_after - r_before) / max(t_after - t_before, 1)
     at = {"c4": "D=100", "c2": "D in {10,20}", "c5": "D=5702 (control)",
           "t7": "D in {1539,1410,1506} (control, Table VII policies)",
-          "c5e16": "D=5702 (control, 16 rollouts per policy)"}[args.workload]
+          "c5e16": "D=5702 (control, 16 rollouts per policy)"}[name]
     ck = "k_ctrl_eval (timed with k_ctrl_rank, k_ctrl_trials, k_ctrl_commit)"
     kern = {"c4": "k_generations_mfma", "c2": "k_generations", "c5": ck, "t7": ck,
             "c5e16": "k_ctrl_eval_mx (timed with k_ctrl_rank, k_ctrl_trials, k_ctrl_commit)"
-            }[args.workload]
+            }[name]
     line = {
         "metric": f"inner-DE individual-evals/sec (runs x N x gens / s) at {at}",
-        "value": evals * args.steps / dt, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": 1000.0 * dt / args.steps, "higher_is_better": True,
+        "value": evals * steps / dt, "unit": "evals/s", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": 1000.0 * dt / steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64" if ctrl else ("bf16+f64" if prec == M.BF16_REFINE else "f32"),
         "data": "synthetic",
         "config": {"workload": wl.name, "runs": wl.n_runs, "gens": wl.G,
-                   "evals_per_step": evals, "precision": args.precision,
+                   "evals_per_step": evals, "precision": precision,
                    "refine_rate": refine_rate if prec == M.BF16_REFINE else None},
         "roofline": {"bound": "alu", "achieved": slots / (avg_ms * 1e-3) / 1e12,
                      "peak": VALU_PEAK_SLOTS / 1e12, "unit": "Tslot/s",
@@ -298,20 +331,20 @@ def bench_batch(args):
                      "rotation_tflops": rot_flops / (avg_ms * 1e-3) / 1e12,
                      "occupied_cu_frac": (1.0 if ctrl else min(wl.n_runs, 256) / 256.0)},
     }
-    if args.workload == "c4":
+    if name == "c4":
         # the D=100 kernel is bound by the rotation on the matrix cores: algorithmic
         # flops 2 N D^2 per trial (the bf16 mode's three split products and its
         # re-evaluations are not counted), against the peak of the dtype it runs in
         peak = MFMA_BF16_PEAK if prec == M.BF16_REFINE else MFMA_F64_PEAK
         ach = rot_flops / (avg_ms * 1e-3)
+        traffic = MEASURED_TRAFFIC.get(kernel_source_hash(kern) + ":" + precision)
         line["roofline"] = {"bound": "mfma", "achieved": ach / 1e12, "peak": peak / 1e12,
-                            "unit": "TFLOP/s", "frac": ach / peak,
-                            "traffic": (MEASURED_TRAFFIC.get(kernel_source_hash(kern))
-                                        if prec == M.FP32 else None),
+                            "unit": "TFLOP/s", "frac": ach / peak, "traffic": traffic,
                             "kernel": kern, "avg_launch_ms": avg_ms, "launches": k_launches,
                             "alu_frac": slots / (avg_ms * 1e-3) / VALU_PEAK_SLOTS,
-                            "occupied_cu_frac": min(wl.n_runs, 256) / 256.0}
-    if args.workload == "c5e16":
+                            "occupied_cu_frac": min(wl.n_runs, 256) / 256.0,
+                            "frac_of_occupied_cus": ach / peak / (min(wl.n_runs, 256) / 256.0)}
+    if name == "c5e16":
         # 16 rollouts per policy: the layers and the plant are float64 matrix-core
         # products; algorithmic flops are two per multiply-add of the rollouts
         # (padding of the tiles not counted), against the float64 matrix peak
@@ -323,7 +356,38 @@ def bench_batch(args):
                             "kernel": kern, "avg_launch_ms": avg_ms, "launches": k_launches,
                             "alu_frac": slots / (avg_ms * 1e-3) / VALU_PEAK_SLOTS,
                             "occupied_cu_frac": 1.0}
+    return line
+
+
+def bench_batch(args):
+    import workloads as W
+    wl = {"c4": W.workload_c4, "c2": W.workload_c2, "c5": W.workload_c5,
+          "t7": W.workload_t7, "c5e16": W.workload_c5e16}[args.workload]()
+    line = measure_batch(wl, args.workload, args.precision, args.steps, args.warmup)
     print(json.dumps(line), flush=True)
+
+
+def d100_object(steps, warmup, pool=None, cpu=True):
+    """The D = 100 half of the metric (128 runs x N = 256, 500 generations, elliptic
+    and Rastrigin): the plain path and the bf16 + exact-refinement path, each with
+    its roofline, plus the oracle timed on the host cores."""
+    import workloads as W
+    wl = W.workload_c4()
+    out = {"workload": ("D=100: 128 executor runs x N=256, 500 generations, shifted-rotated "
+                        "elliptic (cond 1e6) and Rastrigin, dense 100x100 rotations"),
+           "evals_per_step": wl.evals_per_pass()}
+    for prec in ("fp32", "bf16"):
+        ln = measure_batch(wl, "c4", prec, steps, warmup)
+        out[prec] = {"value": ln["value"], "unit": "evals/s", "ms_per_step": ln["ms_per_step"],
+                     "dtype": ln["dtype"], "refine_rate": ln["config"]["refine_rate"],
+                     "roofline": ln["roofline"]}
+    out["bf16_speedup"] = out["bf16"]["value"] / out["fp32"]["value"]
+    if cpu:
+        cb = cpu_baseline_c4(wl)
+        if pool and "c4" in pool:
+            cb["all_cores"] = pool["c4"]
+        out["cpu_baseline"] = cb
+    return out
 
 
 def bench_c3_repetitions(args, reps=4):
@@ -412,6 +476,8 @@ def main():
                     help="fitness contraction: plain (float64-accumulated) or bf16 matrix cores "
                          "with plain re-evaluation of near ties")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-d100", action="store_true",
+                    help="default workload only: leave out the D=100 object")
     ap.add_argument("--budget-seconds", type=float, default=0.0,
                     help="c3 / paper only: equal-wall-clock mode, report the function "
                          "evaluations done within this many seconds")
@@ -513,8 +579,13 @@ def main():
     }
     if not args.no_cpu_baseline and args.workload == "c3":
         line["cpu_baseline"] = cpu_baseline(wl)
-        if getattr(args, "pool_baseline", None):
-            line["cpu_baseline"]["all_cores"] = args.pool_baseline
+        pool = getattr(args, "pool_baseline", None)
+        if pool and "c3" in pool:
+            line["cpu_baseline"]["all_cores"] = pool["c3"]
+    if args.workload == "c3" and not args.no_d100:
+        line["d100"] = d100_object(max(2, min(args.steps, 5)), 1,
+                                   pool=getattr(args, "pool_baseline", None),
+                                   cpu=not args.no_cpu_baseline)
     print(json.dumps(line), flush=True)
 
 

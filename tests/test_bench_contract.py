@@ -43,3 +43,15 @@ def test_default_line_fields():
     assert cb["kind"] == "oracle" and cb["cores"] >= 1 and cb["value"] > 0 and cb["sample"]
     ac = cb["all_cores"]   # the oracle on a pool of one-thread worker processes
     assert ac["cores"] >= 1 and ac["value"] > 0 and ac["sample"]
+    d = d["d100"]   # the D = 100 half of the metric, both precisions, with its oracle baseline
+    assert d["evals_per_step"] == 128 * 256 * 500
+    for prec in ("fp32", "bf16"):
+        v = d[prec]
+        assert v["value"] > 0 and v["ms_per_step"] > 0
+        rf = v["roofline"]
+        assert rf["bound"] == "mfma" and 0 < rf["frac"] < 1
+        assert abs(rf["frac"] - rf["achieved"] / rf["peak"]) < 1e-9
+    assert d["bf16"]["refine_rate"] is not None and 0 <= d["bf16"]["refine_rate"] <= 1
+    cb = d["cpu_baseline"]
+    assert cb["kind"] == "oracle" and cb["cores"] == 1 and cb["value"] > 0 and cb["sample"]
+    assert cb["all_cores"]["cores"] >= 1 and cb["all_cores"]["value"] > 0
