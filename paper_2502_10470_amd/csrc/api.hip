@@ -999,6 +999,16 @@ metade_status metade_get_bound_check(metade_ctx *c, uint64_t *checked, uint64_t 
   return METADE_OK;
 }
 
+#ifdef MDE_STAGE_CLOCKS
+// Diagnostic builds only: per-(block, wave, stage) cycle totals of the last
+// launch of the lane kernel (which = 0) or the matrix-core kernel (which = 1).
+int metade_debug_stage_clocks(int which, void *dst, size_t bytes) {
+  const hipError_t e = which ? mde::read_stage_clocks_mfma(dst, bytes)
+                             : mde::read_stage_clocks(dst, bytes);
+  return e == hipSuccess ? 0 : -1;
+}
+#endif
+
 const char *metade_last_error(const metade_ctx *c) {
   return c ? c->err.c_str() : g_init_error.c_str();
 }

@@ -39,6 +39,38 @@ constexpr int CT_MAX_ACT = 8;
 constexpr int CT_MAX_N = 1024;
 constexpr float SCHWEFEL_ZSTAR = 420.96875f;
 
+// ---------------------------------------------------------------- stage clocks
+//
+// Diagnostic builds only (compiled with MDE_STAGE_CLOCKS): every wave of a
+// generation kernel adds the cycles it spends in each stage of every
+// generation to a per-(block, wave, stage) total, written once at the end of
+// the launch to a device array of the kernel's source file.  In ordinary
+// builds the hooks expand to nothing.
+#ifdef MDE_STAGE_CLOCKS
+constexpr int STAGE_MAX_BLOCKS = 256, STAGE_MAX_WAVES = 16, STAGE_N = 8;
+#define MDE_STAGE_ARRAY \
+  static __device__ unsigned long long mde_stage_clk[STAGE_MAX_BLOCKS * STAGE_MAX_WAVES * STAGE_N]
+#define MDE_STAGE_BEGIN                         \
+  unsigned long long mde_st_t = clock64();      \
+  unsigned long long mde_st_acc[STAGE_N] = {};
+#define MDE_STAGE(k)                            \
+  {                                             \
+    const unsigned long long t_ = clock64();    \
+    mde_st_acc[k] += t_ - mde_st_t;             \
+    mde_st_t = t_;                              \
+  }
+#define MDE_STAGE_END                                                                  \
+  if ((threadIdx.x & 63) == 0 && blockIdx.x < (unsigned)STAGE_MAX_BLOCKS)             \
+    for (int k_ = 0; k_ < STAGE_N; ++k_)                                               \
+      mde_stage_clk[(blockIdx.x * STAGE_MAX_WAVES + threadIdx.x / 64) * STAGE_N + k_] = \
+          mde_st_acc[k_];
+#else
+#define MDE_STAGE_ARRAY
+#define MDE_STAGE_BEGIN
+#define MDE_STAGE(k)
+#define MDE_STAGE_END
+#endif
+
 // ---------------------------------------------------------------- tables
 
 // One executor run.  Theta fields are written by the decode kernel.

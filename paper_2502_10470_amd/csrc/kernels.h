@@ -48,6 +48,10 @@ struct CtrlArgs {
   uint32_t *acc;          // [sum N] selection decisions
 };
 
+#ifdef MDE_STAGE_CLOCKS
+hipError_t read_stage_clocks(void *dst, size_t bytes);
+hipError_t read_stage_clocks_mfma(void *dst, size_t bytes);
+#endif
 hipError_t set_lds_limits();
 hipError_t launch_tables64(const float *R, const float *o, double *Rt, double *o64, uint32_t D,
                            hipStream_t s);

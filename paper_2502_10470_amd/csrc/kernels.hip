@@ -11,6 +11,8 @@
 
 namespace mde {
 
+MDE_STAGE_ARRAY;
+
 // ---------------------------------------------------------------- fitness of one row, split by output
 
 // acc[q] = sum_k R[jc+q][k] (u_k - o_k) in float64 for q < J, from the
@@ -179,81 +181,94 @@ __global__ __launch_bounds__(INIT_THREADS) void k_init(const RunDev *__restrict_
 //   draws, pbest rank, j_rand, K, exponential length from the nibbles) |
 //   S4 selection + commit by the items of S2.
 
+// Producer waves: the random draws of generation g + 1 while the consumers
+// work on generation g.  Runs the same barrier sequence as gen_consumers
+// (one before the loop, four per generation, one after it), so the two roles
+// keep separate loops and neither holds the other's registers.
+__device__ __forceinline__ void gen_producers(const Lds &lay, unsigned char *smem,
+                                              const RunDev &run, uint32_t g0, uint32_t n_gens,
+                                              uint32_t k0, uint32_t k1, uint32_t ptid) {
+  const uint32_t N = run.N, D = run.D, Q = run.Dp / 4, kp = run.kp;
+  uint8_t *msk = reinterpret_cast<uint8_t *>(smem + lay.msk);
+  uint4 *dsc = reinterpret_cast<uint4 *>(smem + lay.dsc);
+  constexpr uint32_t NP = GEN_THREADS - GEN_CONSUMERS;
+  produce_masks(ptid, NP, run, N, Q, g0, k0, k1, msk + (g0 & 1u) * N * Q);
+  __syncthreads();
+  produce_desc_direct(ptid, NP, run, N, D, kp, g0, k0, k1, msk + (g0 & 1u) * N * Q, dsc);
+  for (uint32_t gg = 0; gg < n_gens; ++gg) {
+    const uint32_t g = g0 + gg;
+    __syncthreads();   // generation g starts (consumers rank)
+    __syncthreads();   // consumers build the trials of g
+    uint8_t *mn = msk + ((g + 1) & 1u) * N * Q;
+    produce_masks(ptid, NP, run, N, Q, g + 1, k0, k1, mn);
+    // block 2 of the next generation's draws now, the rest during the
+    // fitness (N <= 256: one trial per producer lane)
+    uint4 wc_next = uint4{};
+    if (ptid < N) wc_next = philox(2, ptid, g + 1, run.stream, k0, k1);
+    __syncthreads();   // consumers evaluate g
+    produce_desc_direct<true>(ptid, NP, run, N, D, kp, g + 1, k0, k1, mn, dsc, wc_next);
+    __syncthreads();   // consumers select and commit g
+  }
+  __syncthreads();
+}
+
+// Consumer waves: ranking, trial construction, fitness, selection and commit
+// of every generation (barrier sequence as gen_producers).
 template <bool TRACE>
-__device__ __forceinline__ void gen_body(unsigned char *smem, const RunDev &run, const ProbDev &p,
-                                         const unsigned char *__restrict__ tab,
-                                         float *__restrict__ pop, float *__restrict__ fit,
-                                         uint32_t g0, uint32_t n_gens, uint32_t k0, uint32_t k1,
-                                         float lb, float ub,
-                                         const TraceArgs &tr) {
+__device__ __forceinline__ void gen_consumers(const Lds &lay, unsigned char *smem,
+                                              const RunDev &run, const ProbDev &p,
+                                              const unsigned char *__restrict__ tab,
+                                              uint32_t g0, uint32_t n_gens, float lb, float ub,
+                                              const TraceArgs &tr, uint32_t tid) {
   const uint32_t N = run.N, D = run.D, Dp = run.Dp, Q = Dp / 4, kp = run.kp, L = run.L,
                  Np = run.Np;
-  const Lds lay = lds_layout(N, Dp, L, Np, true);
   float *pop_s = reinterpret_cast<float *>(smem + lay.pop);
   uint64_t *key_s = reinterpret_cast<uint64_t *>(smem + lay.key);
   float *fit_s = reinterpret_cast<float *>(smem + lay.fit);
   float *fx_s = reinterpret_cast<float *>(smem + lay.fx);
   uint32_t *topk = reinterpret_cast<uint32_t *>(smem + lay.topk);
   double2 *Ps = reinterpret_cast<double2 *>(smem + lay.ps);
-  uint8_t *msk = reinterpret_cast<uint8_t *>(smem + lay.msk);
-  uint4 *dsc = reinterpret_cast<uint4 *>(smem + lay.dsc);
+  const uint8_t *msk = reinterpret_cast<const uint8_t *>(smem + lay.msk);
+  const uint4 *dsc = reinterpret_cast<const uint4 *>(smem + lay.dsc);
   float *T = reinterpret_cast<float *>(smem + lay.T);
   const uint32_t ts = Np;
-  const uint32_t tid = threadIdx.x;
-  const bool producer = tid >= GEN_CONSUMERS;  // whole waves
-  const uint32_t ptid = tid - GEN_CONSUMERS;
   const uint32_t l = __builtin_amdgcn_readfirstlane(tid / Np);
   const uint32_t i = tid - l * Np;
-  const bool act = !producer && l < L && i < N;
+  const bool act = l < L && i < N;
   const uint32_t j0 = l * D / L, j1 = (l + 1) * D / L;
   const int use_rand = (run.bl == RAND || run.br == RAND) ? 1 : 0;
 
-  for (uint32_t u = tid; u < N * Dp; u += GEN_THREADS) {
-    const uint32_t r = u / Dp, j = u - r * Dp;
-    pop_s[u] = j < D ? pop[run.pop_off + (size_t)r * D + j] : 0.0f;
-  }
-  for (uint32_t r = tid; r < N; r += GEN_THREADS) {
-    const float f = fit[run.fit_off + r];
-    fit_s[r] = f;
-    key_s[r] = mkkey(f, r);
-  }
-  // draws of the first generation
-  if (producer)
-    produce_masks(ptid, GEN_THREADS - GEN_CONSUMERS, run, N, Q, g0, k0, k1, msk + (g0 & 1u) * N * Q);
-  __syncthreads();
-  if (producer)
-    produce_desc_direct(ptid, GEN_THREADS - GEN_CONSUMERS, run, N, D, kp, g0, k0, k1,
-                        msk + (g0 & 1u) * N * Q, dsc);
-
+  __syncthreads();   // draws of the first generation are being made
+  MDE_STAGE_BEGIN
   for (uint32_t gg = 0; gg < n_gens; ++gg) {
     const uint32_t g = g0 + gg;
     __syncthreads();
+    MDE_STAGE(0)
     // S0: ranks and the top-p list (first is the best).  Four consumer lanes
     // per individual each count the keys below it in a quarter of the
     // population; lane shuffles add the four counts.
-    if (!producer) {
-      for (uint32_t base = 0; base < N; base += GEN_CONSUMERS / 4) {
-        const uint32_t ri = base + (tid >> 2), rq = tid & 3u;
-        uint32_t cnt = 0;
-        if (ri < N) {
-          const uint64_t ki = key_s[ri];
-          const uint32_t a = rq * N / 4, b = (rq + 1) * N / 4;
-          uint32_t j = a;
-          for (; j + 8 <= b; j += 8) {
-            uint64_t kv[8];
+    for (uint32_t base = 0; base < N; base += GEN_CONSUMERS / 4) {
+      const uint32_t ri = base + (tid >> 2), rq = tid & 3u;
+      uint32_t cnt = 0;
+      if (ri < N) {
+        const uint64_t ki = key_s[ri];
+        const uint32_t a = rq * N / 4, b = (rq + 1) * N / 4;
+        uint32_t j = a;
+        for (; j + 8 <= b; j += 8) {
+          uint64_t kv[8];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) kv[q] = key_s[j + q];
+          for (int q = 0; q < 8; ++q) kv[q] = key_s[j + q];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) cnt += kv[q] < ki ? 1u : 0u;
-          }
-          for (; j < b; ++j) cnt += key_s[j] < ki ? 1u : 0u;
+          for (int q = 0; q < 8; ++q) cnt += kv[q] < ki ? 1u : 0u;
         }
-        cnt += __shfl_xor(cnt, 1);
-        cnt += __shfl_xor(cnt, 2);
-        if (ri < N && rq == 0 && cnt < kp) topk[cnt] = ri;
+        for (; j < b; ++j) cnt += key_s[j] < ki ? 1u : 0u;
       }
+      cnt += __shfl_xor(cnt, 1);
+      cnt += __shfl_xor(cnt, 2);
+      if (ri < N && rq == 0 && cnt < kp) topk[cnt] = ri;
     }
     __syncthreads();
+    MDE_STAGE(1)
     // S2: mutation, crossover, clip.  Consumer lane c builds quads it = c,
     // c + 512, ... of the generation's N x Q quads (trial it / Q, genes
     // 4 (it mod Q) .. +3): every lane has at most one quad more than any
@@ -262,12 +277,12 @@ __device__ __forceinline__ void gen_body(unsigned char *smem, const RunDev &run,
     float4 keep = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     uint32_t ki = 0, kq = 0;
     float kfx = 0.0f;
-    if (!producer && tid < N * Q) {
+    if (tid < N * Q) {
       ki = tid / Q;
       kq = tid - ki * Q;
       kfx = fit_s[ki];
     }
-    if (!producer) {
+    {
       const uint8_t *mg = msk + (g & 1u) * N * Q;
       for (uint32_t it = tid; it < N * Q; it += GEN_CONSUMERS) {
         const uint32_t ti = it == tid ? ki : it / Q, q = it == tid ? kq : it - (it / Q) * Q;
@@ -306,65 +321,88 @@ __device__ __forceinline__ void gen_body(unsigned char *smem, const RunDev &run,
         if (it == tid) keep = uu;
       }
     }
-    uint4 wc_next = uint4{};
-    if (producer) {
-      produce_masks(ptid, GEN_THREADS - GEN_CONSUMERS, run, N, Q, g + 1, k0, k1,
-                    msk + ((g + 1) & 1u) * N * Q);
-      // block 2 of the next generation's draws now, the rest in S3 (N <= 256:
-      // one trial per producer lane)
-      if (ptid < N) wc_next = philox(2, ptid, g + 1, run.stream, k0, k1);
-    }
     __syncthreads();
-    // S3: this part's share of the fitness; producers draw generation g+1
+    MDE_STAGE(2)
+    // S3: this part's share of the fitness (producers draw generation g+1)
     if (act) {
       double s0, s1;
       eval_part(tab, p, D, j0, j1, T + i, ts, s0, s1);
       Ps[l * Np + i] = make_double2(s0, s1);
     }
-    if (producer)
-      produce_desc_direct<true>(ptid, GEN_THREADS - GEN_CONSUMERS, run, N, D, kp, g + 1, k0, k1,
-                                msk + ((g + 1) & 1u) * N * Q, dsc, wc_next);
     __syncthreads();
+    MDE_STAGE(3)
     // S4: greedy selection and commit, by the lanes of S2: each lane sums the
     // parts of its trial (all lanes of a trial take the same decision) and
     // writes its quad back; the quad-0 lane updates fitness and key.
-    if (!producer) {
-      for (uint32_t it = tid; it < N * Q; it += GEN_CONSUMERS) {
-        const uint32_t ti = it == tid ? ki : it / Q, q = it == tid ? kq : it - (it / Q) * Q;
-        const float fx = it == tid ? kfx : fx_s[ti];
-        double s0 = 0.0, s1 = 0.0;
-        for (uint32_t ll = 0; ll < L; ++ll) {
-          const double2 v = Ps[ll * Np + ti];
-          s0 += v.x;
-          s1 += v.y;
-        }
-        const float f = finish_f32(p, s0, s1);
-        const bool a = accept_trial(f, fx);
-        if (a) {
-          float4 x = keep;
-          if (it != tid) {
+    for (uint32_t it = tid; it < N * Q; it += GEN_CONSUMERS) {
+      const uint32_t ti = it == tid ? ki : it / Q, q = it == tid ? kq : it - (it / Q) * Q;
+      const float fx = it == tid ? kfx : fx_s[ti];
+      double s0 = 0.0, s1 = 0.0;
+      for (uint32_t ll = 0; ll < L; ++ll) {
+        const double2 v = Ps[ll * Np + ti];
+        s0 += v.x;
+        s1 += v.y;
+      }
+      const float f = finish_f32(p, s0, s1);
+      const bool a = accept_trial(f, fx);
+      if (a) {
+        float4 x = keep;
+        if (it != tid) {
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-              const uint32_t j = 4 * q + t;
-              set_comp(x, t, j < D ? T[j * ts + ti] : 0.0f);
-            }
+          for (int t = 0; t < 4; ++t) {
+            const uint32_t j = 4 * q + t;
+            set_comp(x, t, j < D ? T[j * ts + ti] : 0.0f);
           }
-          st4(pop_s, ti * Dp + 4 * q, x);
         }
-        if (q == 0) {
-          if (a) {
-            fit_s[ti] = f;
-            key_s[ti] = mkkey(f, ti);
-          }
-          if (TRACE) {
-            tr.fu[run.fit_off + ti] = f;
-            tr.desc[(size_t)(run.fit_off + ti) * 16 + 15] = a ? 1 : 0;
-          }
+        st4(pop_s, ti * Dp + 4 * q, x);
+      }
+      if (q == 0) {
+        if (a) {
+          fit_s[ti] = f;
+          key_s[ti] = mkkey(f, ti);
+        }
+        if (TRACE) {
+          tr.fu[run.fit_off + ti] = f;
+          tr.desc[(size_t)(run.fit_off + ti) * 16 + 15] = a ? 1 : 0;
         }
       }
     }
   }
   __syncthreads();
+  MDE_STAGE(0)
+  MDE_STAGE_END
+}
+
+// Persistent generation loop of one run (one workgroup): load the run into
+// LDS, run the consumer and producer roles side by side, write the run back.
+template <bool TRACE>
+__device__ __forceinline__ void gen_body(unsigned char *smem, const RunDev &run, const ProbDev &p,
+                                         const unsigned char *__restrict__ tab,
+                                         float *__restrict__ pop, float *__restrict__ fit,
+                                         uint32_t g0, uint32_t n_gens, uint32_t k0, uint32_t k1,
+                                         float lb, float ub,
+                                         const TraceArgs &tr) {
+  const uint32_t N = run.N, D = run.D, Dp = run.Dp;
+  const Lds lay = lds_layout(N, Dp, run.L, run.Np, true);
+  float *pop_s = reinterpret_cast<float *>(smem + lay.pop);
+  uint64_t *key_s = reinterpret_cast<uint64_t *>(smem + lay.key);
+  float *fit_s = reinterpret_cast<float *>(smem + lay.fit);
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t u = tid; u < N * Dp; u += GEN_THREADS) {
+    const uint32_t r = u / Dp, j = u - r * Dp;
+    pop_s[u] = j < D ? pop[run.pop_off + (size_t)r * D + j] : 0.0f;
+  }
+  for (uint32_t r = tid; r < N; r += GEN_THREADS) {
+    const float f = fit[run.fit_off + r];
+    fit_s[r] = f;
+    key_s[r] = mkkey(f, r);
+  }
+  // the role is uniform per wave (whole waves on either side of GEN_CONSUMERS)
+  const bool producer = __builtin_amdgcn_readfirstlane(tid >> 6) >= GEN_CONSUMERS / 64;
+  if (producer)
+    gen_producers(lay, smem, run, g0, n_gens, k0, k1, tid - GEN_CONSUMERS);
+  else
+    gen_consumers<TRACE>(lay, smem, run, p, tab, g0, n_gens, lb, ub, tr, tid);
   for (uint32_t u = tid; u < N * D; u += GEN_THREADS) {
     const uint32_t r = u / D, j = u - r * D;
     pop[run.pop_off + u] = pop_s[r * Dp + j];
@@ -401,6 +439,12 @@ __global__ __launch_bounds__(GEN_THREADS) void k_generations(
   }
 #undef MDE_KIND
 }
+
+#ifdef MDE_STAGE_CLOCKS
+hipError_t read_stage_clocks(void *dst, size_t bytes) {
+  return hipMemcpyFromSymbol(dst, HIP_SYMBOL(mde_stage_clk), bytes, 0, hipMemcpyDeviceToHost);
+}
+#endif
 
 // ---------------------------------------------------------------- best record in float64
 

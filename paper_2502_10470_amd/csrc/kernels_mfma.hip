@@ -27,6 +27,8 @@
 
 namespace mde {
 
+MDE_STAGE_ARRAY;
+
 typedef double d4v __attribute__((ext_vector_type(4)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
@@ -290,6 +292,40 @@ struct BoundCheck {
   double max_ratio;
 };
 
+// Producer waves: the random draws of generation g + 1 (crossover-test
+// nibbles during the rotation, packed draws after the decisions).  Runs the
+// same barrier sequence as mfma_consumers -- one before the loop, five per
+// generation (eight in the bf16 mode), one after it -- so the two roles keep
+// separate loops and neither holds the other's registers.
+template <bool BF16>
+__device__ __forceinline__ void mfma_producers(const MLds &lay, unsigned char *smem,
+                                               const RunDev &run, uint32_t g0, uint32_t n_gens,
+                                               uint32_t k0, uint32_t k1, uint32_t ptid) {
+  const uint32_t N = run.N, D = run.D, Q = run.Dp / 4, kp = run.kp;
+  uint8_t *msk = reinterpret_cast<uint8_t *>(smem + lay.msk);
+  uint4 *dsc = reinterpret_cast<uint4 *>(smem + lay.dsc);
+  constexpr uint32_t NP = MF_THREADS - MF_CONSUMERS;
+  produce_masks(ptid, NP, run, N, Q, g0, k0, k1, msk);
+  __syncthreads();
+  produce_desc_direct(ptid, NP, run, N, D, kp, g0, k0, k1, msk, dsc);
+  for (uint32_t gg = 0; gg < n_gens; ++gg) {
+    const uint32_t g = g0 + gg;
+    __syncthreads();   // generation g: consumers count ranks
+    __syncthreads();   // top-p list
+    __syncthreads();   // trial construction (reads the masks of g)
+    __syncthreads();   // rotation: the masks of g are free
+    produce_masks(ptid, NP, run, N, Q, g + 1, k0, k1, msk);
+    __syncthreads();   // decisions (plain) or screen (bf16)
+    if (BF16) {
+      __syncthreads(); // candidate counts
+      __syncthreads(); // candidate list
+      __syncthreads(); // re-evaluation
+    }
+    produce_desc_direct(ptid, NP, run, N, D, kp, g + 1, k0, k1, msk, dsc);
+  }
+  __syncthreads();
+}
+
 template <bool BF16, bool TRACE>
 __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run,
                                           const ProbDev &p, const unsigned char *__restrict__ tab,
@@ -330,26 +366,6 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
   const float *R32 = tab_ptr<float>(tab, p.r64t_off + (uint64_t)D * Dr * sizeof(double));
 
   const uint32_t tid = threadIdx.x;
-  const uint32_t lane = tid & 63;
-  const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const bool producer = tid >= MF_CONSUMERS;
-  const uint32_t ptid = tid - MF_CONSUMERS;
-  // ranking geometry: L parts of Np lanes
-  const uint32_t l = __builtin_amdgcn_readfirstlane(tid / Np);
-  const uint32_t ir = tid - l * Np;
-  const bool act_r = !producer && l < L && ir < N;
-  const uint32_t kr0 = l * N / L, kr1 = (l + 1) * N / L;
-  // decision lane of trial tid
-  const bool dec = !producer && tid < N;
-  // output tile of this consumer wave in the bf16 rotation (its bf16 parts of R
-  // stay in registers); the float64 tiles are dealt to the waves as items
-  const uint32_t ct = wave;
-  const bool has_ct = !producer && ct < NCT;
-  const uint32_t jcol = 16 * ct + (lane & 15);
-  const int use_rand = (run.bl == RAND || run.br == RAND) ? 1 : 0;
-  // trial construction: P lanes per trial, the largest power of two <= 32 with N P <= consumers
-  uint32_t P = 1;
-  while (P < 32 && N * (2 * P) <= MF_CONSUMERS) P *= 2;
 
   for (uint32_t u = tid; u < N * Dp; u += MF_THREADS) {
     const uint32_t r = u / Dp, j = u - r * Dp;
@@ -377,6 +393,29 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
         Yl[at] = (__bf16)0.0f;
       }
     }
+  // the role is uniform per wave (whole waves on either side of MF_CONSUMERS)
+  if (__builtin_amdgcn_readfirstlane(tid >> 6) >= MF_CONSUMERS / 64) {
+    mfma_producers<BF16>(lay, smem, run, g0, n_gens, k0, k1, tid - MF_CONSUMERS);
+  } else {
+  constexpr bool producer = false;
+  const uint32_t lane = tid & 63;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  // ranking geometry: L parts of Np lanes
+  const uint32_t l = __builtin_amdgcn_readfirstlane(tid / Np);
+  const uint32_t ir = tid - l * Np;
+  const bool act_r = l < L && ir < N;
+  const uint32_t kr0 = l * N / L, kr1 = (l + 1) * N / L;
+  // decision lane of trial tid
+  const bool dec = tid < N;
+  // output tile of this consumer wave in the bf16 rotation (its bf16 parts of R
+  // stay in registers); the float64 tiles are dealt to the waves as items
+  const uint32_t ct = wave;
+  const bool has_ct = ct < NCT;
+  const uint32_t jcol = 16 * ct + (lane & 15);
+  const int use_rand = (run.bl == RAND || run.br == RAND) ? 1 : 0;
+  // trial construction: P lanes per trial, the largest power of two <= 32 with N P <= consumers
+  uint32_t P = 1;
+  while (P < 32 && N * (2 * P) <= MF_CONSUMERS) P *= 2;
   // this wave's slice of R: the bf16 splits stay in registers for the launch;
   // the float64 slice is read from the table (L1/L2 resident) block by block
   bf8v bhi[KSB], blo[KSB];
@@ -394,16 +433,15 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
       }
     }
   }
-  if (producer) produce_masks(ptid, MF_THREADS - MF_CONSUMERS, run, N, Q, g0, k0, k1, msk);
-  __syncthreads();
-  if (producer)
-    produce_desc_direct(ptid, MF_THREADS - MF_CONSUMERS, run, N, D, kp, g0, k0, k1, msk, dsc);
+  __syncthreads();   // draws of the first generation are being made
   unsigned long long refined = 0;
   BoundCheck chk{0, 0, 0, 0, 0.0};
+  MDE_STAGE_BEGIN
 
   for (uint32_t gg = 0; gg < n_gens; ++gg) {
     const uint32_t g = g0 + gg;
     __syncthreads();
+    MDE_STAGE(0)
     // S0: partial ranks
     if (act_r) {
       const uint64_t ki = key_s[ir];
@@ -419,6 +457,7 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
       rk[l * Np + ir] = c;
     }
     __syncthreads();
+    MDE_STAGE(1)
     // S1: top-p list; the decision lane keeps its target's fitness
     float fx = 0.0f;
     if (dec) fx = fit_s[tid];
@@ -428,6 +467,7 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
       if (rank < kp) topk[rank] = ir;
     }
     __syncthreads();
+    MDE_STAGE(2)
     // S2: trial genes -> global trial rows.  P lanes per trial (a power of
     // two, as many as the consumers allow) take its quads in turn; in the bf16
     // mode they also write the splits of y = u - o and combine ||y||^2 by shuffles.
@@ -493,6 +533,7 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
       }
     }
     __syncthreads();
+    MDE_STAGE(3)
     // S3: rotation on the matrix cores + element terms; producers: masks of g+1
     if (BF16 && has_ct) {
       // the bf16 parts of R stay in registers: one output tile per wave
@@ -539,8 +580,8 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
         }
       }
     }
-    if (producer) produce_masks(ptid, MF_THREADS - MF_CONSUMERS, run, N, Q, g + 1, k0, k1, msk);
     __syncthreads();
+    MDE_STAGE(4)
     // S4: plain mode decides and commits; bf16 mode selects the candidates
     bool cand = false, screen = false;
     float fh = 0.0f;
@@ -574,6 +615,7 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
       const unsigned long long bal = __ballot(cand);
       if (!producer && lane == 0) cnt[wave] = (uint32_t)__popcll(bal);
       __syncthreads();
+      MDE_STAGE(5)
       uint32_t base = 0, total = 0;
       for (uint32_t w = 0; w < MF_CONSUMERS / 64; ++w) {
         const uint32_t cw = cnt[w];
@@ -585,6 +627,7 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
         cl[pos] = tid;
       }
       __syncthreads();
+      MDE_STAGE(6)
       // S5: plain re-evaluation of the candidates on compacted row tiles,
       // (output tile, row tile group) items dealt to all consumer waves
       if (!producer) {
@@ -612,6 +655,7 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
         }
       }
       __syncthreads();
+      MDE_STAGE(7)
       // S6: decisions of the candidates from their plain values, commit
       if (!producer && tid < total) {
         const uint32_t t = cl[tid];
@@ -643,15 +687,10 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
       }
       refined += total;
     }
-    if (producer)
-      produce_desc_direct(ptid, MF_THREADS - MF_CONSUMERS, run, N, D, kp, g + 1, k0, k1, msk, dsc);
   }
   __syncthreads();
-  for (uint32_t u = tid; u < N * D; u += MF_THREADS) {
-    const uint32_t r = u / D, j = u - r * D;
-    pop[run.pop_off + u] = pop_s[r * Dp + j];
-  }
-  for (uint32_t r = tid; r < N; r += MF_THREADS) fit[run.fit_off + r] = fit_s[r];
+  MDE_STAGE(0)
+  MDE_STAGE_END
   if (BF16 && tid == 0) atomicAdd(counters, refined);
   if (BF16 && TRACE) {
     if (chk.checked) atomicAdd(counters + 1, chk.checked);
@@ -662,6 +701,12 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
     if (chk.max_ratio > 0.0)
       atomicMax(counters + 5, (unsigned long long)__double_as_longlong(chk.max_ratio));
   }
+  }
+  for (uint32_t u = tid; u < N * D; u += MF_THREADS) {
+    const uint32_t r = u / D, j = u - r * D;
+    pop[run.pop_off + u] = pop_s[r * Dp + j];
+  }
+  for (uint32_t r = tid; r < N; r += MF_THREADS) fit[run.fit_off + r] = fit_s[r];
 }
 
 template <bool BF16, bool TRACE>
@@ -693,6 +738,12 @@ __global__ __launch_bounds__(MF_THREADS) void k_generations_mfma(
   }
 #undef MDE_KIND
 }
+
+#ifdef MDE_STAGE_CLOCKS
+hipError_t read_stage_clocks_mfma(void *dst, size_t bytes) {
+  return hipMemcpyFromSymbol(dst, HIP_SYMBOL(mde_stage_clk), bytes, 0, hipMemcpyDeviceToHost);
+}
+#endif
 
 hipError_t set_lds_limits_mfma() {
   const void *ks[4] = {(const void *)k_generations_mfma<false, false>,
