@@ -10,7 +10,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/metade.h"
+#include "metade.h"
 #include "device.h"
 #include "kernels.h"
 
@@ -215,10 +215,11 @@ metade_status plan_config(const metade_config *cfg, Plan &pl, std::string &msg) 
     // read-only table layout of this problem
     p.o_off = take((size_t)q.D * sizeof(float));
     p.o64_off = take((size_t)q.D * sizeof(double));
-    // transposed float64 rotation [D][rt_stride], then the row-major float32 one
-    // [D][round4(D)] (zero padded) that the matrix-core kernel reads
-    p.r64t_off = take((size_t)q.D * mde::rt_stride(q.D) * sizeof(double) +
-                      (size_t)q.D * round4(q.D) * sizeof(float));
+    // transposed float64 rotation [D][rt_stride]; the row-major float32 one
+    // zero padded to whole 16-wide tiles, and R o, that the matrix-core kernel reads
+    p.r64t_off = take((size_t)q.D * mde::rt_stride(q.D) * sizeof(double));
+    p.r32_off = take((size_t)mde::r32_stride(q.D) * mde::r32_stride(q.D) * sizeof(float));
+    p.ro64_off = take((size_t)mde::r32_stride(q.D) * sizeof(double));
     p.ew_off = take((size_t)q.D * sizeof(float));
     p.ew64_off = take((size_t)q.D * sizeof(double));
     p.ek_off = take((size_t)q.D * sizeof(uint32_t));
@@ -272,22 +273,26 @@ metade_status plan_config(const metade_config *cfg, Plan &pl, std::string &msg) 
     d.prob = cfg->problem[r];
     d.stream = cfg->stream_id[r];
     d.kp = std::max<uint32_t>(1, (N * 10 + 99) / 100);
-    // lanes per part: whole waves covering N; parts: as many as fit the block
+    // lanes per part: whole waves covering N; parts: as many as fit the
+    // consumer lanes of the kernel the run goes to
     d.Np = ((N + 63u) / 64u) * 64u;
-    d.L = std::max<uint32_t>(1, std::min<uint32_t>(8, mde::GEN_CONSUMERS / d.Np));
+    const uint32_t L_lane = std::max<uint32_t>(1, std::min<uint32_t>(8, mde::GEN_CONSUMERS / d.Np));
+    const uint32_t L_mf = std::max<uint32_t>(1, std::min<uint32_t>(8, mde::MF_CONSUMERS / d.Np));
     d.Dk = ((D + 31u) / 32u) * 32u;
     d.NCT = (D + 15u) / 16u;
     const bool rosen = pl.probs[d.prob].kind == mde::FN_ROSENBROCK;
-    const uint32_t lane_bytes = mde::lds_layout(N, d.Dp, d.L, d.Np, true).total;
-    const uint32_t mf_bytes = mde::mfma_layout(N, d.Dp, d.Dk, d.L, d.Np, d.NCT, rosen).total;
+    const uint32_t lane_bytes = mde::lds_layout(N, d.Dp, L_lane, d.Np, true).total;
+    const uint32_t mf_bytes = mde::mfma_layout(N, d.Dp, d.Dk, L_mf, d.Np, d.NCT, rosen).total;
     if (cfg->precision == METADE_FP32 && lane_bytes <= mde::LDS_BUDGET) {
       d.kern = 0;
       d.t_lds = 1;
+      d.L = L_lane;
       pl.lds_bytes = std::max(pl.lds_bytes, lane_bytes);
       pl.lane_list.push_back(r);
     } else if (mf_bytes <= mde::LDS_BUDGET) {
       d.kern = 1;
       d.t_lds = 0;
+      d.L = L_mf;
       pl.mfma_lds_bytes = std::max(pl.mfma_lds_bytes, mf_bytes);
       pl.mfma_list.push_back(r);
     } else {
@@ -615,14 +620,9 @@ metade_status metade_init(const metade_config *cfg, metade_ctx **out) {
     if (e4 == hipSuccess)
       e4 = mde::launch_tables64(q.R, q.o, reinterpret_cast<double *>(t + p.r64t_off),
                                 reinterpret_cast<double *>(t + p.o64_off), p.D, c->stream);
-    if (e4 == hipSuccess) {
-      unsigned char *r32 = t + p.r64t_off + (size_t)p.D * mde::rt_stride(p.D) * sizeof(double);
-      const size_t pitch = (size_t)round4(p.D) * sizeof(float);
-      e4 = hipMemsetAsync(r32, 0, (size_t)p.D * pitch, c->stream);
-      if (e4 == hipSuccess)
-        e4 = hipMemcpy2DAsync(r32, pitch, q.R, (size_t)p.D * sizeof(float),
-                              (size_t)p.D * sizeof(float), p.D, hipMemcpyDeviceToDevice, c->stream);
-    }
+    if (e4 == hipSuccess)
+      e4 = mde::launch_tables_mfma(q.R, q.o, reinterpret_cast<float *>(t + p.r32_off),
+                                   reinterpret_cast<double *>(t + p.ro64_off), p.D, c->stream);
     if (e4 != hipSuccess) { c->err = std::string("problem tables: ") + hipGetErrorString(e4); return bail(METADE_EDEVICE); }
   }
   hipError_t e = mde::set_lds_limits();

@@ -97,8 +97,9 @@ struct ProbDev {
   double cs_d;
   uint64_t o_off;               // float  [D]    shift
   uint64_t o64_off;             // double [D]    same in float64
-  uint64_t r64t_off;            // double [D][rt_stride] rotation transposed: (k, j) = R[j][k];
-                                //   followed by float [D][round4(D)] row-major R, zero padded
+  uint64_t r64t_off;            // double [D][rt_stride] rotation transposed: (k, j) = R[j][k]
+  uint64_t r32_off;             // float  [Rs][Rs] row-major R zero padded to Rs = r32_stride(D)
+  uint64_t ro64_off;            // double [Rs]   R o (zero past D): z = R u - R o
   uint64_t ew_off;              // float  [D]    elliptic weight of output j
   uint64_t ew64_off;            // double [D]    same in float64
   uint64_t ek_off;              // uint32 [D]    hybrid block of output j (0 Schwefel, 1 Rastrigin, 2 elliptic)
@@ -111,6 +112,9 @@ struct ProbDev {
 // Row stride of the transposed float64 rotation: D plus zero padding for the
 // widest output block (16), rounded to 4 doubles.
 __host__ __device__ inline uint32_t rt_stride(uint32_t D) { return ((D + 16u) + 3u) & ~3u; }
+// Rows and row stride of the padded float32 rotation the matrix-core kernel
+// reads: D rounded up to whole 16-wide tiles in both directions.
+__host__ __device__ inline uint32_t r32_stride(uint32_t D) { return (D + 15u) & ~15u; }
 
 template <typename T>
 __host__ __device__ __forceinline__ const T *tab_ptr(const unsigned char *tab, uint64_t off) {
@@ -219,7 +223,7 @@ constexpr uint32_t MF_THREADS = 768;
 constexpr uint32_t MF_CONSUMERS = 512;
 
 struct MLds {
-  uint32_t pop, key, fit, topk, rk, msk, dsc, ps, pb, zf, zl, oc, ek, ew, cl, cnt, ysq, total;
+  uint32_t pop, key, fit, topk, rk, msk, dsc, ps, pb, zf, zl, oc, ro, ek, ew, cl, cnt, ysq, total;
 };
 
 __host__ __device__ inline MLds mfma_layout(uint32_t N, uint32_t Dp, uint32_t Dk, uint32_t L,
@@ -238,6 +242,7 @@ __host__ __device__ inline MLds mfma_layout(uint32_t N, uint32_t Dp, uint32_t Dk
   l.zf = o;   o += rosen ? al16(NCT * N * 4) : 0u;
   l.zl = o;   o += rosen ? al16(NCT * N * 4) : 0u;
   l.oc = o;   o += al16(Dk * 4);
+  l.ro = o;   o += al16(Dk * 8);
   l.ek = o;   o += al16(Dk * 4);
   l.ew = o;   o += al16(Dk * 4);
   l.cl = o;   o += al16(N * 4);

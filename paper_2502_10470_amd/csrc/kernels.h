@@ -59,6 +59,9 @@ hipError_t launch_init(const LaunchArgs &a, double lb, double ub);
 hipError_t launch_generations(const LaunchArgs &a, const uint32_t *list, uint32_t n,
                               uint32_t g0, uint32_t n_gens, float lb, float ub, TraceArgs tr);
 hipError_t set_lds_limits_mfma();
+// padded float32 rotation [Rs][Rs] and R o in float64 for the matrix-core kernel
+hipError_t launch_tables_mfma(const float *R, const float *o, float *R32, double *ro64, uint32_t D,
+                              hipStream_t s);
 hipError_t launch_generations_mfma(const LaunchArgs &a, const uint32_t *list, uint32_t n,
                                    bool bf16, uint32_t g0, uint32_t n_gens, float lb, float ub,
                                    unsigned long long *counters, TraceArgs tr);

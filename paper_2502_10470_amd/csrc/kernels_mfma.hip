@@ -44,45 +44,45 @@ constexpr float E_COEF = 1.2207031e-4f;  // 2^-13
 
 // ---------------------------------------------------------------- rotation tiles
 
-// Plain mode.  The product is formed transposed, z^T = R y^T: the A operand
-// is the wave's 16 rows of R, the B operand 16 trial rows, so that each lane
-// ends with one trial and four of its outputs.  Any consistent assignment of
-// the physical k to (step, lane) slots gives the same product, so the k order
-// is permuted inside each block of four steps: lane l feeds steps 4b..4b+3
-// with k = 16 b + 4 (l/16) + 0..3, one contiguous float4 of its trial row.
-// Result element v is z[trial 16 rt + l%16][output 16 ct + l/16 + 4v].
-// RR row tiles at once (rows given per tile): RR independent accumulator
-// chains sharing the B loads, so that consecutive matrix-core instructions
-// do not wait on each other's results.  The plain rotation takes four row
-// tiles per item, the bf16 tiles and the bf16 mode's re-evaluation two
-// (measured best for each; more rows per item spill registers in the bf16
-// kernel).
+// Plain mode.  The product is formed transposed, z^T = R u^T: the A operand
+// is 16 rows of R, the B operand 16 trial rows, so that each lane ends with
+// one trial and four of its outputs; R o is subtracted afterwards (z = R u -
+// R o; the products of two float32 values are exact in float64, so only the
+// float64 sums round).  Any consistent assignment of the physical k to
+// (step, lane) slots gives the same product, so the k order is permuted inside
+// each block of four steps: lane l feeds steps 4b..4b+3 with k = 16 b +
+// 4 (l/16) + 0..3, one contiguous float4 of its trial row and of its row of R.
+// Result element v is (R u)[trial 16 rt + l%16][output 16 ct + l/16 + 4v].
+// The rotation is zero padded to whole tiles (row stride Rs) and the trial
+// rows are zero beyond D, so no operand needs a bounds test.  RR row tiles at
+// once (rows given per tile): RR independent accumulator chains sharing the A
+// loads, so that consecutive matrix-core instructions do not wait on each
+// other's results.  The plain rotation takes four row tiles per item, the
+// bf16 mode's re-evaluation two.  (Storing the operands in float64 to spare
+// the conversions was measured slower: the rotation waits on its loads, and
+// float64 operands double them.)
 constexpr int RT = 2;
 constexpr int RT_F64 = 4;
 
 template <int RR>
-__device__ __forceinline__ void tiles_f64(const float *__restrict__ Tg, uint32_t Dk, uint32_t D,
-                                          const float *oc, const bool (&row_ok)[RR],
+__device__ __forceinline__ void tiles_f64(const float *__restrict__ Tg, uint32_t Dk,
+                                          const bool (&row_ok)[RR],
                                           const uint32_t (&row_trial)[RR],
-                                          const float *__restrict__ R32, uint32_t D4, uint32_t j,
+                                          const float *__restrict__ R32, uint32_t Rs, uint32_t j,
                                           uint32_t lane, d4v (&acc)[RR]) {
   const uint32_t kq = lane >> 4;
-  const uint32_t nb = (D + 15) / 16;  // blocks of 16 k (four steps of 4)
-  const bool jok = j < D;
+  const uint32_t nb = Rs / 16;  // blocks of 16 k (four steps of 4)
 #pragma unroll
   for (int r = 0; r < RR; ++r) acc[r] = d4v{0.0, 0.0, 0.0, 0.0};
-  // operands of block b: the lane's float4 of each trial row and the four R
-  // coefficients R[j][kb .. kb+3], one float4 of the row-major float32
-  // rotation (row stride D4, zero padding; the values are the problem's
-  // float32 coefficients, so widening them is exact)
+  const float *rrow = R32 + (size_t)j * Rs + 4 * kq;
+  // operands of block b: the lane's float4 of each trial row and of its row of R
   auto load = [&](uint32_t b, float4 (&tv)[RR], float4 &bv) {
     const uint32_t kb = 16 * b + 4 * kq;
 #pragma unroll
     for (int r = 0; r < RR; ++r)
       tv[r] = row_ok[r] ? *reinterpret_cast<const float4 *>(Tg + (size_t)row_trial[r] * Dk + kb)
                         : make_float4(0.f, 0.f, 0.f, 0.f);
-    bv = (jok && kb < D4) ? *reinterpret_cast<const float4 *>(R32 + (size_t)j * D4 + kb)
-                          : make_float4(0.f, 0.f, 0.f, 0.f);
+    bv = *reinterpret_cast<const float4 *>(rrow + 16 * b);
   };
   float4 tn[RR], tm[RR];
   float4 bn, bm;
@@ -97,16 +97,59 @@ __device__ __forceinline__ void tiles_f64(const float *__restrict__ Tg, uint32_t
     const float4 bv = bn;
     bn = bm;
     if (b + 2 < nb) load(b + 2, tm, bm);
-    const uint32_t kb = 16 * b + 4 * kq;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const bool kin = kb + e < D;
-      const double oe = kin ? (double)oc[kb + e] : 0.0;
+      const double re = (double)comp(bv, e);
 #pragma unroll
-      for (int r = 0; r < RR; ++r) {
-        const double a = kin ? (double)comp(tv[r], e) - oe : 0.0;
-        acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)comp(bv, e), a, acc[r], 0, 0, 0);
-      }
+      for (int r = 0; r < RR; ++r)
+        acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(re, (double)comp(tv[r], e), acc[r], 0, 0, 0);
+    }
+  }
+}
+
+// z = R u - R o of the four outputs a lane holds after a plain tile
+// (outputs 16 ct + l/16 + 4 v), rounded once to float32.
+__device__ __forceinline__ void tile_z(const d4v &acc, const double *ro, uint32_t ct,
+                                       uint32_t lane, float (&z)[4]) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) z[v] = (float)(acc[v] - ro[16 * ct + (lane >> 4) + 4 * v]);
+}
+
+// The plain rotation of a generation as (output tile, group of RT_F64 row
+// tiles) items, fetched from a counter in LDS by every wave that calls this
+// (the consumers as soon as the trials are built, the producers once their
+// crossover tests of the next generation are drawn).  Items that share row
+// tiles are adjacent in the order, so their trial rows are read from cache.
+struct PlainRot {
+  const float *Tg;
+  const float *R32;
+  const double *ro;
+  uint32_t *ctr;
+  uint32_t Dk, Rs, N, NCT, n_items;
+};
+
+template <typename EPI>
+__device__ __forceinline__ void plain_items(const PlainRot &q, uint32_t lane, EPI &&epi) {
+  for (;;) {
+    uint32_t it = 0;
+    if (lane == 0) it = atomicAdd(q.ctr, 1u);
+    it = __builtin_amdgcn_readfirstlane(it);
+    if (it >= q.n_items) break;
+    const uint32_t ci = it % q.NCT, rt0 = (it / q.NCT) * RT_F64;
+    bool rok[RT_F64];
+    uint32_t rtr[RT_F64];
+#pragma unroll
+    for (int r = 0; r < RT_F64; ++r) {
+      rtr[r] = 16 * (rt0 + r) + (lane & 15);
+      rok[r] = rtr[r] < q.N;
+    }
+    d4v acc[RT_F64];
+    tiles_f64(q.Tg, q.Dk, rok, rtr, q.R32, q.Rs, 16 * ci + (lane & 15), lane, acc);
+#pragma unroll
+    for (int r = 0; r < RT_F64; ++r) {
+      float z[4];
+      tile_z(acc[r], q.ro, ci, lane, z);
+      epi(z, rtr[r], rok[r], ci);
     }
   }
 }
@@ -238,7 +281,10 @@ __device__ __forceinline__ void tile_epilogue(const ProbDev &p, const uint32_t *
     for (int v = 0; v < 4; ++v) {
       const uint32_t j = STRIDED ? 16 * ct + grp + 4 * v : 16 * ct + 4 * grp + v;
       if (ok && j < D) {
-        const ColInfo c{ek_s[j], ew_s[j]};
+        // the kind is a constant of the generation loop except for the hybrid,
+        // whose outputs fall in different blocks
+        const uint32_t kind = p.kind == FN_HYBRID ? ek_s[j] : p.kind;
+        const ColInfo c{kind, kind == FN_ELLIPTIC ? ew_s[j] : 0.0f};
         float a0, a1;
         col_term(p, c, z[v], a0, a1);
         t0 += a0;
@@ -297,10 +343,11 @@ struct BoundCheck {
 // same barrier sequence as mfma_consumers -- one before the loop, five per
 // generation (eight in the bf16 mode), one after it -- so the two roles keep
 // separate loops and neither holds the other's registers.
-template <bool BF16>
+template <bool BF16, typename EPI>
 __device__ __forceinline__ void mfma_producers(const MLds &lay, unsigned char *smem,
                                                const RunDev &run, uint32_t g0, uint32_t n_gens,
-                                               uint32_t k0, uint32_t k1, uint32_t ptid) {
+                                               uint32_t k0, uint32_t k1, uint32_t ptid,
+                                               const PlainRot &rot, EPI &&epi) {
   const uint32_t N = run.N, D = run.D, Q = run.Dp / 4, kp = run.kp;
   uint8_t *msk = reinterpret_cast<uint8_t *>(smem + lay.msk);
   uint4 *dsc = reinterpret_cast<uint4 *>(smem + lay.dsc);
@@ -315,6 +362,7 @@ __device__ __forceinline__ void mfma_producers(const MLds &lay, unsigned char *s
     __syncthreads();   // trial construction (reads the masks of g)
     __syncthreads();   // rotation: the masks of g are free
     produce_masks(ptid, NP, run, N, Q, g + 1, k0, k1, msk);
+    if (!BF16) plain_items(rot, ptid & 63, epi);   // then help with the rotation
     __syncthreads();   // decisions (plain) or screen (bf16)
     if (BF16) {
       __syncthreads(); // candidate counts
@@ -361,9 +409,10 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
   __bf16 *Yl = Yh + (size_t)N * Dk;
   const double *Rt = tab_ptr<double>(tab, p.r64t_off);
   const uint32_t Dr = rt_stride(D);
-  // row-major float32 rotation [D][D4] stored after the transposed float64 one
-  const uint32_t D4 = (D + 3u) & ~3u;
-  const float *R32 = tab_ptr<float>(tab, p.r64t_off + (uint64_t)D * Dr * sizeof(double));
+  // row-major float32 rotation, zero padded to Rs x Rs, and R o
+  const uint32_t Rs = r32_stride(D);
+  const float *R32 = tab_ptr<float>(tab, p.r32_off);
+  double *ro_s = reinterpret_cast<double *>(smem + lay.ro);
 
   const uint32_t tid = threadIdx.x;
 
@@ -377,8 +426,10 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
     key_s[r] = mkkey(f, r);
   }
   const float *og = tab_ptr<float>(tab, p.o_off);
+  const double *rog = tab_ptr<double>(tab, p.ro64_off);
   for (uint32_t k = tid; k < Dk; k += MF_THREADS) {
     oc[k] = k < D ? og[k] : 0.0f;
+    ro_s[k] = k < Rs ? rog[k] : 0.0;
     const ColInfo c = col_info(tab, p, k);
     ek_s[k] = c.kind;
     ew_s[k] = c.w;
@@ -393,9 +444,15 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
         Yl[at] = (__bf16)0.0f;
       }
     }
+  // the plain rotation's items, shared by consumers and producers
+  const PlainRot rot{Tg, R32, ro_s, cnt + 15, Dk, Rs, N, NCT, NCT * ((NRT + RT_F64 - 1) / RT_F64)};
+  auto epi = [&](const float (&z)[4], uint32_t slot, bool ok, uint32_t ci) {
+    tile_epilogue<false, true>(p, ek_s, ew_s, z, slot, ok, 0.0f, D, ci, N, tid & 63, Ps, Pb, zf,
+                               zl);
+  };
   // the role is uniform per wave (whole waves on either side of MF_CONSUMERS)
   if (__builtin_amdgcn_readfirstlane(tid >> 6) >= MF_CONSUMERS / 64) {
-    mfma_producers<BF16>(lay, smem, run, g0, n_gens, k0, k1, tid - MF_CONSUMERS);
+    mfma_producers<BF16>(lay, smem, run, g0, n_gens, k0, k1, tid - MF_CONSUMERS, rot, epi);
   } else {
   constexpr bool producer = false;
   const uint32_t lane = tid & 63;
@@ -471,6 +528,7 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
     // S2: trial genes -> global trial rows.  P lanes per trial (a power of
     // two, as many as the consumers allow) take its quads in turn; in the bf16
     // mode they also write the splits of y = u - o and combine ||y||^2 by shuffles.
+    if (!BF16 && tid == 0) cnt[15] = 0;   // the rotation's item counter
     if (!producer) {
       const uint32_t lp = tid & (P - 1), per = MF_CONSUMERS / P;
       for (uint32_t i0 = 0; i0 < N; i0 += per) {
@@ -555,30 +613,8 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
                                      Pb, zf, zl);
         }
       }
-    } else if (!BF16 && !producer) {
-      // (output tile, group of RT_F64 row tiles) items dealt to all consumer waves
-      // in turn, so that no wave idles when D spans fewer output tiles than
-      // there are waves
-      const uint32_t n_items = NCT * ((NRT + RT_F64 - 1) / RT_F64);
-      for (uint32_t it = wave; it < n_items; it += MF_CONSUMERS / 64) {
-        const uint32_t ci = it % NCT, rt0 = (it / NCT) * RT_F64;
-        bool rok[RT_F64];
-        uint32_t rtr[RT_F64];
-#pragma unroll
-        for (int r = 0; r < RT_F64; ++r) {
-          rtr[r] = 16 * (rt0 + r) + (lane & 15);
-          rok[r] = rtr[r] < N;
-        }
-        d4v acc[RT_F64];
-        tiles_f64(Tg, Dk, D, oc, rok, rtr, R32, D4, 16 * ci + (lane & 15), lane, acc);
-#pragma unroll
-        for (int r = 0; r < RT_F64; ++r) {
-          const float z[4] = {(float)acc[r][0], (float)acc[r][1], (float)acc[r][2],
-                              (float)acc[r][3]};
-          tile_epilogue<false, true>(p, ek_s, ew_s, z, rtr[r], rok[r], 0.0f, D, ci, N, lane,
-                                     Ps, Pb, zf, zl);
-        }
-      }
+    } else if (!BF16) {
+      plain_items(rot, lane, epi);
     }
     __syncthreads();
     MDE_STAGE(4)
@@ -643,11 +679,11 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
             rtr[r] = rok[r] ? cl[srow] : 0u;
           }
           d4v acc[RT];
-          tiles_f64(Tg, Dk, D, oc, rok, rtr, R32, D4, 16 * ci + (lane & 15), lane, acc);
+          tiles_f64(Tg, Dk, rok, rtr, R32, Rs, 16 * ci + (lane & 15), lane, acc);
 #pragma unroll
           for (int r = 0; r < RT; ++r) {
-            const float z[4] = {(float)acc[r][0], (float)acc[r][1], (float)acc[r][2],
-                                (float)acc[r][3]};
+            float z[4];
+            tile_z(acc[r], ro_s, ci, lane, z);
             const uint32_t slot = 16 * (rt0 + r) + (lane & 15);   // position in the candidate list
             tile_epilogue<false, true>(p, ek_s, ew_s, z, slot, rok[r], 0.0f, D, ci, N, lane, Ps,
                                        Pb, zf, zl);
@@ -737,6 +773,31 @@ __global__ __launch_bounds__(MF_THREADS) void k_generations_mfma(
     default: break;
   }
 #undef MDE_KIND
+}
+
+// Padded float32 rotation [Rs][Rs] (zero outside D x D) and R o in float64
+// (k ascending, one fused multiply-add per term; zero past D).
+__global__ void k_tables_mfma(const float *__restrict__ R, const float *__restrict__ o,
+                              float *__restrict__ R32, double *__restrict__ ro64, uint32_t D,
+                              uint32_t Rs) {
+  const uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= Rs * Rs) return;
+  const uint32_t j = u / Rs, k = u - j * Rs;
+  R32[u] = (j < D && k < D) ? R[(size_t)j * D + k] : 0.0f;
+  if (k == 0) {
+    double acc = 0.0;
+    if (j < D)
+      for (uint32_t kk = 0; kk < D; ++kk) acc = fma((double)R[(size_t)j * D + kk], (double)o[kk], acc);
+    ro64[j] = acc;
+  }
+}
+
+hipError_t launch_tables_mfma(const float *R, const float *o, float *R32, double *ro64, uint32_t D,
+                              hipStream_t s) {
+  const uint32_t Rs = r32_stride(D);
+  hipLaunchKernelGGL(k_tables_mfma, dim3((Rs * Rs + 255) / 256), dim3(256), 0, s, R, o, R32, ro64,
+                     D, Rs);
+  return hipGetLastError();
 }
 
 #ifdef MDE_STAGE_CLOCKS
