@@ -282,7 +282,8 @@ metade_status plan_config(const metade_config *cfg, Plan &pl, std::string &msg) 
     d.NCT = (D + 15u) / 16u;
     const bool rosen = pl.probs[d.prob].kind == mde::FN_ROSENBROCK;
     const uint32_t lane_bytes = mde::lds_layout(N, d.Dp, L_lane, d.Np, true).total;
-    const uint32_t mf_bytes = mde::mfma_layout(N, d.Dp, d.Dk, L_mf, d.Np, d.NCT, rosen).total;
+    const uint32_t mf_bytes = mde::mfma_layout(N, d.Dp, d.Dk, L_mf, d.Np, d.NCT, rosen,
+                                               cfg->precision == METADE_BF16_REFINE).total;
     if (cfg->precision == METADE_FP32 && lane_bytes <= mde::LDS_BUDGET) {
       d.kern = 0;
       d.t_lds = 1;

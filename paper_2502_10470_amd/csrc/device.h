@@ -215,19 +215,19 @@ __host__ __device__ inline Lds lds_layout(uint32_t N, uint32_t Dp, uint32_t L, u
 // in a global buffer [N][Dk] (Dk = D rounded up to 32, zero padding), followed
 // in the bf16 mode by the bf16 splits of y = u - o ([N][Dk] high parts, then
 // low parts); LDS holds the population, ranking state, the producers' mask
-// nibbles and packed draws, per (output tile, trial) partial sums and bounds,
-// Rosenbrock boundary values, the shift, the element kind and elliptic weight
-// of every output, the candidate list of the bf16 mode, per-wave counts and
-// the bf16 mode's ||y||^2 per trial.
+// nibbles and packed draws, per (output tile, trial) partial sums (and
+// bounds in the bf16 mode), Rosenbrock
+// boundary values, the shift, R o, the element kind and elliptic weight of
+// every output, the candidate list of the bf16 mode and per-wave counts.
 constexpr uint32_t MF_THREADS = 768;
 constexpr uint32_t MF_CONSUMERS = 512;
 
 struct MLds {
-  uint32_t pop, key, fit, topk, rk, msk, dsc, ps, pb, zf, zl, oc, ro, ek, ew, cl, cnt, ysq, total;
+  uint32_t pop, key, fit, topk, rk, msk, dsc, ps, pb, zf, zl, oc, ro, ek, ew, cl, cnt, total;
 };
 
 __host__ __device__ inline MLds mfma_layout(uint32_t N, uint32_t Dp, uint32_t Dk, uint32_t L,
-                                            uint32_t Np, uint32_t NCT, bool rosen) {
+                                            uint32_t Np, uint32_t NCT, bool rosen, bool bf16) {
   MLds l;
   uint32_t o = 0;
   l.pop = o;  o += al16(N * Dp * 4);
@@ -238,16 +238,15 @@ __host__ __device__ inline MLds mfma_layout(uint32_t N, uint32_t Dp, uint32_t Dk
   l.msk = o;  o += al16(N * (Dp / 4));
   l.dsc = o;  o += al16(N * 16);
   l.ps = o;   o += al16(NCT * N * 8);
-  l.pb = o;   o += al16(NCT * N * 4);
+  l.pb = o;   o += bf16 ? al16(NCT * N * 4) : 0u;
   l.zf = o;   o += rosen ? al16(NCT * N * 4) : 0u;
   l.zl = o;   o += rosen ? al16(NCT * N * 4) : 0u;
   l.oc = o;   o += al16(Dk * 4);
   l.ro = o;   o += al16(Dk * 8);
   l.ek = o;   o += al16(Dk * 4);
   l.ew = o;   o += al16(Dk * 4);
-  l.cl = o;   o += al16(N * 4);
+  l.cl = o;   o += bf16 ? al16(N * 4) : 0u;
   l.cnt = o;  o += al16(16 * 4);
-  l.ysq = o;  o += al16(N * 4);
   l.total = o;
   return l;
 }

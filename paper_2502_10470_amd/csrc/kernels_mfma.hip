@@ -14,7 +14,8 @@
 // accuracy as the lane kernel's float64 accumulation.
 // bf16 mode: the product is formed from bf16 splits, y R ~ y_hi R_hi +
 // y_hi R_lo + y_lo R_hi with v_mfma_f32_16x16x32_bf16 and float32
-// accumulation.  Each trial gets a certified bound E on |f_hat - f|; a trial
+// accumulation.  Each trial gets a certified bound E on |f_hat - f| (from a
+// per-output error radius: a fourth product of the bf16 magnitudes); a trial
 // with f_hat - E > f(target) would be rejected by the plain evaluation too, so
 // it is rejected at once; every other trial is re-evaluated in plain mode (on
 // compacted row tiles) and decided from that value.  Decisions -- hence
@@ -34,13 +35,20 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 
 constexpr int KSB = 4;        // bf16 k-steps of 32 (D <= 128)
-// |z_hat - z| <= E_COEF * ||u - o||_2 for the three-product bf16 split with
-// float32 accumulation: the residues of the two splits and the dropped
-// lo * lo product give 3 * 2^-16 sum_k |R_jk| |y_k|, float32 accumulation of
-// 3 * 128 products 384 * 2^-24 of the same sum, rounding u - o to float32
-// 2^-24; the sum is at most ||y||_2 (rows of R have unit norm), so the total
-// is below 7e-5 ||y||_2 and 2^-13 leaves a margin of 1.7.
-constexpr float E_COEF = 1.2207031e-4f;  // 2^-13
+// Per-output error radius of the three-product bf16 split with float32
+// accumulation: |z_hat_j - z_j| <= E_AB * S_j, S_j = sum_k |R_jk| |y_k|.
+// With u_b = 2^-8 the unit roundoff of bf16, the splits y = y_hi + y_lo + dy,
+// R = R_hi + R_lo + dR leave |dy| <= u_b^2 |y|, |dR| <= u_b^2 |R|; the products
+// y_hi R_hi + y_hi R_lo + y_lo R_hi miss y_lo R_lo + (y_hi + y_lo) dR +
+// dy (R_hi + R_lo) + dy dR, at most (3 + 2^-15) 2^-16 |y| |R| per term; the
+// float32 sum of the 3 Dk <= 384 exact bf16 products adds at most
+// 384 2^-24 (1 + 2^-7) of the same sum, and rounding u - o to float32 2^-24:
+// in all below 6.92e-5 S_j.  S_j itself comes from a fourth product of the
+// bf16 magnitudes, |R_hi| |y_hi|, summed in float32: each magnitude is within
+// a factor 1/(1 - 2^-8) of its rounded value and the float32 sum of
+// non-negative terms within 1/(1 - 384 2^-24), so S_j <= 1.0079 S_hat_j.
+// E_AB = 6.92e-5 * 1.0079 rounded up.
+constexpr float E_AB = 7.0e-5f;
 
 // ---------------------------------------------------------------- rotation tiles
 
@@ -115,42 +123,21 @@ __device__ __forceinline__ void tile_z(const d4v &acc, const double *ro, uint32_
   for (int v = 0; v < 4; ++v) z[v] = (float)(acc[v] - ro[16 * ct + (lane >> 4) + 4 * v]);
 }
 
-// The plain rotation of a generation as (output tile, group of RT_F64 row
-// tiles) items, fetched from a counter in LDS by every wave that calls this
-// (the consumers as soon as the trials are built, the producers once their
-// crossover tests of the next generation are drawn).  Items that share row
-// tiles are adjacent in the order, so their trial rows are read from cache.
-struct PlainRot {
-  const float *Tg;
-  const float *R32;
-  const double *ro;
-  uint32_t *ctr;
-  uint32_t Dk, Rs, N, NCT, n_items;
-};
-
-template <typename EPI>
-__device__ __forceinline__ void plain_items(const PlainRot &q, uint32_t lane, EPI &&epi) {
+// The rotation of a generation as (output tile, group of row tiles) items,
+// fetched from a counter in LDS by every wave that calls this (the consumers
+// as soon as the trials are built, the producers once their crossover tests
+// of the next generation are drawn), so that one wave's products run while
+// another waits for its loads or forms the element terms.  Items that share
+// row tiles are adjacent in the order, so their trial rows come from cache.
+template <typename BODY>
+__device__ __forceinline__ void rotation_items(uint32_t *ctr, uint32_t n_items, uint32_t lane,
+                                               BODY &&body) {
   for (;;) {
     uint32_t it = 0;
-    if (lane == 0) it = atomicAdd(q.ctr, 1u);
+    if (lane == 0) it = atomicAdd(ctr, 1u);
     it = __builtin_amdgcn_readfirstlane(it);
-    if (it >= q.n_items) break;
-    const uint32_t ci = it % q.NCT, rt0 = (it / q.NCT) * RT_F64;
-    bool rok[RT_F64];
-    uint32_t rtr[RT_F64];
-#pragma unroll
-    for (int r = 0; r < RT_F64; ++r) {
-      rtr[r] = 16 * (rt0 + r) + (lane & 15);
-      rok[r] = rtr[r] < q.N;
-    }
-    d4v acc[RT_F64];
-    tiles_f64(q.Tg, q.Dk, rok, rtr, q.R32, q.Rs, 16 * ci + (lane & 15), lane, acc);
-#pragma unroll
-    for (int r = 0; r < RT_F64; ++r) {
-      float z[4];
-      tile_z(acc[r], q.ro, ci, lane, z);
-      epi(z, rtr[r], rok[r], ci);
-    }
+    if (it >= n_items) break;
+    body(it);
   }
 }
 
@@ -158,19 +145,49 @@ __device__ __forceinline__ void plain_items(const PlainRot &q, uint32_t lane, EP
 // with k = 32 s + 8 (l/16) + e; result element v is
 // z_hat[trial 16 rt + l%16][output 16 ct + 4 (l/16) + v].  The trial operands
 // are the bf16 splits of y = u - o written once per trial when it is built.
+// ab[r] receives sum_k |R_hi jk| |y_hi k| for the outputs' error radii.
+__device__ __forceinline__ bf8v abs8(const bf8v &x) {
+  uint4 u = __builtin_bit_cast(uint4, x);
+  u.x &= 0x7FFF7FFFu;
+  u.y &= 0x7FFF7FFFu;
+  u.z &= 0x7FFF7FFFu;
+  u.w &= 0x7FFF7FFFu;
+  return __builtin_bit_cast(bf8v, u);
+}
+
 __device__ __forceinline__ void tiles_bf16(const __bf16 *__restrict__ Yh,
                                            const __bf16 *__restrict__ Yl, uint32_t Dk,
                                            const bool (&row_ok)[RT],
                                            const uint32_t (&row_trial)[RT],
-                                           const bf8v (&bhi)[KSB], const bf8v (&blo)[KSB],
-                                           uint32_t lane, f4v (&acc)[RT]) {
+                                           const float *__restrict__ Rrow, uint32_t Rs,
+                                           uint32_t lane, f4v (&acc)[RT], f4v (&ab)[RT]) {
   const uint32_t Ksb = Dk / 32;
 #pragma unroll
-  for (int r = 0; r < RT; ++r) acc[r] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int r = 0; r < RT; ++r) {
+    acc[r] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
+    ab[r] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
+  }
 #pragma unroll
   for (int s = 0; s < KSB; ++s) {
     if ((uint32_t)s < Ksb) {
       const uint32_t k0 = 32 * s + 8 * (lane >> 4);
+      // this lane's eight coefficients of R, split into bf16 parts here (a
+      // table of the splits would add to the generation's cache footprint)
+      bf8v bh, bl;
+      {
+        float4 ra = make_float4(0.f, 0.f, 0.f, 0.f), rb = ra;
+        if (k0 < Rs) {
+          ra = *reinterpret_cast<const float4 *>(Rrow + k0);
+          rb = *reinterpret_cast<const float4 *>(Rrow + k0 + 4);
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const float r = e < 4 ? comp(ra, e) : comp(rb, e - 4);
+          const __bf16 h = (__bf16)r;
+          bh[e] = h;
+          bl[e] = (__bf16)(r - (float)h);
+        }
+      }
       bf8v ah[RT], al[RT];
 #pragma unroll
       for (int r = 0; r < RT; ++r) {
@@ -184,11 +201,14 @@ __device__ __forceinline__ void tiles_bf16(const __bf16 *__restrict__ Yh,
         }
       }
 #pragma unroll
-      for (int r = 0; r < RT; ++r) acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bhi[s], al[r], acc[r], 0, 0, 0);
+      for (int r = 0; r < RT; ++r) acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh, al[r], acc[r], 0, 0, 0);
 #pragma unroll
-      for (int r = 0; r < RT; ++r) acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(blo[s], ah[r], acc[r], 0, 0, 0);
+      for (int r = 0; r < RT; ++r) acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bl, ah[r], acc[r], 0, 0, 0);
 #pragma unroll
-      for (int r = 0; r < RT; ++r) acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bhi[s], ah[r], acc[r], 0, 0, 0);
+      for (int r = 0; r < RT; ++r) acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh, ah[r], acc[r], 0, 0, 0);
+      const bf8v bab = abs8(bh);
+#pragma unroll
+      for (int r = 0; r < RT; ++r) ab[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bab, abs8(ah[r]), ab[r], 0, 0, 0);
     }
   }
 }
@@ -252,7 +272,8 @@ __device__ __forceinline__ float term_bound(const ProbDev &p, const ColInfo &c, 
 template <bool BOUND, bool STRIDED>
 __device__ __forceinline__ void tile_epilogue(const ProbDev &p, const uint32_t *ek_s,
                                               const float *ew_s, const float (&z)[4],
-                                              uint32_t slot, bool ok, float e, uint32_t D,
+                                              uint32_t slot, bool ok, const float (&e)[4],
+                                              uint32_t D,
                                               uint32_t ct, uint32_t nslot, uint32_t lane,
                                               float2 *Ps, float *Pb, float *zf, float *zl) {
   const uint32_t grp = lane >> 4;
@@ -289,7 +310,7 @@ __device__ __forceinline__ void tile_epilogue(const ProbDev &p, const uint32_t *
         col_term(p, c, z[v], a0, a1);
         t0 += a0;
         t1 += a1;
-        if (BOUND) bd += term_bound(p, c, z[v], e, a0);
+        if (BOUND) bd += term_bound(p, c, z[v], e[v], a0);
       }
     }
   }
@@ -343,11 +364,11 @@ struct BoundCheck {
 // same barrier sequence as mfma_consumers -- one before the loop, five per
 // generation (eight in the bf16 mode), one after it -- so the two roles keep
 // separate loops and neither holds the other's registers.
-template <bool BF16, typename EPI>
+template <bool BF16, typename BODY>
 __device__ __forceinline__ void mfma_producers(const MLds &lay, unsigned char *smem,
                                                const RunDev &run, uint32_t g0, uint32_t n_gens,
                                                uint32_t k0, uint32_t k1, uint32_t ptid,
-                                               const PlainRot &rot, EPI &&epi) {
+                                               uint32_t *ctr, uint32_t n_items, BODY &&item) {
   const uint32_t N = run.N, D = run.D, Q = run.Dp / 4, kp = run.kp;
   uint8_t *msk = reinterpret_cast<uint8_t *>(smem + lay.msk);
   uint4 *dsc = reinterpret_cast<uint4 *>(smem + lay.dsc);
@@ -362,7 +383,7 @@ __device__ __forceinline__ void mfma_producers(const MLds &lay, unsigned char *s
     __syncthreads();   // trial construction (reads the masks of g)
     __syncthreads();   // rotation: the masks of g are free
     produce_masks(ptid, NP, run, N, Q, g + 1, k0, k1, msk);
-    if (!BF16) plain_items(rot, ptid & 63, epi);   // then help with the rotation
+    rotation_items(ctr, n_items, ptid & 63, item);   // then help with the rotation
     __syncthreads();   // decisions (plain) or screen (bf16)
     if (BF16) {
       __syncthreads(); // candidate counts
@@ -386,7 +407,7 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
                  L = run.L, Np = run.Np, NCT = run.NCT;
   const uint32_t NRT = (N + 15) / 16;
   const bool rosen = p.kind == FN_ROSENBROCK;
-  const MLds lay = mfma_layout(N, Dp, Dk, L, Np, NCT, rosen);
+  const MLds lay = mfma_layout(N, Dp, Dk, L, Np, NCT, rosen, BF16);
   float *pop_s = reinterpret_cast<float *>(smem + lay.pop);
   uint64_t *key_s = reinterpret_cast<uint64_t *>(smem + lay.key);
   float *fit_s = reinterpret_cast<float *>(smem + lay.fit);
@@ -403,7 +424,6 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
   float *ew_s = reinterpret_cast<float *>(smem + lay.ew);
   uint32_t *cl = reinterpret_cast<uint32_t *>(smem + lay.cl);
   uint32_t *cnt = reinterpret_cast<uint32_t *>(smem + lay.cnt);
-  float *ysq_s = reinterpret_cast<float *>(smem + lay.ysq);
   // bf16 mode: splits of y = u - o after the trial rows
   __bf16 *Yh = reinterpret_cast<__bf16 *>(Tg + (size_t)N * Dk);
   __bf16 *Yl = Yh + (size_t)N * Dk;
@@ -444,15 +464,49 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
         Yl[at] = (__bf16)0.0f;
       }
     }
-  // the plain rotation's items, shared by consumers and producers
-  const PlainRot rot{Tg, R32, ro_s, cnt + 15, Dk, Rs, N, NCT, NCT * ((NRT + RT_F64 - 1) / RT_F64)};
-  auto epi = [&](const float (&z)[4], uint32_t slot, bool ok, uint32_t ci) {
-    tile_epilogue<false, true>(p, ek_s, ew_s, z, slot, ok, 0.0f, D, ci, N, tid & 63, Ps, Pb, zf,
-                               zl);
+  // the rotation's items, shared by consumers and producers: plain, (output
+  // tile, RT_F64 row tiles) in float64; bf16, (output tile, RT row tiles)
+  // from the bf16 splits with each output's error radius
+  constexpr uint32_t RTI = BF16 ? RT : RT_F64;
+  const uint32_t n_items = NCT * ((NRT + RTI - 1) / RTI);
+  auto item = [&](uint32_t it) {
+    const uint32_t lane = tid & 63;
+    const uint32_t ci = it % NCT, rt0 = (it / NCT) * RTI;
+    bool rok[RTI];
+    uint32_t rtr[RTI];
+#pragma unroll
+    for (int r = 0; r < (int)RTI; ++r) {
+      rtr[r] = 16 * (rt0 + r) + (lane & 15);
+      rok[r] = rtr[r] < N;
+    }
+    if constexpr (BF16) {
+      f4v acc[RT], ab[RT];
+      tiles_bf16(Yh, Yl, Dk, rok, rtr, R32 + (size_t)(16 * ci + (lane & 15)) * Rs, Rs, lane, acc,
+                 ab);
+#pragma unroll
+      for (int r = 0; r < RT; ++r) {
+        const float z[4] = {acc[r][0], acc[r][1], acc[r][2], acc[r][3]};
+        const float e[4] = {E_AB * ab[r][0], E_AB * ab[r][1], E_AB * ab[r][2], E_AB * ab[r][3]};
+        tile_epilogue<true, false>(p, ek_s, ew_s, z, rtr[r], rok[r], e, D, ci, N, lane, Ps, Pb,
+                                   zf, zl);
+      }
+    } else {
+      d4v acc[RT_F64];
+      tiles_f64(Tg, Dk, rok, rtr, R32, Rs, 16 * ci + (lane & 15), lane, acc);
+#pragma unroll
+      for (int r = 0; r < RT_F64; ++r) {
+        float z[4];
+        tile_z(acc[r], ro_s, ci, lane, z);
+        const float e0[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        tile_epilogue<false, true>(p, ek_s, ew_s, z, rtr[r], rok[r], e0, D, ci, N, lane, Ps, Pb,
+                                   zf, zl);
+      }
+    }
   };
   // the role is uniform per wave (whole waves on either side of MF_CONSUMERS)
   if (__builtin_amdgcn_readfirstlane(tid >> 6) >= MF_CONSUMERS / 64) {
-    mfma_producers<BF16>(lay, smem, run, g0, n_gens, k0, k1, tid - MF_CONSUMERS, rot, epi);
+    mfma_producers<BF16>(lay, smem, run, g0, n_gens, k0, k1, tid - MF_CONSUMERS, cnt + 15,
+                         n_items, item);
   } else {
   constexpr bool producer = false;
   const uint32_t lane = tid & 63;
@@ -464,32 +518,10 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
   const uint32_t kr0 = l * N / L, kr1 = (l + 1) * N / L;
   // decision lane of trial tid
   const bool dec = tid < N;
-  // output tile of this consumer wave in the bf16 rotation (its bf16 parts of R
-  // stay in registers); the float64 tiles are dealt to the waves as items
-  const uint32_t ct = wave;
-  const bool has_ct = ct < NCT;
-  const uint32_t jcol = 16 * ct + (lane & 15);
   const int use_rand = (run.bl == RAND || run.br == RAND) ? 1 : 0;
   // trial construction: P lanes per trial, the largest power of two <= 32 with N P <= consumers
   uint32_t P = 1;
   while (P < 32 && N * (2 * P) <= MF_CONSUMERS) P *= 2;
-  // this wave's slice of R: the bf16 splits stay in registers for the launch;
-  // the float64 slice is read from the table (L1/L2 resident) block by block
-  bf8v bhi[KSB], blo[KSB];
-  {
-    const uint32_t kq = lane >> 4;
-#pragma unroll
-    for (int s = 0; s < KSB; ++s) {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const uint32_t k = 32 * s + 8 * kq + e;
-        const float r = (BF16 && has_ct && k < D && jcol < D) ? (float)Rt[(size_t)k * Dr + jcol] : 0.0f;
-        const __bf16 h = (__bf16)r;
-        bhi[s][e] = h;
-        blo[s][e] = (__bf16)(r - (float)h);
-      }
-    }
-  }
   __syncthreads();   // draws of the first generation are being made
   unsigned long long refined = 0;
   BoundCheck chk{0, 0, 0, 0, 0.0};
@@ -527,14 +559,14 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
     MDE_STAGE(2)
     // S2: trial genes -> global trial rows.  P lanes per trial (a power of
     // two, as many as the consumers allow) take its quads in turn; in the bf16
-    // mode they also write the splits of y = u - o and combine ||y||^2 by shuffles.
-    if (!BF16 && tid == 0) cnt[15] = 0;   // the rotation's item counter
+    // mode they also write the bf16 splits of y = u - o.
+    if (tid == 0) cnt[15] = 0;   // the rotation's item counter
+    const uint8_t *mg = msk;
     if (!producer) {
       const uint32_t lp = tid & (P - 1), per = MF_CONSUMERS / P;
       for (uint32_t i0 = 0; i0 < N; i0 += per) {
         const uint32_t i = i0 + tid / P;
         const bool valid = i < N;
-        float part = 0.0f;
         if (valid) {
           const uint4 d = dsc[i];
           const uint32_t r0 = byte_of(d.z, 0), pb = byte_of(d.z, 1);
@@ -542,7 +574,7 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
           const uint32_t ibl = run.bl == RAND ? r0 : (run.bl == BEST ? ibest : (run.bl == PBEST ? ipb : i));
           const uint32_t ibr = run.br == RAND ? r0 : (run.br == BEST ? ibest : (run.br == PBEST ? ipb : i));
           for (uint32_t q = lp; q < Q; q += P) {
-            const uint32_t nib = run.cs == BIN ? msk[i * Q + q] : 0u;
+            const uint32_t nib = run.cs == BIN ? mg[i * Q + q] : 0u;
             const float4 uu = trial_quad(pop_s, Dp, D, i, q, ibl, ibr, d, nib, run, lb, ub);
             *reinterpret_cast<float4 *>(Tg + (size_t)i * Dk + 4 * q) = uu;
             if (BF16) {
@@ -550,7 +582,6 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
 #pragma unroll
               for (int t = 0; t < 4; ++t) {
                 const float y = comp(uu, t) - oc[4 * q + t];
-                part = fmaf(y, y, part);
                 const __bf16 h = (__bf16)y;
                 const __bf16 lo = (__bf16)(y - (float)h);
                 hb[t] = __builtin_bit_cast(uint16_t, h);
@@ -584,38 +615,13 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
             o[15] = 0;
           }
         }
-        if (BF16) {
-          for (uint32_t sft = 1; sft < P; sft <<= 1) part += __shfl_xor(part, (int)sft);
-          if (valid && lp == 0) ysq_s[i] = part;
-        }
       }
     }
     __syncthreads();
     MDE_STAGE(3)
-    // S3: rotation on the matrix cores + element terms; producers: masks of g+1
-    if (BF16 && has_ct) {
-      // the bf16 parts of R stay in registers: one output tile per wave
-      for (uint32_t rt0 = 0; rt0 < NRT; rt0 += RT) {
-        bool rok[RT];
-        uint32_t rtr[RT];
-#pragma unroll
-        for (int r = 0; r < RT; ++r) {
-          rtr[r] = 16 * (rt0 + r) + (lane & 15);
-          rok[r] = rtr[r] < N;
-        }
-        f4v acc[RT];
-        tiles_bf16(Yh, Yl, Dk, rok, rtr, bhi, blo, lane, acc);
-#pragma unroll
-        for (int r = 0; r < RT; ++r) {
-          const float z[4] = {acc[r][0], acc[r][1], acc[r][2], acc[r][3]};
-          const float e = rok[r] ? E_COEF * (sqrtf(ysq_s[rtr[r]]) * 1.0001f) : 0.0f;
-          tile_epilogue<true, false>(p, ek_s, ew_s, z, rtr[r], rok[r], e, D, ct, N, lane, Ps,
-                                     Pb, zf, zl);
-        }
-      }
-    } else if (!BF16) {
-      plain_items(rot, lane, epi);
-    }
+    // S3: rotation on the matrix cores + element terms (producers join once
+    // the masks of g+1 are drawn)
+    rotation_items(cnt + 15, n_items, lane, item);
     __syncthreads();
     MDE_STAGE(4)
     // S4: plain mode decides and commits; bf16 mode selects the candidates
@@ -685,7 +691,8 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
             float z[4];
             tile_z(acc[r], ro_s, ci, lane, z);
             const uint32_t slot = 16 * (rt0 + r) + (lane & 15);   // position in the candidate list
-            tile_epilogue<false, true>(p, ek_s, ew_s, z, slot, rok[r], 0.0f, D, ci, N, lane, Ps,
+            const float e0[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            tile_epilogue<false, true>(p, ek_s, ew_s, z, slot, rok[r], e0, D, ci, N, lane, Ps,
                                        Pb, zf, zl);
           }
         }
