@@ -319,6 +319,40 @@ metade_status metade_kernel_time(metade_ctx *ctx, double *ms, uint64_t *launches
  * re-evaluated exactly by the BF16_REFINE mode (0 otherwise). */
 metade_status metade_get_counters(metade_ctx *ctx, uint64_t *trials, uint64_t *refined);
 
+/* Launch-shape choices of the generation kernels.  Results do not depend on
+ * mfma_rows; lane_parts regroups the float64 sums of a trial's terms, which
+ * can move a float32 fitness by one unit in the last place.
+ *   lane_parts: parts per trial in the lane kernel's fitness stage (each
+ *               part a whole number of waves covering the population): 0 =
+ *               as many as fit the consumer lanes (at most 8), else 1, 2, 4
+ *               or 8, capped at that number;
+ *   mfma_rows:  row tiles (16 trials each) per rotation item of the
+ *               matrix-core kernel's plain evaluation: 2 or 4 (0 = 4). */
+typedef struct {
+  uint32_t lane_parts;
+  uint32_t mfma_rows;
+} metade_tuning;
+
+/* Read or set the context's tuning (set: METADE_EINVAL for values outside
+ * the lists above; synchronises). */
+metade_status metade_get_tuning(metade_ctx *ctx, metade_tuning *t);
+metade_status metade_set_tuning(metade_ctx *ctx, const metade_tuning *t);
+
+/* Autotuner: time n_generations of the context's own runs under every
+ * candidate tuning of the kernels it uses (lane_parts 0/4/2/1 when it has
+ * lane-kernel runs; mfma_rows 4/2 when it has matrix-core runs in float32
+ * precision), each from the same checkpoint, fastest of two timed passes
+ * after a warm-up, and keep the fastest.  The context's state (populations,
+ * counters, records) is restored afterwards, so results do not depend on
+ * the search itself.  With cache_path != NULL the choice is looked up first
+ * in that text file, one line per key "<16 hex digits> <lane_parts>
+ * <mfma_rows> <ms>", the key hashing the runs' (N, D, kind) multiset, the
+ * precision and n_generations; a measured choice is appended to it.
+ * chosen and best_ms (the chosen tuning's time for n_generations) may be
+ * NULL.  Synchronises. */
+metade_status metade_autotune(metade_ctx *ctx, uint32_t n_generations, const char *cache_path,
+                              metade_tuning *chosen, double *best_ms);
+
 /* Readable message of the last error on ctx (or of the last failed
  * metade_init when ctx is NULL).  Never NULL. */
 const char *metade_last_error(const metade_ctx *ctx);

@@ -6,7 +6,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <mutex>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -70,6 +72,9 @@ struct metade_ctx {
   unsigned long long *counters_d = nullptr;
   int device = 0;
   float *scratch_d = nullptr;   // this device's copy of the static workspace
+  // tuning: row tiles per plain rotation item (matrix-core kernel) and parts
+  // per trial in the lane kernel's fitness stage (0 = as many as fit)
+  uint32_t mfma_rows = 4, lane_parts = 0;
   uint32_t gen = 0;
   // control runs: device copy of the generation counter, and the generation
   // loop captured as HIP graphs (one per sequence length, replayed on stream)
@@ -334,6 +339,7 @@ LaunchArgs largs(metade_ctx *c) {
   a.mfma_lds_bytes = c->mfma_lds_bytes;
   a.k0 = (uint32_t)(c->seed & 0xFFFFFFFFu);
   a.k1 = (uint32_t)(c->seed >> 32);
+  a.mfma_rows = c->mfma_rows;
   a.stream = c->stream;
   return a;
 }
@@ -1009,6 +1015,151 @@ int metade_debug_stage_clocks(int which, void *dst, size_t bytes) {
   return e == hipSuccess ? 0 : -1;
 }
 #endif
+
+metade_status metade_get_tuning(metade_ctx *c, metade_tuning *t) {
+  if (!c || !t) return fail(c, METADE_EINVAL, "ctx and t are required");
+  t->lane_parts = c->lane_parts;
+  t->mfma_rows = c->mfma_rows;
+  return METADE_OK;
+}
+
+metade_status metade_set_tuning(metade_ctx *c, const metade_tuning *t) {
+  if (!c || !t) return fail(c, METADE_EINVAL, "ctx and t are required");
+  const uint32_t rows = t->mfma_rows ? t->mfma_rows : 4u;
+  if (rows != 2 && rows != 4) return fail(c, METADE_EINVAL, "mfma_rows must be 0, 2 or 4");
+  const uint32_t lp = t->lane_parts;
+  if (lp != 0 && lp != 1 && lp != 2 && lp != 4 && lp != 8)
+    return fail(c, METADE_EINVAL, "lane_parts must be 0, 1, 2, 4 or 8");
+  if (c->n_lane) {
+    // parts per trial of the lane runs (the device table also holds the decoded
+    // theta, so only L is changed there)
+    std::vector<RunDev> runs(c->n_runs);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipMemcpy(runs.data(), c->runs_d, c->n_runs * sizeof(RunDev), hipMemcpyDeviceToHost));
+    uint32_t lds = 0;
+    for (uint32_t r = 0; r < c->n_runs; ++r) {
+      RunDev &d = runs[r];
+      if (d.kern != 0) continue;
+      const uint32_t lmax = std::max<uint32_t>(1, std::min<uint32_t>(8, mde::GEN_CONSUMERS / d.Np));
+      d.L = lp ? std::min(lp, lmax) : lmax;
+      c->runs_h[r].L = d.L;
+      lds = std::max(lds, mde::lds_layout(d.N, d.Dp, d.L, d.Np, true).total);
+    }
+    HIP_TRY(c, hipMemcpy(c->runs_d, runs.data(), c->n_runs * sizeof(RunDev), hipMemcpyHostToDevice));
+    c->lds_bytes = lds;
+  }
+  c->lane_parts = lp;
+  c->mfma_rows = rows;
+  return METADE_OK;
+}
+
+namespace {
+// Key of a tuning choice: the shapes of the runs (as a multiset), the
+// precision and the generation count the choice was measured with.
+uint64_t tuning_key(const metade_ctx *c, uint32_t n_gens) {
+  std::vector<uint64_t> shapes;
+  for (const RunDev &r : c->runs_h)
+    shapes.push_back(((uint64_t)r.N << 40) | ((uint64_t)r.D << 16) |
+                     (uint64_t)c->probs_h[r.prob].kind);
+  std::sort(shapes.begin(), shapes.end());
+  uint64_t h = 0xcbf29ce484222325ull;
+  auto mix = [&](uint64_t v) {
+    for (int b = 0; b < 8; ++b) {
+      h ^= (v >> (8 * b)) & 0xffu;
+      h *= 0x100000001b3ull;
+    }
+  };
+  mix(0x6766783935300000ull);  // tag of this library's kernels on gfx950
+  mix(c->precision);
+  mix(n_gens);
+  for (uint64_t v : shapes) mix(v);
+  return h;
+}
+}  // namespace
+
+metade_status metade_autotune(metade_ctx *c, uint32_t n_gens, const char *cache_path,
+                              metade_tuning *chosen, double *best_ms) {
+  if (!c) return fail(nullptr, METADE_EINVAL, "ctx is NULL");
+  if (n_gens == 0) return fail(c, METADE_EINVAL, "n_gens must be >= 1");
+  const uint64_t key = tuning_key(c, n_gens);
+  char keyhex[17];
+  std::snprintf(keyhex, sizeof(keyhex), "%016llx", (unsigned long long)key);
+  if (cache_path) {
+    std::ifstream in(cache_path);
+    std::string line;
+    while (std::getline(in, line)) {
+      std::istringstream ls(line);
+      std::string k;
+      metade_tuning t{0, 0};
+      double ms = 0.0;
+      if ((ls >> k >> t.lane_parts >> t.mfma_rows >> ms) && k == keyhex) {
+        TRY(metade_set_tuning(c, &t));
+        if (chosen) *chosen = t;
+        if (best_ms) *best_ms = ms;
+        return METADE_OK;
+      }
+    }
+  }
+  // candidates: only the knobs of the kernels this context runs
+  std::vector<uint32_t> rows = {4};
+  if (c->n_mfma && c->precision == METADE_FP32) rows.push_back(2);
+  std::vector<uint32_t> parts = {0};
+  if (c->n_lane) parts.insert(parts.end(), {4, 2, 1});
+  // the search runs the context's own generations from a checkpoint, which is
+  // restored after every candidate and at the end: the context's results do
+  // not depend on it
+  size_t bytes = 0;
+  TRY(metade_get_state(c, nullptr, &bytes));
+  std::vector<unsigned char> blob(bytes);
+  TRY(metade_get_state(c, blob.data(), &bytes));
+  const uint64_t trials0 = c->trials;
+  unsigned long long cnt0[N_COUNTERS];
+  HIP_TRY(c, hipMemcpy(cnt0, c->counters_d, sizeof(cnt0), hipMemcpyDeviceToHost));
+  const bool timing0 = c->timing;
+  c->timing = false;
+  metade_tuning best{c->lane_parts, c->mfma_rows};
+  double best_t = 1e300;
+  hipEvent_t ea = nullptr, eb = nullptr;
+  HIP_TRY(c, hipEventCreate(&ea));
+  HIP_TRY(c, hipEventCreate(&eb));
+  metade_status st = METADE_OK;
+  for (uint32_t r : rows) {
+    for (uint32_t lp : parts) {
+      const metade_tuning t{lp, r};
+      if ((st = metade_set_tuning(c, &t)) != METADE_OK) break;
+      double tmin = 1e300;
+      for (int rep = 0; rep < 3 && st == METADE_OK; ++rep) {   // first run warms up
+        if ((st = metade_set_state(c, blob.data(), bytes)) != METADE_OK) break;
+        hipError_t e = hipEventRecord(ea, c->stream);
+        if (e == hipSuccess && (st = run_generations(c, n_gens, mde::TraceArgs{nullptr, nullptr, nullptr})) != METADE_OK) break;
+        if (e == hipSuccess) e = hipEventRecord(eb, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(eb);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, ea, eb);
+        if (e != hipSuccess) { st = fail(c, METADE_EDEVICE, std::string("autotune timing: ") + hipGetErrorString(e)); break; }
+        if (rep > 0) tmin = std::min(tmin, (double)ms);
+      }
+      if (st != METADE_OK) break;
+      if (tmin < best_t) { best_t = tmin; best = t; }
+    }
+    if (st != METADE_OK) break;
+  }
+  (void)hipEventDestroy(ea);
+  (void)hipEventDestroy(eb);
+  c->timing = timing0;
+  if (st != METADE_OK) return st;
+  TRY(metade_set_tuning(c, &best));
+  TRY(metade_set_state(c, blob.data(), bytes));
+  c->trials = trials0;
+  HIP_TRY(c, hipMemcpy(c->counters_d, cnt0, sizeof(cnt0), hipMemcpyHostToDevice));
+  if (cache_path) {
+    std::ofstream out(cache_path, std::ios::app);
+    if (out) out << keyhex << " " << best.lane_parts << " " << best.mfma_rows << " " << best_t << "\n";
+  }
+  if (chosen) *chosen = best;
+  if (best_ms) *best_ms = best_t;
+  return METADE_OK;
+}
 
 const char *metade_last_error(const metade_ctx *c) {
   return c ? c->err.c_str() : g_init_error.c_str();

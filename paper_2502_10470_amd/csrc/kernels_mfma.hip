@@ -65,12 +65,11 @@ constexpr float E_AB = 7.0e-5f;
 // rows are zero beyond D, so no operand needs a bounds test.  RR row tiles at
 // once (rows given per tile): RR independent accumulator chains sharing the A
 // loads, so that consecutive matrix-core instructions do not wait on each
-// other's results.  The plain rotation takes four row tiles per item, the
-// bf16 mode's re-evaluation two.  (Storing the operands in float64 to spare
+// other's results.  The plain rotation takes two or four row tiles per item
+// (a tuning choice, RTF), the bf16 mode's re-evaluation two.  (Storing the operands in float64 to spare
 // the conversions was measured slower: the rotation waits on its loads, and
 // float64 operands double them.)
 constexpr int RT = 2;
-constexpr int RT_F64 = 4;
 
 template <int RR>
 __device__ __forceinline__ void tiles_f64(const float *__restrict__ Tg, uint32_t Dk,
@@ -395,7 +394,7 @@ __device__ __forceinline__ void mfma_producers(const MLds &lay, unsigned char *s
   __syncthreads();
 }
 
-template <bool BF16, bool TRACE>
+template <bool BF16, bool TRACE, int RTF>
 __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run,
                                           const ProbDev &p, const unsigned char *__restrict__ tab,
                                           float *__restrict__ pop, float *__restrict__ fit,
@@ -465,9 +464,9 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
       }
     }
   // the rotation's items, shared by consumers and producers: plain, (output
-  // tile, RT_F64 row tiles) in float64; bf16, (output tile, RT row tiles)
+  // tile, RTF row tiles) in float64; bf16, (output tile, RT row tiles)
   // from the bf16 splits with each output's error radius
-  constexpr uint32_t RTI = BF16 ? RT : RT_F64;
+  constexpr uint32_t RTI = BF16 ? RT : RTF;
   const uint32_t n_items = NCT * ((NRT + RTI - 1) / RTI);
   auto item = [&](uint32_t it) {
     const uint32_t lane = tid & 63;
@@ -491,10 +490,10 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
                                    zf, zl);
       }
     } else {
-      d4v acc[RT_F64];
+      d4v acc[RTF];
       tiles_f64(Tg, Dk, rok, rtr, R32, Rs, 16 * ci + (lane & 15), lane, acc);
 #pragma unroll
-      for (int r = 0; r < RT_F64; ++r) {
+      for (int r = 0; r < RTF; ++r) {
         float z[4];
         tile_z(acc[r], ro_s, ci, lane, z);
         const float e0[4] = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -752,7 +751,7 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
   for (uint32_t r = tid; r < N; r += MF_THREADS) fit[run.fit_off + r] = fit_s[r];
 }
 
-template <bool BF16, bool TRACE>
+template <bool BF16, bool TRACE, int RTF>
 __global__ __launch_bounds__(MF_THREADS) void k_generations_mfma(
     const RunDev *__restrict__ runs, const uint32_t *__restrict__ list,
     const ProbDev *__restrict__ probs, const unsigned char *__restrict__ tab,
@@ -767,7 +766,7 @@ __global__ __launch_bounds__(MF_THREADS) void k_generations_mfma(
 #define MDE_KIND(K)                                                                     \
   case K:                                                                               \
     p.kind = K;                                                                         \
-    mfma_body<BF16, TRACE>(smem, run, p, tab, pop, fit, g0, n_gens, k0, k1, lb, ub,     \
+    mfma_body<BF16, TRACE, RTF>(smem, run, p, tab, pop, fit, g0, n_gens, k0, k1, lb, ub, \
                            tbuf + run.pend_off, counters, tr);                          \
     break;
   switch (p.kind) {
@@ -814,10 +813,12 @@ hipError_t read_stage_clocks_mfma(void *dst, size_t bytes) {
 #endif
 
 hipError_t set_lds_limits_mfma() {
-  const void *ks[4] = {(const void *)k_generations_mfma<false, false>,
-                       (const void *)k_generations_mfma<false, true>,
-                       (const void *)k_generations_mfma<true, false>,
-                       (const void *)k_generations_mfma<true, true>};
+  const void *ks[6] = {(const void *)k_generations_mfma<false, false, 2>,
+                       (const void *)k_generations_mfma<false, true, 2>,
+                       (const void *)k_generations_mfma<false, false, 4>,
+                       (const void *)k_generations_mfma<false, true, 4>,
+                       (const void *)k_generations_mfma<true, false, RT>,
+                       (const void *)k_generations_mfma<true, true, RT>};
   for (const void *k : ks) {
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BUDGET);
     if (e != hipSuccess) return e;
@@ -830,14 +831,16 @@ hipError_t launch_generations_mfma(const LaunchArgs &a, const uint32_t *list, ui
                                    unsigned long long *counters, TraceArgs tr) {
   if (n == 0) return hipSuccess;
   const bool trace = tr.u != nullptr;
-#define MDE_LAUNCH(B, T)                                                                       \
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_generations_mfma<B, T>), dim3(n), dim3(MF_THREADS),     \
+#define MDE_LAUNCH(B, T, R)                                                                    \
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_generations_mfma<B, T, R>), dim3(n), dim3(MF_THREADS),  \
                      a.mfma_lds_bytes, a.stream, a.runs, list, a.probs, a.tab, a.pop, a.fit, g0, \
                      n_gens, a.k0, a.k1, lb, ub, a.pending, counters, tr)
   if (bf16) {
-    if (trace) MDE_LAUNCH(true, true); else MDE_LAUNCH(true, false);
+    if (trace) MDE_LAUNCH(true, true, RT); else MDE_LAUNCH(true, false, RT);
+  } else if (a.mfma_rows == 2) {
+    if (trace) MDE_LAUNCH(false, true, 2); else MDE_LAUNCH(false, false, 2);
   } else {
-    if (trace) MDE_LAUNCH(false, true); else MDE_LAUNCH(false, false);
+    if (trace) MDE_LAUNCH(false, true, 4); else MDE_LAUNCH(false, false, 4);
   }
 #undef MDE_LAUNCH
   return hipGetLastError();

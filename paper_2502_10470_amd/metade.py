@@ -49,6 +49,10 @@ class MetadeConfig(ctypes.Structure):
     ]
 
 
+class MetadeTuning(ctypes.Structure):
+    _fields_ = [("lane_parts", ctypes.c_uint32), ("mfma_rows", ctypes.c_uint32)]
+
+
 class MetadeError(RuntimeError):
     pass
 
@@ -77,6 +81,10 @@ _SIGS = {
     "metade_get_counters": [_vp, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)],
     "metade_get_bound_check": [_vp] + [ctypes.POINTER(ctypes.c_uint64)] * 4
                               + [ctypes.POINTER(ctypes.c_double)],
+    "metade_get_tuning": [_vp, ctypes.POINTER(MetadeTuning)],
+    "metade_set_tuning": [_vp, ctypes.POINTER(MetadeTuning)],
+    "metade_autotune": [_vp, _u32, ctypes.c_char_p, ctypes.POINTER(MetadeTuning),
+                        ctypes.POINTER(ctypes.c_double)],
 }
 EXPORTED = tuple(_SIGS) + ("metade_last_error", "metade_destroy")
 
@@ -230,6 +238,27 @@ def metade_get_bound_check(ctx):
     return tuple(int(x.value) for x in v) + (float(r.value),)
 
 
+def metade_get_tuning(ctx):
+    t = MetadeTuning()
+    _check(lib().metade_get_tuning(ctx, ctypes.byref(t)), ctx)
+    return {"lane_parts": int(t.lane_parts), "mfma_rows": int(t.mfma_rows)}
+
+
+def metade_set_tuning(ctx, lane_parts: int = 0, mfma_rows: int = 0):
+    t = MetadeTuning(lane_parts, mfma_rows)
+    _check(lib().metade_set_tuning(ctx, ctypes.byref(t)), ctx)
+
+
+def metade_autotune(ctx, n_generations: int, cache_path: Optional[str] = None):
+    """(chosen tuning as a dict, its milliseconds for n_generations)."""
+    t = MetadeTuning()
+    ms = ctypes.c_double()
+    path = cache_path.encode() if cache_path else None
+    _check(lib().metade_autotune(ctx, int(n_generations), path, ctypes.byref(t), ctypes.byref(ms)),
+           ctx)
+    return {"lane_parts": int(t.lane_parts), "mfma_rows": int(t.mfma_rows)}, float(ms.value)
+
+
 def metade_last_error(ctx=None) -> str:
     return lib().metade_last_error(ctx).decode()
 
@@ -381,6 +410,15 @@ class Batch:
 
     def bound_check(self):
         return metade_get_bound_check(self.ctx)
+
+    def tuning(self):
+        return metade_get_tuning(self.ctx)
+
+    def set_tuning(self, lane_parts=0, mfma_rows=0):
+        metade_set_tuning(self.ctx, lane_parts, mfma_rows)
+
+    def autotune(self, n_generations, cache_path=None):
+        return metade_autotune(self.ctx, n_generations, cache_path)
 
     # -- host views (synchronise)
     def host_state(self):

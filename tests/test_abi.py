@@ -41,6 +41,7 @@ def test_struct_layout_matches_c(tmp_path):
     fields_c = [f[0] for f in M.MetadeConfig._fields_]
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "metade.h"', 'int main(void){']
     lines.append('printf("%zu %zu\\n", sizeof(metade_problem), sizeof(metade_config));')
+    lines.append('printf("%zu %zu\\n", sizeof(metade_tuning), offsetof(metade_tuning, mfma_rows));')
     for f in fields_p:
         lines.append(f'printf("%zu\\n", offsetof(metade_problem, {f}));')
     for f in fields_c:
@@ -51,7 +52,8 @@ def test_struct_layout_matches_c(tmp_path):
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
     assert vals[0] == ctypes.sizeof(M.MetadeProblem) and vals[1] == ctypes.sizeof(M.MetadeConfig)
-    k = 2
+    assert vals[2] == ctypes.sizeof(M.MetadeTuning) and vals[3] == M.MetadeTuning.mfma_rows.offset
+    k = 4
     for f in fields_p:
         assert vals[k] == getattr(M.MetadeProblem, f).offset, f
         k += 1
