@@ -47,10 +47,10 @@ KERNEL_SOURCES = {
                            "paper_2502_10470_amd/csrc/device.h"),
 }
 MEASURED_TRAFFIC = {
-    "4cd7f07d5b083480": (797.0 * 2.0 + 3854.0 * 1.0) * 1024,          # k_generations, C3
-    # k_generations_mfma at D = 100 (key: hash + precision); measured on an earlier
-    # version of the kernel, so it no longer matches and reports null
-    "d60c363f3e1b744e:fp32": (21362.5 * 2.0 + 7197942.1 * 1.0) * 1024,
+    "4a124848dc423847": (518.3 * 2.0 + 526.0 * 1.0) * 1024,            # k_generations, C3
+    # k_generations_mfma at D = 100, keyed by hash and precision
+    "e3cf82535a853f79:fp32": (18273.4 * 2.0 + 7728055.5 * 1.0) * 1024,
+    "e3cf82535a853f79:bf16": (2736613.3 * 2.0 + 12924027.0 * 1.0) * 1024,
 }
 
 PHILOX_SLOTS = 100   # 10 rounds x (2 quarter-rate 32x32->64 multiplies + 2 three-input XORs)
