@@ -220,16 +220,15 @@ metade_status metade_inner_step(metade_ctx *ctx, uint32_t n_generations);
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid allocation): exactly
  * metade_inner_step(ctx, n_generations), same kernels and same results, but
- * the matrix-core kernel's trial rows (and the bf16 mode's splits) live in
- * the library's static workspace instead of the context's scratch, and the
- * call allocates nothing: no hipMalloc, no events (it is not timed by
- * metade_kernel_timing), no graphs.  Asynchronous on the context's stream.
+ * the matrix-core kernel's trial rows live in the library's static workspace
+ * instead of the context's scratch, and the call allocates nothing: no
+ * hipMalloc, no events (it is not timed by metade_kernel_timing), no graphs.  Asynchronous on the context's stream.
  * The workspace is shared by every call on a GPU and keeps the last call's
  * contents (nothing in it needs to start at zero): calls that overlap on one
  * GPU -- from contexts on different streams or threads -- race and must be
  * serialised by the caller.  METADE_EINVAL if the context has control runs,
  * if its trial rows need more than METADE_STATIC_SCRATCH_BYTES (sum over the
- * matrix-core runs of N * Dk * 8 bytes, Dk = D rounded up to 32), or if the
+ * matrix-core runs of N * Dk * 4 bytes, Dk = D rounded up to 32), or if the
  * current device is not the one the context was created on. */
 metade_status metade_inner_step_static(metade_ctx *ctx, uint32_t n_generations);
 

@@ -21,7 +21,7 @@ using mde::ProbDev;
 using mde::RunDev;
 
 // Workspace of metade_inner_step_static: the matrix-core kernel's trial rows
-// (and the bf16 mode's splits) of every run, at the run offsets the context
+// of every run, at the run offsets the context
 // uses for its own trial buffer.  One copy per GPU, held until the process
 // ends.  In host code this name is only a stand-in for the symbol: kernels
 // get the per-device address that hipGetSymbolAddress returns at init.
@@ -310,9 +310,9 @@ metade_status plan_config(const metade_config *cfg, Plan &pl, std::string &msg) 
     d.pend_off = pl.pend_floats;
     d.fit_off = (uint32_t)pl.fit_n;
     d.bx_off = (uint32_t)pl.bx_n;
-    // matrix-core runs: trial rows [N][Dk] float32, then the bf16 splits of
-    // u - o ([N][Dk] high parts and [N][Dk] low parts, as many bytes again)
-    if (d.kern == 1) pl.pend_floats += (size_t)N * d.Dk * 2;
+    // matrix-core runs: trial rows [N][Dk] float32 (both precisions; the bf16
+    // mode splits them in registers)
+    if (d.kern == 1) pl.pend_floats += (size_t)N * d.Dk;
     pl.pop_floats += (size_t)N * D;
     pl.fit_n += N;
     pl.bx_n += D;

@@ -212,9 +212,8 @@ __host__ __device__ inline Lds lds_layout(uint32_t N, uint32_t Dp, uint32_t L, u
 
 // Matrix-core generation kernel (runs whose trial rows do not fit in LDS, and
 // the bf16 precision mode; 512 consumer + 256 producer lanes): trial rows live
-// in a global buffer [N][Dk] (Dk = D rounded up to 32, zero padding), followed
-// in the bf16 mode by the bf16 splits of y = u - o ([N][Dk] high parts, then
-// low parts); LDS holds the population, ranking state, the producers' mask
+// in a global buffer [N][Dk] (Dk = D rounded up to 32, zero padding); LDS
+// holds the population, ranking state, the producers' mask
 // nibbles and packed draws, per (output tile, trial) partial sums (and
 // bounds in the bf16 mode), Rosenbrock
 // boundary values, the shift, R o, the element kind and elliptic weight of

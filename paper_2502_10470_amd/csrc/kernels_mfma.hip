@@ -5,10 +5,10 @@
 // run; lanes 0..511 are consumers, 512..767 producers of the next
 // generation's random draws (as in the lane-per-trial kernel).  The rotation
 // z = R (u - o) of all trials of a generation is a [N x D] x [D x D] product
-// done on the matrix cores: consumer wave w owns the 16-wide output tile w.
-// The bf16 mode keeps that tile's slice of R (split in bf16 parts) in
-// registers for the whole launch; the plain mode reads its float64
-// coefficients from the table for every block of k.
+// done on the matrix cores, dealt to the waves as (output tile, row tiles)
+// items from an LDS counter.  Both modes read a row-major float32 copy of R,
+// zero padded to whole tiles, and the float32 trial rows from a global
+// buffer.
 //
 // Plain mode: v_mfma_f64_16x16x4 on y = u - o in float64 (exact), the same
 // accuracy as the lane kernel's float64 accumulation.
@@ -143,8 +143,10 @@ __device__ __forceinline__ void rotation_items(uint32_t *ctr, uint32_t n_items, 
 // bf16 mode, transposed like the plain mode.  Lane l feeds trial 16 rt + l%16
 // with k = 32 s + 8 (l/16) + e; result element v is
 // z_hat[trial 16 rt + l%16][output 16 ct + 4 (l/16) + v].  The trial operands
-// are the bf16 splits of y = u - o written once per trial when it is built.
-// ab[r] receives sum_k |R_hi jk| |y_hi k| for the outputs' error radii.
+// are the bf16 splits of y = u - o (float32 subtraction), formed here from the
+// float32 trial rows, which the exact re-evaluation reads as well: one buffer
+// per run in the cache instead of three.  ab[r] receives
+// sum_k |R_hi jk| |y_hi k| for the outputs' error radii.
 __device__ __forceinline__ bf8v abs8(const bf8v &x) {
   uint4 u = __builtin_bit_cast(uint4, x);
   u.x &= 0x7FFF7FFFu;
@@ -154,8 +156,19 @@ __device__ __forceinline__ bf8v abs8(const bf8v &x) {
   return __builtin_bit_cast(bf8v, u);
 }
 
-__device__ __forceinline__ void tiles_bf16(const __bf16 *__restrict__ Yh,
-                                           const __bf16 *__restrict__ Yl, uint32_t Dk,
+// bf16 parts of eight float32 values: hi = bf16(x), lo = bf16(x - hi).
+__device__ __forceinline__ void split8(const float4 &a, const float4 &b, bf8v &hi, bf8v &lo) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const float x = e < 4 ? comp(a, e) : comp(b, e - 4);
+    const __bf16 h = (__bf16)x;
+    hi[e] = h;
+    lo[e] = (__bf16)(x - (float)h);
+  }
+}
+
+__device__ __forceinline__ void tiles_bf16(const float *__restrict__ Tg,
+                                           const float *__restrict__ oc, uint32_t Dk,
                                            const bool (&row_ok)[RT],
                                            const uint32_t (&row_trial)[RT],
                                            const float *__restrict__ Rrow, uint32_t Rs,
@@ -179,21 +192,20 @@ __device__ __forceinline__ void tiles_bf16(const __bf16 *__restrict__ Yh,
           ra = *reinterpret_cast<const float4 *>(Rrow + k0);
           rb = *reinterpret_cast<const float4 *>(Rrow + k0 + 4);
         }
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const float r = e < 4 ? comp(ra, e) : comp(rb, e - 4);
-          const __bf16 h = (__bf16)r;
-          bh[e] = h;
-          bl[e] = (__bf16)(r - (float)h);
-        }
+        split8(ra, rb, bh, bl);
       }
+      const float4 oa = *reinterpret_cast<const float4 *>(oc + k0);
+      const float4 ob = *reinterpret_cast<const float4 *>(oc + k0 + 4);
       bf8v ah[RT], al[RT];
 #pragma unroll
       for (int r = 0; r < RT; ++r) {
-        const size_t off = (size_t)row_trial[r] * Dk + k0;
         if (row_ok[r]) {
-          ah[r] = *reinterpret_cast<const bf8v *>(Yh + off);
-          al[r] = *reinterpret_cast<const bf8v *>(Yl + off);
+          const float *t = Tg + (size_t)row_trial[r] * Dk + k0;
+          float4 ya = *reinterpret_cast<const float4 *>(t);
+          float4 yb = *reinterpret_cast<const float4 *>(t + 4);
+          ya.x -= oa.x; ya.y -= oa.y; ya.z -= oa.z; ya.w -= oa.w;
+          yb.x -= ob.x; yb.y -= ob.y; yb.z -= ob.z; yb.w -= ob.w;
+          split8(ya, yb, ah[r], al[r]);
         } else {
 #pragma unroll
           for (int e = 0; e < 8; ++e) ah[r][e] = al[r][e] = (__bf16)0.0f;
@@ -423,9 +435,6 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
   float *ew_s = reinterpret_cast<float *>(smem + lay.ew);
   uint32_t *cl = reinterpret_cast<uint32_t *>(smem + lay.cl);
   uint32_t *cnt = reinterpret_cast<uint32_t *>(smem + lay.cnt);
-  // bf16 mode: splits of y = u - o after the trial rows
-  __bf16 *Yh = reinterpret_cast<__bf16 *>(Tg + (size_t)N * Dk);
-  __bf16 *Yl = Yh + (size_t)N * Dk;
   const double *Rt = tab_ptr<double>(tab, p.r64t_off);
   const uint32_t Dr = rt_stride(D);
   // row-major float32 rotation, zero padded to Rs x Rs, and R o
@@ -458,10 +467,6 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
       const uint32_t r = u / (Dk - Dp);
       const size_t at = (size_t)r * Dk + Dp + (u - r * (Dk - Dp));
       Tg[at] = 0.0f;
-      if (BF16) {
-        Yh[at] = (__bf16)0.0f;
-        Yl[at] = (__bf16)0.0f;
-      }
     }
   // the rotation's items, shared by consumers and producers: plain, (output
   // tile, RTF row tiles) in float64; bf16, (output tile, RT row tiles)
@@ -480,7 +485,7 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
     }
     if constexpr (BF16) {
       f4v acc[RT], ab[RT];
-      tiles_bf16(Yh, Yl, Dk, rok, rtr, R32 + (size_t)(16 * ci + (lane & 15)) * Rs, Rs, lane, acc,
+      tiles_bf16(Tg, oc, Dk, rok, rtr, R32 + (size_t)(16 * ci + (lane & 15)) * Rs, Rs, lane, acc,
                  ab);
 #pragma unroll
       for (int r = 0; r < RT; ++r) {
@@ -557,8 +562,7 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
     __syncthreads();
     MDE_STAGE(2)
     // S2: trial genes -> global trial rows.  P lanes per trial (a power of
-    // two, as many as the consumers allow) take its quads in turn; in the bf16
-    // mode they also write the bf16 splits of y = u - o.
+    // two, as many as the consumers allow) take its quads in turn.
     if (tid == 0) cnt[15] = 0;   // the rotation's item counter
     const uint8_t *mg = msk;
     if (!producer) {
@@ -576,21 +580,6 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
             const uint32_t nib = run.cs == BIN ? mg[i * Q + q] : 0u;
             const float4 uu = trial_quad(pop_s, Dp, D, i, q, ibl, ibr, d, nib, run, lb, ub);
             *reinterpret_cast<float4 *>(Tg + (size_t)i * Dk + 4 * q) = uu;
-            if (BF16) {
-              uint32_t hb[4], lb16[4];
-#pragma unroll
-              for (int t = 0; t < 4; ++t) {
-                const float y = comp(uu, t) - oc[4 * q + t];
-                const __bf16 h = (__bf16)y;
-                const __bf16 lo = (__bf16)(y - (float)h);
-                hb[t] = __builtin_bit_cast(uint16_t, h);
-                lb16[t] = __builtin_bit_cast(uint16_t, lo);
-              }
-              *reinterpret_cast<uint2 *>(Yh + (size_t)i * Dk + 4 * q) =
-                  make_uint2(hb[0] | (hb[1] << 16), hb[2] | (hb[3] << 16));
-              *reinterpret_cast<uint2 *>(Yl + (size_t)i * Dk + 4 * q) =
-                  make_uint2(lb16[0] | (lb16[1] << 16), lb16[2] | (lb16[3] << 16));
-            }
             if (TRACE) {
 #pragma unroll
               for (int t = 0; t < 4; ++t)
