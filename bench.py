@@ -49,8 +49,8 @@ KERNEL_SOURCES = {
 MEASURED_TRAFFIC = {
     "4a124848dc423847": (518.3 * 2.0 + 526.0 * 1.0) * 1024,            # k_generations, C3
     # k_generations_mfma at D = 100, keyed by hash and precision
-    "e3cf82535a853f79:fp32": (18273.4 * 2.0 + 7728055.5 * 1.0) * 1024,
-    "e3cf82535a853f79:bf16": (2736613.3 * 2.0 + 12924027.0 * 1.0) * 1024,
+    "5cb28480fc3526b7:fp32": (18280.9 * 2.0 + 7227947.7 * 1.0) * 1024,
+    "5cb28480fc3526b7:bf16": (18513.0 * 2.0 + 6394125.6 * 1.0) * 1024,
 }
 
 PHILOX_SLOTS = 100   # 10 rounds x (2 quarter-rate 32x32->64 multiplies + 2 three-input XORs)

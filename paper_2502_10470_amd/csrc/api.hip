@@ -311,8 +311,13 @@ metade_status plan_config(const metade_config *cfg, Plan &pl, std::string &msg) 
     d.fit_off = (uint32_t)pl.fit_n;
     d.bx_off = (uint32_t)pl.bx_n;
     // matrix-core runs: trial rows [N][Dk] float32 (both precisions; the bf16
-    // mode splits them in registers)
-    if (d.kern == 1) pl.pend_floats += (size_t)N * d.Dk;
+    // mode splits them in registers), each run's rows 4 KB after the previous
+    // run's end.  Without the skew the runs that share an XCD (every eighth
+    // workgroup) start their rows at the same offset within the L2's set
+    // period, and the sets they share overflow: at D = 100 the rotation's
+    // re-reads of the rows then came from memory (7.8 GB per launch instead of
+    // 37 MB) with no change in time.
+    if (d.kern == 1) pl.pend_floats += (size_t)N * d.Dk + 1024;
     pl.pop_floats += (size_t)N * D;
     pl.fit_n += N;
     pl.bx_n += D;
