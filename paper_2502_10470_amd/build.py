@@ -1,4 +1,4 @@
-"""Build of libmetade.so (gfx950) and of the oracle's C helpers.
+"""Build of libmetade.so for gfx950 with hipcc.
 
 Run as ``python -m paper_2502_10470_amd.build``.  The library is compiled
 in-tree so it travels with the source tree.
