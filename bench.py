@@ -47,7 +47,7 @@ KERNEL_SOURCES = {
                            "paper_2502_10470_amd/csrc/device.h"),
 }
 MEASURED_TRAFFIC = {
-    "4a124848dc423847": (518.3 * 2.0 + 526.0 * 1.0) * 1024,            # k_generations, C3
+    "58978f79ff493ee0": (529.85 * 2.0 + 526.0 * 1.0) * 1024,           # k_generations, C3
     # k_generations_mfma at D = 100, keyed by hash and precision
     "5cb28480fc3526b7:fp32": (18280.9 * 2.0 + 7227947.7 * 1.0) * 1024,
     "5cb28480fc3526b7:bf16": (18513.0 * 2.0 + 6394125.6 * 1.0) * 1024,

@@ -15,15 +15,17 @@ MDE_STAGE_ARRAY;
 
 // ---------------------------------------------------------------- fitness of one row, split by output
 
-// acc[q] = sum_k R[jc+q][k] (u_k - o_k) in float64 for q < J, from the
-// transposed rotation Rt[k][j]: the J coefficients of one k are contiguous
-// and wave-uniform, so they arrive by wide scalar loads and feed the FMAs as
-// scalar operands.  u_k = t[k*ts] is the lane's own trial.  Outputs past D
-// read the padding columns of Rt (zero) and are not used.
+// acc[q] = sum_k R[jc+q][k] u_k in float64 for q < J, from the transposed
+// rotation Rt[k][j]: the J coefficients of one k are contiguous and
+// wave-uniform, so they arrive by wide scalar loads and feed the FMAs as
+// scalar operands.  u_k = t[k*ts] is the lane's own trial.  The products of
+// two float32 values are exact in float64; R o is subtracted per output
+// afterwards (z = R u - R o, R o precomputed in float64), which spares a
+// subtraction and a load per k.  Outputs past D read the padding columns of
+// Rt (zero) and are not used.
 template <int J, typename TP>
 __device__ __forceinline__ void rot_block(const double *__restrict__ Rt, uint32_t D, uint32_t Dr,
-                                          uint32_t jc, TP t, uint32_t ts,
-                                          const double *__restrict__ o, double (&acc)[J]) {
+                                          uint32_t jc, TP t, uint32_t ts, double (&acc)[J]) {
 #pragma unroll
   for (int q = 0; q < J; ++q) acc[q] = 0.0;
   const double *col = Rt + jc;
@@ -34,14 +36,14 @@ __device__ __forceinline__ void rot_block(const double *__restrict__ Rt, uint32_
     for (int kk = 0; kk < 8; ++kk) tv[kk] = t[(k + kk) * ts];
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk) {
-      const double yk = (double)tv[kk] - o[k + kk];
+      const double yk = (double)tv[kk];
       const double *c = col + (size_t)(k + kk) * Dr;
 #pragma unroll
       for (int q = 0; q < J; ++q) acc[q] = fma(c[q], yk, acc[q]);
     }
   }
   for (; k < D; ++k) {
-    const double yk = (double)t[k * ts] - o[k];
+    const double yk = (double)t[k * ts];
     const double *c = col + (size_t)k * Dr;
 #pragma unroll
     for (int q = 0; q < J; ++q) acc[q] = fma(c[q], yk, acc[q]);
@@ -61,8 +63,8 @@ __device__ __forceinline__ void consume(const unsigned char *tab, const ProbDev 
 #pragma unroll
   for (int q = 0; q < J; ++q) {
     if ((uint32_t)q < n) {
-      const float z = (float)a[q];
       const uint32_t j = jc + q;
+      const float z = (float)(a[q] - tab_ptr<double>(tab, p.ro64_off)[j]);
       if (p.kind == FN_ROSENBROCK) {
         if (ta.have && j - 1 < j1) ta.s0 += (double)h_rosenbrock<float>(ta.prevz, z);
         ta.prevz = z;
@@ -78,16 +80,16 @@ __device__ __forceinline__ void consume(const unsigned char *tab, const ProbDev 
 }
 
 // Sum of the element terms of outputs [j0, j1) of the row at t (gene stride
-// ts).  Plain path: z = R (u - o) accumulated in float64 -- y is exact, so a
-// small z_j that cancels between large products keeps its relative accuracy --
-// z rounded once to float32, element terms in float32, sums in float64.
+// ts).  Plain path: z = R u - R o accumulated in float64 -- the products are
+// exact and the sums round at 2^-53 of |R| |u|, so a small z_j that cancels
+// between large terms still comes out far below float32 resolution -- z
+// rounded once to float32, element terms in float32, sums in float64.
 template <typename TP>
 __device__ __forceinline__ void eval_part(const unsigned char *__restrict__ tab, const ProbDev &p,
                                           uint32_t D, uint32_t j0, uint32_t j1, TP t, uint32_t ts,
                                           double &s0, double &s1) {
   const double *Rt = tab_ptr<double>(tab, p.r64t_off);
   const uint32_t Dr = rt_stride(D);
-  const double *o = tab_ptr<double>(tab, p.o64_off);
   TermAcc ta{0.0, 0.0, 0.0f, false};
   const uint32_t jend = p.kind == FN_ROSENBROCK ? min(j1 + 1, D) : j1;
   uint32_t jc = j0;
@@ -96,7 +98,7 @@ __device__ __forceinline__ void eval_part(const unsigned char *__restrict__ tab,
 #define MDE_BLOCK(JJ)                                        \
   {                                                          \
     double a[JJ];                                            \
-    rot_block<JJ>(Rt, D, Dr, jc, t, ts, o, a);               \
+    rot_block<JJ>(Rt, D, Dr, jc, t, ts, a);                  \
     consume<JJ>(tab, p, a, jc, min(rem, (uint32_t)JJ), j1, ta); \
     jc += JJ;                                                \
   }
