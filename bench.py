@@ -47,10 +47,10 @@ KERNEL_SOURCES = {
                            "paper_2502_10470_amd/csrc/device.h"),
 }
 MEASURED_TRAFFIC = {
-    "58978f79ff493ee0": (529.85 * 2.0 + 526.0 * 1.0) * 1024,           # k_generations, C3
+    "cf68567609c41e3d": (529.51 * 2.0 + 526.0 * 1.0) * 1024,           # k_generations, C3
     # k_generations_mfma at D = 100, keyed by hash and precision
-    "5cb28480fc3526b7:fp32": (18280.9 * 2.0 + 7227947.7 * 1.0) * 1024,
-    "5cb28480fc3526b7:bf16": (18513.0 * 2.0 + 6394125.6 * 1.0) * 1024,
+    "fdba902ee34142a7:fp32": (34160.9 * 2.0 + 6982593.3 * 1.0) * 1024,
+    "fdba902ee34142a7:bf16": (32223.1 * 2.0 + 6183809.1 * 1.0) * 1024,
 }
 
 PHILOX_SLOTS = 100   # 10 rounds x (2 quarter-rate 32x32->64 multiplies + 2 three-input XORs)

@@ -219,7 +219,6 @@ metade_status plan_config(const metade_config *cfg, Plan &pl, std::string &msg) 
     (void)cond;
     // read-only table layout of this problem
     p.o_off = take((size_t)q.D * sizeof(float));
-    p.o64_off = take((size_t)q.D * sizeof(double));
     // transposed float64 rotation [D][rt_stride]; the row-major float32 one
     // zero padded to whole 16-wide tiles, and R o, that the matrix-core kernel reads
     p.r64t_off = take((size_t)q.D * mde::rt_stride(q.D) * sizeof(double));
@@ -630,8 +629,7 @@ metade_status metade_init(const metade_config *cfg, metade_ctx **out) {
     if (e4 == hipSuccess) e4 = hipMemcpy(t + p.ek_off, ek.data(), p.D * sizeof(uint32_t), hipMemcpyHostToDevice);
     if (e4 == hipSuccess) e4 = hipMemcpy(t + p.o_off, q.o, p.D * sizeof(float), hipMemcpyDeviceToDevice);
     if (e4 == hipSuccess)
-      e4 = mde::launch_tables64(q.R, q.o, reinterpret_cast<double *>(t + p.r64t_off),
-                                reinterpret_cast<double *>(t + p.o64_off), p.D, c->stream);
+      e4 = mde::launch_tables64(q.R, reinterpret_cast<double *>(t + p.r64t_off), p.D, c->stream);
     if (e4 == hipSuccess)
       e4 = mde::launch_tables_mfma(q.R, q.o, reinterpret_cast<float *>(t + p.r32_off),
                                    reinterpret_cast<double *>(t + p.ro64_off), p.D, c->stream);

@@ -96,7 +96,6 @@ struct ProbDev {
   float bias, cs_f;             // cs = Schwefel constant z* sin(sqrt z*)
   double cs_d;
   uint64_t o_off;               // float  [D]    shift
-  uint64_t o64_off;             // double [D]    same in float64
   uint64_t r64t_off;            // double [D][rt_stride] rotation transposed: (k, j) = R[j][k]
   uint64_t r32_off;             // float  [Rs][Rs] row-major R zero padded to Rs = r32_stride(D)
   uint64_t ro64_off;            // double [Rs]   R o (zero past D): z = R u - R o

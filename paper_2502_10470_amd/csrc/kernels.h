@@ -54,8 +54,7 @@ hipError_t read_stage_clocks(void *dst, size_t bytes);
 hipError_t read_stage_clocks_mfma(void *dst, size_t bytes);
 #endif
 hipError_t set_lds_limits();
-hipError_t launch_tables64(const float *R, const float *o, double *Rt, double *o64, uint32_t D,
-                           hipStream_t s);
+hipError_t launch_tables64(const float *R, double *Rt, uint32_t D, hipStream_t s);
 hipError_t launch_init(const LaunchArgs &a, double lb, double ub);
 hipError_t launch_generations(const LaunchArgs &a, const uint32_t *list, uint32_t n,
                               uint32_t g0, uint32_t n_gens, float lb, float ub, TraceArgs tr);

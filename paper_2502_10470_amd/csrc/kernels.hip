@@ -858,11 +858,9 @@ __global__ void k_outer_best(const double *__restrict__ y, uint32_t P, int32_t *
 
 // Rt[k][j] = R[j][k] in float64, row stride Dr >= D + 16 (zero padding so a
 // block of 16 outputs starting anywhere below D stays inside the row).
-__global__ void k_tables64(const float *__restrict__ R, const float *__restrict__ o,
-                           double *__restrict__ Rt, double *__restrict__ o64, uint32_t D,
+__global__ void k_tables64(const float *__restrict__ R, double *__restrict__ Rt, uint32_t D,
                            uint32_t Dr) {
   const uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
-  if (u < D) o64[u] = (double)o[u];
   if (u >= D * Dr) return;
   const uint32_t k = u / Dr, j = u - k * Dr;
   Rt[u] = j < D ? (double)R[(size_t)j * D + k] : 0.0;
@@ -870,11 +868,9 @@ __global__ void k_tables64(const float *__restrict__ R, const float *__restrict_
 
 // ---------------------------------------------------------------- launchers
 
-hipError_t launch_tables64(const float *R, const float *o, double *Rt, double *o64, uint32_t D,
-                           hipStream_t s) {
+hipError_t launch_tables64(const float *R, double *Rt, uint32_t D, hipStream_t s) {
   const uint32_t n = D * rt_stride(D);
-  hipLaunchKernelGGL(k_tables64, dim3((n + 255) / 256), dim3(256), 0, s, R, o, Rt, o64, D,
-                     rt_stride(D));
+  hipLaunchKernelGGL(k_tables64, dim3((n + 255) / 256), dim3(256), 0, s, R, Rt, D, rt_stride(D));
   return hipGetLastError();
 }
 

@@ -384,7 +384,7 @@ __device__ __forceinline__ void mfma_producers(const MLds &lay, unsigned char *s
   uint8_t *msk = reinterpret_cast<uint8_t *>(smem + lay.msk);
   uint4 *dsc = reinterpret_cast<uint4 *>(smem + lay.dsc);
   constexpr uint32_t NP = MF_THREADS - MF_CONSUMERS;
-  produce_masks(ptid, NP, run, N, Q, g0, k0, k1, msk);
+  produce_masks<true>(ptid, NP, run, N, Q, g0, k0, k1, msk);
   __syncthreads();
   produce_desc_direct(ptid, NP, run, N, D, kp, g0, k0, k1, msk, dsc);
   for (uint32_t gg = 0; gg < n_gens; ++gg) {
@@ -393,7 +393,7 @@ __device__ __forceinline__ void mfma_producers(const MLds &lay, unsigned char *s
     __syncthreads();   // top-p list
     __syncthreads();   // trial construction (reads the masks of g)
     __syncthreads();   // rotation: the masks of g are free
-    produce_masks(ptid, NP, run, N, Q, g + 1, k0, k1, msk);
+    produce_masks<true>(ptid, NP, run, N, Q, g + 1, k0, k1, msk);
     rotation_items(ctr, n_items, ptid & 63, item);   // then help with the rotation
     __syncthreads();   // decisions (plain) or screen (bf16)
     if (BF16) {
