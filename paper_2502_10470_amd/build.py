@@ -34,13 +34,16 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source to its own object (in parallel), then link."""
+def build(verbose: bool = False, defines: tuple = (), tag: str = "") -> str:
+    """Compile every source to its own object (in parallel), then link.  With
+    a tag, the objects go to _build/<tag> and the library to
+    libmetade_<tag>.so (diagnostic builds with extra -D defines)."""
     from concurrent.futures import ThreadPoolExecutor
 
-    objdir = os.path.join(HERE, "_build")
+    objdir = os.path.join(HERE, "_build", tag) if tag else os.path.join(HERE, "_build")
+    out = os.path.join(HERE, f"libmetade_{tag}.so") if tag else LIB
     os.makedirs(objdir, exist_ok=True)
-    compile_flags = [f for f in HIP_FLAGS if f != "-shared"]
+    compile_flags = [f for f in HIP_FLAGS if f != "-shared"] + [f"-D{d}" for d in defines]
 
     def compile_one(src: str) -> str:
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
@@ -56,16 +59,16 @@ def build(verbose: bool = False) -> str:
 
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         objs = list(ex.map(compile_one, SOURCES))
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed linking libmetade.so")
-    os.replace(tmp, LIB)
-    return LIB
+        raise RuntimeError(f"hipcc failed linking {os.path.basename(out)}")
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -109,3 +109,23 @@ def test_words_uniform_chi2():
     w = philox.words(3, np.arange(4000), 0, 0, 16).ravel()
     counts = np.bincount(philox.lemire(w, 16), minlength=16)
     assert chisquare(counts).pvalue > 1e-4
+
+
+def test_integer_crossover_test_is_the_float_rule():
+    """The matrix-core kernel draws its crossover tests as (w >> 8) <
+    floor(CR 2^24) in integers; that must be exactly the rule r <= CR (Eqs. (8),
+    (9)) for the oracle's uniform r = ((w >> 8) + 1) 2^-24 and every float32 CR in
+    [0, 1], the end points and the values next to every threshold included."""
+    rng = np.random.default_rng(17)
+    crs = np.concatenate([rng.random(3000).astype(np.float32),
+                          np.array([0.0, 1.0, 0.5, 2.0 ** -24, 2.0 ** -25, 1.0 - 2.0 ** -24,
+                                    np.nextafter(np.float32(1), np.float32(0))], np.float32)])
+    for cr in crs:
+        thr = np.uint64(np.float32(cr) * np.float32(16777216.0))   # floor: CR 2^24 is exact
+        # words on both sides of the threshold, plus random ones
+        edge = np.array([min(max(int(thr) + d, 0), 2 ** 24 - 1) for d in (-1, 0, 1)],
+                        np.uint64) << np.uint64(8)   # 32-bit words only
+        w = np.concatenate([edge, edge + np.uint64(255), rng.integers(0, 2 ** 32, 256, dtype=np.uint64)])
+        want = philox.unit_open_closed(w) <= np.float32(cr)
+        got = (w >> np.uint64(8)) < thr
+        assert np.array_equal(got, want), float(cr)
