@@ -47,10 +47,10 @@ KERNEL_SOURCES = {
                            "paper_2502_10470_amd/csrc/device.h"),
 }
 MEASURED_TRAFFIC = {
-    "cf68567609c41e3d": (529.51 * 2.0 + 526.0 * 1.0) * 1024,           # k_generations, C3
+    "3eda44612ce39c50": (500.31 * 2.0 + 526.0 * 1.0) * 1024,           # k_generations, C3
     # k_generations_mfma at D = 100, keyed by hash and precision
-    "fdba902ee34142a7:fp32": (34160.9 * 2.0 + 6982593.3 * 1.0) * 1024,
-    "fdba902ee34142a7:bf16": (32223.1 * 2.0 + 6183809.1 * 1.0) * 1024,
+    "3bbe1aaa40bcd651:fp32": (24256.8 * 2.0 + 7058663.8 * 1.0) * 1024,
+    "3bbe1aaa40bcd651:bf16": (22847.2 * 2.0 + 6280852.6 * 1.0) * 1024,
 }
 
 PHILOX_SLOTS = 100   # 10 rounds x (2 quarter-rate 32x32->64 multiplies + 2 three-input XORs)

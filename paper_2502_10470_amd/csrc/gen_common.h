@@ -54,8 +54,10 @@ __device__ __forceinline__ void produce_masks(uint32_t ptid, uint32_t nprod, con
                                               uint32_t k1, uint8_t *msk) {
   if (run.cs != BIN && run.cs != EXP) return;
   const uint32_t thr = (uint32_t)(run.CR * 16777216.0f);
+  // item it = i Q + q, stepped by nprod without a division per item
+  const uint32_t di = nprod / Q, dq = nprod - di * Q;
+  uint32_t i = ptid / Q, q = ptid - i * Q;
   for (uint32_t it = ptid; it < N * Q; it += nprod) {
-    const uint32_t i = it / Q, q = it - i * Q;
     const uint4 w = philox(W_GENE0 / 4 + q, i, g, run.stream, k0, k1);
     uint32_t nib = 0;
 #pragma unroll
@@ -64,6 +66,12 @@ __device__ __forceinline__ void produce_masks(uint32_t ptid, uint32_t nprod, con
       nib |= (pass ? 1u : 0u) << t;
     }
     msk[it] = (uint8_t)nib;
+    i += di;
+    q += dq;
+    if (q >= Q) {
+      q -= Q;
+      ++i;
+    }
   }
 }
 
@@ -183,7 +191,11 @@ __device__ __forceinline__ float4 trial_quad(const float *pop_s, uint32_t Dp, ui
     const uint32_t n0 = byte_of(d.z, 2), Lx = d.z >> 24;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      const uint32_t off = (j0 + t + D - n0) % D;
+      // (j0 + t - n0) mod D: for a gene j0 + t < D the sum lies in [1, 2D), so
+      // one conditional subtraction is the remainder (padding genes past D
+      // take any value; they never reach a fitness)
+      uint32_t off = j0 + t + D - n0;
+      off = off >= D ? off - D : off;
       set_comp(uu, t, off < Lx ? comp(v, t) : comp(xi, t));
     }
   }
