@@ -221,7 +221,7 @@ constexpr uint32_t MF_THREADS = 768;
 constexpr uint32_t MF_CONSUMERS = 512;
 
 struct MLds {
-  uint32_t pop, key, fit, topk, rk, msk, dsc, ps, pb, zf, zl, oc, ro, ek, ew, cl, cnt, total;
+  uint32_t pop, key, fit, topk, rk, msk, dsc, ps, pb, zf, zl, oc, ro, ek, ew, cl, cnt, msk2, total;
 };
 
 __host__ __device__ inline MLds mfma_layout(uint32_t N, uint32_t Dp, uint32_t Dk, uint32_t L,
@@ -245,6 +245,16 @@ __host__ __device__ inline MLds mfma_layout(uint32_t N, uint32_t Dp, uint32_t Dk
   l.ew = o;   o += al16(Dk * 4);
   l.cl = o;   o += bf16 ? al16(N * 4) : 0u;
   l.cnt = o;  o += al16(16 * 4);
+  // plain mode: a second mask buffer where it fits, so that the producers
+  // draw the next generation's crossover tests while the consumers build this
+  // generation's trials (msk2 == msk: one buffer, the tests drawn during the
+  // rotation, as in the bf16 mode, whose rotation is not bound by the float64
+  // products)
+  l.msk2 = l.msk;
+  if (!bf16 && o + al16(N * (Dp / 4)) <= LDS_BUDGET) {
+    l.msk2 = o;
+    o += al16(N * (Dp / 4));
+  }
   l.total = o;
   return l;
 }

@@ -381,19 +381,26 @@ __device__ __forceinline__ void mfma_producers(const MLds &lay, unsigned char *s
                                                uint32_t k0, uint32_t k1, uint32_t ptid,
                                                uint32_t *ctr, uint32_t n_items, BODY &&item) {
   const uint32_t N = run.N, D = run.D, Q = run.Dp / 4, kp = run.kp;
-  uint8_t *msk = reinterpret_cast<uint8_t *>(smem + lay.msk);
+  uint8_t *const mbuf[2] = {reinterpret_cast<uint8_t *>(smem + lay.msk),
+                            reinterpret_cast<uint8_t *>(smem + lay.msk2)};
+  const bool two = lay.msk2 != lay.msk;
   uint4 *dsc = reinterpret_cast<uint4 *>(smem + lay.dsc);
   constexpr uint32_t NP = MF_THREADS - MF_CONSUMERS;
-  produce_masks<true>(ptid, NP, run, N, Q, g0, k0, k1, msk);
+  // with two mask buffers the tests of g+1 are drawn during the trial
+  // construction, which waits on LDS gathers, instead of during the rotation,
+  // whose float64 products the vector work would hold up
+  produce_masks<true>(ptid, NP, run, N, Q, g0, k0, k1, mbuf[g0 & 1u]);
   __syncthreads();
-  produce_desc_direct(ptid, NP, run, N, D, kp, g0, k0, k1, msk, dsc);
+  produce_desc_direct(ptid, NP, run, N, D, kp, g0, k0, k1, mbuf[g0 & 1u], dsc);
   for (uint32_t gg = 0; gg < n_gens; ++gg) {
     const uint32_t g = g0 + gg;
+    uint8_t *mn = two ? mbuf[(g + 1) & 1u] : mbuf[0];
     __syncthreads();   // generation g: consumers count ranks
     __syncthreads();   // top-p list
     __syncthreads();   // trial construction (reads the masks of g)
+    if (two) produce_masks<true>(ptid, NP, run, N, Q, g + 1, k0, k1, mn);
     __syncthreads();   // rotation: the masks of g are free
-    produce_masks<true>(ptid, NP, run, N, Q, g + 1, k0, k1, msk);
+    if (!two) produce_masks<true>(ptid, NP, run, N, Q, g + 1, k0, k1, mn);
     rotation_items(ctr, n_items, ptid & 63, item);   // then help with the rotation
     __syncthreads();   // decisions (plain) or screen (bf16)
     if (BF16) {
@@ -401,7 +408,7 @@ __device__ __forceinline__ void mfma_producers(const MLds &lay, unsigned char *s
       __syncthreads(); // candidate list
       __syncthreads(); // re-evaluation
     }
-    produce_desc_direct(ptid, NP, run, N, D, kp, g + 1, k0, k1, msk, dsc);
+    produce_desc_direct(ptid, NP, run, N, D, kp, g + 1, k0, k1, mn, dsc);
   }
   __syncthreads();
 }
@@ -564,7 +571,7 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
     // S2: trial genes -> global trial rows.  P lanes per trial (a power of
     // two, as many as the consumers allow) take its quads in turn.
     if (tid == 0) cnt[15] = 0;   // the rotation's item counter
-    const uint8_t *mg = msk;
+    const uint8_t *mg = msk + ((g & 1u) && lay.msk2 != lay.msk ? lay.msk2 - lay.msk : 0u);
     if (!producer) {
       const uint32_t lp = tid & (P - 1), per = MF_CONSUMERS / P;
       for (uint32_t i0 = 0; i0 < N; i0 += per) {
