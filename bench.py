@@ -47,10 +47,10 @@ KERNEL_SOURCES = {
                            "paper_2502_10470_amd/csrc/device.h"),
 }
 MEASURED_TRAFFIC = {
-    "3eda44612ce39c50": (500.31 * 2.0 + 526.0 * 1.0) * 1024,           # k_generations, C3
+    "b82b40f0651230e2": (500.31 * 2.0 + 526.0 * 1.0) * 1024,           # k_generations, C3
     # k_generations_mfma at D = 100, keyed by hash and precision
-    "3bbe1aaa40bcd651:fp32": (24256.8 * 2.0 + 7058663.8 * 1.0) * 1024,
-    "3bbe1aaa40bcd651:bf16": (22847.2 * 2.0 + 6280852.6 * 1.0) * 1024,
+    "5811758e93956fc4:fp32": (24557.9 * 2.0 + 7096852.1 * 1.0) * 1024,
+    "5811758e93956fc4:bf16": (22831.3 * 2.0 + 6285051.7 * 1.0) * 1024,
 }
 
 PHILOX_SLOTS = 100   # 10 rounds x (2 quarter-rate 32x32->64 multiplies + 2 three-input XORs)
