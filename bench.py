@@ -47,10 +47,10 @@ KERNEL_SOURCES = {
                            "paper_2502_10470_amd/csrc/device.h"),
 }
 MEASURED_TRAFFIC = {
-    "b82b40f0651230e2": (500.31 * 2.0 + 526.0 * 1.0) * 1024,           # k_generations, C3
+    "8f8747193f8c8855": (500.21 * 2.0 + 526.0 * 1.0) * 1024,           # k_generations, C3
     # k_generations_mfma at D = 100, keyed by hash and precision
-    "5811758e93956fc4:fp32": (24557.9 * 2.0 + 7096852.1 * 1.0) * 1024,
-    "5811758e93956fc4:bf16": (22831.3 * 2.0 + 6285051.7 * 1.0) * 1024,
+    "aaa5981486cb1d34:fp32": (37080.5 * 2.0 + 6881282.3 * 1.0) * 1024,
+    "aaa5981486cb1d34:bf16": (34000.4 * 2.0 + 6125759.1 * 1.0) * 1024,
 }
 
 PHILOX_SLOTS = 100   # 10 rounds x (2 quarter-rate 32x32->64 multiplies + 2 three-input XORs)

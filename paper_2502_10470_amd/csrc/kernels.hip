@@ -265,8 +265,10 @@ __device__ __forceinline__ void gen_consumers(const Lds &lay, unsigned char *sme
         }
         for (; j < b; ++j) cnt += key_s[j] < ki ? 1u : 0u;
       }
-      cnt += __shfl_xor(cnt, 1);
-      cnt += __shfl_xor(cnt, 2);
+      // the four counts of an individual sit in one lane quad: two DPP quad
+      // permutes (lane ^ 1, lane ^ 2) add them without an LDS round trip
+      cnt += (uint32_t)__builtin_amdgcn_mov_dpp((int)cnt, 0xB1, 0xF, 0xF, false);
+      cnt += (uint32_t)__builtin_amdgcn_mov_dpp((int)cnt, 0x4E, 0xF, 0xF, false);
       if (ri < N && rq == 0 && cnt < kp) topk[cnt] = ri;
     }
     __syncthreads();

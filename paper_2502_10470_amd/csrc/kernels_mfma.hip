@@ -273,6 +273,22 @@ __device__ __forceinline__ float term_bound(const ProbDev &p, const ColInfo &c, 
   return b * 1.0001f + 2.4e-7f * (fabsf(t) + 30.0f);
 }
 
+// x + x[lane ^ 16] and x + x[lane ^ 32] with the gfx950 row swaps: called
+// with both operands x, v_permlane16_swap leaves in every lane one of its own
+// value and its partner's (which one depends on the row's parity), so their
+// sum is the butterfly step bit for bit (addition commutes), with no LDS
+// round trip.
+__device__ __forceinline__ float xsum16(float x) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false,
+                                                  false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float xsum32(float x) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false,
+                                                  false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
 // Terms of the four results a lane holds after a transposed tile (one trial,
 // outputs j(v): 16 ct + l/16 + 4 v for the plain tiles (STRIDED), 16 ct +
 // 4 (l/16) + v for the bf16 tiles) and their sum over the tile's 16 outputs:
@@ -325,16 +341,9 @@ __device__ __forceinline__ void tile_epilogue(const ProbDev &p, const uint32_t *
       }
     }
   }
-  t0 += __shfl_xor(t0, 16);
-  t0 += __shfl_xor(t0, 32);
-  if (p.kind == FN_ACKLEY) {
-    t1 += __shfl_xor(t1, 16);
-    t1 += __shfl_xor(t1, 32);
-  }
-  if (BOUND) {
-    bd += __shfl_xor(bd, 16);
-    bd += __shfl_xor(bd, 32);
-  }
+  t0 = xsum32(xsum16(t0));
+  if (p.kind == FN_ACKLEY) t1 = xsum32(xsum16(t1));
+  if (BOUND) bd = xsum32(xsum16(bd));
   if (ok && grp == 0) {
     Ps[ct * nslot + slot] = make_float2(t0, t1);
     if (BOUND) Pb[ct * nslot + slot] = bd;
