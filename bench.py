@@ -49,8 +49,8 @@ KERNEL_SOURCES = {
 MEASURED_TRAFFIC = {
     "8f8747193f8c8855": (500.21 * 2.0 + 526.0 * 1.0) * 1024,           # k_generations, C3
     # k_generations_mfma at D = 100, keyed by hash and precision
-    "aaa5981486cb1d34:fp32": (37080.5 * 2.0 + 6881282.3 * 1.0) * 1024,
-    "aaa5981486cb1d34:bf16": (34000.4 * 2.0 + 6125759.1 * 1.0) * 1024,
+    "24e4b90aaccabd81:fp32": (26553.1 * 2.0 + 7045710.8 * 1.0) * 1024,
+    "24e4b90aaccabd81:bf16": (25155.5 * 2.0 + 6229626.4 * 1.0) * 1024,
 }
 
 PHILOX_SLOTS = 100   # 10 rounds x (2 quarter-rate 32x32->64 multiplies + 2 three-input XORs)

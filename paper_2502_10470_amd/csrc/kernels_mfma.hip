@@ -555,6 +555,13 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
     if (act_r) {
       const uint64_t ki = key_s[ir];
       uint32_t c = 0, j = kr0;
+      for (; j + 16 <= kr1; j += 16) {
+        uint64_t kv[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) kv[q] = key_s[j + q];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) c += kv[q] < ki ? 1u : 0u;
+      }
       for (; j + 8 <= kr1; j += 8) {
         uint64_t kv[8];
 #pragma unroll
