@@ -47,10 +47,12 @@ KERNEL_SOURCES = {
                            "paper_2502_10470_amd/csrc/device.h"),
 }
 MEASURED_TRAFFIC = {
-    "8f8747193f8c8855": (500.21 * 2.0 + 526.0 * 1.0) * 1024,           # k_generations, C3
-    # k_generations_mfma at D = 100, keyed by hash and precision
-    "24e4b90aaccabd81:fp32": (26553.1 * 2.0 + 7045710.8 * 1.0) * 1024,
-    "24e4b90aaccabd81:bf16": (25155.5 * 2.0 + 6229626.4 * 1.0) * 1024,
+    # keyed by the kernel's source hash and the launch configuration the counters were
+    # taken in (parts per trial, or precision and row tiles per rotation item)
+    "8f8747193f8c8855:lp2": (500.21 * 2.0 + 526.0 * 1.0) * 1024,       # k_generations, C3
+    "8f8747193f8c8855:lp4": (496.71 * 2.0 + 526.0 * 1.0) * 1024,
+    "24e4b90aaccabd81:fp32:r2": (26553.1 * 2.0 + 7045710.8 * 1.0) * 1024,
+    "24e4b90aaccabd81:bf16:r4": (25155.5 * 2.0 + 6229626.4 * 1.0) * 1024,
 }
 
 PHILOX_SLOTS = 100   # 10 rounds x (2 quarter-rate 32x32->64 multiplies + 2 three-input XORs)
@@ -342,7 +344,8 @@ def measure_batch(wl, name, precision, steps, warmup):
         # re-evaluations are not counted), against the peak of the dtype it runs in
         peak = MFMA_BF16_PEAK if prec == M.BF16_REFINE else MFMA_F64_PEAK
         ach = rot_flops / (avg_ms * 1e-3)
-        traffic = MEASURED_TRAFFIC.get(kernel_source_hash(kern) + ":" + precision)
+        traffic = MEASURED_TRAFFIC.get(f"{kernel_source_hash(kern)}:{precision}"
+                                       f":r{tuning['mfma_rows']}")
         line["roofline"] = {"bound": "mfma", "achieved": ach / 1e12, "peak": peak / 1e12,
                             "unit": "TFLOP/s", "frac": ach / peak, "traffic": traffic,
                             "kernel": kern, "avg_launch_ms": avg_ms, "launches": k_launches,
@@ -579,7 +582,8 @@ def main():
                    "tuning": tuning},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_SLOTS / 1e12,
                      "unit": "Tslot/s", "frac": achieved / VALU_PEAK_SLOTS,
-                     "traffic": (MEASURED_TRAFFIC.get(kernel_source_hash())
+                     "traffic": (MEASURED_TRAFFIC.get(f"{kernel_source_hash()}"
+                                                      f":lp{tuning['lane_parts']}")
                                  if args.workload == "c3" else None),
                      "kernel": "k_generations", "avg_launch_ms": avg_launch_ms,
                      "launches": k_launches, "slots_per_launch": slots_per_launch,

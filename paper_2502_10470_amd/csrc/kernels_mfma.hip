@@ -124,8 +124,9 @@ __device__ __forceinline__ void tile_z(const d4v &acc, const double *ro, uint32_
 
 // The rotation of a generation as (output tile, group of row tiles) items,
 // fetched from a counter in LDS by every wave that calls this (the consumers
-// as soon as the trials are built, the producers once their crossover tests
-// of the next generation are drawn), so that one wave's products run while
+// as soon as the trials are built, the producers once the next generation's
+// crossover tests are drawn: before the rotation with two mask buffers,
+// during it with one), so that one wave's products run while
 // another waits for its loads or forms the element terms.  Items that share
 // row tiles are adjacent in the order, so their trial rows come from cache.
 template <typename BODY>
@@ -630,8 +631,8 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
     }
     __syncthreads();
     MDE_STAGE(3)
-    // S3: rotation on the matrix cores + element terms (producers join once
-    // the masks of g+1 are drawn)
+    // S3: rotation on the matrix cores + element terms (the producers join
+    // once the masks of g+1 are drawn)
     rotation_items(cnt + 15, n_items, lane, item);
     __syncthreads();
     MDE_STAGE(4)
