@@ -59,6 +59,10 @@ constexpr int STAGE_MAX_BLOCKS = 256, STAGE_MAX_WAVES = 16, STAGE_N = 8;
     mde_st_acc[k] += t_ - mde_st_t;             \
     mde_st_t = t_;                              \
   }
+// the cycles since the last MDE_STAGE, without starting a new interval: placed
+// just before a barrier, the wave's own work in the stage, its wait left out
+#define MDE_STAGE_WORK(k) \
+  { mde_st_acc[k] += clock64() - mde_st_t; }
 #define MDE_STAGE_END                                                                  \
   if ((threadIdx.x & 63) == 0 && blockIdx.x < (unsigned)STAGE_MAX_BLOCKS)             \
     for (int k_ = 0; k_ < STAGE_N; ++k_)                                               \
@@ -68,6 +72,7 @@ constexpr int STAGE_MAX_BLOCKS = 256, STAGE_MAX_WAVES = 16, STAGE_N = 8;
 #define MDE_STAGE_ARRAY
 #define MDE_STAGE_BEGIN
 #define MDE_STAGE(k)
+#define MDE_STAGE_WORK(k)
 #define MDE_STAGE_END
 #endif
 

@@ -197,21 +197,30 @@ __device__ __forceinline__ void gen_producers(const Lds &lay, unsigned char *sme
   produce_masks(ptid, NP, run, N, Q, g0, k0, k1, msk + (g0 & 1u) * N * Q);
   __syncthreads();
   produce_desc_direct(ptid, NP, run, N, D, kp, g0, k0, k1, msk + (g0 & 1u) * N * Q, dsc);
+  MDE_STAGE_BEGIN
   for (uint32_t gg = 0; gg < n_gens; ++gg) {
     const uint32_t g = g0 + gg;
     __syncthreads();   // generation g starts (consumers rank)
+    MDE_STAGE(0)
     __syncthreads();   // consumers build the trials of g
+    MDE_STAGE(1)
     uint8_t *mn = msk + ((g + 1) & 1u) * N * Q;
     produce_masks(ptid, NP, run, N, Q, g + 1, k0, k1, mn);
     // block 2 of the next generation's draws now, the rest during the
     // fitness (N <= 256: one trial per producer lane)
     uint4 wc_next = uint4{};
     if (ptid < N) wc_next = philox(2, ptid, g + 1, run.stream, k0, k1);
+    MDE_STAGE_WORK(6)
     __syncthreads();   // consumers evaluate g
+    MDE_STAGE(2)
     produce_desc_direct<true>(ptid, NP, run, N, D, kp, g + 1, k0, k1, mn, dsc, wc_next);
+    MDE_STAGE_WORK(7)
     __syncthreads();   // consumers select and commit g
+    MDE_STAGE(3)
   }
   __syncthreads();
+  MDE_STAGE(0)
+  MDE_STAGE_END
 }
 
 // Consumer waves: ranking, trial construction, fitness, selection and commit
@@ -244,6 +253,7 @@ __device__ __forceinline__ void gen_consumers(const Lds &lay, unsigned char *sme
   MDE_STAGE_BEGIN
   for (uint32_t gg = 0; gg < n_gens; ++gg) {
     const uint32_t g = g0 + gg;
+    MDE_STAGE_WORK(4)
     __syncthreads();
     MDE_STAGE(0)
     // S0: ranks and the top-p list (first is the best).  Four consumer lanes
@@ -271,6 +281,7 @@ __device__ __forceinline__ void gen_consumers(const Lds &lay, unsigned char *sme
       cnt += (uint32_t)__builtin_amdgcn_mov_dpp((int)cnt, 0x4E, 0xF, 0xF, false);
       if (ri < N && rq == 0 && cnt < kp) topk[cnt] = ri;
     }
+    MDE_STAGE_WORK(5)
     __syncthreads();
     MDE_STAGE(1)
     // S2: mutation, crossover, clip.  Consumer lane c builds quads it = c,
@@ -325,6 +336,7 @@ __device__ __forceinline__ void gen_consumers(const Lds &lay, unsigned char *sme
         if (it == tid) keep = uu;
       }
     }
+    MDE_STAGE_WORK(6)
     __syncthreads();
     MDE_STAGE(2)
     // S3: this part's share of the fitness (producers draw generation g+1)
@@ -333,6 +345,7 @@ __device__ __forceinline__ void gen_consumers(const Lds &lay, unsigned char *sme
       eval_part(tab, p, D, j0, j1, T + i, ts, s0, s1);
       Ps[l * Np + i] = make_double2(s0, s1);
     }
+    MDE_STAGE_WORK(7)
     __syncthreads();
     MDE_STAGE(3)
     // S4: greedy selection and commit, by the lanes of S2: each lane sums the
@@ -372,6 +385,7 @@ __device__ __forceinline__ void gen_consumers(const Lds &lay, unsigned char *sme
       }
     }
   }
+  MDE_STAGE_WORK(4)
   __syncthreads();
   MDE_STAGE(0)
   MDE_STAGE_END

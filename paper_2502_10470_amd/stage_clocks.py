@@ -2,11 +2,15 @@
 
     python -m paper_2502_10470_amd.stage_clocks build       # libmetade_stage.so
     python -m paper_2502_10470_amd.stage_clocks c3 c4 c4bf16
+    python -m paper_2502_10470_amd.stage_clocks --all-waves c3     # every wave
 
 The diagnostic build compiles the library with -DMDE_STAGE_CLOCKS: every wave
 of a generation kernel reads clock64 after each barrier and adds the cycles
 since the previous read to a per-(block, wave, stage) total, written to a
 device array at the end of the launch (ordinary builds contain none of it).
+In the lane kernel every wave, producers included, also reads it just before
+each barrier: the cycles from the previous barrier to that point are the
+wave's own work in the stage, the rest of the stage its wait for the others.
 The runs: the D = 20 executor launch of full MetaDE (64 runs, the first
 evolver generation's theta from the library's own evolver, 1000 generations,
 tuned part count) and the D = 100 launch (128 runs x N = 256, 500
@@ -27,7 +31,8 @@ ROOT = os.path.dirname(HERE)
 STAGE_LIB = os.path.join(HERE, "libmetade_stage.so")
 SB, SW, SN = 256, 16, 8   # blocks, waves per block and stages recorded (device.h)
 
-LANE_STAGES = ["commit+draws", "ranking", "trials", "fitness"]
+LANE_STAGES = ["commit+draws", "ranking", "trials", "fitness",
+               "work:commit", "work:ranking", "work:trials", "work:fitness"]
 MFMA_STAGES = ["commit+draws", "ranking", "top-p", "trials", "rotation", "screen",
                "candidates", "re-evaluation"]
 
@@ -45,16 +50,17 @@ def _clocks(L, which: int) -> np.ndarray:
 
 
 def _report(L, name, which, n_blocks, G, waves, labels):
+    n_int = sum(not x.startswith("work:") for x in labels)   # barrier-to-barrier stages
     c = _clocks(L, which)[:n_blocks] / G
     print(f"== {name}: cycles per generation, mean over {n_blocks} runs; "
-          f"total per wave {c[:, waves[0], :].sum(axis=1).mean():.0f}")
+          f"total per wave {c[:, waves[0], :n_int].sum(axis=1).mean():.0f}")
     for w in waves:
         row = c[:, w, :].mean(axis=0)
         print(f"  wave {w:2d}: " + "  ".join(f"{labels[k]} {row[k]:.0f}"
                                              for k in range(len(labels))))
 
 
-def main(names) -> None:
+def main(names, all_waves: bool = False) -> None:
     if not os.path.exists(STAGE_LIB):
         raise SystemExit(f"{STAGE_LIB} is missing: run `python -m {__package__}.stage_clocks build`")
     sys.path.insert(0, ROOT)
@@ -91,14 +97,18 @@ def main(names) -> None:
         b.kernel_timing(False)
         torch.cuda.synchronize()
         print(f"{name}: launch {ms:.2f} ms for {G} generations", flush=True)
+        if all_waves:
+            waves = list(range(SW))
         _report(L, name, which, wl.n_runs, G, waves, labels)
         sys.stdout.flush()
         b.close()
 
 
 if __name__ == "__main__":
-    args = sys.argv[1:] or ["c3", "c4", "c4bf16"]
+    args = sys.argv[1:]
+    all_waves = "--all-waves" in args
+    args = [a for a in args if a != "--all-waves"] or ["c3", "c4", "c4bf16"]
     if args == ["build"]:
         print(build())
     else:
-        main(args)
+        main(args, all_waves)
