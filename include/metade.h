@@ -348,7 +348,9 @@ metade_status metade_set_tuning(metade_ctx *ctx, const metade_tuning *t);
  * <mfma_rows> <ms>", the key hashing the runs' (N, D, kind) multiset, the
  * precision and n_generations; a measured choice is appended to it.
  * chosen and best_ms (the chosen tuning's time for n_generations) may be
- * NULL.  Synchronises. */
+ * NULL.  Synchronises.  On an error during the search the
+ * context is put back, as far as the device allows, to the tuning and the
+ * state it had before the call, and metade_last_error names the failure. */
 metade_status metade_autotune(metade_ctx *ctx, uint32_t n_generations, const char *cache_path,
                               metade_tuning *chosen, double *best_ms);
 

@@ -1120,13 +1120,18 @@ metade_status metade_autotune(metade_ctx *c, uint32_t n_gens, const char *cache_
   HIP_TRY(c, hipMemcpy(cnt0, c->counters_d, sizeof(cnt0), hipMemcpyDeviceToHost));
   const bool timing0 = c->timing;
   c->timing = false;
-  metade_tuning best{c->lane_parts, c->mfma_rows};
+  const metade_tuning orig{c->lane_parts, c->mfma_rows};
+  metade_tuning best = orig;
   double best_t = 1e300;
   hipEvent_t ea = nullptr, eb = nullptr;
-  HIP_TRY(c, hipEventCreate(&ea));
-  HIP_TRY(c, hipEventCreate(&eb));
   metade_status st = METADE_OK;
+  {
+    hipError_t e = hipEventCreate(&ea);
+    if (e == hipSuccess) e = hipEventCreate(&eb);
+    if (e != hipSuccess) st = fail(c, METADE_EDEVICE, std::string("autotune events: ") + hipGetErrorString(e));
+  }
   for (uint32_t r : rows) {
+    if (st != METADE_OK) break;
     for (uint32_t lp : parts) {
       const metade_tuning t{lp, r};
       if ((st = metade_set_tuning(c, &t)) != METADE_OK) break;
@@ -1147,10 +1152,20 @@ metade_status metade_autotune(metade_ctx *c, uint32_t n_gens, const char *cache_
     }
     if (st != METADE_OK) break;
   }
-  (void)hipEventDestroy(ea);
-  (void)hipEventDestroy(eb);
+  if (ea) (void)hipEventDestroy(ea);
+  if (eb) (void)hipEventDestroy(eb);
   c->timing = timing0;
-  if (st != METADE_OK) return st;
+  if (st != METADE_OK) {
+    // best effort: the launch shape and the state the context had before the
+    // search, keeping the search's own error message
+    const std::string err = c->err;
+    (void)metade_set_tuning(c, &orig);
+    (void)metade_set_state(c, blob.data(), bytes);
+    c->trials = trials0;
+    (void)hipMemcpy(c->counters_d, cnt0, sizeof(cnt0), hipMemcpyHostToDevice);
+    c->err = err;
+    return st;
+  }
   TRY(metade_set_tuning(c, &best));
   TRY(metade_set_state(c, blob.data(), bytes));
   c->trials = trials0;
