@@ -274,7 +274,8 @@ metade_status metade_outer_reset(metade_ctx *ctx);
  * (same streams: one-shot evaluation) and run for G_inner generations
  * (G_inner * power_up if power_up > 1: Sec. III-D); y* of each run; the
  * trial replaces its target (PSO: the position replaces the personal best)
- * iff y*(trial) <= y(target).  Asynchronous. */
+ * iff y*(trial) <= y(target).  METADE_EINVAL if G_inner * power_up does not
+ * fit in 32 bits.  Asynchronous. */
 metade_status metade_outer_step(metade_ctx *ctx, uint32_t G_inner, uint32_t power_up);
 
 /* Copy the evolver state to host memory (synchronises): X[n_runs][6],
@@ -283,7 +284,10 @@ metade_status metade_outer_step(metade_ctx *ctx, uint32_t G_inner, uint32_t powe
 metade_status metade_get_outer(metade_ctx *ctx, float *X, double *y, float *U, double *y_trial);
 
 /* Set the evolver state from host memory (X[n_runs][6], y[n_runs]) and the
- * outer generation counter. */
+ * outer generation counter.  For the PSO, CSO and NES evolvers, whose other
+ * state (positions and velocities, the search distribution) X and y do not
+ * carry, metade_outer_reset must have been called on the context first
+ * (METADE_ESTATE otherwise); that state is left as it is. */
 metade_status metade_set_outer(metade_ctx *ctx, const float *X, const double *y, uint32_t gen);
 
 /* Whole MetaDE run (synchronises): outer reset, outer_gens outer generations

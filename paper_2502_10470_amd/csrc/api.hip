@@ -746,6 +746,8 @@ metade_status metade_outer_reset(metade_ctx *c) {
 metade_status metade_outer_step(metade_ctx *c, uint32_t G_inner, uint32_t power_up) {
   if (!c) return fail(nullptr, METADE_EINVAL, "ctx is NULL");
   if (!c->outer_ready) return fail(c, METADE_ESTATE, "metade_outer_reset must come first");
+  if (power_up > 1 && G_inner > UINT32_MAX / power_up)
+    return fail(c, METADE_EINVAL, "G_inner * power_up exceeds 2^32 - 1");
   const uint32_t G = G_inner * (power_up > 1 ? power_up : 1);
   const uint32_t k0 = (uint32_t)(c->seed & 0xFFFFFFFFu), k1 = (uint32_t)(c->seed >> 32);
   if (c->evolver == METADE_EVOLVER_PSO) {
@@ -803,6 +805,10 @@ metade_status metade_get_outer(metade_ctx *c, float *X, double *y, float *U, dou
 
 metade_status metade_set_outer(metade_ctx *c, const float *X, const double *y, uint32_t gen) {
   if (!c || !X || !y) return fail(c, METADE_EINVAL, "ctx, X and y are required");
+  if (c->evolver != METADE_EVOLVER_DE && !c->outer_ready)
+    return fail(c, METADE_ESTATE,
+                "metade_outer_reset must come first for this evolver: its positions, "
+                "velocities or search distribution are not part of X and y");
   HIP_TRY(c, hipMemcpyAsync(c->Xo, X, (size_t)c->n_runs * 6 * sizeof(float), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipMemcpyAsync(c->yo, y, c->n_runs * sizeof(double), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));

@@ -85,3 +85,18 @@ def test_pso_run_and_checkpoint():
     assert by == y[k] and np.array_equal(bt, X[k])
     lo, hi = pde.theta_bounds(wl.n_cs)
     assert np.all(X >= lo) and np.all(X <= hi)
+
+
+def test_pso_set_outer_needs_reset_and_outer_step_checks_g():
+    # host-side checks only: no generation runs
+    from paper_2502_10470_amd import metade as M
+    wl = W.workload_c1()
+    b = _batch(wl)
+    X = np.zeros((wl.n_runs, 6), np.float32)
+    y = np.zeros(wl.n_runs, np.float64)
+    with pytest.raises(M.MetadeError, match=r"status -4: metade_outer_reset must come first"):
+        b.set_outer(X, y, 0)
+    b.outer_reset()
+    b.set_outer(*b.get_outer()[:2], 0)
+    with pytest.raises(M.MetadeError, match=r"status -1: G_inner \* power_up exceeds"):
+        b.outer_step(1 << 30, 5)
