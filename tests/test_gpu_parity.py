@@ -67,6 +67,26 @@ def test_tiles_and_ragged_tails(N, D):
     assert out["compared"] == 15
 
 
+def test_largest_population_that_fits_and_the_first_that_does_not():
+    """N = 256 at D = 124, the largest dimension whose population, draws and
+    per-tile partial sums fit the 160 KB of LDS of the matrix-core kernel in
+    the plain precision (Rosenbrock, with two more per-tile arrays, and the
+    bf16 mode reach 112 and 116), against the oracle; D = 128 at N = 256 is
+    rejected at set-up with the LDS message, before any launch."""
+    from paper_2502_10470_amd import metade as M
+    wl = W.small_batch(256124, ["rastrigin", "elliptic"], [256] * 2, [124] * 2, n_cs=3)
+    out = trajectory_parity(_batch(wl), wl, G=2)
+    assert out["compared"] == 4
+    wl = W.small_batch(256116, ["ackley"], [256], [116], n_cs=3)
+    out = trajectory_parity(_batch(wl, precision=M.BF16_REFINE), wl, G=2)
+    assert out["compared"] == 2
+    for kind, D, kw in (("rastrigin", 128, {}), ("rosenbrock", 116, {}),
+                        ("ackley", 120, {"precision": M.BF16_REFINE})):
+        wl = W.small_batch(7, [kind], [256], [D], n_cs=3)
+        with pytest.raises(M.MetadeError, match="does not fit in LDS"):
+            _batch(wl, **kw)
+
+
 def test_hybrid_function():
     p = W.make_problem("hybrid", 20, 2, 0)
     wl = W.small_batch(2, ["hybrid"], [100] * 6, [20] * 6, n_cs=2)
