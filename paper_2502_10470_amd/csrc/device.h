@@ -47,7 +47,7 @@ constexpr float SCHWEFEL_ZSTAR = 420.96875f;
 // the launch to a device array of the kernel's source file.  In ordinary
 // builds the hooks expand to nothing.
 #ifdef MDE_STAGE_CLOCKS
-constexpr int STAGE_MAX_BLOCKS = 256, STAGE_MAX_WAVES = 16, STAGE_N = 8;
+constexpr int STAGE_MAX_BLOCKS = 256, STAGE_MAX_WAVES = 16, STAGE_N = 16;
 #define MDE_STAGE_ARRAY \
   static __device__ unsigned long long mde_stage_clk[STAGE_MAX_BLOCKS * STAGE_MAX_WAVES * STAGE_N]
 #define MDE_STAGE_BEGIN                         \

@@ -402,25 +402,39 @@ __device__ __forceinline__ void mfma_producers(const MLds &lay, unsigned char *s
   produce_masks<true>(ptid, NP, run, N, Q, g0, k0, k1, mbuf[g0 & 1u]);
   __syncthreads();
   produce_desc_direct(ptid, NP, run, N, D, kp, g0, k0, k1, mbuf[g0 & 1u], dsc);
+  MDE_STAGE_BEGIN
   for (uint32_t gg = 0; gg < n_gens; ++gg) {
     const uint32_t g = g0 + gg;
     uint8_t *mn = two ? mbuf[(g + 1) & 1u] : mbuf[0];
     __syncthreads();   // generation g: consumers count ranks
+    MDE_STAGE(0)
     __syncthreads();   // top-p list
+    MDE_STAGE(1)
     __syncthreads();   // trial construction (reads the masks of g)
+    MDE_STAGE(2)
     if (two) produce_masks<true>(ptid, NP, run, N, Q, g + 1, k0, k1, mn);
+    MDE_STAGE_WORK(11)
     __syncthreads();   // rotation: the masks of g are free
+    MDE_STAGE(3)
     if (!two) produce_masks<true>(ptid, NP, run, N, Q, g + 1, k0, k1, mn);
     rotation_items(ctr, n_items, ptid & 63, item);   // then help with the rotation
+    MDE_STAGE_WORK(12)
     __syncthreads();   // decisions (plain) or screen (bf16)
+    MDE_STAGE(4)
     if (BF16) {
       __syncthreads(); // candidate counts
+      MDE_STAGE(5)
       __syncthreads(); // candidate list
+      MDE_STAGE(6)
       __syncthreads(); // re-evaluation
+      MDE_STAGE(7)
     }
     produce_desc_direct(ptid, NP, run, N, D, kp, g + 1, k0, k1, mn, dsc);
+    MDE_STAGE_WORK(8)
   }
   __syncthreads();
+  MDE_STAGE(0)
+  MDE_STAGE_END
 }
 
 template <bool BF16, bool TRACE, int RTF>
@@ -550,6 +564,7 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
 
   for (uint32_t gg = 0; gg < n_gens; ++gg) {
     const uint32_t g = g0 + gg;
+    MDE_STAGE_WORK(8)
     __syncthreads();
     MDE_STAGE(0)
     // S0: partial ranks
@@ -573,6 +588,7 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
       for (; j < kr1; ++j) c += key_s[j] < ki ? 1u : 0u;
       rk[l * Np + ir] = c;
     }
+    MDE_STAGE_WORK(9)
     __syncthreads();
     MDE_STAGE(1)
     // S1: top-p list; the decision lane keeps its target's fitness
@@ -583,6 +599,7 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
       for (uint32_t ll = 0; ll < L; ++ll) rank += rk[ll * Np + ir];
       if (rank < kp) topk[rank] = ir;
     }
+    MDE_STAGE_WORK(10)
     __syncthreads();
     MDE_STAGE(2)
     // S2: trial genes -> global trial rows.  P lanes per trial (a power of
@@ -629,11 +646,13 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
         }
       }
     }
+    MDE_STAGE_WORK(11)
     __syncthreads();
     MDE_STAGE(3)
     // S3: rotation on the matrix cores + element terms (the producers join
     // once the masks of g+1 are drawn)
     rotation_items(cnt + 15, n_items, lane, item);
+    MDE_STAGE_WORK(12)
     __syncthreads();
     MDE_STAGE(4)
     // S4: plain mode decides and commits; bf16 mode selects the candidates
@@ -668,6 +687,7 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
       // deterministic compaction of the candidates (ascending trial index)
       const unsigned long long bal = __ballot(cand);
       if (!producer && lane == 0) cnt[wave] = (uint32_t)__popcll(bal);
+      MDE_STAGE_WORK(13)
       __syncthreads();
       MDE_STAGE(5)
       uint32_t base = 0, total = 0;
@@ -680,6 +700,7 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
         const uint32_t pos = base + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
         cl[pos] = tid;
       }
+      MDE_STAGE_WORK(14)
       __syncthreads();
       MDE_STAGE(6)
       // S5: plain re-evaluation of the candidates on compacted row tiles,
@@ -709,6 +730,7 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
           }
         }
       }
+      MDE_STAGE_WORK(15)
       __syncthreads();
       MDE_STAGE(7)
       // S6: decisions of the candidates from their plain values, commit
@@ -743,6 +765,7 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
       refined += total;
     }
   }
+  MDE_STAGE_WORK(8)
   __syncthreads();
   MDE_STAGE(0)
   MDE_STAGE_END

@@ -8,9 +8,9 @@ The diagnostic build compiles the library with -DMDE_STAGE_CLOCKS: every wave
 of a generation kernel reads clock64 after each barrier and adds the cycles
 since the previous read to a per-(block, wave, stage) total, written to a
 device array at the end of the launch (ordinary builds contain none of it).
-In the lane kernel every wave, producers included, also reads it just before
-each barrier: the cycles from the previous barrier to that point are the
-wave's own work in the stage, the rest of the stage its wait for the others.
+Every wave, producers included, also reads it just before each barrier: the
+cycles from the previous barrier to that point are the wave's own work in
+the stage, the rest of the stage its wait for the others.
 The runs: the D = 20 executor launch of full MetaDE (64 runs, the first
 evolver generation's theta from the library's own evolver, 1000 generations,
 tuned part count) and the D = 100 launch (128 runs x N = 256, 500
@@ -29,12 +29,14 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 STAGE_LIB = os.path.join(HERE, "libmetade_stage.so")
-SB, SW, SN = 256, 16, 8   # blocks, waves per block and stages recorded (device.h)
+SB, SW, SN = 256, 16, 16   # blocks, waves per block and stage slots recorded (device.h)
 
 LANE_STAGES = ["commit+draws", "ranking", "trials", "fitness",
                "work:commit", "work:ranking", "work:trials", "work:fitness"]
 MFMA_STAGES = ["commit+draws", "ranking", "top-p", "trials", "rotation", "screen",
-               "candidates", "re-evaluation"]
+               "candidates", "re-evaluation", "work:commit", "work:ranking", "work:top-p",
+               "work:trials", "work:rotation", "work:screen", "work:candidates",
+               "work:re-evaluation"]
 
 
 def build() -> str:
