@@ -369,3 +369,36 @@ def test_resync_c4_late_generation(G):
     out = resync_parity(b, wl, G, wl.theta)
     print(out, flush=True)
     assert out["compared"] == 128 and out["trials"] == 128 * 256
+
+
+@pytest.mark.parametrize("seed", [777, 2002])
+def test_random_batches(seed):
+    """Seeded random batches: 1 to 6 runs each, every kind, N in 10..256,
+    D in 1..128 (3.. for the hybrid), two or three crossover schemes, both
+    precisions; each batch is checked against the oracle for 3 generations.
+    A batch that fits no generation kernel's LDS must be rejected at set-up."""
+    from paper_2502_10470_amd import metade as M
+    rng = np.random.default_rng(seed)
+    kinds_all = ["rastrigin", "rosenbrock", "ackley", "elliptic", "schwefel", "hybrid"]
+    compared = 0
+    for case in range(30):
+        runs = int(rng.integers(1, 7))
+        Ns = [int(rng.integers(10, 257)) for _ in range(runs)]
+        Ds = [int(rng.integers(1, 129)) for _ in range(runs)]
+        kinds = [kinds_all[int(rng.integers(0, 6))] for _ in range(runs)]
+        Ds = [max(d, 3) if k == "hybrid" else d for d, k in zip(Ds, kinds)]
+        prec = M.BF16_REFINE if rng.random() < 0.3 else M.FP32
+        n_cs = int(rng.integers(2, 4))
+        wl = W.small_batch(int(rng.integers(0, 2**31)), kinds, Ns, Ds, n_cs=n_cs)
+        print(f"[case {case}] precision={prec} runs={list(zip(kinds, Ns, Ds))}", flush=True)
+        try:
+            b = _batch(wl, precision=prec)
+        except M.MetadeError as e:
+            assert "does not fit in LDS" in str(e), str(e)
+            continue
+        out = trajectory_parity(b, wl, G=3)
+        assert out["compared"] == 3 * runs
+        compared += out["compared"]
+        b.close()
+    print("run-generations compared:", compared)
+    assert compared >= 200
