@@ -64,6 +64,7 @@ struct metade_ctx {
   float *pend_d = nullptr;
   size_t pop_floats = 0, fit_n = 0, bx_n = 0, pend_floats = 0;
   uint32_t lds_bytes = 0, init_lds_bytes = 0, mfma_lds_bytes = 0;
+  int lane_kind = -1;   // one kind for every lane-kernel run: its own kernel (else -1)
   uint32_t n_lane = 0, n_mfma = 0, n_ctrl = 0, ctrl_max_n = 0, ctrl_hidden = 0, ctrl_lanes = 32;
   uint32_t ctrl_mx = 0;
   uint32_t *lane_list_d = nullptr, *mfma_list_d = nullptr, *ctrl_list_d = nullptr;
@@ -122,6 +123,7 @@ struct Plan {
   bool ctrl_roll16 = true;   // every control problem has a multiple of 16 rollouts
   size_t pop_floats = 0, fit_n = 0, bx_n = 0, pend_floats = 0;
   uint32_t lds_bytes = 0;
+  int lane_kind = -1;        // the kind of every lane-kernel run, -1 if they differ
 };
 
 metade_status plan_config(const metade_config *cfg, Plan &pl, std::string &msg) {
@@ -326,6 +328,11 @@ metade_status plan_config(const metade_config *cfg, Plan &pl, std::string &msg) 
     d.dn = 1;
     d.cs = mde::BIN;
   }
+  // one function kind for every lane-kernel run: the kernel of that kind
+  for (size_t k = 0; k < pl.lane_list.size(); ++k) {
+    const int kind = (int)pl.probs[pl.runs[pl.lane_list[k]].prob].kind;
+    pl.lane_kind = k == 0 ? kind : (pl.lane_kind == kind ? kind : -1);
+  }
   return METADE_OK;
 }
 
@@ -344,6 +351,7 @@ LaunchArgs largs(metade_ctx *c) {
   a.k0 = (uint32_t)(c->seed & 0xFFFFFFFFu);
   a.k1 = (uint32_t)(c->seed >> 32);
   a.mfma_rows = c->mfma_rows;
+  a.lane_kind = c->lane_kind;
   a.stream = c->stream;
   return a;
 }
@@ -501,6 +509,7 @@ metade_status metade_init(const metade_config *cfg, metade_ctx **out) {
   c->bx_n = pl.bx_n;
   c->pend_floats = pl.pend_floats;
   c->lds_bytes = pl.lds_bytes;
+  c->lane_kind = pl.lane_kind;
   c->init_lds_bytes = pl.init_lds_bytes;
   c->mfma_lds_bytes = pl.mfma_lds_bytes;
   c->n_lane = (uint32_t)pl.lane_list.size();

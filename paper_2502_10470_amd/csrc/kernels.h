@@ -27,6 +27,7 @@ struct LaunchArgs {
   uint32_t mfma_lds_bytes;
   uint32_t k0, k1;
   uint32_t mfma_rows;   // row tiles per plain rotation item of the matrix-core kernel: 2 or 4
+  int lane_kind;        // the function kind of every lane-kernel run, or -1 if they differ
   hipStream_t stream;
 };
 

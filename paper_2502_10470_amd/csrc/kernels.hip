@@ -458,6 +458,23 @@ __global__ __launch_bounds__(GEN_THREADS) void k_generations(
 #undef MDE_KIND
 }
 
+// The same generation loop for launches whose runs all have one function
+// kind: a kernel that holds a single loop gets a register allocation of its
+// own, where the six loops of k_generations share one (for the hybrid, 71
+// scalar-register spills against 392).
+template <bool TRACE, int KIND>
+__global__ __launch_bounds__(GEN_THREADS) void k_generations_kind(
+    const RunDev *__restrict__ runs, const uint32_t *__restrict__ list,
+    const ProbDev *__restrict__ probs, const unsigned char *__restrict__ tab,
+    float *__restrict__ pop, float *__restrict__ fit, uint32_t g0, uint32_t n_gens, uint32_t k0,
+    uint32_t k1, float lb, float ub, TraceArgs tr) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const RunDev run = runs[list[blockIdx.x]];
+  ProbDev p = probs[run.prob];
+  p.kind = KIND;
+  gen_body<TRACE>(smem, run, p, tab, pop, fit, g0, n_gens, k0, k1, lb, ub, tr);
+}
+
 #ifdef MDE_STAGE_CLOCKS
 hipError_t read_stage_clocks(void *dst, size_t bytes) {
   return hipMemcpyFromSymbol(dst, HIP_SYMBOL(mde_stage_clk), bytes, 0, hipMemcpyDeviceToHost);
@@ -890,13 +907,20 @@ hipError_t launch_tables64(const float *R, double *Rt, uint32_t D, hipStream_t s
   return hipGetLastError();
 }
 
+#define MDE_KINDS(X)                                                                        \
+  X(FN_RASTRIGIN) X(FN_ROSENBROCK) X(FN_ACKLEY) X(FN_ELLIPTIC) X(FN_SCHWEFEL) X(FN_HYBRID)
+
 hipError_t set_lds_limits() {
-  hipError_t e = hipFuncSetAttribute((const void *)k_generations<false>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BUDGET);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void *)k_generations<true>,
-                          hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BUDGET);
-  if (e != hipSuccess) return e;
+  const void *ks[14] = {(const void *)k_generations<false>, (const void *)k_generations<true>,
+#define MDE_KIND_PTRS(K) (const void *)k_generations_kind<false, K>, \
+                         (const void *)k_generations_kind<true, K>,
+                        MDE_KINDS(MDE_KIND_PTRS)};
+#undef MDE_KIND_PTRS
+  hipError_t e = hipSuccess;
+  for (const void *k : ks) {
+    e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BUDGET);
+    if (e != hipSuccess) return e;
+  }
   e = hipFuncSetAttribute((const void *)k_init, hipFuncAttributeMaxDynamicSharedMemorySize,
                           LDS_BUDGET);
   if (e != hipSuccess) return e;
@@ -912,7 +936,23 @@ hipError_t launch_init(const LaunchArgs &a, double lb, double ub) {
 hipError_t launch_generations(const LaunchArgs &a, const uint32_t *list, uint32_t n,
                               uint32_t g0, uint32_t n_gens, float lb, float ub, TraceArgs tr) {
   if (n == 0) return hipSuccess;
-  if (tr.u)
+  const bool trace = tr.u != nullptr;
+#define MDE_LAUNCH_KIND(T, K)                                                                   \
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_generations_kind<T, K>), dim3(n), dim3(GEN_THREADS),     \
+                     a.lds_bytes, a.stream, a.runs, list, a.probs, a.tab, a.pop, a.fit, g0,      \
+                     n_gens, a.k0, a.k1, lb, ub, tr)
+#define MDE_KIND_CASE(K)                      \
+  case K:                                     \
+    if (trace) MDE_LAUNCH_KIND(true, K);      \
+    else MDE_LAUNCH_KIND(false, K);           \
+    return hipGetLastError();
+  switch (a.lane_kind) {
+    MDE_KINDS(MDE_KIND_CASE)
+    default: break;
+  }
+#undef MDE_KIND_CASE
+#undef MDE_LAUNCH_KIND
+  if (trace)
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_generations<true>), dim3(n), dim3(GEN_THREADS),
                        a.lds_bytes, a.stream, a.runs, list, a.probs, a.tab, a.pop, a.fit, g0,
                        n_gens, a.k0, a.k1, lb, ub, tr);
