@@ -49,8 +49,7 @@ KERNEL_SOURCES = {
 MEASURED_TRAFFIC = {
     # keyed by the kernel's source hash and the launch configuration the counters were
     # taken in (parts per trial, or precision and row tiles per rotation item)
-    "1eb6d7bc90409b0c:lp2": (500.21 * 2.0 + 526.0 * 1.0) * 1024,       # k_generations, C3
-    "1eb6d7bc90409b0c:lp4": (496.71 * 2.0 + 526.0 * 1.0) * 1024,
+    "a2860e14e11811ba:lp0": (472.075 * 2.0 + 526.0 * 1.0) * 1024,      # k_generations_kind, C3
     "e6e8e54ceeb0ff0f:fp32:r2": (26553.1 * 2.0 + 7045710.8 * 1.0) * 1024,
     "e6e8e54ceeb0ff0f:bf16:r4": (25155.5 * 2.0 + 6229626.4 * 1.0) * 1024,
 }
@@ -589,7 +588,7 @@ def main():
                      "traffic": (MEASURED_TRAFFIC.get(f"{kernel_source_hash()}"
                                                       f":lp{tuning['lane_parts']}")
                                  if args.workload == "c3" else None),
-                     "kernel": "k_generations", "avg_launch_ms": avg_launch_ms,
+                     "kernel": "k_generations_kind<hybrid>", "avg_launch_ms": avg_launch_ms,
                      "launches": k_launches, "slots_per_launch": slots_per_launch,
                      "occupied_cu_frac": min(P, 256) / 256.0,
                      "frac_of_occupied_cus": achieved / VALU_PEAK_SLOTS / (min(P, 256) / 256.0)},
