@@ -381,15 +381,17 @@ struct BoundCheck {
 };
 
 // Producer waves: the random draws of generation g + 1 (crossover-test
-// nibbles during the rotation, packed draws after the decisions).  Runs the
-// same barrier sequence as mfma_consumers -- one before the loop, five per
-// generation (eight in the bf16 mode), one after it -- so the two roles keep
-// separate loops and neither holds the other's registers.
-template <bool BF16, typename BODY>
+// nibbles during the trial construction or the rotation, packed draws after
+// the decisions), rotation items, and in the bf16 mode a third of the exact
+// re-evaluation's items.  Runs the same barrier sequence as the consumers --
+// one before the loop, five per generation (eight in the bf16 mode), one
+// after it -- so the two roles keep separate loops.
+template <bool BF16, typename BODY, typename REEVAL>
 __device__ __forceinline__ void mfma_producers(const MLds &lay, unsigned char *smem,
                                                const RunDev &run, uint32_t g0, uint32_t n_gens,
                                                uint32_t k0, uint32_t k1, uint32_t ptid,
-                                               uint32_t *ctr, uint32_t n_items, BODY &&item) {
+                                               uint32_t *ctr, uint32_t n_items, BODY &&item,
+                                               const uint32_t *cnts, REEVAL &&reeval) {
   const uint32_t N = run.N, D = run.D, Q = run.Dp / 4, kp = run.kp;
   uint8_t *const mbuf[2] = {reinterpret_cast<uint8_t *>(smem + lay.msk),
                             reinterpret_cast<uint8_t *>(smem + lay.msk2)};
@@ -426,6 +428,17 @@ __device__ __forceinline__ void mfma_producers(const MLds &lay, unsigned char *s
       MDE_STAGE(5)
       __syncthreads(); // candidate list
       MDE_STAGE(6)
+      {
+        // help with the exact re-evaluation: the candidate count from the
+        // consumers' per-wave counts, items dealt as to the consumers
+        uint32_t total = 0;
+        for (uint32_t w = 0; w < MF_CONSUMERS / 64; ++w) total += cnts[w];
+        const uint32_t NCT = run.NCT;
+        const uint32_t n_re = NCT * (((total + 15) / 16 + RT - 1) / RT);
+        for (uint32_t it = MF_CONSUMERS / 64 + ptid / 64; it < n_re; it += MF_THREADS / 64)
+          reeval(it, total);
+      }
+      MDE_STAGE_WORK(15)
       __syncthreads(); // re-evaluation
       MDE_STAGE(7)
     }
@@ -538,10 +551,35 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
       }
     }
   };
+  // bf16 mode: one (output tile, row tile group) item of the exact re-evaluation
+  // of the candidate list (total candidates, cl), run by consumers and producers
+  auto reeval = [&](uint32_t it, uint32_t total) {
+    const uint32_t lane = tid & 63;
+    const uint32_t ci = it % NCT, rt0 = (it / NCT) * RT;
+    bool rok[RT];
+    uint32_t rtr[RT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+      const uint32_t srow = 16 * (rt0 + r) + (lane & 15);
+      rok[r] = srow < total;
+      rtr[r] = rok[r] ? cl[srow] : 0u;
+    }
+    d4v acc[RT];
+    tiles_f64(Tg, Dk, rok, rtr, R32, Rs, 16 * ci + (lane & 15), lane, acc);
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+      float z[4];
+      tile_z(acc[r], ro_s, ci, lane, z);
+      const uint32_t slot = 16 * (rt0 + r) + (lane & 15);
+      const float e0[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+      tile_epilogue<false, true>(p, ek_s, ew_s, z, slot, rok[r], e0, D, ci, N, lane, Ps, Pb, zf,
+                                 zl);
+    }
+  };
   // the role is uniform per wave (whole waves on either side of MF_CONSUMERS)
   if (__builtin_amdgcn_readfirstlane(tid >> 6) >= MF_CONSUMERS / 64) {
     mfma_producers<BF16>(lay, smem, run, g0, n_gens, k0, k1, tid - MF_CONSUMERS, cnt + 15,
-                         n_items, item);
+                         n_items, item, cnt, reeval);
   } else {
   constexpr bool producer = false;
   const uint32_t lane = tid & 63;
@@ -704,31 +742,11 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
       __syncthreads();
       MDE_STAGE(6)
       // S5: plain re-evaluation of the candidates on compacted row tiles,
-      // (output tile, row tile group) items dealt to all consumer waves
+      // (output tile, row tile group) items dealt to all twelve waves (the
+      // producers take items 8..11, 20..23, ...)
       if (!producer) {
-        const uint32_t n_items = NCT * (((total + 15) / 16 + RT - 1) / RT);
-        for (uint32_t it = wave; it < n_items; it += MF_CONSUMERS / 64) {
-          const uint32_t ci = it % NCT, rt0 = (it / NCT) * RT;
-          bool rok[RT];
-          uint32_t rtr[RT];
-#pragma unroll
-          for (int r = 0; r < RT; ++r) {
-            const uint32_t srow = 16 * (rt0 + r) + (lane & 15);
-            rok[r] = srow < total;
-            rtr[r] = rok[r] ? cl[srow] : 0u;
-          }
-          d4v acc[RT];
-          tiles_f64(Tg, Dk, rok, rtr, R32, Rs, 16 * ci + (lane & 15), lane, acc);
-#pragma unroll
-          for (int r = 0; r < RT; ++r) {
-            float z[4];
-            tile_z(acc[r], ro_s, ci, lane, z);
-            const uint32_t slot = 16 * (rt0 + r) + (lane & 15);   // position in the candidate list
-            const float e0[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-            tile_epilogue<false, true>(p, ek_s, ew_s, z, slot, rok[r], e0, D, ci, N, lane, Ps,
-                                       Pb, zf, zl);
-          }
-        }
+        const uint32_t n_re = NCT * (((total + 15) / 16 + RT - 1) / RT);
+        for (uint32_t it = wave; it < n_re; it += MF_THREADS / 64) reeval(it, total);
       }
       MDE_STAGE_WORK(15)
       __syncthreads();
