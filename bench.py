@@ -50,8 +50,8 @@ MEASURED_TRAFFIC = {
     # keyed by the kernel's source hash and the launch configuration the counters were
     # taken in (parts per trial, or precision and row tiles per rotation item)
     "a2860e14e11811ba:lp0": (472.075 * 2.0 + 526.0 * 1.0) * 1024,      # k_generations_kind, C3
-    "2239c0e3f9ad6ca5:fp32:r2": (24760.75 * 2.0 + 7106766.4 * 1.0) * 1024,
-    "2239c0e3f9ad6ca5:bf16:r4": (22846.5 * 2.0 + 6336031.8 * 1.0) * 1024,
+    "03581fcbb624626c:fp32:r2": (74185.1 * 2.0 + 6963525.1 * 1.0) * 1024,
+    "03581fcbb624626c:bf16:r4": (66481.4 * 2.0 + 6232878.6 * 1.0) * 1024,
 }
 
 PHILOX_SLOTS = 100   # 10 rounds x (2 quarter-rate 32x32->64 multiplies + 2 three-input XORs)

@@ -91,19 +91,7 @@ __device__ __forceinline__ void tiles_f64(const float *__restrict__ Tg, uint32_t
                         : make_float4(0.f, 0.f, 0.f, 0.f);
     bv = *reinterpret_cast<const float4 *>(rrow + 16 * b);
   };
-  float4 tn[RR], tm[RR];
-  float4 bn, bm;
-  load(0, tn, bn);
-  if (nb > 1) load(1, tm, bm);
-#pragma unroll 1
-  for (uint32_t b = 0; b < nb; ++b) {
-    // the loads of the next two blocks are in flight while this block's products run
-    float4 tv[RR];
-#pragma unroll
-    for (int r = 0; r < RR; ++r) { tv[r] = tn[r]; tn[r] = tm[r]; }
-    const float4 bv = bn;
-    bn = bm;
-    if (b + 2 < nb) load(b + 2, tm, bm);
+  auto products = [&](const float4 (&tv)[RR], const float4 &bv) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const double re = (double)comp(bv, e);
@@ -111,6 +99,24 @@ __device__ __forceinline__ void tiles_f64(const float *__restrict__ Tg, uint32_t
       for (int r = 0; r < RR; ++r)
         acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(re, (double)comp(tv[r], e), acc[r], 0, 0, 0);
     }
+  };
+  // three operand buffers in turn, the loop unrolled by three so that the
+  // turn is a renaming at compile time (no register moves between products);
+  // the loads of the next two blocks are in flight while a block's products run
+  float4 t0[RR], t1[RR], t2[RR];
+  float4 b0, b1, b2;
+  load(0, t0, b0);
+  if (nb > 1) load(1, t1, b1);
+#pragma unroll 1
+  for (uint32_t b = 0; b < nb; b += 3) {
+    if (b + 2 < nb) load(b + 2, t2, b2);
+    products(t0, b0);
+    if (b + 1 >= nb) break;
+    if (b + 3 < nb) load(b + 3, t0, b0);
+    products(t1, b1);
+    if (b + 2 >= nb) break;
+    if (b + 4 < nb) load(b + 4, t1, b1);
+    products(t2, b2);
   }
 }
 
