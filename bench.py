@@ -50,9 +50,8 @@ MEASURED_TRAFFIC = {
     # keyed by the kernel's source hash and the launch configuration the counters were
     # taken in (parts per trial, or precision and row tiles per rotation item)
     "a2860e14e11811ba:lp0": (472.075 * 2.0 + 526.0 * 1.0) * 1024,      # k_generations_kind, C3
-    "03581fcbb624626c:fp32:r2": (74185.1 * 2.0 + 6963525.1 * 1.0) * 1024,
-    "03581fcbb624626c:fp32:r4": (32727.6 * 2.0 + 7070244.9 * 1.0) * 1024,
-    "03581fcbb624626c:bf16:r4": (23111.8 * 2.0 + 6363139.1 * 1.0) * 1024,
+    "a5bacdb1c5c69aa0:fp32:r4": (31523.5 * 2.0 + 7060453.8 * 1.0) * 1024,
+    "a5bacdb1c5c69aa0:bf16:r4": (26674.3 * 2.0 + 6219097.7 * 1.0) * 1024,
 }
 
 PHILOX_SLOTS = 100   # 10 rounds x (2 quarter-rate 32x32->64 multiplies + 2 three-input XORs)

@@ -152,7 +152,7 @@ __device__ __forceinline__ void rotation_items(uint32_t *ctr, uint32_t n_items, 
 // z_hat[trial 16 rt + l%16][output 16 ct + 4 (l/16) + v].  The trial operands
 // are the bf16 splits of y = u - o (float32 subtraction), formed here from the
 // float32 trial rows, which the exact re-evaluation reads as well: one buffer
-// per run in the cache instead of three.  ab[r] receives
+// per run in the cache instead of three.  ab[c][r] receives
 // sum_k |R_hi jk| |y_hi k| for the outputs' error radii.
 __device__ __forceinline__ bf8v abs8(const bf8v &x) {
   uint4 u = __builtin_bit_cast(uint4, x);
@@ -174,33 +174,28 @@ __device__ __forceinline__ void split8(const float4 &a, const float4 &b, bf8v &h
   }
 }
 
+// Two output tiles per call (R rows Rrow0 and Rrow0 + 16 Rs; col1 false: the
+// second is past the last tile), so that the splits of each trial value,
+// the bulk of this vector-bound stage, are formed once for both.
 __device__ __forceinline__ void tiles_bf16(const float *__restrict__ Tg,
                                            const float *__restrict__ oc, uint32_t Dk,
                                            const bool (&row_ok)[RT],
                                            const uint32_t (&row_trial)[RT],
-                                           const float *__restrict__ Rrow, uint32_t Rs,
-                                           uint32_t lane, f4v (&acc)[RT], f4v (&ab)[RT]) {
+                                           const float *__restrict__ Rrow0, bool col1,
+                                           uint32_t Rs, uint32_t lane, f4v (&acc)[2][RT],
+                                           f4v (&ab)[2][RT]) {
   const uint32_t Ksb = Dk / 32;
 #pragma unroll
-  for (int r = 0; r < RT; ++r) {
-    acc[r] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
-    ab[r] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
-  }
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+      acc[c][r] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
+      ab[c][r] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
+    }
 #pragma unroll
   for (int s = 0; s < KSB; ++s) {
     if ((uint32_t)s < Ksb) {
       const uint32_t k0 = 32 * s + 8 * (lane >> 4);
-      // this lane's eight coefficients of R, split into bf16 parts here (a
-      // table of the splits would add to the generation's cache footprint)
-      bf8v bh, bl;
-      {
-        float4 ra = make_float4(0.f, 0.f, 0.f, 0.f), rb = ra;
-        if (k0 < Rs) {
-          ra = *reinterpret_cast<const float4 *>(Rrow + k0);
-          rb = *reinterpret_cast<const float4 *>(Rrow + k0 + 4);
-        }
-        split8(ra, rb, bh, bl);
-      }
       const float4 oa = *reinterpret_cast<const float4 *>(oc + k0);
       const float4 ob = *reinterpret_cast<const float4 *>(oc + k0 + 4);
       bf8v ah[RT], al[RT];
@@ -218,18 +213,36 @@ __device__ __forceinline__ void tiles_bf16(const float *__restrict__ Tg,
           for (int e = 0; e < 8; ++e) ah[r][e] = al[r][e] = (__bf16)0.0f;
         }
       }
+      bf8v aab[RT];
 #pragma unroll
-      for (int r = 0; r < RT; ++r) acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh, al[r], acc[r], 0, 0, 0);
+      for (int r = 0; r < RT; ++r) aab[r] = abs8(ah[r]);
 #pragma unroll
-      for (int r = 0; r < RT; ++r) acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bl, ah[r], acc[r], 0, 0, 0);
+      for (int c = 0; c < 2; ++c) {
+        if (c == 1 && !col1) break;
+        bf8v bh, bl;
+        {
+          const float *Rrow = Rrow0 + (size_t)(16 * c) * Rs;
+          float4 ra = make_float4(0.f, 0.f, 0.f, 0.f), rb = ra;
+          if (k0 < Rs) {
+            ra = *reinterpret_cast<const float4 *>(Rrow + k0);
+            rb = *reinterpret_cast<const float4 *>(Rrow + k0 + 4);
+          }
+          split8(ra, rb, bh, bl);
+        }
 #pragma unroll
-      for (int r = 0; r < RT; ++r) acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh, ah[r], acc[r], 0, 0, 0);
-      const bf8v bab = abs8(bh);
+        for (int r = 0; r < RT; ++r) acc[c][r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh, al[r], acc[c][r], 0, 0, 0);
 #pragma unroll
-      for (int r = 0; r < RT; ++r) ab[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bab, abs8(ah[r]), ab[r], 0, 0, 0);
+        for (int r = 0; r < RT; ++r) acc[c][r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bl, ah[r], acc[c][r], 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < RT; ++r) acc[c][r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh, ah[r], acc[c][r], 0, 0, 0);
+        const bf8v bab = abs8(bh);
+#pragma unroll
+        for (int r = 0; r < RT; ++r) ab[c][r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bab, aab[r], ab[c][r], 0, 0, 0);
+      }
     }
   }
 }
+
 
 // ---------------------------------------------------------------- element terms and bounds
 
@@ -522,7 +535,9 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
   // tile, RTF row tiles) in float64; bf16, (output tile, RT row tiles)
   // from the bf16 splits with each output's error radius
   constexpr uint32_t RTI = BF16 ? RT : RTF;
-  const uint32_t n_items = NCT * ((NRT + RTI - 1) / RTI);
+  // bf16 mode: items of 2 output tiles x RT row tiles
+  const uint32_t NCP = (NCT + 1) / 2;
+  const uint32_t n_items = BF16 ? NCP * ((NRT + RT - 1) / RT) : NCT * ((NRT + RTI - 1) / RTI);
   auto item = [&](uint32_t it) {
     const uint32_t lane = tid & 63;
     const uint32_t ci = it % NCT, rt0 = (it / NCT) * RTI;
@@ -534,15 +549,29 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
       rok[r] = rtr[r] < N;
     }
     if constexpr (BF16) {
-      f4v acc[RT], ab[RT];
-      tiles_bf16(Tg, oc, Dk, rok, rtr, R32 + (size_t)(16 * ci + (lane & 15)) * Rs, Rs, lane, acc,
-                 ab);
+      const uint32_t c0 = 2 * (it % NCP), rb0 = (it / NCP) * RT;
+      const bool col1 = c0 + 1 < NCT;
+      bool rok2[RT];
+      uint32_t rtr2[RT];
 #pragma unroll
       for (int r = 0; r < RT; ++r) {
-        const float z[4] = {acc[r][0], acc[r][1], acc[r][2], acc[r][3]};
-        const float e[4] = {E_AB * ab[r][0], E_AB * ab[r][1], E_AB * ab[r][2], E_AB * ab[r][3]};
-        tile_epilogue<true, false>(p, ek_s, ew_s, z, rtr[r], rok[r], e, D, ci, N, lane, Ps, Pb,
-                                   zf, zl);
+        rtr2[r] = 16 * (rb0 + r) + (lane & 15);
+        rok2[r] = rtr2[r] < N;
+      }
+      f4v acc[2][RT], ab[2][RT];
+      tiles_bf16(Tg, oc, Dk, rok2, rtr2, R32 + (size_t)(16 * c0 + (lane & 15)) * Rs, col1, Rs,
+                 lane, acc, ab);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        if (c == 1 && !col1) break;
+#pragma unroll
+        for (int r = 0; r < RT; ++r) {
+          const float z[4] = {acc[c][r][0], acc[c][r][1], acc[c][r][2], acc[c][r][3]};
+          const float e[4] = {E_AB * ab[c][r][0], E_AB * ab[c][r][1], E_AB * ab[c][r][2],
+                              E_AB * ab[c][r][3]};
+          tile_epilogue<true, false>(p, ek_s, ew_s, z, rtr2[r], rok2[r], e, D, c0 + c, N, lane,
+                                     Ps, Pb, zf, zl);
+        }
       }
     } else {
       d4v acc[RTF];
