@@ -50,8 +50,8 @@ MEASURED_TRAFFIC = {
     # keyed by the kernel's source hash and the launch configuration the counters were
     # taken in (parts per trial, or precision and row tiles per rotation item)
     "a2860e14e11811ba:lp0": (472.075 * 2.0 + 526.0 * 1.0) * 1024,      # k_generations_kind, C3
-    "a5bacdb1c5c69aa0:fp32:r4": (31523.5 * 2.0 + 7060453.8 * 1.0) * 1024,
-    "a5bacdb1c5c69aa0:bf16:r4": (26674.3 * 2.0 + 6219097.7 * 1.0) * 1024,
+    "3760489cb2075ba0:fp32:r4": (30396.6 * 2.0 + 7063607.6 * 1.0) * 1024,
+    "3760489cb2075ba0:bf16:r4": (46001.8 * 2.0 + 6020998.0 * 1.0) * 1024,
 }
 
 PHILOX_SLOTS = 100   # 10 rounds x (2 quarter-rate 32x32->64 multiplies + 2 three-input XORs)

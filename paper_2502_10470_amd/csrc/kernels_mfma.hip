@@ -128,13 +128,14 @@ __device__ __forceinline__ void tile_z(const d4v &acc, const double *ro, uint32_
   for (int v = 0; v < 4; ++v) z[v] = (float)(acc[v] - ro[16 * ct + (lane >> 4) + 4 * v]);
 }
 
-// The rotation of a generation as (output tile, group of row tiles) items,
+// The rotation of a generation as (output tiles, group of row tiles) items,
 // fetched from a counter in LDS by every wave that calls this (the consumers
 // as soon as the trials are built, the producers once the next generation's
 // crossover tests are drawn: before the rotation with two mask buffers,
 // during it with one), so that one wave's products run while
-// another waits for its loads or forms the element terms.  Items that share
-// row tiles are adjacent in the order, so their trial rows come from cache.
+// another waits for its loads or forms the element terms.  In the plain mode
+// items that share row tiles are adjacent in the order, so their trial rows
+// come from cache; the bf16 mode orders its items by output-tile group.
 template <typename BODY>
 __device__ __forceinline__ void rotation_items(uint32_t *ctr, uint32_t n_items, uint32_t lane,
                                                BODY &&body) {
@@ -174,19 +175,20 @@ __device__ __forceinline__ void split8(const float4 &a, const float4 &b, bf8v &h
   }
 }
 
-// Two output tiles per call (R rows Rrow0 and Rrow0 + 16 Rs; col1 false: the
-// second is past the last tile), so that the splits of each trial value,
-// the bulk of this vector-bound stage, are formed once for both.
+// BCT output tiles per call (R rows Rrow0, Rrow0 + 16 Rs, ...; the first ncol
+// of them exist), so that the splits of each trial value, the bulk of this
+// vector-bound stage, are formed once for all of them.
+constexpr int BCT = 4;
 __device__ __forceinline__ void tiles_bf16(const float *__restrict__ Tg,
                                            const float *__restrict__ oc, uint32_t Dk,
                                            const bool (&row_ok)[RT],
                                            const uint32_t (&row_trial)[RT],
-                                           const float *__restrict__ Rrow0, bool col1,
-                                           uint32_t Rs, uint32_t lane, f4v (&acc)[2][RT],
-                                           f4v (&ab)[2][RT]) {
+                                           const float *__restrict__ Rrow0, uint32_t ncol,
+                                           uint32_t Rs, uint32_t lane, f4v (&acc)[BCT][RT],
+                                           f4v (&ab)[BCT][RT]) {
   const uint32_t Ksb = Dk / 32;
 #pragma unroll
-  for (int c = 0; c < 2; ++c)
+  for (int c = 0; c < BCT; ++c)
 #pragma unroll
     for (int r = 0; r < RT; ++r) {
       acc[c][r] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
@@ -217,8 +219,8 @@ __device__ __forceinline__ void tiles_bf16(const float *__restrict__ Tg,
 #pragma unroll
       for (int r = 0; r < RT; ++r) aab[r] = abs8(ah[r]);
 #pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        if (c == 1 && !col1) break;
+      for (int c = 0; c < BCT; ++c) {
+        if ((uint32_t)c >= ncol) break;
         bf8v bh, bl;
         {
           const float *Rrow = Rrow0 + (size_t)(16 * c) * Rs;
@@ -535,8 +537,8 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
   // tile, RTF row tiles) in float64; bf16, (output tile, RT row tiles)
   // from the bf16 splits with each output's error radius
   constexpr uint32_t RTI = BF16 ? RT : RTF;
-  // bf16 mode: items of 2 output tiles x RT row tiles
-  const uint32_t NCP = (NCT + 1) / 2;
+  // bf16 mode: items of BCT output tiles x RT row tiles
+  const uint32_t NCP = (NCT + BCT - 1) / BCT;
   const uint32_t n_items = BF16 ? NCP * ((NRT + RT - 1) / RT) : NCT * ((NRT + RTI - 1) / RTI);
   auto item = [&](uint32_t it) {
     const uint32_t lane = tid & 63;
@@ -549,8 +551,12 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
       rok[r] = rtr[r] < N;
     }
     if constexpr (BF16) {
-      const uint32_t c0 = 2 * (it % NCP), rb0 = (it / NCP) * RT;
-      const bool col1 = c0 + 1 < NCT;
+      // items of the first (full) group of output tiles first: the group that
+      // holds the last tiles can be narrower, and its shorter items end the
+      // stage with less of a tail
+      const uint32_t NRG = (NRT + RT - 1) / RT;
+      const uint32_t c0 = BCT * (it / NRG), rb0 = (it % NRG) * RT;
+      const uint32_t ncol = min(NCT - c0, (uint32_t)BCT);
       bool rok2[RT];
       uint32_t rtr2[RT];
 #pragma unroll
@@ -558,12 +564,12 @@ __device__ __forceinline__ void mfma_body(unsigned char *smem, const RunDev &run
         rtr2[r] = 16 * (rb0 + r) + (lane & 15);
         rok2[r] = rtr2[r] < N;
       }
-      f4v acc[2][RT], ab[2][RT];
-      tiles_bf16(Tg, oc, Dk, rok2, rtr2, R32 + (size_t)(16 * c0 + (lane & 15)) * Rs, col1, Rs,
+      f4v acc[BCT][RT], ab[BCT][RT];
+      tiles_bf16(Tg, oc, Dk, rok2, rtr2, R32 + (size_t)(16 * c0 + (lane & 15)) * Rs, ncol, Rs,
                  lane, acc, ab);
 #pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        if (c == 1 && !col1) break;
+      for (int c = 0; c < BCT; ++c) {
+        if ((uint32_t)c >= ncol) break;
 #pragma unroll
         for (int r = 0; r < RT; ++r) {
           const float z[4] = {acc[c][r][0], acc[c][r][1], acc[c][r][2], acc[c][r][3]};
