@@ -402,3 +402,21 @@ def test_random_batches(seed):
         b.close()
     print("run-generations compared:", compared)
     assert compared >= 200
+
+
+def test_per_kind_kernel_matches_generic_kernel():
+    """A batch whose runs all have one kind runs that kind's own generation
+    kernel, a batch of several kinds the generic one; both hold the same loop,
+    so the same runs must end bit for bit equal after a full-length launch."""
+    kinds = ["hybrid", "hybrid", "hybrid", "rastrigin"]
+    wl_one = W.small_batch(4242, kinds[:3], [100] * 3, [20] * 3, n_cs=3)
+    wl_mix = W.small_batch(4242, kinds, [100] * 4, [20] * 4, n_cs=3)
+    assert np.array_equal(wl_one.theta, wl_mix.theta[:3])
+    a, b = _batch(wl_one), _batch(wl_mix)
+    a.inner_step(300)
+    b.inner_step(300)
+    pa, fa = a.host_state()
+    pb, fb = b.host_state()
+    for r in range(3):
+        assert np.array_equal(a.run_pop(pa, r), b.run_pop(pb, r)), f"run {r}: populations differ"
+        assert np.array_equal(a.run_fit(fa, r), b.run_fit(fb, r)), f"run {r}: fitness differs"
